@@ -1,0 +1,991 @@
+/*
+ * oracle.c -- plain, slow CPU oracle for splitting the Mandelbrot polynomials
+ *
+ *     p_n(c)     = f_c^n(0)                     (Section 1, eq. def:hyp_poly)
+ *     q_{l,n}(c) = p_{l+n}(c) - p_l(c)          (Section 1, eq. def:mis_poly)
+ *
+ * TEST INFRASTRUCTURE.  Only tests/, the smoke check of __graft_entry__ and the
+ * cpu_baseline leg of bench.py load this library.  The product library
+ * (paper_2402_06083_amd/) never links, calls or loads it, and the two share no
+ * code, headers or constant tables.
+ *
+ * Arithmetic: x87 long double (64-bit significand) for every step of the method,
+ * a hand-written double-double (Dekker splitting, no FMA) for the final Newton
+ * polish and for the multiple-root test of q_{l,n}, and long-double disk
+ * arithmetic with radii evaluated in the FPU's round-upward mode for the
+ * certificate.  Compiled with -frounding-math -ffp-contract=off.
+ *
+ * The steps follow the paper in its order:
+ *   1. real end points of the level curve |P| = lambda_0 by dichotomy
+ *      (Section 6.3.1, implementation of the level line algorithm);
+ *   2. the discrete level line L_{lambda_0,N}(P) walked with the Newton map
+ *      with target, M points per turn (Section 4.1, Prop. computeLevelLine and
+ *      the remark that follows it);
+ *   3. for large degrees the coarse line L_{lambda_0,2^15}(p_16), each point
+ *      lifted p_k -> p_{k+1} by solving p_{k+1} = lambda_0^2 and then lowering
+ *      the target radius back to lambda_0 (Section 4.2, Algorithm S_par and the
+ *      text after it); for q_{l,n} the lifted p_{l+n} points are corrected onto
+ *      q_{l,n} = lambda_0 (their phase index is unchanged because |p_l| is small
+ *      against lambda_0 on that curve);
+ *   4. the segments between consecutive coarse points walked independently,
+ *      every (M/4)-th point (values lambda_0 * {1, i, -1, -i}, Thm practicalFTA)
+ *      being a starting point; each segment must end on the next coarse point;
+ *   5. a Newton descent from every starting point, capped at
+ *      max{20, I_N log d} steps (Section 4.2), discarded on divergence
+ *      (non-finite, far from D(0,2), long-distance jump) or time-out;
+ *   6. collection in the nset sense (Section 6.1): upper half plane only,
+ *      |Im| < eps/2 snapped to the real axis, lexicographic order, points closer
+ *      than eps in both coordinates identified;
+ *   7. classification: p_n -- exact period by lookup among the roots of p_k,
+ *      k | n (computed by the same oracle), cross-checked by the Newton distance
+ *      |p_k / p_k'|; q_{l,n} -- membership of Mis(l,n) from its definition
+ *      (eq. def:mis) with the Newton distance as the zero test, after removing
+ *      descents that stalled near a multiple (hyperbolic) root;
+ *   8. certification by Thm proofRoots in disk arithmetic (Thm diskArithmetic).
+ */
+#include <complex.h>
+#include <fenv.h>
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef long double ld;
+typedef long double complex cld;
+
+#define PI_L 3.141592653589793238462643383279502884L
+
+/* ------------------------------------------------------------------------- */
+/* Polynomial evaluation through the critical orbit.                          */
+/* Section 2, eq. defFundMap: p_k(c) = f_c^k(0), so p_{k+1} = p_k^2 + c, and  */
+/* by the chain rule p'_{k+1} = 2 p_k p'_k + 1 (Section 6.3.2 derives the     */
+/* same derivative in closed form, eq. DerParamDyna).  q_{0,n} = p_n since    */
+/* p_0 = 0 (eq. hypCase).                                                     */
+/* ------------------------------------------------------------------------- */
+static void eval_q(int l, int n, cld c, cld *P, cld *dP)
+{
+    cld z = 0, dz = 0, zl = 0, dzl = 0;
+    for (int k = 1; k <= l + n; k++) {
+        dz = 2 * z * dz + 1; /* uses p_{k-1} */
+        z = z * z + c;
+        if (k == l) { zl = z; dzl = dz; }
+    }
+    *P = z - zl;
+    *dP = dz - dzl;
+}
+
+/* p_k and p_k' for k = 0..N in one pass */
+static void orbit_all(int N, cld c, cld *z, cld *dz)
+{
+    z[0] = 0; dz[0] = 0;
+    for (int k = 1; k <= N; k++) {
+        dz[k] = 2 * z[k - 1] * dz[k - 1] + 1;
+        z[k] = z[k - 1] * z[k - 1] + c;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Double-double, Dekker/Knuth error-free transformations (no FMA).           */
+/* ------------------------------------------------------------------------- */
+typedef struct { double hi, lo; } dd;
+typedef struct { dd re, im; } cdd;
+
+static inline dd two_sum(double a, double b)
+{
+    double s = a + b, bb = s - a;
+    dd r = { s, (a - (s - bb)) + (b - bb) };
+    return r;
+}
+static inline dd quick_two_sum(double a, double b)
+{
+    double s = a + b;
+    dd r = { s, b - (s - a) };
+    return r;
+}
+static inline void split(double a, double *h, double *l)
+{
+    double t = 134217729.0 * a; /* 2^27 + 1 */
+    *h = t - (t - a);
+    *l = a - *h;
+}
+static inline dd two_prod(double a, double b)
+{
+    double p = a * b, ah, al, bh, bl;
+    split(a, &ah, &al);
+    split(b, &bh, &bl);
+    dd r = { p, ((ah * bh - p) + ah * bl + al * bh) + al * bl };
+    return r;
+}
+static inline dd dd_add(dd a, dd b)
+{
+    dd s = two_sum(a.hi, b.hi), t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = quick_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+static inline dd dd_neg(dd a) { dd r = { -a.hi, -a.lo }; return r; }
+static inline dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+static inline dd dd_mul(dd a, dd b)
+{
+    dd p = two_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo + a.lo * b.hi;
+    return quick_two_sum(p.hi, p.lo);
+}
+static inline dd dd_div(dd a, dd b)
+{
+    double q1 = a.hi / b.hi;
+    dd r = dd_sub(a, dd_mul((dd){ q1, 0 }, b));
+    double q2 = r.hi / b.hi;
+    r = dd_sub(r, dd_mul((dd){ q2, 0 }, b));
+    double q3 = r.hi / b.hi;
+    dd q = quick_two_sum(q1, q2);
+    return dd_add(q, (dd){ q3, 0 });
+}
+static inline cdd cdd_add(cdd a, cdd b) { cdd r = { dd_add(a.re, b.re), dd_add(a.im, b.im) }; return r; }
+static inline cdd cdd_sub(cdd a, cdd b) { cdd r = { dd_sub(a.re, b.re), dd_sub(a.im, b.im) }; return r; }
+static inline cdd cdd_mul(cdd a, cdd b)
+{
+    cdd r = { dd_sub(dd_mul(a.re, b.re), dd_mul(a.im, b.im)),
+              dd_add(dd_mul(a.re, b.im), dd_mul(a.im, b.re)) };
+    return r;
+}
+static inline cdd cdd_div(cdd a, cdd b)
+{
+    dd den = dd_add(dd_mul(b.re, b.re), dd_mul(b.im, b.im));
+    cdd num = { dd_add(dd_mul(a.re, b.re), dd_mul(a.im, b.im)),
+                dd_sub(dd_mul(a.im, b.re), dd_mul(a.re, b.im)) };
+    cdd r = { dd_div(num.re, den), dd_div(num.im, den) };
+    return r;
+}
+static inline dd dd_from_ld(ld x)
+{
+    double h = (double)x;
+    dd r = { h, (double)(x - (ld)h) };
+    return r;
+}
+static inline ld ld_from_dd(dd a) { return (ld)a.hi + (ld)a.lo; }
+
+/* Newton step of q_{l,n} evaluated in double-double: returns P/P' */
+static cdd dd_newton_step(int l, int n, cdd c)
+{
+    cdd z = { { 0, 0 }, { 0, 0 } }, dz = z, zl = z, dzl = z;
+    const cdd one = { { 1, 0 }, { 0, 0 } };
+    for (int k = 1; k <= l + n; k++) {
+        cdd t = cdd_mul(z, dz);
+        dz = cdd_add(cdd_add(t, t), one);
+        z = cdd_add(cdd_mul(z, z), c);
+        if (k == l) { zl = z; dzl = dz; }
+    }
+    return cdd_div(cdd_sub(z, zl), cdd_sub(dz, dzl));
+}
+
+/* ------------------------------------------------------------------------- */
+/* Parameters of the method (Section 4.2 and Section 6.3.1).                   */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int l, n;          /* type; l = 0 is p_n */
+    int order;         /* l + n; deg P = 2^(order-1) */
+    int64_t D;         /* degree */
+    ld level;          /* lambda_0: 5 for p_n, 100 for q_{l,n} */
+    int M;             /* points per turn */
+    int cap;           /* Newton cap max{20, I_N log d} */
+} method_t;
+
+static void method_init(method_t *m, int l, int n)
+{
+    m->l = l; m->n = n; m->order = l + n;
+    m->D = (int64_t)1 << (m->order - 1);
+    m->level = (l == 0) ? 5.0L : 100.0L;
+    m->M = (l == 0 && m->order >= 30) ? 16 : 8;
+    ld IN = (l == 0) ? 1.0L : 2.6L;
+    ld capf = ceill(IN * logl((ld)m->D));
+    m->cap = capf > 20 ? (int)capf : 20;
+}
+
+/* Thresholds of the oracle's own stopping rules (long double). */
+#define TOL_SOLVE 0x1p-58L   /* Newton-with-target: relative step */
+#define MAXIT_SOLVE 64
+#define TOL_DESC 0x1p-56L    /* descent: relative step */
+#define DIVERGE_RADIUS 8.0L
+#define MAX_HALVINGS 8
+
+/* ------------------------------------------------------------------------- */
+/* Newton map with target (Section 4.1): iterate N_{P - T} from *z.           */
+/* Returns the number of steps when the step fell below TOL_SOLVE, 0 if it    */
+/* did not converge, -1 if the iterate became non-finite.                     */
+/* ------------------------------------------------------------------------- */
+static int solve_target(int l, int n, cld *z, cld T, int64_t *steps)
+{
+    cld w = *z;
+    for (int it = 1; it <= MAXIT_SOLVE; it++) {
+        cld P, dP;
+        eval_q(l, n, w, &P, &dP);
+        cld s = (P - T) / dP;
+        w -= s;
+        (*steps)++;
+        if (!isfinite(creall(w)) || !isfinite(cimagl(w))) return -1;
+        if (cabsl(s) <= TOL_SOLVE * fmaxl(cabsl(w), 0x1p-8L)) {
+            *z = w;
+            return it;
+        }
+    }
+    return 0;
+}
+
+/* Target value lambda_0 * exp(2 i pi a / den), reduced exactly mod den. */
+static cld target(ld level, int64_t a, int64_t den)
+{
+    int64_t r = a % den;
+    if (r < 0) r += den;
+    ld t = 2 * PI_L * (ld)r / (ld)den;
+    return level * (cosl(t) + I * sinl(t));
+}
+
+/* Move *z along the level line from value phase 2 pi a/den to 2 pi b/den
+ * (b - a is small).  When the Newton map with target fails, the phase step is
+ * halved (more points per turn, which Prop. computeLevelLine allows). */
+static int walk_arc(const method_t *m, cld *z, int64_t a, int64_t b, int64_t den, int depth,
+                    int64_t *steps)
+{
+    cld w = *z;
+    if (solve_target(m->l, m->n, &w, target(m->level, b, den), steps) > 0) {
+        *z = w;
+        return 0;
+    }
+    if (depth >= MAX_HALVINGS) return -1;
+    if (walk_arc(m, z, 2 * a, a + b, 2 * den, depth + 1, steps)) return -1;
+    return walk_arc(m, z, a + b, 2 * b, 2 * den, depth + 1, steps);
+}
+
+/* Walk fine points s0+1 .. s0+F (fine index s has value phase 2 pi s / M),
+ * storing the starting points (s multiple of M/4) at starts[s / (M/4)]. */
+static int walk_segment(const method_t *m, cld z, int64_t s0, int64_t F, cld *starts, cld *end,
+                        int64_t *steps)
+{
+    const int64_t q = m->M / 4;
+    for (int64_t s = s0 + 1; s <= s0 + F; s++) {
+        if (walk_arc(m, &z, s - 1, s, m->M, 0, steps)) return -1;
+        if (starts && s % q == 0) starts[s / q] = z;
+    }
+    *end = z;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Real end points of |P| = level by dichotomy (Section 6.3.1).               */
+/* Right: P is increasing on x >= 1/4 and P(1/4) < level <= P(level).         */
+/* Left:  P(-2) <= 2 < level, and P grows without bound to the left of -2.    */
+/* For P = p_1 = z the curve is the circle |z| = level.                       */
+/* ------------------------------------------------------------------------- */
+static ld bisect_real(const method_t *m, ld a, ld b)
+{
+    /* invariant: P(a) - level and P(b) - level have opposite signs */
+    cld Pa, dPa;
+    eval_q(m->l, m->n, a, &Pa, &dPa);
+    int sa = creall(Pa) > m->level;
+    for (int it = 0; it < 200; it++) {
+        ld c = 0.5L * (a + b);
+        if (c == a || c == b) break;
+        cld Pc, dPc;
+        eval_q(m->l, m->n, c, &Pc, &dPc);
+        if ((creall(Pc) > m->level) == sa) a = c; else b = c;
+    }
+    return 0.5L * (a + b);
+}
+
+static void endpoints(const method_t *m, ld *xl, ld *xr)
+{
+    if (m->order == 1) { *xr = m->level; *xl = -m->level; return; }
+    *xr = bisect_real(m, 0.25L, m->level);
+    /* widen the left bracket until P exceeds the level there */
+    ld b = -3.0L;
+    for (int it = 0; it < 16; it++) {
+        cld Pb, dPb;
+        eval_q(m->l, m->n, b, &Pb, &dPb);
+        if (creall(Pb) > m->level) break;
+        b = -2.0L + 2 * (b + 2.0L);
+    }
+    *xl = bisect_real(m, b, -2.0L);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Starting points.                                                           */
+/* ------------------------------------------------------------------------- */
+#define COARSE_ORDER 16 /* L_{lambda_0, 2^15}(p_16), Section 4.2 */
+
+typedef struct {
+    int64_t walk_steps, lift_steps, phase_fail, halvings;
+} start_stats;
+
+/* Coarse level line of P with all its points of value phase 0, upper half:
+ * out[j] = point of Phi-angle 2 pi j / N0, j = 0..N0/2, N0 = deg P. */
+static int coarse_line(const method_t *m, cld *out, int64_t *steps)
+{
+    ld xl, xr;
+    endpoints(m, &xl, &xr);
+    cld z = xr;
+    out[0] = z;
+    const int64_t N0 = m->D;
+    for (int64_t j = 1; j <= N0 / 2; j++) {
+        cld e;
+        if (walk_segment(m, z, (j - 1) * m->M, m->M, NULL, &e, steps)) return -1;
+        z = e;
+        out[j] = z;
+    }
+    /* the walk must close on the left end point */
+    if (cabsl(out[N0 / 2] - xl) > 1e-12L) return -2;
+    out[N0 / 2] = xl;
+    return 0;
+}
+
+/* Lift a point of P_k^{-1}(level) to P_{k+1}^{-1}(level) keeping its phase
+ * index (Section 4.2): p_{k+1}(z) = level^2 + z, so first solve
+ * p_{k+1}(w) = level^2 from z, then lower the target radius to level. */
+#define LIFT_RADII 8
+static int lift_point(int k1, ld level, cld *z, int64_t *steps)
+{
+    cld w = *z;
+    if (solve_target(0, k1, &w, level * level, steps) <= 0) return -1;
+    for (int i = 1; i <= LIFT_RADII; i++) {
+        ld r = powl(level, 2.0L - (ld)i / LIFT_RADII);
+        if (solve_target(0, k1, &w, r, steps) <= 0) return -1;
+    }
+    *z = w;
+    return 0;
+}
+
+/* All 2D+1 starting points of the upper half plane: starts[k] has
+ * P(starts[k]) = level * i^k.  Returns 0 on success. */
+static int make_starts(const method_t *m, cld *starts, start_stats *st)
+{
+    memset(st, 0, sizeof(*st));
+    const int64_t q = m->M / 4;
+    if (m->order <= COARSE_ORDER) {
+        /* one walk over the whole upper half (the hypQuick layout) */
+        ld xl, xr;
+        endpoints(m, &xl, &xr);
+        cld e;
+        starts[0] = xr;
+        if (walk_segment(m, xr, 0, (int64_t)m->M * m->D / 2, starts, &e, &st->walk_steps)) return -1;
+        if (cabsl(e - xl) > 1e-12L) { st->phase_fail++; return -2; }
+        starts[(int64_t)m->M * m->D / 2 / q] = xl;
+        return 0;
+    }
+    /* coarse level line of p_16 at this level, lifted to p_order */
+    method_t cm;
+    method_init(&cm, 0, COARSE_ORDER);
+    cm.level = m->level;
+    cm.M = 8;
+    const int64_t N0 = cm.D;          /* 2^15 */
+    const int64_t nseed = N0 / 2 + 1; /* upper half plane */
+    cld *seed = malloc(sizeof(cld) * nseed);
+    if (coarse_line(&cm, seed, &st->lift_steps)) { free(seed); return -3; }
+    int fail = 0;
+    int64_t lift_steps = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : lift_steps) reduction(| : fail)
+    for (int64_t j = 0; j < nseed; j++) {
+        cld z = seed[j];
+        for (int k1 = COARSE_ORDER + 1; k1 <= m->order; k1++)
+            if (lift_point(k1, m->level, &z, &lift_steps)) { fail = 1; break; }
+        if (m->l > 0 && !fail) {
+            /* onto q_{l,n} = level, same phase index */
+            if (solve_target(m->l, m->n, &z, m->level, &lift_steps) <= 0) fail = 1;
+        }
+        seed[j] = z;
+    }
+    st->lift_steps += lift_steps;
+    if (fail) { free(seed); return -4; }
+    /* refine: walk each segment between consecutive seeds */
+    const int64_t F = (int64_t)m->M * m->D / N0;
+    int64_t walk_steps = 0, phase_fail = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : walk_steps, phase_fail)
+    for (int64_t j = 0; j < nseed - 1; j++) {
+        cld e;
+        starts[j * F / q] = seed[j];
+        if (walk_segment(m, seed[j], j * F, F, starts, &e, &walk_steps)) { phase_fail++; continue; }
+        if (cabsl(e - seed[j + 1]) > 0x1p-56L * fmaxl(cabsl(e), 1.0L)) phase_fail++;
+    }
+    starts[(nseed - 1) * F / q] = seed[nseed - 1];
+    st->walk_steps += walk_steps;
+    st->phase_fail += phase_fail;
+    free(seed);
+    return phase_fail ? -5 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Newton descent (Section 4.2, Algorithm S_par; discard rules Section 6.4.3) */
+/* ------------------------------------------------------------------------- */
+enum { D_CONVERGED = 1, D_DIVERGED = 2, D_TIMEOUT = 3 };
+
+static int descend(const method_t *m, cld *z, int64_t *steps)
+{
+    cld w = *z;
+    ld prev = INFINITY;
+    for (int it = 1; it <= m->cap; it++) {
+        cld P, dP;
+        eval_q(m->l, m->n, w, &P, &dP);
+        cld s = P / dP;
+        w -= s;
+        (*steps)++;
+        ld a = cabsl(s);
+        if (!isfinite(a) || !isfinite(creall(w)) || !isfinite(cimagl(w)) ||
+            cabsl(w) > DIVERGE_RADIUS)
+            return D_DIVERGED;
+        if (it > 3 && a > 8 * prev) return D_DIVERGED; /* long-distance jump */
+        if (a <= TOL_DESC * fmaxl(cabsl(w), 0x1p-8L)) {
+            eval_q(m->l, m->n, w, &P, &dP); /* one more step */
+            w -= P / dP;
+            (*steps)++;
+            *z = w;
+            return D_CONVERGED;
+        }
+        prev = a;
+    }
+    *z = w;
+    return D_TIMEOUT;
+}
+
+/* ------------------------------------------------------------------------- */
+/* nset collection (Section 6.1), on double-double polished points.           */
+/* ------------------------------------------------------------------------- */
+static inline int dd_lt(dd a, dd b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+static inline double dd_absdiff(dd a, dd b) { dd d = dd_sub(a, b); return fabs(d.hi + d.lo); }
+
+static int cmp_lex(const void *pa, const void *pb)
+{
+    const cdd *a = pa, *b = pb;
+    if (dd_lt(a->re, b->re)) return -1;
+    if (dd_lt(b->re, a->re)) return 1;
+    if (dd_lt(a->im, b->im)) return -1;
+    if (dd_lt(b->im, a->im)) return 1;
+    return 0;
+}
+
+/* fold to the closed upper half plane, snap |Im| < eps/2 to the real axis,
+ * sort lexicographically and identify points closer than eps in both
+ * coordinates (the first one kept); returns the number kept in pts[0..] */
+static int64_t nset_collect(cdd *pts, int64_t cnt, double eps)
+{
+    for (int64_t i = 0; i < cnt; i++) {
+        if (pts[i].im.hi < 0) pts[i].im = dd_neg(pts[i].im);
+        if (pts[i].im.hi < eps / 2) pts[i].im = (dd){ 0, 0 };
+    }
+    qsort(pts, cnt, sizeof(cdd), cmp_lex);
+    int64_t kept = 0;
+    for (int64_t i = 0; i < cnt; i++) {
+        int dup = 0;
+        for (int64_t j = kept - 1; j >= 0 && dd_absdiff(pts[i].re, pts[j].re) < eps; j--)
+            if (dd_absdiff(pts[j].im, pts[i].im) < eps) { dup = 1; break; }
+        if (!dup) pts[kept++] = pts[i];
+    }
+    return kept;
+}
+
+static int nset_contains(const cdd *a, int64_t cnt, cdd z, double eps)
+{
+    int64_t lo = 0, hi = cnt;
+    dd key = dd_sub(z.re, (dd){ eps, 0 });
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (dd_lt(a[mid].re, key)) lo = mid + 1; else hi = mid;
+    }
+    for (int64_t i = lo; i < cnt && dd_absdiff(a[i].re, z.re) < eps; i++)
+        if (dd_absdiff(a[i].im, z.im) < eps) return 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Public entry points.                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* statistics slots */
+enum {
+    S_STARTS, S_CONVERGED, S_DIVERGED, S_TIMEOUT, S_UNIQUE, S_REAL, S_PHASE_FAIL,
+    S_WALK_STEPS, S_LIFT_STEPS, S_DESC_STEPS, S_LOOKUP_MISMATCH, S_DISCARD_HYP,
+    S_DISCARD_LOWER, S_STATUS, S_NSTATS = 16
+};
+
+/* P and P' at c in long double, for tests of the evaluation itself */
+void oracle_eval(int l, int n, const long double *c2, long double *out4)
+{
+    cld P, dP;
+    eval_q(l, n, c2[0] + I * c2[1], &P, &dP);
+    out4[0] = creall(P); out4[1] = cimagl(P);
+    out4[2] = creall(dP); out4[3] = cimagl(dP);
+}
+
+void oracle_endpoints(int l, int n, long double *xl, long double *xr)
+{
+    method_t m;
+    method_init(&m, l, n);
+    endpoints(&m, xl, xr);
+}
+
+/* The 2D+1 starting points of the closed upper half plane, start k being the
+ * level-line point of value lambda_0 * i^k.  cap >= 2D+1.  Returns the count
+ * or a negative status. */
+int64_t oracle_starts(int l, int n, int64_t cap, long double *re, long double *im, int64_t *stats)
+{
+    method_t m;
+    method_init(&m, l, n);
+    int64_t ns = 2 * m.D + 1;
+    if (cap < ns) return -100;
+    cld *st = calloc(ns, sizeof(cld));
+    start_stats ss;
+    int r = make_starts(&m, st, &ss);
+    for (int64_t k = 0; k < ns; k++) { re[k] = creall(st[k]); im[k] = cimagl(st[k]); }
+    free(st);
+    if (stats) {
+        stats[S_WALK_STEPS] = ss.walk_steps;
+        stats[S_LIFT_STEPS] = ss.lift_steps;
+        stats[S_PHASE_FAIL] = ss.phase_fail;
+    }
+    return r ? r : ns;
+}
+
+/* Is c (a converged descent of q_{l,n}) sitting next to a multiple root?
+ * The multiple roots of q_{l,n} are the hyperbolic centres of the periods
+ * k | n (Thm fact_mis).  Near one of them p_k/p_k' is small; a genuine simple
+ * root of q then has a double-double Newton step at rounding level, whereas a
+ * point stalled at the precision floor of a multiple root does not. */
+static int near_multiple_root(const method_t *m, cld c)
+{
+    cld z[80], dz[80];
+    orbit_all(m->order, c, z, dz);
+    int close = 0;
+    for (int k = 1; k <= m->n; k++)
+        if (m->n % k == 0 && cabsl(z[k] / dz[k]) < 1e-6L) close = 1;
+    if (!close) return 0;
+    cdd cc = { dd_from_ld(creall(c)), dd_from_ld(cimagl(c)) };
+    cdd s = dd_newton_step(m->l, m->n, cc);
+    ld a = hypotl(ld_from_dd(s.re), ld_from_dd(s.im));
+    return a > 1e-15L * fmaxl(cabsl(c), 1e-3L);
+}
+
+/* Zero test by the double-double Newton distance |Q/Q'| of Q = q_{l,n}. */
+#define TAU_ZERO 1e-24
+static int newton_zero(int l, int n, cdd c)
+{
+    cdd s = dd_newton_step(l, n, c);
+    double a = hypot(s.re.hi + s.re.lo, s.im.hi + s.im.lo);
+    return !(a >= TAU_ZERO); /* also true for an exact zero (0/0 -> NaN) */
+}
+
+/* Membership in Mis(l,n) from eq. def:mis: not a root of q_{l-1,n}, and not a
+ * root of q_{l,k} for a strict divisor k of n. */
+static int is_mis_type(const method_t *m, cdd c)
+{
+    if (newton_zero(m->l - 1, m->n, c)) return 0;
+    for (int k = 1; k < m->n; k++)
+        if (m->n % k == 0 && newton_zero(m->l, k, c)) return 0;
+    return 1;
+}
+
+/* Three double-double Newton steps from a converged long-double point. */
+static cdd polish(const method_t *m, cld z)
+{
+    cdd c = { dd_from_ld(creall(z)), dd_from_ld(cimagl(z)) };
+    for (int it = 0; it < 3; it++) {
+        cdd s = dd_newton_step(m->l, m->n, c);
+        if (!isfinite(s.re.hi) || !isfinite(s.im.hi)) break; /* exact zero */
+        c = cdd_sub(c, s);
+    }
+    return c;
+}
+
+#define EPS_COLLECT 0x1p-70 /* identification radius on polished points */
+
+static int64_t split_impl(int l, int n, int64_t cap, double *re_hi, double *re_lo, double *im_hi,
+                          double *im_lo, int32_t *period, int64_t *stats);
+
+/* Split P = q_{l,n} (l = 0: p_n).  Outputs the closed-upper-half-plane roots,
+ * lexicographically ordered, as double-double (hi + lo), with
+ *   p_n:     period[i] = exact period (least k | n with p_k(root) = 0);
+ *   q_{l,n}: only Mis(l,n) is kept, period[i] = n.
+ * Returns the number of roots, or a negative status (capacity: -100). */
+int64_t oracle_split(int l, int n, int64_t cap, double *re_hi, double *re_lo, double *im_hi,
+                     double *im_lo, int32_t *period, int64_t *stats)
+{
+    return split_impl(l, n, cap, re_hi, re_lo, im_hi, im_lo, period, stats);
+}
+
+static int64_t split_impl(int l, int n, int64_t cap, double *re_hi, double *re_lo, double *im_hi,
+                          double *im_lo, int32_t *period, int64_t *stats)
+{
+    int64_t st_local[S_NSTATS];
+    if (!stats) stats = st_local;
+    memset(stats, 0, sizeof(int64_t) * S_NSTATS);
+    if (n < 1 || l < 0 || l == 1 || l + n > 40) return -101;
+    method_t m;
+    method_init(&m, l, n);
+    const int64_t ns = 2 * m.D + 1;
+    cld *pts = malloc(sizeof(cld) * ns);
+    start_stats ss;
+    int r = make_starts(&m, pts, &ss);
+    stats[S_WALK_STEPS] = ss.walk_steps;
+    stats[S_LIFT_STEPS] = ss.lift_steps;
+    stats[S_PHASE_FAIL] = ss.phase_fail;
+    stats[S_STARTS] = ns;
+    if (r) { free(pts); stats[S_STATUS] = r; return r; }
+
+    /* descents, in parallel; each start is independent */
+    unsigned char *status = malloc(ns);
+    int64_t desc_steps = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : desc_steps)
+    for (int64_t k = 0; k < ns; k++) status[k] = (unsigned char)descend(&m, &pts[k], &desc_steps);
+    stats[S_DESC_STEPS] = desc_steps;
+    int64_t cnt = 0;
+    for (int64_t k = 0; k < ns; k++) {
+        if (status[k] == D_CONVERGED) pts[cnt++] = pts[k];
+        else if (status[k] == D_DIVERGED) stats[S_DIVERGED]++;
+        else stats[S_TIMEOUT]++;
+    }
+    free(status);
+    stats[S_CONVERGED] = cnt;
+
+    /* q_{l,n}: drop descents stalled next to a multiple (hyperbolic) root */
+    unsigned char *drop = calloc(cnt ? cnt : 1, 1);
+    if (l > 0) {
+        int64_t nh = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nh)
+        for (int64_t i = 0; i < cnt; i++)
+            if (near_multiple_root(&m, pts[i])) { drop[i] = 1; nh++; }
+        stats[S_DISCARD_HYP] = nh;
+    }
+    cdd *pol = malloc(sizeof(cdd) * (cnt ? cnt : 1));
+    int64_t np = 0;
+    for (int64_t i = 0; i < cnt; i++)
+        if (!drop[i]) pol[np++].re.hi = (double)i; /* placeholder index */
+    {
+        int64_t *idx = malloc(sizeof(int64_t) * (np ? np : 1));
+        for (int64_t i = 0; i < np; i++) idx[i] = (int64_t)pol[i].re.hi;
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < np; i++) pol[i] = polish(&m, pts[idx[i]]);
+        free(idx);
+    }
+    free(drop);
+    free(pts);
+    cnt = nset_collect(pol, np, EPS_COLLECT);
+
+    int32_t *lab = malloc(sizeof(int32_t) * (cnt ? cnt : 1));
+    if (l == 0) {
+        /* exact period by lookup among the roots of p_k, k | n, k < n */
+        for (int64_t i = 0; i < cnt; i++) lab[i] = n;
+        for (int k = 1; k < n; k++) {
+            if (n % k) continue;
+            int64_t dk = ((int64_t)1 << (k - 1)) + 1;
+            double *a = malloc(sizeof(double) * 4 * dk);
+            int32_t *pk = malloc(sizeof(int32_t) * dk);
+            int64_t ck = split_impl(0, k, dk, a, a + dk, a + 2 * dk, a + 3 * dk, pk, NULL);
+            if (ck < 0) { free(a); free(pk); free(lab); free(pol); stats[S_STATUS] = -6; return -6; }
+            cdd *rk = malloc(sizeof(cdd) * (ck ? ck : 1));
+            for (int64_t i = 0; i < ck; i++) {
+                rk[i].re = (dd){ a[i], a[dk + i] };
+                rk[i].im = (dd){ a[2 * dk + i], a[3 * dk + i] };
+            }
+            for (int64_t i = 0; i < cnt; i++)
+                if (lab[i] == n && nset_contains(rk, ck, pol[i], EPS_COLLECT)) lab[i] = k;
+            free(rk); free(a); free(pk);
+        }
+        /* cross-check: least k | n whose Newton distance vanishes */
+        int64_t mism = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : mism)
+        for (int64_t i = 0; i < cnt; i++) {
+            int kk = n;
+            for (int k = 1; k < n; k++)
+                if (n % k == 0 && newton_zero(0, k, pol[i])) { kk = k; break; }
+            if (kk != lab[i]) mism++;
+        }
+        stats[S_LOOKUP_MISMATCH] = mism;
+    } else {
+        unsigned char *keep = malloc(cnt ? cnt : 1);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < cnt; i++) keep[i] = (unsigned char)is_mis_type(&m, pol[i]);
+        int64_t kept = 0;
+        for (int64_t i = 0; i < cnt; i++) {
+            if (!keep[i]) { stats[S_DISCARD_LOWER]++; continue; }
+            pol[kept] = pol[i];
+            lab[kept++] = n;
+        }
+        free(keep);
+        cnt = kept;
+    }
+    stats[S_UNIQUE] = cnt;
+    if (cnt > cap) { free(lab); free(pol); stats[S_STATUS] = -100; return -100; }
+    for (int64_t i = 0; i < cnt; i++) {
+        re_hi[i] = pol[i].re.hi; re_lo[i] = pol[i].re.lo;
+        im_hi[i] = pol[i].im.hi; im_lo[i] = pol[i].im.lo;
+        period[i] = lab[i];
+        if (im_hi[i] == 0) stats[S_REAL]++;
+    }
+    free(lab);
+    free(pol);
+    return cnt;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Certification: Thm proofRoots with the disk arithmetic of                   */
+/* Thm diskArithmetic, radii rounded upward (FE_UPWARD honoured by x87).      */
+/* ------------------------------------------------------------------------- */
+
+/* ulp of a long double (64-bit significand): 2^(e(x) - 64) with x in
+ * 2^e [1/2, 1); the subnormal spacing for 0 and subnormals. */
+static ld ulp_ld(ld x)
+{
+    if (x == 0 || fabsl(x) < LDBL_MIN) return LDBL_TRUE_MIN;
+    int e;
+    frexpl(x, &e);
+    return ldexpl(1.0L, e - 64);
+}
+static ld ulp_c(cld z)
+{
+    /* complex ulp: sqrt(ulp(x)^2 + ulp(y)^2) <= ulp(x) + ulp(y) */
+    return ulp_ld(creall(z)) + ulp_ld(cimagl(z));
+}
+
+#define MAXN 72
+typedef struct {
+    int N;
+    cld Z[MAXN + 1], DZ[MAXN + 1];   /* centres (round to nearest) */
+    ld abZ[MAXN + 1], abDZ[MAXN + 1];/* |centre| rounded upward (pass 2) */
+    ld Rsq[MAXN], Rpr[MAXN];         /* R_* of the squaring and of z*dz */
+    ld hz[MAXN + 1], hdz[MAXN + 1];  /* half ulp of the rounded centres */
+} centre_orbit;
+
+/* pass 1, round to nearest: centre orbit and the rounding terms of
+ * Thm diskArithmetic (products of exact centres, then the sum). */
+static void centre_pass(centre_orbit *o, cld c, int N)
+{
+    o->N = N;
+    o->Z[0] = 0; o->DZ[0] = 0; o->hz[0] = 0; o->hdz[0] = 0;
+    for (int k = 0; k < N; k++) {
+        ld x = creall(o->Z[k]), y = cimagl(o->Z[k]);
+        ld u = creall(o->DZ[k]), v = cimagl(o->DZ[k]);
+        /* z^2 */
+        ld xx = x * x, yy = y * y, xy = x * y;
+        cld sq = (xx - yy) + I * (2 * xy);
+        o->Rsq[k] = 0.5L * ulp_c(sq) + 0.5L * (ulp_ld(xx) + ulp_ld(yy) + 2 * ulp_ld(xy));
+        o->Z[k + 1] = sq + c;
+        o->hz[k + 1] = 0.5L * ulp_c(o->Z[k + 1]);
+        /* z * dz */
+        ld xu = x * u, yv = y * v, xv = x * v, yu = y * u;
+        cld pr = (xu - yv) + I * (xv + yu);
+        o->Rpr[k] = 0.5L * ulp_c(pr) + 0.5L * (ulp_ld(xu) + ulp_ld(yv) + ulp_ld(xv) + ulp_ld(yu));
+        o->DZ[k + 1] = 2 * pr + 1;
+        o->hdz[k + 1] = 0.5L * ulp_c(o->DZ[k + 1]);
+    }
+}
+
+/* pass 2 helpers, to be called in FE_UPWARD */
+static ld abs_up(cld z)
+{
+    ld x = fabsl(creall(z)), y = fabsl(cimagl(z));
+    return sqrtl(x * x + y * y);
+}
+/* lower bound of |z|^2 in FE_UPWARD: -(RU(-x*x) + RU(-y*y)) rounded up */
+static ld abs2_down(cld z)
+{
+    ld x = creall(z), y = cimagl(z);
+    ld a = (-x) * x, b = (-y) * y;
+    return -(a + b);
+}
+
+typedef struct {
+    ld e[MAXN + 1];      /* radius of p_k at the exact centre */
+    ld rho[MAXN + 1];    /* radius of p_k over D(c, R) */
+    ld sig[MAXN + 1];    /* radius of p_k' over D(c, R) */
+} radii_t;
+
+static void __attribute__((noinline)) radius_pass(const centre_orbit *o, ld R, radii_t *r, ld *abZ, ld *abDZ)
+{
+    r->e[0] = 0; r->rho[0] = 0; r->sig[0] = 0;
+    for (int k = 0; k <= o->N; k++) { abZ[k] = abs_up(o->Z[k]); abDZ[k] = abs_up(o->DZ[k]); }
+    for (int k = 0; k < o->N; k++) {
+        ld e = r->e[k], rho = r->rho[k], sig = r->sig[k];
+        /* D(Z,e)^2 then + c (exact, radius 0) */
+        r->e[k + 1] = (e * e + 2 * e * abZ[k] + o->Rsq[k]) + o->hz[k + 1];
+        /* D(Z,rho)^2 then + D(c,R) */
+        r->rho[k + 1] = ((rho * rho + 2 * rho * abZ[k] + o->Rsq[k]) + R) + o->hz[k + 1];
+        /* 2 * D(Z,rho) * D(DZ,sig) + 1 ; doubling is exact */
+        ld pr = rho * sig + rho * abDZ[k] + sig * abZ[k] + o->Rpr[k];
+        r->sig[k + 1] = 2 * pr + o->hdz[k + 1];
+    }
+}
+
+/* radius of a difference of two disks of the same orbit, upward */
+static ld diff_radius(ld ra, ld rb, cld centre) { return ra + rb + 0.5L * ulp_c(centre); }
+
+/* Certify one candidate c for q_{l,n} (l = 0: p_n) with the label lab
+ * (p_n: claimed exact period; q: must be n).  Tries radii R, 16R, 256R.
+ * Returns flags: 1 = a unique root of P lies in D(c, R_out);
+ *                2 = the label is proven on that disk. */
+static int certify_one(int l, int n, int lab, cld c, ld *R_out)
+{
+    centre_orbit o;
+    radii_t rr;
+    int N = l + n;
+    centre_pass(&o, c, N);
+    cld Pc = o.Z[N] - o.Z[l];
+    cld dPc = o.DZ[N] - o.DZ[l];
+
+    int old = fegetround();
+    fesetround(FE_UPWARD);
+    ld abZ[MAXN + 1], abDZ[MAXN + 1];
+    radius_pass(&o, 0, &rr, abZ, abDZ);
+    ld eP = diff_radius(rr.e[N], rr.e[l], Pc);
+    ld Pup = abs_up(Pc) + eP;
+    ld dlow = sqrtl(fmaxl(abs2_down(dPc), 0)); /* sqrt rounds up: only a guide */
+    ld R0 = 4 * Pup / fmaxl(dlow, LDBL_MIN);
+    if (!(R0 > LDBL_MIN)) R0 = LDBL_MIN;
+    int e2;
+    frexpl(R0, &e2);
+    ld R = ldexpl(1.0L, e2); /* power of two >= R0 */
+    int flags = 0;
+    for (int attempt = 0; attempt < 3 && !flags; attempt++, R *= 16) {
+        radius_pass(&o, R, &rr, abZ, abDZ);
+        ld sP = diff_radius(rr.sig[N], rr.sig[l], dPc);
+        ld t = Pup / R + sP;        /* need |P'| - sP > Pup / R */
+        ld t2 = t * t;
+        if (abs2_down(dPc) > t2) {
+            flags = 1;
+            /* label on the same disk */
+            int okl = 1;
+            if (l == 0) {
+                /* root of p_lab in the disk: Thm proofRoots for p_lab */
+                cld Pk = o.Z[lab], dPk = o.DZ[lab];
+                radius_pass(&o, 0, &rr, abZ, abDZ);
+                ld ek = rr.e[lab] + 0.5L * ulp_c(Pk);
+                radius_pass(&o, R, &rr, abZ, abDZ);
+                ld tk = (abs_up(Pk) + ek) / R + rr.sig[lab];
+                if (!(abs2_down(dPk) > tk * tk)) okl = 0;
+                /* p_j has no zero on the disk for every strict divisor j of lab */
+                for (int j = 1; j < lab && okl; j++) {
+                    if (lab % j) continue;
+                    ld rj = rr.rho[j];
+                    if (!(abs2_down(o.Z[j]) > rj * rj)) okl = 0;
+                }
+            } else {
+                /* q_{l-1,n} and q_{l,k} (k strict divisor of n) do not vanish */
+                cld a = o.Z[l - 1 + n] - o.Z[l - 1];
+                ld ra = diff_radius(rr.rho[l - 1 + n], rr.rho[l - 1], a);
+                if (!(abs2_down(a) > ra * ra)) okl = 0;
+                for (int k = 1; k < n && okl; k++) {
+                    if (n % k) continue;
+                    cld b = o.Z[l + k] - o.Z[l];
+                    ld rb = diff_radius(rr.rho[l + k], rr.rho[l], b);
+                    if (!(abs2_down(b) > rb * rb)) okl = 0;
+                }
+                if (lab != n) okl = 0;
+            }
+            if (okl) flags |= 2;
+            break;
+        }
+    }
+    fesetround(old);
+    *R_out = R;
+    return flags;
+}
+
+/* Certify candidates given as double-double (hi + lo).  The long-double centre
+ * is the rounded input; the reported radius covers that rounding too.
+ * ok[i] gets the flags of certify_one, radius[i] the radius (upward). */
+void oracle_certify(int l, int n, int64_t count, const double *re_hi, const double *re_lo,
+                    const double *im_hi, const double *im_lo, const int32_t *label, uint8_t *ok,
+                    double *radius)
+{
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < count; i++) {
+        ld x = (ld)re_hi[i] + (ld)(re_lo ? re_lo[i] : 0.0);
+        ld y = (ld)im_hi[i] + (ld)(im_lo ? im_lo[i] : 0.0);
+        ld R;
+        int f = certify_one(l, n, label ? label[i] : (l == 0 ? n : n), x + I * y, &R);
+        /* distance from the input to the long-double centre, upward */
+        int old = fegetround();
+        fesetround(FE_UPWARD);
+        ld dx = fabsl(((ld)re_hi[i] - x) + (ld)(re_lo ? re_lo[i] : 0.0));
+        ld dy = fabsl(((ld)im_hi[i] - y) + (ld)(im_lo ? im_lo[i] : 0.0));
+        ld Rt = R + (dx + dy) + 2 * ulp_ld(x) + 2 * ulp_ld(y);
+        fesetround(old);
+        double Rd = (double)Rt;
+        if ((ld)Rd < Rt) Rd = nextafter(Rd, INFINITY); /* round the conversion up */
+        ok[i] = (uint8_t)f;
+        radius[i] = Rd;
+    }
+}
+
+/* Global checks of Thm certif on a certified list (closed upper half plane,
+ * sorted lexicographically by the caller): disks pairwise disjoint, disjoint
+ * from their conjugates unless centred on the real axis, and, with the
+ * quarter-separation reading, |z_i - z_j| >= 4 max(R_i, R_j).
+ * out[0] = 1 if disjoint, out[1] = 1 if quarter-separated, out[2] = #real,
+ * out[3] = #non-real; min_sep = least distance among the roots and their
+ * conjugates (double). */
+void oracle_check_set(int64_t count, const double *re, const double *im, const double *radius,
+                      int64_t *out, double *min_sep)
+{
+    int64_t disjoint = 1, quarter = 1, nreal = 0, ncplx = 0;
+    ld Rmax = 0, best = INFINITY;
+    for (int64_t i = 0; i < count; i++) Rmax = fmaxl(Rmax, radius[i]);
+    for (int64_t i = 0; i < count; i++) {
+        ld xi = re[i], yi = im[i], Ri = radius[i];
+        if (yi == 0) nreal++;
+        else {
+            ncplx++;
+            if (!(yi > Ri * (1 + 1e-15L))) disjoint = 0;
+            if (!(yi >= 2 * Ri * (1 + 1e-15L))) quarter = 0;
+            best = fminl(best, 2 * yi);
+        }
+        ld win = fmaxl(4 * (Ri + Rmax), best) * (1 + 1e-12L);
+        for (int64_t j = i + 1; j < count && (ld)re[j] - xi <= win; j++) {
+            ld dx = (ld)re[j] - xi, dy = (ld)im[j] - yi;
+            ld d = sqrtl(dx * dx + dy * dy);
+            ld Rj = radius[j];
+            if (d < best) best = d;
+            if (!(d > (Ri + Rj) * (1 + 1e-15L))) disjoint = 0;
+            if (!(d >= 4 * fmaxl(Ri, Rj) * (1 + 1e-15L))) quarter = 0;
+            win = fmaxl(4 * (Ri + Rmax), best) * (1 + 1e-12L);
+        }
+    }
+    out[0] = disjoint; out[1] = quarter; out[2] = nreal; out[3] = ncplx;
+    *min_sep = (double)best;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Disk enclosures used by the certificate, exposed for tests of the disk
+ * arithmetic itself: out[0..1] = P(c) centre, out[2] = its radius at the point
+ * c; out[3..4] = P'(c) centre, out[5] = radius of P'(D(c,R)); out[6] = radius
+ * of P(D(c,R)).  Radii are rounded upward. */
+void oracle_disk_enclosure(int l, int n, const long double *c3, long double *out)
+{
+    centre_orbit o;
+    radii_t rr;
+    int N = l + n;
+    cld c = c3[0] + I * c3[1];
+    ld R = c3[2];
+    centre_pass(&o, c, N);
+    cld Pc = o.Z[N] - o.Z[l], dPc = o.DZ[N] - o.DZ[l];
+    int old = fegetround();
+    fesetround(FE_UPWARD);
+    ld abZ[MAXN + 1], abDZ[MAXN + 1];
+    radius_pass(&o, 0, &rr, abZ, abDZ);
+    ld eP = diff_radius(rr.e[N], rr.e[l], Pc);
+    radius_pass(&o, R, &rr, abZ, abDZ);
+    ld sP = diff_radius(rr.sig[N], rr.sig[l], dPc);
+    ld rP = diff_radius(rr.rho[N], rr.rho[l], Pc);
+    fesetround(old);
+    out[0] = creall(Pc); out[1] = cimagl(Pc); out[2] = eP;
+    out[3] = creall(dPc); out[4] = cimagl(dPc); out[5] = sP; out[6] = rP;
+}
