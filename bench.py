@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark: certified roots per second of the level-line splitter on one GPU.
+
+Workload (default ``batch24``): every p_n, n = 1..24, split in one batch --
+16 777 215 roots of degree 1 to 8 388 608 -- and every returned root certified
+by the disk-arithmetic certificate (Thm proofRoots), in FP64 and in mixed
+FP32 -> FP64 precision.  A step is one pass of the whole hot path over that
+batch: seeds, level-line walk, descents, collection, classification,
+certificate.  The inputs are the integers n themselves (no dataset exists for
+this problem); nothing is cached between steps.
+
+Prints one JSON line (metric, value, roofline of the dominant kernel, CPU
+oracle baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 FLOP/clk)
+
+# algorithmic flops of one evaluation + update of order N:
+# the orbit step (dz <- 2 z dz + 1, z <- z^2 + c) is 16 real flops;
+# the Newton update z -= P/P' is 14; the log-Newton level-line update
+# (T/P, log1p series, scaling by P/P') is 62.
+FLOPS_ORBIT_STEP = 16
+FLOPS_NEWTON_UPDATE = 14
+FLOPS_WALK_UPDATE = 62
+
+WORKLOADS = {
+    "batch24": ("p_1..p_24 batched, all roots certified", [(0, n) for n in range(1, 25)]),
+    "p20": ("p_20, all roots certified", [(0, 20)]),
+    "p24": ("p_24, all roots certified", [(0, 24)]),
+}
+
+
+def certified_roots(stats_list):
+    """Roots counted as roots of P: a certified non-real root in the upper
+    half plane stands for itself and its conjugate."""
+    tot = 0
+    for st in stats_list:
+        if st["certified"] == st["unique"]:
+            tot += st["total"]
+        else:
+            tot += st["certified"]  # conservative
+    return tot
+
+
+def kernel_flops(pairs, stats_list):
+    desc = walk = 0.0
+    t_desc = t_walk = 0.0
+    for (l, n), st in zip(pairs, stats_list):
+        N = l + n
+        desc += st["steps_desc"] * (FLOPS_ORBIT_STEP * N + FLOPS_NEWTON_UPDATE)
+        desc += st["steps_fp32"] * (FLOPS_ORBIT_STEP * N + FLOPS_NEWTON_UPDATE)
+        walk += st["steps_walk"] * (FLOPS_ORBIT_STEP * N + FLOPS_WALK_UPDATE)
+        t_desc += st["ms_stage"]["descend"]
+        t_walk += st["ms_stage"]["walk"]
+    return desc, t_desc, walk, t_walk
+
+
+def run_gpu(pairs, precision, steps, warmup):
+    import torch
+    from paper_2402_06083_amd import batch, msplit
+    opts = msplit.make_options(precision=precision, certify=True)
+    runner = batch.BatchRunner(pairs, opts)
+    for _ in range(warmup):
+        r = runner.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg = None
+    for _ in range(steps):
+        r = runner.run()
+        if r not in (0,):
+            raise RuntimeError(f"msplit_batch failed: {msplit.strerror(r)}")
+        res = runner.result(r)
+        sts = [st for (_, st, _) in res.per_pair]
+        d, td, w, tw = kernel_flops(pairs, sts)
+        cr = certified_roots(sts)
+        if agg is None:
+            agg = dict(desc=0.0, t_desc=0.0, walk=0.0, t_walk=0.0, roots=0, ms_device=0.0,
+                       stages={k: 0.0 for k in msplit.Stats.STAGES})
+        agg["desc"] += d
+        agg["t_desc"] += td
+        agg["walk"] += w
+        agg["t_walk"] += tw
+        agg["roots"] += cr
+        agg["ms_device"] += sum(st["ms_device"] for st in sts)
+        for st in sts:
+            for k, v in st["ms_stage"].items():
+                agg["stages"][k] += v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    agg["wall"] = wall
+    agg["last_stats"] = sts
+    return agg
+
+
+def cpu_baseline():
+    """The oracle as it stands on this host's cores, on a bounded sample of
+    the same workload: p_1..p_20 split and every root certified."""
+    import oracle
+    t0 = time.perf_counter()
+    roots = 0
+    for n in range(1, 21):
+        r = oracle.split(0, n)
+        ok, rad = oracle.certify(0, n, r.re_hi, r.im_hi, r.re_lo, r.im_lo, r.period)
+        nr = int((r.im_hi[ok & 1 == 1] == 0).sum())
+        roots += nr + 2 * (int((ok & 1).sum()) - nr)
+    dt = time.perf_counter() - t0
+    return {"value": roots / dt, "unit": "certified roots/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"p_1..p_20 split and certified by the long-double oracle ({roots} roots, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batch24", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the second precision")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not a run)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    desc, pairs = WORKLOADS[args.workload]
+    main_prec = args.precision
+    other = "mixed" if main_prec == "fp64" else "fp64"
+    res = run_gpu(pairs, main_prec, args.steps, args.warmup)
+    value = res["roots"] / res["wall"]
+    ms_per_step = 1e3 * res["wall"] / args.steps
+    # dominant kernel: the stage with the larger device time
+    if res["t_desc"] >= res["t_walk"]:
+        kname, flops, tms = "k_descend", res["desc"], res["t_desc"]
+    else:
+        kname, flops, tms = "k_walk", res["walk"], res["t_walk"]
+    achieved = flops / (tms * 1e-3) / 1e12 if tms > 0 else 0.0
+    out = {
+        "metric": "certified roots/sec (all periods 1..24 batched; FP64 vs mixed precision)",
+        "value": value,
+        "unit": "certified roots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_prec == "fp64" else "f32+f64",
+        "data": "synthetic: the integers n = 1..24 (no dataset exists for this problem)",
+        "config": {"workload": desc, "periods": [p[1] for p in pairs], "roots_per_step": res["roots"] // args.steps,
+                   "precision": main_prec, "certified": True, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel_ms_per_step": tms / args.steps},
+        "stage_ms_per_step": {k: v / args.steps for k, v in res["stages"].items()},
+    }
+    if not args.no_compare:
+        r2 = run_gpu(pairs, other, args.steps, args.warmup)
+        out[other] = {"value": r2["roots"] / r2["wall"], "ms_per_step": 1e3 * r2["wall"] / args.steps,
+                      "stage_ms_per_step": {k: v / args.steps for k, v in r2["stages"].items()}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * msplit.h -- C ABI of libmsplit, an MI355X (gfx950) splitter for the
+ * Mandelbrot polynomials of Mihalache & Vigneron, "How to split a
+ * tera-polynomial" (arXiv 2402.06083):
+ *
+ *   p_n(c)     = f_c^n(0),  f_c(z) = z^2 + c,  deg p_n = 2^(n-1)
+ *                (Section 1, eq. def:hyp_poly; roots = hyperbolic centres)
+ *   q_{l,n}(c) = p_{l+n}(c) - p_l(c),  deg = 2^(l+n-1)
+ *                (Section 1, eq. def:mis_poly; roots include Mis(l,n))
+ *
+ * A splitting call returns the list of all roots (Section 3: a splitting
+ * algorithm provides the list of all the roots of P), found by the level-line
+ * method of Section 4: starting points on the discrete level line
+ * L_{lambda_0, 4d}(P) (Thm practicalFTA, Prop. computeLevelLine, Algorithm
+ * S_par), a capped Newton descent from each of them, collection in the nset
+ * sense (Section 6.1) and, on request, the disk-arithmetic certificate of
+ * Thm proofRoots / Thm certif (Section 5, Section 6.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array pointers inside msplit_roots and the workspace are HIP DEVICE
+ *   pointers owned by the caller.  Scalars (counts, stats) are HOST pointers.
+ *   The library never allocates or frees device memory; it uses the
+ *   workspace only, whose size msplit_workspace_size() reports.
+ * - stream is a hipStream_t (NULL = the null stream).  Kernels are enqueued
+ *   on it; every entry point synchronises that stream before returning
+ *   because it reports counts on the host.  Calls on distinct streams with
+ *   distinct workspaces may run concurrently; calls sharing a workspace must
+ *   not overlap.
+ * - Roots are returned in the closed upper half plane (Section 6.1: only
+ *   Im >= 0 is stored; p_n and q_{l,n} have integer coefficients): a real
+ *   root appears once with im == 0 exactly, a non-real root stands for
+ *   itself and its conjugate.  Order: increasing real part.
+ * - Return value: MSPLIT_OK (0) or a negative msplit_status.  No C++
+ *   exception crosses the ABI.
+ */
+#ifndef MSPLIT_H
+#define MSPLIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+enum msplit_status {
+    MSPLIT_OK = 0,
+    MSPLIT_E_ARG = -1,        /* bad (l, n), null pointer, bad option */
+    MSPLIT_E_CAPACITY = -2,   /* output capacity too small; *count holds the need */
+    MSPLIT_E_WORKSPACE = -3,  /* workspace smaller than msplit_workspace_size() */
+    MSPLIT_E_DEVICE = -4,     /* a HIP call failed (stats->hip_error holds it) */
+    MSPLIT_E_INCOMPLETE = -5, /* fewer roots than the exact count (stats->missing) */
+    MSPLIT_E_PRECISION = -6,  /* the requested precision cannot separate the roots */
+    MSPLIT_E_UNSUPPORTED = -7 /* valid request this build does not implement */
+};
+
+/* --------------------------------------------------------------- precision */
+enum msplit_precision {
+    MSPLIT_FP64 = 0,  /* walk and descent in FP64 */
+    MSPLIT_MIXED = 1, /* descent starts in FP32, FP64 refinement */
+    MSPLIT_DD = 2     /* double-double refinement (reserved) */
+};
+
+/* ------------------------------------------------------------------- flags */
+enum msplit_flags {
+    MSPLIT_F_CERTIFY = 1u, /* run the disk-arithmetic certificate (Thm proofRoots) */
+    MSPLIT_F_NO_LABEL = 2u /* skip period / type classification */
+};
+
+/* per-root flag bits written to msplit_roots.flags */
+enum msplit_root_flags {
+    MSPLIT_R_REAL = 1u,      /* im == 0: the root is real (proven when certified) */
+    MSPLIT_R_CERTIFIED = 2u, /* D(root, radius) holds exactly one root of P */
+    MSPLIT_R_LABEL = 4u      /* the period / type label is proven on that disk */
+};
+
+/* Options.  Zero in any field selects the default shown. */
+typedef struct msplit_options {
+    uint32_t struct_size;     /* sizeof(msplit_options) */
+    int32_t precision;        /* msplit_precision, default MSPLIT_FP64 */
+    double level;             /* lambda_0: 5 for p_n, 100 for q_{l,n} (Section 4.2) */
+    uint32_t points_per_turn; /* M, level-line points per turn: 8 (Section 6.3.1) */
+    uint32_t seg_points;      /* fine level-line points walked per lane: auto */
+    uint32_t min_cap;         /* Newton cap floor: 20 (Algorithm S_par) */
+    double cap_factor;        /* I_N of the cap max{20, I_N log d}: 1 (p), 2.6 (q) */
+    uint32_t block_size;      /* threads per block: 256 */
+    uint32_t flags;           /* msplit_flags */
+    double fp32_switch;       /* MIXED: relative step at which a lane leaves FP32: 2^-14 */
+} msplit_options;
+
+/* Output arrays (device pointers, each of `capacity` elements). */
+typedef struct msplit_roots {
+    double *re, *im;       /* root centres */
+    double *re_lo, *im_lo; /* nullable: low parts of a double-double root */
+    int32_t *period;       /* nullable: p_n: exact period k | n; q_{l,n}: n */
+    int32_t *preperiod;    /* nullable: q_{l,n}: l; p_n: 0 */
+    uint8_t *flags;        /* nullable: msplit_root_flags */
+    double *radius;        /* nullable: certificate radius (0 if not certified) */
+    uint64_t capacity;
+} msplit_roots;
+
+/* Statistics (host). */
+typedef struct msplit_stats {
+    uint64_t starts;        /* level-line starting points (closed upper half plane) */
+    uint64_t converged;     /* descents that converged */
+    uint64_t diverged;      /* descents discarded as divergent */
+    uint64_t timeouts;      /* descents that hit the cap */
+    uint64_t unique;        /* roots after collection */
+    uint64_t n_real;        /* real roots among them */
+    uint64_t total;         /* n_real + 2 (unique - n_real): roots counted in C */
+    uint64_t expected;      /* exact count: 2^(n-1) for p_n, |Mis(l,n)| for q */
+    uint64_t missing;       /* expected - total when positive */
+    uint64_t phase_fail;    /* level-line segments whose end missed the next seed */
+    uint64_t certified;     /* roots with MSPLIT_R_CERTIFIED */
+    uint64_t label_proven;  /* roots with MSPLIT_R_LABEL */
+    uint64_t overlaps;      /* certified disks that are not quarter-separated */
+    uint64_t steps_lift;    /* polynomial evaluations in the seed lift */
+    uint64_t steps_walk;    /* ... in the level-line walk */
+    uint64_t steps_desc;    /* ... in the descents */
+    uint64_t steps_fp32;    /* ... of which in FP32 (MIXED) */
+    double min_sep;         /* least distance between returned roots (and conjugates) */
+    double max_radius;      /* largest certificate radius */
+    double ms_device;       /* device time of the call, milliseconds */
+    /* device time of each stage, milliseconds, from events on `stream`:
+     * [0] seeds, [1] level-line walk, [2] descents, [3] collection,
+     * [4] classification, [5] certificate and separation */
+    double ms_stage[6];
+    int32_t hip_error;      /* last hipError_t on MSPLIT_E_DEVICE */
+    int32_t reserved;
+} msplit_stats;
+
+/* Human-readable text of a status code (static storage). */
+const char *msplit_strerror(int status);
+
+/* Exact root counts (Thm countingHyp, eq. HypCount; eq. MisCount):
+ *   l == 0: primitive_only ? |Hyp(n)| : 2^(n-1)   (all roots of p_n)
+ *   l >= 2: |Mis(l,n)| = Phi(l,n) |Hyp(n)|
+ * Returns 0 for invalid (l, n). */
+uint64_t msplit_expected_count(int l, int n, int primitive_only);
+
+/* Workspace bytes needed to split q_{l,n} (l = 0: p_n) with these options
+ * (NULL = defaults).  Returns MSPLIT_E_ARG for an invalid (l, n). */
+int msplit_workspace_size(int l, int n, const msplit_options *opts, uint64_t *bytes);
+
+/* Split p_n, 1 <= n <= 30 (Section 4.2, Algorithm S_par; Section 6.3.1).
+ * Writes all roots of p_n (closed upper half plane) to out, their exact period
+ * to out->period, and *count = number written.  count and stats are host
+ * pointers; stats may be NULL.  With MSPLIT_F_CERTIFY every root is checked
+ * by Thm proofRoots in disk arithmetic and its period by the same disk.
+ * Errors: MSPLIT_E_ARG, MSPLIT_E_WORKSPACE, MSPLIT_E_CAPACITY (then *count
+ * is the capacity needed), MSPLIT_E_DEVICE, MSPLIT_E_INCOMPLETE (roots are
+ * still written), MSPLIT_E_PRECISION (n beyond what FP64 separates). */
+int msplit_hyperbolic(int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes,
+                      msplit_roots *out, uint64_t *count, msplit_stats *stats, void *stream);
+
+/* Split q_{l,n}, l >= 2, n >= 1 (Section 2.2, eq. def:mis; Section 6.3.1,
+ * misQuick) and keep Mis(l,n): roots of q_{l,n} that are neither roots of
+ * q_{l-1,n} nor of q_{l,k} for a strict divisor k of n.  Same contract as
+ * msplit_hyperbolic. */
+int msplit_misiurewicz(int l, int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes,
+                       msplit_roots *out, uint64_t *count, msplit_stats *stats, void *stream);
+
+/* Certify `count` candidate roots of q_{l,n} (l = 0: p_n) already in device
+ * memory (Thm proofRoots with the disk arithmetic of Thm diskArithmetic, in
+ * FP64 with round-to-nearest and explicit radius inflation).  Reads re, im
+ * (and period for p_n labels); writes flags (MSPLIT_R_*) and radius.  The
+ * list must be sorted by increasing real part for the separation check.
+ * stats (nullable) receives certified, label_proven, overlaps, min_sep,
+ * max_radius, n_real, total. */
+int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *workspace,
+                   uint64_t workspace_bytes, msplit_stats *stats, void *stream);
+
+/* The level-line starting points alone (Section 4.1, the discrete level line
+ * L_{lambda_0, 4D}(P) of Prop. computeLevelLine; the levelSets / misSets
+ * stage of Section 6.4.1): start k, k = 0 .. 2D, is the point of the closed
+ * upper half plane with P = lambda_0 i^k, approximately (|P / (lambda_0 i^k)
+ * - 1| < 2^-5: a start only has to lie in the Newton basin of its root).
+ * re, im: device arrays of capacity >= 2D + 1.  *count = 2D + 1.  stats
+ * receives phase_fail, steps_lift, steps_walk and the stage times. */
+int msplit_starts(int l, int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes,
+                  double *re, double *im, uint64_t capacity, uint64_t *count, msplit_stats *stats, void *stream);
+
+/* Split a list of types in one call: ln_pairs holds npairs (l, n) pairs
+ * (l = 0 for p_n).  Roots of pair i are written at out[offsets[i] ..
+ * offsets[i] + counts[i]) where offsets[i] is the running sum of the
+ * capacities caps[i] (host array).  counts (host, npairs) receives the
+ * counts; stats (host, npairs, nullable) the per-pair statistics. */
+int msplit_batch(const int32_t *ln_pairs, int npairs, const msplit_options *opts, void *workspace,
+                 uint64_t workspace_bytes, msplit_roots *out, const uint64_t *caps, uint64_t *counts,
+                 msplit_stats *stats, void *stream);
+
+/* Workspace bytes for msplit_batch over these pairs. */
+int msplit_batch_workspace_size(const int32_t *ln_pairs, int npairs, const msplit_options *opts,
+                                uint64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSPLIT_H */

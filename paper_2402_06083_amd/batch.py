@@ -1,0 +1,75 @@
+"""Batched splits through ``msplit_batch`` with preallocated device buffers.
+
+The benchmark and the batch parity test share this runner so that both use the
+same launch configuration.
+"""
+import ctypes
+
+import torch
+
+from . import msplit
+
+
+class BatchResult:
+    def __init__(self, pairs, caps, counts, stats, statuses, bufs):
+        self.pairs = pairs
+        self.caps = caps
+        self.per_pair = list(zip(counts, stats, statuses))
+        self.bufs = bufs
+
+
+class BatchRunner:
+    """Buffers sized once for a list of (l, n) pairs; ``run()`` splits all."""
+
+    def __init__(self, pairs, opts, device="cuda"):
+        self.pairs = list(pairs)
+        self.opts = opts
+        L = msplit.lib()
+        self.arr = (ctypes.c_int32 * (2 * len(self.pairs)))(*[v for p in self.pairs for v in p])
+        b = ctypes.c_uint64()
+        r = L.msplit_batch_workspace_size(self.arr, len(self.pairs), ctypes.byref(opts), ctypes.byref(b))
+        if r:
+            raise msplit.MsplitError(r, "msplit_batch_workspace_size")
+        self.ws_bytes = int(b.value)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        # capacity per pair: all roots of q_{l,n} fit in 2^(l+n-1) upper-half slots
+        self.caps = [1 << (l + n - 1) for (l, n) in self.pairs]
+        tot = sum(self.caps)
+        self.re = torch.empty(tot, dtype=torch.float64, device=device)
+        self.im = torch.empty(tot, dtype=torch.float64, device=device)
+        self.period = torch.empty(tot, dtype=torch.int32, device=device)
+        self.preperiod = torch.empty(tot, dtype=torch.int32, device=device)
+        self.flags = torch.empty(tot, dtype=torch.uint8, device=device)
+        self.radius = torch.empty(tot, dtype=torch.float64, device=device)
+        self.caps_arr = (ctypes.c_uint64 * len(self.pairs))(*self.caps)
+        self.counts = (ctypes.c_uint64 * len(self.pairs))()
+        self.stats = (msplit.Stats * len(self.pairs))()
+        self.roots = msplit.RootsC(self.re.data_ptr(), self.im.data_ptr(), None, None, self.period.data_ptr(),
+                                   self.preperiod.data_ptr(), self.flags.data_ptr(), self.radius.data_ptr(), tot)
+
+    def run(self, stream=None):
+        L = msplit.lib()
+        sh = msplit._stream_handle(stream)
+        r = L.msplit_batch(self.arr, len(self.pairs), ctypes.byref(self.opts), ctypes.c_void_p(self.ws.data_ptr()),
+                           self.ws_bytes, ctypes.byref(self.roots), self.caps_arr, self.counts, self.stats, sh)
+        return r
+
+    def result(self, status):
+        counts = [int(c) for c in self.counts]
+        stats = [s.as_dict() for s in self.stats]
+        statuses = [0 if st["missing"] == 0 else msplit.E_INCOMPLETE for st in stats] if status == 0 else \
+            [status] * len(self.pairs)
+        return BatchResult(self.pairs, self.caps, counts, stats, statuses, self)
+
+    def slices(self, i):
+        off = sum(self.caps[:i])
+        c = int(self.counts[i])
+        return slice(off, off + c)
+
+
+def run_batch(pairs, certify=True, precision="fp64"):
+    opts = msplit.make_options(precision=precision, certify=certify)
+    runner = BatchRunner(pairs, opts)
+    r = runner.run()
+    torch.cuda.synchronize()
+    return runner.result(r)

@@ -1,0 +1,128 @@
+// common.hpp -- device helpers shared by the kernels of libmsplit (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msplit {
+
+// ---------------------------------------------------------------- complex
+struct cd { double re, im; };
+struct cf { float re, im; };
+
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ double cabs(cd a) { return sqrt(cabs2(a)); }
+// a / b through one reciprocal of |b|^2, after scaling both by the same
+// power of two so that |b|^2 cannot overflow or underflow: near escaping
+// iterates |P'| exceeds 1e154 while |P| does not, and an unscaled |P'|^2
+// would turn the Newton step P/P' into an exact zero.  (The same common
+// factor cancellation the paper applies to its FP80 steps, Section 6.3.2.)
+// b = 0 or a non-finite b yields a non-finite quotient.
+__device__ __forceinline__ cd cdiv(cd a, cd b)
+{
+    const double m = fmax(fabs(b.re), fabs(b.im));
+    const double s = ldexp(1.0, -ilogb(m));
+    const cd bs = {b.re * s, b.im * s}, as = {a.re * s, a.im * s};
+    const double r = 1.0 / cabs2(bs);
+    return {(as.re * bs.re + as.im * bs.im) * r, (as.im * bs.re - as.re * bs.im) * r};
+}
+__device__ __forceinline__ bool cfinite(cd a) { return isfinite(a.re) && isfinite(a.im); }
+
+// Principal complex logarithm; for |w - 1| < 1/64 a short series of log1p
+// (error |v|^6 / 6 < 1e-11 |v|, far below what a Newton iteration needs).
+__device__ __forceinline__ cd clog_near1(cd w)
+{
+    cd v = {w.re - 1.0, w.im};
+    double a2 = cabs2(v);
+    if (a2 < (1.0 / 4096.0)) {
+        // v - v^2/2 + v^3/3 - v^4/4 + v^5/5 (Horner)
+        cd acc = {0.2, 0.0};
+        acc = cadd(cmul(acc, v), {-0.25, 0.0});
+        acc = cadd(cmul(acc, v), {1.0 / 3.0, 0.0});
+        acc = cadd(cmul(acc, v), {-0.5, 0.0});
+        acc = cadd(cmul(acc, v), {1.0, 0.0});
+        return cmul(acc, v);
+    }
+    return {0.5 * log(cabs2(w)), atan2(w.im, w.re)};
+}
+
+// ---------------------------------------------------------------- orbit
+// Critical orbit p_0 = 0, p_{k+1} = p_k^2 + c and p'_{k+1} = 2 p_k p'_k + 1
+// (Section 2, eq. defFundMap; the derivative is the chain rule of the same
+// recurrence).  q_{l,n} = p_{l+n} - p_l; l = 0 gives p_n since p_0 = 0.
+template <typename T>
+struct orbit_state { T zr, zi, dr, di; };
+
+template <typename T>
+__device__ __forceinline__ void orbit_step(orbit_state<T> &s, T cr, T ci)
+{
+    // dz <- 2 z dz + 1 with the old z, then z <- z^2 + c
+    T tr = s.zr * s.dr - s.zi * s.di;
+    T ti = s.zr * s.di + s.zi * s.dr;
+    T nr = s.zr * s.zr - s.zi * s.zi + cr;
+    T ni = (s.zr + s.zr) * s.zi + ci;
+    s.dr = tr + tr + T(1);
+    s.di = ti + ti;
+    s.zr = nr;
+    s.zi = ni;
+}
+
+// P = q_{l,n}(c), dP = q_{l,n}'(c), N = l + n (l = 0: p_N)
+__device__ __forceinline__ void eval_q(int l, int N, cd c, cd &P, cd &dP)
+{
+    orbit_state<double> s = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k < l; ++k) orbit_step(s, c.re, c.im);
+    cd zl = {s.zr, s.zi}, dzl = {s.dr, s.di};
+    for (; k < N; ++k) orbit_step(s, c.re, c.im);
+    P = {s.zr - zl.re, s.zi - zl.im};
+    dP = {s.dr - dzl.re, s.di - dzl.im};
+}
+
+__device__ __forceinline__ void eval_q_f32(int l, int N, cf c, cf &P, cf &dP)
+{
+    orbit_state<float> s = {0.f, 0.f, 0.f, 0.f};
+    int k = 0;
+    for (; k < l; ++k) orbit_step(s, c.re, c.im);
+    cf zl = {s.zr, s.zi}, dzl = {s.dr, s.di};
+    for (; k < N; ++k) orbit_step(s, c.re, c.im);
+    P = {s.zr - zl.re, s.zi - zl.im};
+    dP = {s.dr - dzl.re, s.di - dzl.im};
+}
+
+// ---------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Wave-aggregated work fetch: lanes with need == true get consecutive
+// indices from *counter; others get ~0.
+__device__ __forceinline__ uint64_t wave_fetch(unsigned long long *counter, bool need)
+{
+    unsigned long long mask = __ballot(need);
+    uint64_t idx = ~0ull;
+    if (mask) {
+        int leader = __ffsll((unsigned long long)mask) - 1;
+        unsigned long long base = 0;
+        if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader);
+        if (need) idx = base + (uint64_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
+    }
+    return idx;
+}
+
+// Wave-reduced atomic add of a per-lane count.
+__device__ __forceinline__ void wave_add(unsigned long long *dst, unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane_id() == 0 && v) atomicAdd(dst, v);
+}
+
+// Order-preserving map of a double onto uint64 (sort key).
+__device__ __forceinline__ uint64_t orderable(double x)
+{
+    uint64_t u = (uint64_t)__double_as_longlong(x);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+
+} // namespace msplit

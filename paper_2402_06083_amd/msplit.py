@@ -1,0 +1,267 @@
+"""ctypes binding of libmsplit (include/msplit.h).
+
+Argument marshalling only: every step of the split runs in the HIP kernels of
+``libmsplit.so``.  torch provides the device memory (workspace and output
+arrays) and the stream.  The binding raises if the library is missing; there
+is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsplit.so")
+
+# status codes
+OK, E_ARG, E_CAPACITY, E_WORKSPACE, E_DEVICE, E_INCOMPLETE, E_PRECISION, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, MIXED, DD = 0, 1, 2
+F_CERTIFY, F_NO_LABEL = 1, 2
+R_REAL, R_CERTIFIED, R_LABEL = 1, 2, 4
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("precision", ctypes.c_int32),
+        ("level", ctypes.c_double),
+        ("points_per_turn", ctypes.c_uint32),
+        ("seg_points", ctypes.c_uint32),
+        ("min_cap", ctypes.c_uint32),
+        ("cap_factor", ctypes.c_double),
+        ("block_size", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("fp32_switch", ctypes.c_double),
+    ]
+
+
+class RootsC(ctypes.Structure):
+    _fields_ = [
+        ("re", ctypes.c_void_p), ("im", ctypes.c_void_p),
+        ("re_lo", ctypes.c_void_p), ("im_lo", ctypes.c_void_p),
+        ("period", ctypes.c_void_p), ("preperiod", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p), ("radius", ctypes.c_void_p),
+        ("capacity", ctypes.c_uint64),
+    ]
+
+
+_STAT_U64 = ["starts", "converged", "diverged", "timeouts", "unique", "n_real", "total", "expected",
+             "missing", "phase_fail", "certified", "label_proven", "overlaps", "steps_lift",
+             "steps_walk", "steps_desc", "steps_fp32"]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in _STAT_U64] + [
+        ("min_sep", ctypes.c_double), ("max_radius", ctypes.c_double), ("ms_device", ctypes.c_double),
+        ("ms_stage", ctypes.c_double * 6),
+        ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+    STAGES = ("seeds", "walk", "descend", "collect", "classify", "certify")
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "ms_stage")}
+        d["ms_stage"] = dict(zip(self.STAGES, list(self.ms_stage)))
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libmsplit.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(python -m paper_2402_06083_amd._build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    pOpt, pRoots, pStats = ctypes.POINTER(Options), ctypes.POINTER(RootsC), ctypes.POINTER(Stats)
+    pu64 = ctypes.POINTER(ctypes.c_uint64)
+    L.msplit_strerror.argtypes = [i32]
+    L.msplit_strerror.restype = ctypes.c_char_p
+    L.msplit_expected_count.argtypes = [i32, i32, i32]
+    L.msplit_expected_count.restype = u64
+    L.msplit_workspace_size.argtypes = [i32, i32, pOpt, pu64]
+    L.msplit_workspace_size.restype = i32
+    L.msplit_hyperbolic.argtypes = [i32, pOpt, vp, u64, pRoots, pu64, pStats, vp]
+    L.msplit_hyperbolic.restype = i32
+    L.msplit_misiurewicz.argtypes = [i32, i32, pOpt, vp, u64, pRoots, pu64, pStats, vp]
+    L.msplit_misiurewicz.restype = i32
+    L.msplit_certify.argtypes = [i32, i32, pRoots, u64, vp, u64, pStats, vp]
+    L.msplit_certify.restype = i32
+    L.msplit_batch.argtypes = [ctypes.POINTER(ctypes.c_int32), i32, pOpt, vp, u64, pRoots, pu64, pu64, pStats, vp]
+    L.msplit_batch.restype = i32
+    L.msplit_starts.argtypes = [i32, i32, pOpt, vp, u64, vp, vp, u64, pu64, pStats, vp]
+    L.msplit_starts.restype = i32
+    L.msplit_batch_workspace_size.argtypes = [ctypes.POINTER(ctypes.c_int32), i32, pOpt, pu64]
+    L.msplit_batch_workspace_size.restype = i32
+    _lib = L
+    return L
+
+
+EXPORTED = ["msplit_strerror", "msplit_expected_count", "msplit_workspace_size", "msplit_hyperbolic",
+            "msplit_misiurewicz", "msplit_certify", "msplit_batch", "msplit_batch_workspace_size",
+            "msplit_starts"]
+
+
+def strerror(status: int) -> str:
+    return lib().msplit_strerror(status).decode()
+
+
+class MsplitError(RuntimeError):
+    def __init__(self, status, what=""):
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+        self.status = status
+
+
+def make_options(precision=FP64, level=0.0, points_per_turn=0, seg_points=0, min_cap=0, cap_factor=0.0,
+                 block_size=0, certify=False, label=True, fp32_switch=0.0):
+    flags = (F_CERTIFY if certify else 0) | (0 if label else F_NO_LABEL)
+    prec = {"fp64": FP64, "mixed": MIXED, "dd": DD}.get(precision, precision)
+    return Options(ctypes.sizeof(Options), prec, level, points_per_turn, seg_points, min_cap, cap_factor,
+                   block_size, flags, fp32_switch)
+
+
+def expected_count(l: int, n: int, primitive_only: bool = False) -> int:
+    return int(lib().msplit_expected_count(l, n, 1 if primitive_only else 0))
+
+
+def workspace_size(l: int, n: int, opts: Options = None) -> int:
+    b = ctypes.c_uint64()
+    r = lib().msplit_workspace_size(l, n, ctypes.byref(opts) if opts else None, ctypes.byref(b))
+    if r:
+        raise MsplitError(r, f"msplit_workspace_size({l},{n})")
+    return int(b.value)
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Result:
+    """Roots of one split (device tensors trimmed to the count)."""
+
+    def __init__(self, l, n, re, im, period, flags, radius, count, stats, status):
+        self.l, self.n = l, n
+        self.re, self.im, self.period, self.flags, self.radius = re, im, period, flags, radius
+        self.count = count
+        self.stats = stats
+        self.status = status
+
+    def __len__(self):
+        return self.count
+
+    def cpu(self):
+        import numpy as np
+        d = {"re": self.re.cpu().numpy(), "im": self.im.cpu().numpy()}
+        for k in ("period", "flags", "radius"):
+            t = getattr(self, k)
+            d[k] = t.cpu().numpy() if t is not None else None
+        d["stats"] = self.stats
+        d["status"] = self.status
+        return type("HostRoots", (), d)() if False else _Host(**d)
+
+
+class _Host:
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    def __len__(self):
+        return len(self.re)
+
+
+class Buffers:
+    """Reusable device buffers for repeated splits of one type (benchmarks)."""
+
+    def __init__(self, l, n, opts, device="cuda"):
+        self.l, self.n, self.opts = l, n, opts
+        self.ws_bytes = workspace_size(l, n, opts)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        cap = 1 << (l + n - 1)
+        self.cap = cap
+        self.re = torch.empty(cap, dtype=torch.float64, device=device)
+        self.im = torch.empty(cap, dtype=torch.float64, device=device)
+        self.period = torch.empty(cap, dtype=torch.int32, device=device)
+        self.preperiod = torch.empty(cap, dtype=torch.int32, device=device)
+        self.flags = torch.empty(cap, dtype=torch.uint8, device=device)
+        self.radius = torch.empty(cap, dtype=torch.float64, device=device)
+
+    def roots_struct(self):
+        return RootsC(self.re.data_ptr(), self.im.data_ptr(), None, None, self.period.data_ptr(),
+                      self.preperiod.data_ptr(), self.flags.data_ptr(), self.radius.data_ptr(), self.cap)
+
+
+def split(l: int, n: int, opts: Options = None, buffers: Buffers = None, stream=None, check=True) -> Result:
+    """Split q_{l,n} (l = 0: p_n) on the current CUDA/HIP device."""
+    opts = opts or make_options()
+    b = buffers or Buffers(l, n, opts)
+    rs = b.roots_struct()
+    cnt = ctypes.c_uint64()
+    st = Stats()
+    sh = _stream_handle(stream)
+    if l == 0:
+        r = lib().msplit_hyperbolic(n, ctypes.byref(opts), ctypes.c_void_p(b.ws.data_ptr()), b.ws_bytes,
+                                    ctypes.byref(rs), ctypes.byref(cnt), ctypes.byref(st), sh)
+    else:
+        r = lib().msplit_misiurewicz(l, n, ctypes.byref(opts), ctypes.c_void_p(b.ws.data_ptr()), b.ws_bytes,
+                                     ctypes.byref(rs), ctypes.byref(cnt), ctypes.byref(st), sh)
+    c = int(cnt.value)
+    if check and r not in (OK,):
+        raise MsplitError(r, f"split({l},{n})")
+    certified = bool(opts.flags & F_CERTIFY)
+    return Result(l, n, b.re[:c], b.im[:c], b.period[:c], b.flags[:c], b.radius[:c] if certified else None, c,
+                  st.as_dict(), r)
+
+
+def hyperbolic(n: int, **kw) -> Result:
+    opts = make_options(**{k: v for k, v in kw.items() if k not in ("stream", "check")})
+    return split(0, n, opts, stream=kw.get("stream"), check=kw.get("check", True))
+
+
+def misiurewicz(l: int, n: int, **kw) -> Result:
+    opts = make_options(**{k: v for k, v in kw.items() if k not in ("stream", "check")})
+    return split(l, n, opts, stream=kw.get("stream"), check=kw.get("check", True))
+
+
+def certify(l: int, n: int, re: torch.Tensor, im: torch.Tensor, period: torch.Tensor = None, stream=None):
+    """Certify candidates (device tensors, sorted by real part).  Returns
+    (flags uint8 tensor, radius float64 tensor, stats dict)."""
+    m = re.numel()
+    dev = re.device
+    re = re.contiguous().to(torch.float64)
+    im = im.contiguous().to(torch.float64)
+    flags = torch.zeros(m, dtype=torch.uint8, device=dev)
+    radius = torch.zeros(m, dtype=torch.float64, device=dev)
+    per = period.contiguous().to(torch.int32) if period is not None else None
+    ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+    rs = RootsC(re.data_ptr(), im.data_ptr(), None, None, per.data_ptr() if per is not None else None, None,
+                flags.data_ptr(), radius.data_ptr(), m)
+    st = Stats()
+    r = lib().msplit_certify(l, n, ctypes.byref(rs), m, ctypes.c_void_p(ws.data_ptr()), 4096, ctypes.byref(st),
+                             _stream_handle(stream))
+    if r:
+        raise MsplitError(r, "msplit_certify")
+    return flags, radius, st.as_dict()
+
+
+def starts(l: int, n: int, opts: Options = None, stream=None, check=True):
+    """Level-line starting points (start k has P ~ lambda_0 i^k), as device
+    tensors (re, im), with the stats dict and status."""
+    opts = opts or make_options()
+    ws_bytes = workspace_size(l, n, opts)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    ns = 2 * (1 << (l + n - 1)) + 1
+    re = torch.empty(ns, dtype=torch.float64, device="cuda")
+    im = torch.empty(ns, dtype=torch.float64, device="cuda")
+    cnt = ctypes.c_uint64()
+    st = Stats()
+    r = lib().msplit_starts(l, n, ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ws_bytes,
+                            ctypes.c_void_p(re.data_ptr()), ctypes.c_void_p(im.data_ptr()), ns, ctypes.byref(cnt),
+                            ctypes.byref(st), _stream_handle(stream))
+    if check and r:
+        raise MsplitError(r, f"msplit_starts({l},{n})")
+    return re, im, st.as_dict(), r

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/msplit.h; host-side logic that needs no GPU (counts, status text)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import counts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msplit.h")
+LIB = os.path.join(ROOT, "paper_2402_06083_amd", "libmsplit.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(msplit_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2402_06083_amd import _build
+        _build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_2402_06083_amd import msplit
+    assert sorted(msplit.EXPORTED) == names
+
+
+def test_struct_sizes_match_binding(lib):
+    from paper_2402_06083_amd import msplit
+    # msplit_options: 4+4+8+4+4+4(pad)+8+4+4+8 = 56 bytes on x86-64 SysV
+    assert ctypes.sizeof(msplit.Options) == 56
+    assert ctypes.sizeof(msplit.RootsC) == 8 * 8 + 8
+    assert ctypes.sizeof(msplit.Stats) == 17 * 8 + 3 * 8 + 6 * 8 + 8
+
+
+def test_expected_counts_match_oracle_counts(lib):
+    from paper_2402_06083_amd import msplit
+    for n in range(1, 31):
+        assert msplit.expected_count(0, n) == 2 ** (n - 1)
+        assert msplit.expected_count(0, n, True) == counts.hyp_count(n)
+    for l in range(2, 12):
+        for n in range(1, 12):
+            assert msplit.expected_count(l, n) == counts.mis_count(l, n), (l, n)
+    assert msplit.expected_count(1, 3) == 0
+    assert msplit.expected_count(0, 0) == 0
+
+
+def test_status_strings(lib):
+    from paper_2402_06083_amd import msplit
+    for code in range(0, -8, -1):
+        s = msplit.strerror(code)
+        assert s and s != "unknown status"
+    assert msplit.strerror(-99) == "unknown status"
+
+
+def test_invalid_arguments_without_device(lib):
+    from paper_2402_06083_amd import msplit
+    b = ctypes.c_uint64()
+    L = msplit.lib()
+    assert L.msplit_workspace_size(1, 3, None, ctypes.byref(b)) == msplit.E_ARG
+    assert L.msplit_workspace_size(0, 0, None, ctypes.byref(b)) == msplit.E_ARG
+    assert L.msplit_workspace_size(0, 31, None, ctypes.byref(b)) == msplit.E_ARG
+    cnt = ctypes.c_uint64(7)
+    assert L.msplit_hyperbolic(0, None, None, 0, None, ctypes.byref(cnt), None, None) == msplit.E_ARG
+    assert cnt.value == 0
+    assert L.msplit_misiurewicz(1, 3, None, None, 0, None, ctypes.byref(cnt), None, None) == msplit.E_ARG

@@ -1,0 +1,228 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar (Section 6.1 / Thm certif reading): identical discrete structure -- same
+root count, a nearest-neighbour bijection with every distance <= 1e-10 and
+<= a quarter of the local root separation, identical period labels and real
+flags.  At the full period-24 size every returned root is checked one by one
+by the oracle's own certificate (Thm proofRoots in long double) on a sample,
+and by the GPU certificate plus exact counts on all of them.
+"""
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import counts
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_06083_amd import msplit
+    msplit.lib()  # raises if the HIP library is missing
+    return torch.device("cuda:0")
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_split(l, n):
+    return oracle.split(l, n)
+
+
+def gpu_split(l, n, **kw):
+    from paper_2402_06083_amd import msplit
+    say(f"[gpu] split l={l} n={n} {kw}")
+    opts = msplit.make_options(**kw)
+    r = msplit.split(l, n, opts, check=False)
+    torch.cuda.synchronize()
+    return r, r.cpu()
+
+
+def compare_sets(g, o, tol=1e-10):
+    """Nearest-neighbour bijection GPU -> oracle; returns max distance."""
+    from scipy.spatial import cKDTree
+    oz = np.stack([o.re_hi, o.im_hi], axis=1)
+    gz = np.stack([g.re, g.im], axis=1)
+    assert len(gz) == len(oz), (len(gz), len(oz))
+    tree = cKDTree(oz)
+    d, idx = tree.query(gz, k=1)
+    assert len(np.unique(idx)) == len(oz), "not a bijection"
+    # local separation of the oracle roots (and their conjugates)
+    if len(oz) > 1:
+        dd, _ = tree.query(oz, k=2)
+        sep = dd[:, 1]
+    else:
+        sep = np.full(1, np.inf)
+    sep = np.minimum(sep, np.where(o.im_hi > 0, 2 * o.im_hi, np.inf))
+    assert d.max() <= tol, d.max()
+    assert np.all(d <= sep[idx] / 4), "a root moved by more than a quarter of its separation"
+    assert np.array_equal(g.period, o.period[idx]), "period labels differ"
+    assert np.array_equal(g.im == 0, o.im_hi[idx] == 0), "real flags differ"
+    return float(d.max()), idx
+
+
+@pytest.mark.parametrize("n", list(range(1, 17)))
+def test_hyperbolic_parity_small(n):
+    from paper_2402_06083_amd import msplit
+    r, g = gpu_split(0, n)
+    assert r.status == msplit.OK, (r.status, r.stats)
+    st = r.stats
+    assert st["phase_fail"] == 0 and st["missing"] == 0 and st["total"] == 2 ** (n - 1)
+    o = oracle_split(0, n)
+    compare_sets(g, o)
+    # increasing real part
+    assert np.all(np.diff(g.re) >= 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_hyperbolic_parity_n20(precision):
+    from paper_2402_06083_amd import msplit
+    r, g = gpu_split(0, 20, precision=precision)
+    assert r.status == msplit.OK, (r.status, r.stats)
+    o = oracle_split(0, 20)
+    dmax, _ = compare_sets(g, o)
+    say(f"[gpu] n=20 {precision}: max |gpu - oracle| = {dmax:.3e}, stats={r.stats}")
+    if precision == "mixed":
+        assert r.stats["steps_fp32"] > 0
+
+
+@pytest.mark.parametrize("n", [12, 18])
+def test_certificate_on_split(n):
+    from paper_2402_06083_amd import msplit
+    r, g = gpu_split(0, n, certify=True)
+    assert r.status == msplit.OK
+    st = r.stats
+    assert st["certified"] == len(g) and st["label_proven"] == len(g), st
+    assert st["overlaps"] == 0
+    assert np.all(g.flags & msplit.R_CERTIFIED) and np.all(g.flags & msplit.R_LABEL)
+    assert g.radius.max() <= 1e-10
+    # the oracle's certificate (long double, round upward) accepts them too
+    ok, rad = oracle.certify(0, n, g.re, g.im, label=g.period)
+    assert np.all(ok == 3)
+
+
+def test_full_size_period_24():
+    """Period 24 at full size (8 388 608 roots): exact counts per period class,
+    every root certified by the GPU, a random sample certified one by one by
+    the oracle, Vieta's sum of the roots."""
+    from paper_2402_06083_amd import msplit
+    n = 24
+    r, g = gpu_split(0, n, certify=True)
+    assert r.status == msplit.OK, (r.status, r.stats)
+    st = r.stats
+    say(f"[gpu] n=24 stats: {st}")
+    assert st["total"] == 2 ** 23 and st["certified"] == len(g) and st["label_proven"] == len(g)
+    assert st["overlaps"] == 0 and g.radius.max() <= 1e-10
+    for k in counts.divisors(n):
+        sel = g.period == k
+        cnt = int((g.im[sel] == 0).sum()) + 2 * int((g.im[sel] > 0).sum())
+        assert cnt == counts.hyp_count(k), (k, cnt)
+    rng = np.random.default_rng(24)
+    idx = rng.choice(len(g), size=20000, replace=False)
+    idx.sort()
+    ok, rad = oracle.certify(0, n, g.re[idx], g.im[idx], label=g.period[idx])
+    assert np.all(ok == 3)
+    assert rad.max() <= 1e-10
+    w = np.where(g.im > 0, 2.0, 1.0)
+    s1 = math.fsum((w * g.re).tolist())
+    assert abs(s1 - (-(2 ** (n - 2)))) < 1e-6
+
+
+def test_batch_periods_1_to_24():
+    """All periods 1..24 through msplit_batch, certified, in the benchmark's
+    launch configuration."""
+    from paper_2402_06083_amd import batch
+    say("[gpu] batch 1..24")
+    res = batch.run_batch([(0, n) for n in range(1, 25)], certify=True)
+    for (l, n), (count, st, status) in zip(res.pairs, res.per_pair):
+        assert status == 0, (n, status, st)
+        assert st["total"] == 2 ** (n - 1) and st["certified"] == count and st["overlaps"] == 0, (n, st)
+
+
+def test_certify_api_and_rejection():
+    from paper_2402_06083_amd import msplit
+    o = oracle_split(0, 12)
+    say("[gpu] msplit_certify on oracle roots")
+    re = torch.tensor(o.re_hi, dtype=torch.float64, device="cuda")
+    im = torch.tensor(o.im_hi, dtype=torch.float64, device="cuda")
+    per = torch.tensor(o.period, dtype=torch.int32, device="cuda")
+    flags, rad, st = msplit.certify(0, 12, re, im, per)
+    f = flags.cpu().numpy()
+    assert np.all(f & msplit.R_CERTIFIED) and np.all(f & msplit.R_LABEL)
+    assert st["overlaps"] == 0
+    # a candidate moved by 1e-3 is not certified within 1e-10, a wrong label fails
+    re2 = re.clone()
+    re2[100] += 1e-3
+    per2 = per.clone()
+    j = int(np.where(o.period == 12)[0][5])
+    per2[j] = 6
+    flags, rad, st = msplit.certify(0, 12, re2, im, per2)
+    f = flags.cpu().numpy()
+    r = rad.cpu().numpy()
+    assert not (f[100] & msplit.R_CERTIFIED and r[100] <= 1e-10)
+    assert (f[j] & msplit.R_CERTIFIED) and not (f[j] & msplit.R_LABEL)
+
+
+def test_error_paths():
+    import ctypes
+    from paper_2402_06083_amd import msplit
+    L = msplit.lib()
+    opts = msplit.make_options()
+    say("[gpu] error paths")
+    ws_bytes = msplit.workspace_size(0, 10, opts)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    cap = 10
+    re = torch.empty(cap, dtype=torch.float64, device="cuda")
+    im = torch.empty(cap, dtype=torch.float64, device="cuda")
+    rs = msplit.RootsC(re.data_ptr(), im.data_ptr(), None, None, None, None, None, None, cap)
+    cnt = ctypes.c_uint64()
+    st = msplit.Stats()
+    sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    r = L.msplit_hyperbolic(10, ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ws_bytes, ctypes.byref(rs),
+                            ctypes.byref(cnt), ctypes.byref(st), sh)
+    assert r == msplit.E_CAPACITY and cnt.value == len(oracle_split(0, 10))
+    r = L.msplit_hyperbolic(10, ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ws_bytes - 4096,
+                            ctypes.byref(rs), ctypes.byref(cnt), ctypes.byref(st), sh)
+    assert r == msplit.E_WORKSPACE
+    r = L.msplit_hyperbolic(28, ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ws_bytes, ctypes.byref(rs),
+                            ctypes.byref(cnt), ctypes.byref(st), sh)
+    assert r == msplit.E_PRECISION
+
+
+def test_deterministic_output():
+    r1, g1 = gpu_split(0, 17)
+    r2, g2 = gpu_split(0, 17)
+    assert np.array_equal(g1.re, g2.re) and np.array_equal(g1.im, g2.im)
+    assert np.array_equal(g1.period, g2.period)
+
+
+@pytest.mark.parametrize("n", [3, 8, 12, 17])
+def test_start_set_matches_oracle(n):
+    """Start k of the GPU level line is the oracle's start k (value lambda_0 i^k),
+    up to the acceptance tolerance of the walk."""
+    from paper_2402_06083_amd import msplit
+    say(f"[gpu] starts n={n}")
+    re, im, st, status = msplit.starts(0, n, check=False)
+    assert status == msplit.OK and st["phase_fail"] == 0, st
+    g = re.cpu().numpy() + 1j * im.cpu().numpy()
+    ore, oim, _ = oracle.starts(0, n)
+    o = ore.astype(np.float64) + 1j * oim.astype(np.float64)
+    assert len(g) == len(o) == 2 ** n + 1
+    gap = np.minimum(np.abs(np.diff(o, prepend=o[1])), np.abs(np.diff(o, append=o[-2])))
+    assert np.all(np.abs(g - o) <= 0.2 * gap)
+    for k in range(0, len(g), max(1, len(g) // 50)):
+        P = oracle.evaluate(0, n, complex(g[k]))
+        val = complex(float(P[0]), float(P[1]))
+        assert abs(val / (5 * [1, 1j, -1, -1j][k % 4]) - 1) < 2 ** -5 + 1e-9, k
