@@ -111,6 +111,37 @@ __device__ __forceinline__ uint64_t wave_fetch(unsigned long long *counter, bool
     return idx;
 }
 
+// Per-wave work queue: the wave owns the index range [next, end) taken from
+// the global counter `chunk` items at a time (one atomic per chunk instead
+// of one per item: a single counter hit by every wave at every Newton step
+// serialises in the L2 atomic unit).  The two fields are wave-uniform: every
+// lane holds the same copy and applies the same updates.  Lanes with need get
+// distinct indices (possibly >= the item count: no work left).  chunk >= 64.
+struct wave_queue { uint64_t next, end; };
+
+__device__ __forceinline__ uint64_t wave_take(wave_queue &q, unsigned long long *counter, uint64_t chunk, bool need)
+{
+    unsigned long long mask = __ballot(need);
+    uint64_t idx = ~0ull;
+    if (!mask) return idx;
+    const uint32_t cnt = (uint32_t)__popcll(mask);
+    const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
+    const uint64_t avail = q.end - q.next;
+    if (avail < cnt) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        unsigned long long b = 0;
+        if (lane_id() == leader) b = atomicAdd(counter, (unsigned long long)chunk);
+        b = __shfl(b, leader);
+        if (need) idx = rank < avail ? q.next + rank : b + (rank - avail);
+        q.next = b + (cnt - avail);
+        q.end = b + chunk;
+    } else {
+        if (need) idx = q.next + rank;
+        q.next += cnt;
+    }
+    return idx;
+}
+
 // Wave-reduced atomic add of a per-lane count.
 __device__ __forceinline__ void wave_add(unsigned long long *dst, unsigned long long v)
 {

@@ -50,6 +50,8 @@ struct plan_t {
     uint32_t divmask_lo;  // bit k set when k | n, k < n (k < 32)
     int precision;
     float fp32_switch;
+    uint32_t chunk_seg;   // work-queue chunk of the walk (segments)
+    uint32_t chunk_start; // work-queue chunk of the descents (starts)
 };
 
 // cis(2 pi s / M) for s = 0..M-1, M <= 64, set by the host
@@ -128,9 +130,10 @@ __global__ void k_walk(plan_t pl, const cd *seeds, cd *starts, uint8_t *seg_flag
     int it = 0;
     cd z = {0.0, 0.0};
     bool done = false;
+    wave_queue wq = {0, 0};
     while (true) {
         bool need = !done && j < 0;
-        uint64_t got = wave_fetch(&ctr[C_SEG_NEXT], need);
+        uint64_t got = wave_take(wq, &ctr[C_SEG_NEXT], pl.chunk_seg, need);
         if (need) {
             if (got >= (uint64_t)pl.S) done = true;
             else { j = (int64_t)got; z = seeds[j]; s = j * pl.F + 1; send = j * pl.F + pl.F; it = 0; }
@@ -194,13 +197,15 @@ __global__ void k_descend(plan_t pl, cd *roots, uint8_t *status, unsigned long l
     unsigned long long steps = 0, steps32 = 0, nconv = 0, ndiv = 0, ntime = 0;
     int64_t k = -1;
     cd z = {0.0, 0.0};
-    double prev = 0.0;
+    double prev = 0.0; // previous step (FP32: length; FP64: squared length)
     int it = 0;
     bool fin = false, done = false, f32 = false;
     const bool mixed = pl.precision == 1;
+    const double tol2 = pl.tol_desc * pl.tol_desc;
+    wave_queue wq = {0, 0};
     while (true) {
         bool need = !done && k < 0;
-        uint64_t got = wave_fetch(&ctr[C_START_NEXT], need);
+        uint64_t got = wave_take(wq, &ctr[C_START_NEXT], pl.chunk_start, need);
         if (need) {
             if (got >= (uint64_t)pl.NS) done = true;
             else { k = (int64_t)got; z = roots[k]; it = 0; prev = 0.0; fin = false; f32 = mixed; }
@@ -221,6 +226,7 @@ __global__ void k_descend(plan_t pl, cd *roots, uint8_t *status, unsigned long l
                 // FP32 is done (or cannot resolve this point): FP64 takes
                 // over from the current point without this step
                 f32 = false;
+                prev = prev * prev;
             } else {
                 float zr = c.re - sr, zi = c.im - si;
                 ++it;
@@ -238,14 +244,15 @@ __global__ void k_descend(plan_t pl, cd *roots, uint8_t *status, unsigned long l
             cd d = cdiv(P, dP);
             z = csub(z, d);
             ++it;
-            double a = cabs(d);
-            double az = cabs(z);
+            // squared lengths: |d|, |z| compared without square roots
+            double a2 = cabs2(d);
+            double az2 = cabs2(z);
             if (fin) st = ST_CONVERGED;
-            else if (!isfinite(a) || !cfinite(z) || az > 8.0) st = ST_DIVERGED;
-            else if (it > 3 && a > 8.0 * prev) st = ST_DIVERGED;
-            else if (a <= pl.tol_desc * fmax(az, 0.00390625)) fin = true;
+            else if (!isfinite(a2) || !cfinite(z) || az2 > 64.0) st = ST_DIVERGED;
+            else if (it > 3 && a2 > 64.0 * prev) st = ST_DIVERGED;
+            else if (a2 <= tol2 * fmax(az2, 0x1p-16)) fin = true;
             else if (it >= pl.cap) st = ST_TIMEOUT;
-            prev = a;
+            prev = a2;
         }
         if (st != ST_NONE) {
             roots[k] = z;

@@ -106,6 +106,14 @@ plan_t make_plan(int l, int n, const msplit_options *o)
     p.divmask_lo = divisor_mask(n);
     p.precision = o->precision;
     p.fp32_switch = o->fp32_switch > 0 ? (float)o->fp32_switch : 0x1p-14f;
+    // work-queue chunks: about four chunks per wave of a full persistent grid
+    auto chunk_for = [](int64_t items) {
+        int64_t waves = 256 * 8 * 4;
+        int64_t c = items / (waves * 4);
+        return (uint32_t)std::max<int64_t>(64, std::min<int64_t>(1024, c));
+    };
+    p.chunk_seg = chunk_for(p.S);
+    p.chunk_start = chunk_for(p.NS);
     return p;
 }
 
