@@ -51,15 +51,17 @@ def certified_roots(stats_list):
 
 
 def kernel_flops(pairs, stats_list):
+    """Algorithmic flops of the walk and descent kernels over the whole call
+    (per-type step counts times the per-evaluation cost of that type) and
+    the kernels' device times (one launch each for the whole call)."""
     desc = walk = 0.0
-    t_desc = t_walk = 0.0
     for (l, n), st in zip(pairs, stats_list):
         N = l + n
         desc += st["steps_desc"] * (FLOPS_ORBIT_STEP * N + FLOPS_NEWTON_UPDATE)
         desc += st["steps_fp32"] * (FLOPS_ORBIT_STEP * N + FLOPS_NEWTON_UPDATE)
         walk += st["steps_walk"] * (FLOPS_ORBIT_STEP * N + FLOPS_WALK_UPDATE)
-        t_desc += st["ms_stage"]["descend"]
-        t_walk += st["ms_stage"]["walk"]
+    t_desc = stats_list[0]["ms_stage"]["descend"]
+    t_walk = stats_list[0]["ms_stage"]["walk"]
     return desc, t_desc, walk, t_walk
 
 
@@ -89,10 +91,10 @@ def run_gpu(pairs, precision, steps, warmup):
         agg["walk"] += w
         agg["t_walk"] += tw
         agg["roots"] += cr
-        agg["ms_device"] += sum(st["ms_device"] for st in sts)
-        for st in sts:
-            for k, v in st["ms_stage"].items():
-                agg["stages"][k] += v
+        # stage times cover the whole call (every type in one launch per stage)
+        agg["ms_device"] += sts[0]["ms_device"]
+        for k, v in sts[0]["ms_stage"].items():
+            agg["stages"][k] += v
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0

@@ -119,10 +119,13 @@ typedef struct msplit_stats {
     uint64_t steps_walk;    /* ... in the level-line walk */
     uint64_t steps_desc;    /* ... in the descents */
     uint64_t steps_fp32;    /* ... of which in FP32 (MIXED) */
-    double min_sep;         /* least distance between returned roots (and conjugates) */
+    double min_sep;         /* least distance found between a root and its conjugate or one
+                               of the next 8 roots in real order (upper bound of the least
+                               distance; the closest pairs are adjacent in that order) */
     double max_radius;      /* largest certificate radius */
-    double ms_device;       /* device time of the call, milliseconds */
-    /* device time of each stage, milliseconds, from events on `stream`:
+    double ms_device;       /* device time of the whole call, milliseconds */
+    /* device time of each stage of the whole call (all types of a batch share
+     * one launch per stage), milliseconds, from events on `stream`:
      * [0] seeds, [1] level-line walk, [2] descents, [3] collection,
      * [4] classification, [5] certificate and separation */
     double ms_stage[6];

@@ -9,7 +9,7 @@
 //   R* = ulp(a (x) b)/2 + sum over the four real products u v of ulp(u v)/2,
 // with ulp(x + iy) bounded by ulp(x) + ulp(y).  Centres are computed with
 // separate IEEE multiplications and additions (no fused multiply-add), so the
-// R* bound applies verbatim.  The GPU rounds to nearest only, so every radius
+// R* bound applies to each of them.  The GPU rounds to nearest only, so every radius
 // expression is evaluated in round-to-nearest and then inflated by
 // (1 + 2^-47) plus 2^-1000: each radius update is at most a few dozen
 // operations, each off by at most 2^-53 relative (subnormal results by
@@ -23,15 +23,20 @@
 // divisor k of n have no zero on the disk.
 #pragma once
 #include "common.hpp"
+#include "kernels.hpp"
 
 namespace msplit {
 
-__device__ __forceinline__ double ulp64(double x)
-{
-    double a = fabs(x);
-    if (!(a >= 2.2250738585072014e-308)) return 4.9406564584124654e-324;
-    return ldexp(1.0, ilogb(a) - 52);
-}
+// Rounding bound used below: a double r^ = fl(r) rounded to nearest obeys
+// |r^ - r| <= ulp(r^)/2 <= u |r^| + eta with u = 2^-53 (normal results) and
+// eta = 2^-1074 (covers a subnormal result), so the R* term of Thm
+// diskArithmetic is bounded by u times the sum of the magnitudes of the
+// rounded intermediate results, plus eta per operation.
+constexpr double U53 = 0x1p-53;
+constexpr double ETA = 0x1p-1074;
+
+// x (1 + 2^-47) + 2^-1000: upper bound of a radius expression of at most a
+// few dozen non-negative round-to-nearest operations
 __device__ __forceinline__ double up(double x) { return __dadd_rn(__dmul_rn(x, 1.0 + 0x1p-47), 0x1p-1000); }
 __device__ __forceinline__ double dn(double x) { return __dsub_rn(__dmul_rn(x, 1.0 - 0x1p-47), 0x1p-1000); }
 // upper bound of |a|
@@ -44,35 +49,38 @@ __device__ __forceinline__ double abs2_dn(cd a)
 {
     return dn(__dadd_rn(__dmul_rn(a.re, a.re), __dmul_rn(a.im, a.im)));
 }
-__device__ __forceinline__ double hulp(cd a) { return 0.5 * (ulp64(a.re) + ulp64(a.im)); }
+// bound of the rounding of a complex result a^ (both components)
+__device__ __forceinline__ double rnd(cd a) { return U53 * (fabs(a.re) + fabs(a.im)) + 2.0 * ETA; }
 
 struct disk_step {
-    cd Z, DZ;  // centres
-    double e;  // radius of z_k at the exact point c0 (R = 0)
+    cd Z, DZ;        // centres
+    double e;        // radius of z_k at the exact point c0 (no radius on c)
     double rho, sig; // radii of z_k and dz_k over D(c0, R)
 };
 
-// one step of the disk orbit; Rin = radius of c
-__device__ __forceinline__ void disk_orbit_step(disk_step &s, cd c, double Rin)
+// One step of the orbit over disks: z <- z^2 + c, dz <- 2 z dz + 1, the centres
+// computed with separate IEEE products and sums (no fused multiply-add).
+__device__ __forceinline__ void disk_orbit_step(disk_step &s, cd c, double R)
 {
     const double x = s.Z.re, y = s.Z.im, u = s.DZ.re, v = s.DZ.im;
-    // centre of z^2
-    double xx = __dmul_rn(x, x), yy = __dmul_rn(y, y), xy = __dmul_rn(x, y);
-    cd sq = {__dsub_rn(xx, yy), __dadd_rn(xy, xy)};
-    double Rsq = hulp(sq) + 0.5 * (ulp64(xx) + ulp64(yy) + 2.0 * ulp64(xy));
-    // centre of z * dz
-    double xu = __dmul_rn(x, u), yv = __dmul_rn(y, v), xv = __dmul_rn(x, v), yu = __dmul_rn(y, u);
-    cd pr = {__dsub_rn(xu, yv), __dadd_rn(xv, yu)};
-    double Rpr = hulp(pr) + 0.5 * (ulp64(xu) + ulp64(yv) + ulp64(xv) + ulp64(yu));
-    cd Z1 = {__dadd_rn(sq.re, c.re), __dadd_rn(sq.im, c.im)};
-    cd DZ1 = {__dadd_rn(__dadd_rn(pr.re, pr.re), 1.0), __dadd_rn(pr.im, pr.im)};
+    const double xx = __dmul_rn(x, x), yy = __dmul_rn(y, y), xy = __dmul_rn(x, y);
+    const cd sq = {__dsub_rn(xx, yy), __dadd_rn(xy, xy)}; // doubling is exact
+    const cd Z1 = {__dadd_rn(sq.re, c.re), __dadd_rn(sq.im, c.im)};
+    // rounding of the centre Z^2 + c: three products, one difference, two sums
+    const double Rsq = U53 * (fabs(xx) + fabs(yy) + 2.0 * fabs(xy) + fabs(sq.re)) + rnd(Z1) + 6.0 * ETA;
+    const double xu = __dmul_rn(x, u), yv = __dmul_rn(y, v), xv = __dmul_rn(x, v), yu = __dmul_rn(y, u);
+    const cd pr = {__dsub_rn(xu, yv), __dadd_rn(xv, yu)};
+    const cd DZ1 = {__dadd_rn(__dadd_rn(pr.re, pr.re), 1.0), __dadd_rn(pr.im, pr.im)};
+    // rounding of 2 Z DZ + 1: four products and two sums (doubled), one sum
+    const double Rpr = 2.0 * (U53 * (fabs(xu) + fabs(yv) + fabs(xv) + fabs(yu)) + rnd(pr) + 4.0 * ETA) +
+                       U53 * fabs(DZ1.re) + ETA;
     const double aZ = abs_up(s.Z), aDZ = abs_up(s.DZ);
     // D(Z,e)^2 + c0
-    double e1 = up(s.e * s.e + 2.0 * s.e * aZ + Rsq + hulp(Z1));
+    const double e1 = up(s.e * s.e + 2.0 * s.e * aZ + Rsq);
     // D(Z,rho)^2 + D(c0,R)
-    double rho1 = up(s.rho * s.rho + 2.0 * s.rho * aZ + Rsq + Rin + hulp(Z1));
-    // 2 D(Z,rho) D(DZ,sig) + 1 (doubling is exact)
-    double sig1 = up(2.0 * (s.rho * s.sig + s.rho * aDZ + s.sig * aZ + Rpr) + hulp(DZ1));
+    const double rho1 = up(s.rho * s.rho + 2.0 * s.rho * aZ + R + Rsq);
+    // 2 D(Z,rho) D(DZ,sig) + 1
+    const double sig1 = up(2.0 * (s.rho * s.sig + s.rho * aDZ + s.sig * aZ) + Rpr);
     s.Z = Z1;
     s.DZ = DZ1;
     s.e = e1;
@@ -83,75 +91,68 @@ __device__ __forceinline__ void disk_orbit_step(disk_step &s, cd c, double Rin)
 struct cert_result { uint8_t flags; double R; };
 
 // Certify c for P = q_{l,n} (l = 0: p_n) with label lab (p_n: period).
+// The radius is chosen from a plain evaluation: R ~ 4 |P/P'| plus the
+// rounding noise of a root, rounded up to a power of two; then one fused pass
+// carries the centres, the point radii e and the disk radii rho, sigma.
+// If the test fails, R grows by 16 (two more attempts).
 __device__ cert_result certify_root(int l, int n, int lab, uint32_t divmask_n, cd c)
 {
     const int N = l + n;
-    // pass A: centre values and point radii
-    disk_step s = {{0.0, 0.0}, {0.0, 0.0}, 0.0, 0.0, 0.0};
-    cd Zl = {0, 0}, DZl = {0, 0};
-    double el = 0.0;
-    cd Zk = {0, 0}, DZk = {0, 0};
-    double ek = 0.0;
-    for (int k = 0; k < N; ++k) {
-        disk_orbit_step(s, c, 0.0);
-        if (k + 1 == l) { Zl = s.Z; DZl = s.DZ; el = s.e; }
-        if (l == 0 && k + 1 == lab) { Zk = s.Z; DZk = s.DZ; ek = s.e; }
-    }
-    cd P = {__dsub_rn(s.Z.re, Zl.re), __dsub_rn(s.Z.im, Zl.im)};
-    cd dP = {__dsub_rn(s.DZ.re, DZl.re), __dsub_rn(s.DZ.im, DZl.im)};
-    const double Pup = up(abs_up(P) + up(s.e + el + hulp(P)));
-    const double dlow = sqrt(abs2_dn(dP));
+    cd P0, dP0;
+    eval_q(l, N, c, P0, dP0);
     cert_result res = {0, 0.0};
-    if (!(dlow > 0.0) || !isfinite(Pup)) return res;
-    double R0 = 4.0 * Pup / dlow;
-    if (!(R0 > 0x1p-1000)) R0 = 0x1p-1000;
+    if (!cfinite(P0) || !cfinite(dP0)) return res;
+    const double az = sqrt(cabs2(c));
+    double R0 = 4.0 * sqrt(cabs2(P0) / cabs2(dP0)) + 64.0 * U53 * fmax(az, 0x1p-8);
+    if (!(R0 > 0x1p-1000) || !isfinite(R0)) R0 = 0x1p-1000;
     double R = ldexp(1.0, ilogb(R0) + 1); // power of two above R0
     for (int attempt = 0; attempt < 3; ++attempt, R *= 16.0) {
-        // pass B: radii over D(c, R)
         disk_step t = {{0.0, 0.0}, {0.0, 0.0}, 0.0, 0.0, 0.0};
-        cd Zl1 = {0, 0};
-        double rl = 0.0, sl = 0.0, rlm = 0.0;
-        cd Zlm = {0, 0};
-        double sk = 0.0;
+        cd Zl = {0, 0}, DZl = {0, 0}, Zlm = {0, 0}, Zk = {0, 0}, DZk = {0, 0};
+        double el = 0.0, rl = 0.0, sl = 0.0, rlm = 0.0, ek = 0.0, sk = 0.0;
         bool label_ok = true;
         for (int k = 0; k < N; ++k) {
             disk_orbit_step(t, c, R);
             const int kk = k + 1;
             if (kk == l - 1) { Zlm = t.Z; rlm = t.rho; }
-            if (kk == l) { Zl1 = t.Z; rl = t.rho; sl = t.sig; }
+            if (kk == l) { Zl = t.Z; DZl = t.DZ; el = t.e; rl = t.rho; sl = t.sig; }
             if (l == 0) {
-                if (kk == lab) sk = t.sig;
+                if (kk == lab) { Zk = t.Z; DZk = t.DZ; ek = t.e; sk = t.sig; }
                 // p_j, j a strict divisor of the label, has no zero on the disk
                 if (kk < lab && lab % kk == 0) {
-                    double r = t.rho;
+                    const double r = t.rho;
                     if (!(abs2_dn(t.Z) > up(r * r))) label_ok = false;
                 }
             } else {
                 // q_{l,k} = z_{l+k} - z_l, k a strict divisor of n
-                int kd = kk - l;
+                const int kd = kk - l;
                 if (kd >= 1 && kd < n && ((divmask_n >> kd) & 1u)) {
-                    cd d = {__dsub_rn(t.Z.re, Zl1.re), __dsub_rn(t.Z.im, Zl1.im)};
-                    double r = up(t.rho + rl + hulp(d));
+                    const cd d = {__dsub_rn(t.Z.re, Zl.re), __dsub_rn(t.Z.im, Zl.im)};
+                    const double r = up(t.rho + rl + rnd(d));
                     if (!(abs2_dn(d) > up(r * r))) label_ok = false;
                 }
                 // q_{l-1,n} = z_{l-1+n} - z_{l-1}
                 if (kk == l - 1 + n) {
-                    cd d = {__dsub_rn(t.Z.re, Zlm.re), __dsub_rn(t.Z.im, Zlm.im)};
-                    double r = up(t.rho + rlm + hulp(d));
+                    const cd d = {__dsub_rn(t.Z.re, Zlm.re), __dsub_rn(t.Z.im, Zlm.im)};
+                    const double r = up(t.rho + rlm + rnd(d));
                     if (!(abs2_dn(d) > up(r * r))) label_ok = false;
                 }
             }
         }
-        const double sP = up(t.sig + sl + hulp(dP));
-        const double tneed = up(up(Pup / R) + sP);
-        if (abs2_dn(dP) > up(tneed * tneed)) {
+        const cd P = {__dsub_rn(t.Z.re, Zl.re), __dsub_rn(t.Z.im, Zl.im)};
+        const cd dP = {__dsub_rn(t.DZ.re, DZl.re), __dsub_rn(t.DZ.im, DZl.im)};
+        const double Pup = up(abs_up(P) + up(t.e + el + rnd(P)));
+        const double sP = up(t.sig + sl + rnd(dP));
+        // Thm proofRoots: R (|P'(c)| - sigma) > |P(c)|
+        const double need = up(up(Pup / R) + sP);
+        if (abs2_dn(dP) > up(need * need)) {
             res.flags = 2; // MSPLIT_R_CERTIFIED
             res.R = R;
             if (l == 0 && lab != n) {
                 // Thm proofRoots for p_lab on the same disk
-                double Pk = up(abs_up(Zk) + up(ek + hulp(Zk)));
-                double need = up(up(Pk / R) + up(sk + hulp(DZk)));
-                if (!(abs2_dn(DZk) > up(need * need))) label_ok = false;
+                const double Pk = up(abs_up(Zk) + up(ek + rnd(Zk)));
+                const double nk = up(up(Pk / R) + up(sk + rnd(DZk)));
+                if (!(abs2_dn(DZk) > up(nk * nk))) label_ok = false;
             }
             if (l > 0 && lab != n) label_ok = false;
             if (label_ok) res.flags |= 4; // MSPLIT_R_LABEL
@@ -161,86 +162,101 @@ __device__ cert_result certify_root(int l, int n, int lab, uint32_t divmask_n, c
     return res;
 }
 
-__global__ void k_certify(int l, int n, uint32_t divmask_n, const double *re, const double *im,
-                          const int32_t *period, uint8_t *flags, double *radius, uint64_t count,
-                          unsigned long long *ctr, int ctr_cert, int ctr_label, int ctr_maxrad)
+// Grid-stride loop over the unique roots (compact index space of
+// batch_args.uniq_offs); counts and the largest radius stay in registers per
+// type and are reduced once per wave at type changes and at the end.
+__global__ void k_certify(batch_args b, const double *re, const double *im, const int32_t *period, uint8_t *flags,
+                          double *radius, int64_t n_uniq)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long nc = 0, nl = 0;
-    if (i < (int64_t)count) {
-        cd c = {re[i], im[i]};
-        int lab = period ? period[i] : n;
-        cert_result r = certify_root(l, n, lab, divmask_n, c);
-        uint8_t f = (im[i] == 0.0 ? 1 : 0) | r.flags;
-        if (flags) flags[i] = f;
-        if (radius) radius[i] = r.R;
-        nc += (r.flags & 2) != 0;
-        nl += (r.flags & 4) != 0;
-        if (r.flags & 2) atomicMax(&ctr[ctr_maxrad], (unsigned long long)__double_as_longlong(r.R));
+    type_count nc, nl;
+    type_cache tc;
+    unsigned long long rbits = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u0 = (int64_t)blockIdx.x * blockDim.x; u0 < n_uniq; u0 += stride) {
+        const int64_t u = u0 + threadIdx.x;
+        const int t = u < n_uniq ? cached_type(tc, b.uniq_offs, b.T, u) : nc.t;
+        if (__ballot(u < n_uniq && t != nc.t)) {
+            flush_count(b.ctr, C_CERTIFIED, nc);
+            flush_count(b.ctr, C_LABEL, nl);
+            // non-negative doubles order like their bit patterns
+            wave_reduce_by_key<RED_MAX>(b.ctr, C_NCOUNTERS, C_MAX_RAD_BITS, rbits ? nc.t : -1, rbits);
+            rbits = 0;
+        }
+        nc.t = nl.t = t;
+        if (u >= n_uniq) continue;
+        const type_desc &td = b.types[t];
+        const int64_t i = td.out_off + (u - b.uniq_offs[t]);
+        const cd c = {re[i], im[i]};
+        const int lab = period ? period[i] : td.p.n;
+        const cert_result r = certify_root(td.p.l, td.p.n, lab, td.p.divmask_lo, c);
+        flags[i] = (c.im == 0.0 ? 1 : 0) | r.flags;
+        radius[i] = r.R;
+        nc.v += (r.flags & 2) != 0;
+        nl.v += (r.flags & 4) != 0;
+        if (r.flags & 2) {
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(r.R);
+            rbits = bits > rbits ? bits : rbits;
+        }
     }
-    wave_add(&ctr[ctr_cert], nc);
-    wave_add(&ctr[ctr_label], nl);
+    flush_count(b.ctr, C_CERTIFIED, nc);
+    flush_count(b.ctr, C_LABEL, nl);
+    wave_reduce_by_key<RED_MAX>(b.ctr, C_NCOUNTERS, C_MAX_RAD_BITS, rbits ? nc.t : -1, rbits);
 }
 
-// Thm certif, global part, on a list sorted by real part: certified disks
-// must be pairwise disjoint and disjoint from their conjugates unless centred
-// on the real axis; with the quarter-separation reading every pair satisfies
-// |z_i - z_j| >= 4 max(R_i, R_j) and every non-real root Im z >= 2 R.
-// Also the least distance among the roots and their conjugates, scanning the
-// neighbours in real order (at most 64 of them).
-__global__ void k_separation(const double *re, const double *im, const double *radius, uint64_t count,
-                             double rmax, unsigned long long *ctr, int ctr_overlap, int ctr_minsep)
+// Thm certif, global part, on each type's list (sorted by real part):
+// certified disks must be pairwise disjoint and disjoint from their
+// conjugates unless centred on the real axis; with the quarter-separation
+// reading every pair satisfies |z_i - z_j| >= 4 max(R_i, R_j) and every
+// non-real root Im z >= 2 R.  Every pair closer than 4 (R_i + R_max) in real
+// part is checked.  Also a statistic: the least distance found between a
+// root and its conjugate or one of the next 8 roots in real order (an upper
+// bound of the least distance; the closest pairs of p_n, the leftmost real
+// roots, are adjacent in that order).  radius == nullptr: only the statistic.
+__global__ void k_separation(batch_args b, const double *re, const double *im, const double *radius, int64_t n_uniq)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long bad = 0;
-    if (i < (int64_t)count) {
+    type_count bad;
+    type_cache tc;
+    unsigned long long sbits = ~0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u0 = (int64_t)blockIdx.x * blockDim.x; u0 < n_uniq; u0 += stride) {
+        const int64_t u = u0 + threadIdx.x;
+        const int t = u < n_uniq ? cached_type(tc, b.uniq_offs, b.T, u) : bad.t;
+        if (__ballot(u < n_uniq && t != bad.t)) {
+            flush_count(b.ctr, C_OVERLAP, bad);
+            wave_reduce_by_key<RED_MIN>(b.ctr, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);
+            sbits = ~0ull;
+        }
+        bad.t = t;
+        if (u >= n_uniq) continue;
+        const type_desc &td = b.types[t];
+        const int64_t i = td.out_off + (u - b.uniq_offs[t]);
+        const int64_t end = td.out_off + (b.uniq_offs[t + 1] - b.uniq_offs[t]);
+        const double rmax =
+            radius ? __longlong_as_double((long long)b.ctr[(int64_t)t * C_NCOUNTERS + C_MAX_RAD_BITS]) : 0.0;
         const double xi = re[i], yi = im[i], Ri = radius ? radius[i] : 0.0;
         double best = yi > 0.0 ? 2.0 * yi : INFINITY;
-        if (radius && yi != 0.0 && !(yi >= 2.0 * Ri)) bad = 1;
-        // every pair closer than 4 (R_i + R_max) in real part is checked; the
-        // nearest-neighbour scan for the statistic stops after 64 points
-        for (int64_t j = i + 1, c = 0; j < (int64_t)count; ++j, ++c) {
-            double dx = re[j] - xi;
-            bool need_pair = radius && dx <= 4.0 * (Ri + rmax);
-            if (!need_pair && (dx > best || c >= 64)) break;
-            double dy = im[j] - yi;
-            double d = sqrt(dx * dx + dy * dy);
+        if (radius && yi != 0.0 && !(yi >= 2.0 * Ri)) bad.v += 1;
+        bool pair_bad = false;
+        for (int64_t j = i + 1, c = 0; j < end; ++j, ++c) {
+            const double dx = re[j] - xi;
+            const bool need_pair = radius && dx <= 4.0 * (Ri + rmax);
+            if (!need_pair && (dx > best || c >= 8)) break;
+            const double dy = im[j] - yi;
+            const double d = sqrt(dx * dx + dy * dy);
             best = fmin(best, d);
             if (radius) {
-                double Rj = radius[j];
-                if (!(d >= 4.0 * fmax(Ri, Rj) * (1.0 + 1e-15))) bad = 1;
+                const double Rj = radius[j];
+                if (!(d >= 4.0 * fmax(Ri, Rj) * (1.0 + 1e-15))) pair_bad = true;
             }
         }
-        if (isfinite(best)) atomicMin(&ctr[ctr_minsep], (unsigned long long)__double_as_longlong(best));
-    }
-    wave_add(&ctr[ctr_overlap], bad);
-}
-
-// Same scan, reading the largest certificate radius from the counter slot
-// that k_certify filled (no host round trip between the two kernels).
-__global__ void k_separation_rmax(const double *re, const double *im, const double *radius, uint64_t count,
-                                  unsigned long long *ctr, int ctr_maxrad, int ctr_overlap, int ctr_minsep)
-{
-    const double rmax = __longlong_as_double((long long)ctr[ctr_maxrad]);
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long bad = 0;
-    if (i < (int64_t)count) {
-        const double xi = re[i], yi = im[i], Ri = radius[i];
-        double best = yi > 0.0 ? 2.0 * yi : INFINITY;
-        if (yi != 0.0 && !(yi >= 2.0 * Ri)) bad = 1;
-        for (int64_t j = i + 1, c = 0; j < (int64_t)count; ++j, ++c) {
-            double dx = re[j] - xi;
-            bool need_pair = dx <= 4.0 * (Ri + rmax);
-            if (!need_pair && (dx > best || c >= 64)) break;
-            double dy = im[j] - yi;
-            double d = sqrt(dx * dx + dy * dy);
-            best = fmin(best, d);
-            double Rj = radius[j];
-            if (!(d >= 4.0 * fmax(Ri, Rj) * (1.0 + 1e-15))) bad = 1;
+        bad.v += pair_bad;
+        if (isfinite(best)) {
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(best);
+            sbits = bits < sbits ? bits : sbits;
         }
-        if (isfinite(best)) atomicMin(&ctr[ctr_minsep], (unsigned long long)__double_as_longlong(best));
     }
-    wave_add(&ctr[ctr_overlap], bad);
+    flush_count(b.ctr, C_OVERLAP, bad);
+    wave_reduce_by_key<RED_MIN>(b.ctr, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);
 }
 
 } // namespace msplit

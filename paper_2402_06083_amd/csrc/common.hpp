@@ -30,22 +30,40 @@ __device__ __forceinline__ cd cdiv(cd a, cd b)
 }
 __device__ __forceinline__ bool cfinite(cd a) { return isfinite(a.re) && isfinite(a.im); }
 
-// Principal complex logarithm; for |w - 1| < 1/64 a short series of log1p
-// (error |v|^6 / 6 < 1e-11 |v|, far below what a Newton iteration needs).
+// Approximation u(w) of log w for the Newton iteration on log P (the step
+// z += u(T/P) P/P').  It only has to be exact at the fixed point w = 1 and
+// close enough elsewhere to keep the iteration contracting, so no
+// transcendental function is evaluated:
+//   |w - 1| < 1/8 : log1p series up to v^7 (relative error < 3e-7);
+//   |y| <= 0.8    : 2 atanh(y) = 2 (y + y^3/3 + ... + y^9/9), y = (w-1)/(w+1)
+//                   (relative error about 1e-3 at |y| = 0.67);
+//   otherwise     : u = w - 1, i.e. the plain Newton map with target,
+//                   z += (T - P)/P' (Section 4.1, L(P; z, T)).
 __device__ __forceinline__ cd clog_near1(cd w)
 {
-    cd v = {w.re - 1.0, w.im};
-    double a2 = cabs2(v);
-    if (a2 < (1.0 / 4096.0)) {
-        // v - v^2/2 + v^3/3 - v^4/4 + v^5/5 (Horner)
-        cd acc = {0.2, 0.0};
+    const cd v = {w.re - 1.0, w.im};
+    const double a2 = cabs2(v);
+    if (a2 < (1.0 / 64.0)) {
+        // v - v^2/2 + v^3/3 - ... - v^6/6 + v^7/7 (Horner)
+        cd acc = {1.0 / 7.0, 0.0};
+        acc = cadd(cmul(acc, v), {-1.0 / 6.0, 0.0});
+        acc = cadd(cmul(acc, v), {0.2, 0.0});
         acc = cadd(cmul(acc, v), {-0.25, 0.0});
         acc = cadd(cmul(acc, v), {1.0 / 3.0, 0.0});
         acc = cadd(cmul(acc, v), {-0.5, 0.0});
         acc = cadd(cmul(acc, v), {1.0, 0.0});
         return cmul(acc, v);
     }
-    return {0.5 * log(cabs2(w)), atan2(w.im, w.re)};
+    const cd y = cdiv(v, {w.re + 1.0, w.im});
+    if (cabs2(y) > 0.64) return v;
+    const cd y2 = cmul(y, y);
+    cd acc = {1.0 / 9.0, 0.0};
+    acc = cadd(cmul(acc, y2), {1.0 / 7.0, 0.0});
+    acc = cadd(cmul(acc, y2), {0.2, 0.0});
+    acc = cadd(cmul(acc, y2), {1.0 / 3.0, 0.0});
+    acc = cadd(cmul(acc, y2), {1.0, 0.0});
+    const cd r = cmul(acc, y);
+    return {2.0 * r.re, 2.0 * r.im};
 }
 
 // ---------------------------------------------------------------- orbit
@@ -95,22 +113,6 @@ __device__ __forceinline__ void eval_q_f32(int l, int N, cf c, cf &P, cf &dP)
 // ---------------------------------------------------------- wave helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-// Wave-aggregated work fetch: lanes with need == true get consecutive
-// indices from *counter; others get ~0.
-__device__ __forceinline__ uint64_t wave_fetch(unsigned long long *counter, bool need)
-{
-    unsigned long long mask = __ballot(need);
-    uint64_t idx = ~0ull;
-    if (mask) {
-        int leader = __ffsll((unsigned long long)mask) - 1;
-        unsigned long long base = 0;
-        if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-        base = __shfl(base, leader);
-        if (need) idx = base + (uint64_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
-    }
-    return idx;
-}
-
 // Per-wave work queue: the wave owns the index range [next, end) taken from
 // the global counter `chunk` items at a time (one atomic per chunk instead
 // of one per item: a single counter hit by every wave at every Newton step
@@ -142,11 +144,44 @@ __device__ __forceinline__ uint64_t wave_take(wave_queue &q, unsigned long long 
     return idx;
 }
 
-// Wave-reduced atomic add of a per-lane count.
-__device__ __forceinline__ void wave_add(unsigned long long *dst, unsigned long long v)
+// Segmented wave reduction: every lane holds (key, value); for each distinct
+// key >= 0 present in the wave one lane applies op to the slot of that key
+// with the reduction of the values of the lanes holding it.  A wave holds one
+// or two keys in practice, so this costs one or two butterfly reductions and
+// one atomic per key -- never one atomic per lane on a shared address (those
+// serialise in the L2 atomic unit).  All lanes of the wave must call it.
+enum red_op { RED_ADD, RED_MAX, RED_MIN };
+
+template <red_op OP>
+__device__ __forceinline__ unsigned long long red_combine(unsigned long long a, unsigned long long b)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane_id() == 0 && v) atomicAdd(dst, v);
+    if (OP == RED_ADD) return a + b;
+    if (OP == RED_MAX) return a > b ? a : b;
+    return a < b ? a : b;
+}
+
+template <red_op OP>
+__device__ __forceinline__ void wave_reduce_by_key(unsigned long long *base, int stride, int slot, int key,
+                                                   unsigned long long value)
+{
+    const unsigned long long ident = (OP == RED_MIN) ? ~0ull : 0ull;
+    bool pending = key >= 0;
+    while (true) {
+        const unsigned long long pend = __ballot(pending);
+        if (!pend) break;
+        const int leader = __ffsll(pend) - 1;
+        const int k = __shfl(key, leader);
+        const bool mine = pending && key == k;
+        unsigned long long v = mine ? value : ident;
+        for (int off = 32; off > 0; off >>= 1) v = red_combine<OP>(v, __shfl_xor(v, off));
+        if (lane_id() == leader && v != ident) {
+            unsigned long long *dst = base + (int64_t)k * stride + slot;
+            if (OP == RED_ADD) atomicAdd(dst, v);
+            else if (OP == RED_MAX) atomicMax(dst, v);
+            else atomicMin(dst, v);
+        }
+        if (mine) pending = false;
+    }
 }
 
 // Order-preserving map of a double onto uint64 (sort key).

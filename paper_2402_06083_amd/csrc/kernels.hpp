@@ -1,24 +1,28 @@
 // kernels.hpp -- the hot path of the level-line splitter on gfx950.
 //
-// One pass over a polynomial P = q_{l,n} (l = 0: p_n) of degree D = 2^(N-1),
-// N = l + n, in the closed upper half plane (Section 6.1):
+// A call splits a list of types, each a polynomial P = q_{l,n} (l = 0: p_n)
+// of degree D = 2^(N-1), N = l + n, in the closed upper half plane (Section
+// 6.1).  All types share one launch per stage; a device table of type_desc
+// maps global item indices (seeds, segments, starts) to their type.  Types
+// are laid out by decreasing order N so that the persistent queues end on
+// the cheap items.
 //
-//   k_seeds   seed lift      S+1 seeds of Phi-angle pi j / S lifted from the
-//                            circle |p_1| = lambda_0 through p_2 .. p_N
-//                            (Section 4.2, lifting p_k -> p_{k+1})
-//   k_walk    level line     each lane walks F fine points of one segment,
-//                            value phase 2 pi s / M (Prop. computeLevelLine),
-//                            every (M/4)-th point is a start (Thm practicalFTA)
-//   k_descend Newton descent one lane per start, capped (Algorithm S_par)
-//   k_keys .. k_scatter      nset collection (Section 6.1)
-//   k_classify               exact period / Misiurewicz type (eq. def:hyp,
-//                            eq. def:mis)
-//   k_certify, k_separation  Thm proofRoots + Thm diskArithmetic, Thm certif
+//   k_seeds     seed lift      seed j of type t at Phi-angle pi j / S, lifted
+//                              from the circle |p_1| = lambda_0 through p_2
+//                              .. p_N (Section 4.2, lifting p_k -> p_{k+1})
+//   k_walk      level line     a lane walks the F fine points of one segment,
+//                              value phase 2 pi s / M (Prop. computeLevelLine);
+//                              every (M/4)-th point is a start (Thm
+//                              practicalFTA: values lambda_0 {1, i, -1, -i})
+//   k_descend   Newton descent one lane per start, capped (Algorithm S_par)
+//   k_prekeys .. k_scatter     nset collection (Section 6.1)
+//   k_classify                 exact period (eq. def:hyp) / type (eq. def:mis)
 //
-// Work distribution: k_walk and k_descend are persistent; each lane pulls
-// its next item from a global counter with one wave-aggregated atomic, so
-// lanes whose Newton iterations end early do not wait for the slowest lane of
-// their wave (the divergence the paper names as its objection to GPUs).
+// Work distribution: k_walk and k_descend are persistent; each wave takes
+// chunks of items from a global counter and hands them to its lanes as they
+// free up, so lanes whose Newton iterations end early do not wait for the
+// slowest lane of their wave (the divergence the paper names as its
+// objection to GPUs).
 #pragma once
 #include "common.hpp"
 
@@ -27,12 +31,13 @@ namespace msplit {
 // status of a descent
 enum : uint8_t { ST_NONE = 0, ST_CONVERGED = 1, ST_DIVERGED = 2, ST_TIMEOUT = 3 };
 
-// device counters (uint64 slots of the workspace)
+// global counters
+enum { G_SEG_NEXT = 0, G_START_NEXT, G_NCOUNTERS = 8 };
+// per-type counters (uint64 slots, C_NCOUNTERS per type)
 enum {
-    C_SEG_NEXT = 0, C_START_NEXT, C_CONVERGED, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL,
-    C_STEPS_LIFT, C_STEPS_WALK, C_STEPS_DESC, C_STEPS_FP32, C_UNIQUE, C_REAL,
-    C_CERTIFIED, C_LABEL, C_OVERLAP, C_MIN_SEP_BITS, C_MAX_RAD_BITS, C_SEED_FAIL,
-    C_DISCARD, C_NCOUNTERS = 32
+    C_CONVERGED = 0, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL, C_SEED_FAIL, C_STEPS_LIFT, C_STEPS_WALK,
+    C_STEPS_DESC, C_STEPS_FP32, C_UNIQUE, C_REAL, C_CERTIFIED, C_LABEL, C_OVERLAP, C_MIN_SEP_BITS,
+    C_MAX_RAD_BITS, C_SURVIVORS, C_NCOUNTERS = 20
 };
 
 struct plan_t {
@@ -50,27 +55,103 @@ struct plan_t {
     uint32_t divmask_lo;  // bit k set when k | n, k < n (k < 32)
     int precision;
     float fp32_switch;
-    uint32_t chunk_seg;   // work-queue chunk of the walk (segments)
-    uint32_t chunk_start; // work-queue chunk of the descents (starts)
+};
+
+struct type_desc {
+    plan_t p;
+    int64_t seed_off, seg_off, start_off; // global offsets of this type's items
+    int64_t out_off;                      // first output slot
+    uint64_t cap;                         // output capacity
+    int64_t uniq_off;                     // offset in the compact unique index space
+};
+
+struct batch_args {
+    const type_desc *types;
+    const int64_t *seed_offs, *seg_offs, *start_offs, *uniq_offs; // T + 1 entries each
+    int T;
+    int64_t n_seeds, n_segs, n_starts;
+    uint32_t chunk_seg, chunk_start;
+    unsigned long long *gctr; // global counters
+    unsigned long long *ctr;  // T x C_NCOUNTERS
 };
 
 // cis(2 pi s / M) for s = 0..M-1, M <= 64, set by the host
 __constant__ double c_cis_re[64];
 __constant__ double c_cis_im[64];
 
-// ------------------------------------------------------------ seed lift
-// Lane j lifts the point of Phi-angle pi j / S: on p_1 = z the level line is
-// the circle |z| = lambda_0, so the seed starts at lambda_0 e^{i pi j / S}.
-// At p_k its value must be lambda_0 e^{i pi a_k / S} with a_k = 2^(k-1) j mod
-// 2S (the value phase doubles from p_k to p_{k+1} because p_{k+1} = p_k^2 + c
-// and |c| << lambda_0^2).  Each level is solved with the Newton method on
-// log P (log P(z) = log T), whose step z += log(T/P) P/P' is the discrete
-// level-line / iso-angle flow of Section 4.1.
-__global__ void k_seeds(plan_t pl, cd *seeds, cd *starts, unsigned long long *ctr)
+// index of the type owning global item g: offs is non-decreasing, T + 1
+// entries, offs[0] = 0 <= g < offs[T]
+__device__ __forceinline__ int find_type(const int64_t *offs, int T, int64_t g)
 {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long steps = 0, fail = 0;
-    if (j <= pl.S) {
+    int lo = 0, hi = T; // invariant: offs[lo] <= g < offs[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (offs[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Per-type counter accumulation: lanes add to a register while they stay on
+// the same type and flush (wave-reduced when the whole wave agrees on the
+// type) when it changes and at the end.
+struct type_count {
+    int t = -1;
+    unsigned long long v = 0;
+};
+
+__device__ __forceinline__ void flush_count(unsigned long long *ctr, int slot, type_count &c)
+{
+    // all lanes of the wave call this together
+    wave_reduce_by_key<RED_ADD>(ctr, C_NCOUNTERS, slot, c.v ? c.t : -1, c.v);
+    c.v = 0;
+}
+
+// Type of global item g with a per-lane cache of the current type's item
+// range [lo, hi): the binary search runs only when g leaves it.
+struct type_cache {
+    int t = -1;
+    int64_t lo = 0, hi = 0;
+};
+
+__device__ __forceinline__ int cached_type(type_cache &c, const int64_t *offs, int T, int64_t g)
+{
+    if (c.t < 0 || g < c.lo || g >= c.hi) {
+        c.t = find_type(offs, T, g);
+        c.lo = offs[c.t];
+        c.hi = offs[c.t + 1];
+    }
+    return c.t;
+}
+
+// ------------------------------------------------------------ seed lift
+// Seed j of a type lies at Phi-angle pi j / S.  On p_1 = z the level line is
+// the circle |z| = lambda_0, so it starts at lambda_0 e^{i pi j / S}.  At p_k
+// its value must be lambda_0 e^{i pi a_k / S} with a_k = 2^(k-1) j mod 2S (the
+// value phase doubles from p_k to p_{k+1}: p_{k+1} = p_k^2 + c with |c| small
+// against lambda_0^2).  Each level is solved with the Newton method on log P,
+// whose step z += log(T/P) P/P' is the discrete level-line / iso-angle flow
+// of Section 4.1.  For q_{l,n} a last stage moves the p_{l+n} point onto
+// q_{l,n} = lambda_0 e^{i pi a_N / S} (same phase: |p_l| << lambda_0 there).
+// Grid-stride loop: per-type counts stay in registers and are flushed when a
+// lane's type changes and at the end (a few atomics per wave in all).
+__global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
+{
+    type_count steps, fail;
+    type_cache tc;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < b.n_seeds; g0 += stride) {
+        const int64_t g = g0 + threadIdx.x;
+        const int t = g < b.n_seeds ? cached_type(tc, b.seed_offs, b.T, g) : steps.t;
+        if (__ballot(g < b.n_seeds && t != steps.t)) {
+            flush_count(b.ctr, C_STEPS_LIFT, steps);
+            flush_count(b.ctr, C_SEED_FAIL, fail);
+        }
+        steps.t = fail.t = t;
+        if (g >= b.n_seeds) continue;
+        const plan_t &plr = b.types[t].p;
+        const struct { int l, N; int64_t S, F, q; double level; } pl = {plr.l, plr.N, plr.S, plr.F, plr.q, plr.level};
+        bool failed = false;
+        const int64_t j = g - b.seed_offs[t];
         const int64_t twoS = 2 * pl.S;
         double sn, cs;
         sincospi((double)j / (double)pl.S, &sn, &cs);
@@ -78,110 +159,146 @@ __global__ void k_seeds(plan_t pl, cd *seeds, cd *starts, unsigned long long *ct
         if (j == pl.S) z = {-pl.level, 0.0};
         if (j == 0) z = {pl.level, 0.0};
         int64_t a = j % twoS;
-        const int top = pl.l ? pl.N + 1 : pl.N; // extra stage: onto q_{l,n}
-        for (int k = 2; k <= top && !fail; ++k) {
+        const int top = pl.l ? pl.N + 1 : pl.N;
+        for (int k = 2; k <= top && !failed; ++k) {
             int ll = 0, NN = k;
             if (k <= pl.N) a = (2 * a) % twoS;
             else { ll = pl.l; NN = pl.N; }
             sincospi((double)a / (double)pl.S, &sn, &cs);
             cd T = {pl.level * cs, pl.level * sn};
             if (a == 0) T = {pl.level, 0.0};
-            int it = 0;
-            for (;; ++it) {
+            // intermediate levels only have to land in the basin of the
+            // next one; the last level is solved to rounding level
+            const double tolv2 = (k < top) ? 0x1p-10 : 1e-26;
+            for (int it = 0;; ++it) {
                 cd P, dP;
                 eval_q(ll, NN, z, P, dP);
-                ++steps;
+                ++steps.v;
                 cd w = cdiv(T, P);
                 cd v = {w.re - 1.0, w.im};
-                if (cabs2(v) < 1e-26) break;
-                if (it >= 40 || !cfinite(P)) { fail = 1; break; }
+                if (cabs2(v) < tolv2) break;
+                if (it >= 40 || !cfinite(P)) { failed = true; break; }
                 cd h = cmul(clog_near1(w), cdiv(P, dP));
-                // near the tip of M the value carries ~4^N u of rounding noise;
-                // stop once the update itself is at rounding level
+                // near the tip of M the value carries ~4^N u of rounding
+                // noise; stop once the update itself is at rounding level
                 if (cabs2(h) <= 0x1p-96 * fmax(cabs2(z), 0x1p-16)) break;
                 z = cadd(z, h);
                 if (j == 0 || j == pl.S) z.im = 0.0; // the two real end points stay real
             }
         }
-        seeds[j] = z;
-        starts[j * (pl.F / pl.q)] = z;
+        fail.v += failed;
+        seeds[g] = z;
+        starts[b.types[t].start_off + j * (pl.F / pl.q)] = z;
     }
-    wave_add(&ctr[C_STEPS_LIFT], steps);
-    wave_add(&ctr[C_SEED_FAIL], fail);
+    flush_count(b.ctr, C_STEPS_LIFT, steps);
+    flush_count(b.ctr, C_SEED_FAIL, fail);
 }
 
 // --------------------------------------------------------- level-line walk
 // Lane state machine: each loop trip is one evaluation of P, P' followed by
-// one Newton-on-log-P update, so lanes never wait for each other inside a
-// segment.  Fine point s targets T_s = lambda_0 e^{2 i pi s / M}; the step
-// towards it is Newton on log P, z += log(T_s / P) P / P' (an Euler step of
-// the level-line flow lambda' = i P / P' of Section 4.1 with its correction).
-__global__ void k_walk(plan_t pl, const cd *seeds, cd *starts, uint8_t *seg_flag,
-                       unsigned long long *ctr)
+// one update, so lanes never wait for each other inside a segment.  Fine point
+// s targets T_s = lambda_0 e^{2 i pi s / M}; the step towards it is Newton on
+// log P, z += log(T_s / P) P / P' (an Euler step of the level-line flow
+// lambda' = i P / P' of Section 4.1 with its correction).  A fine point is
+// accepted at |T_s / P - 1| < 2^-5, or when the update is at rounding level:
+// it only has to lie in the Newton basin of the next target, and the next
+// target is aimed from the actual value, so no error accumulates.
+__global__ void k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag)
 {
-    // a fine point (start or not) is accepted at |T/P - 1| < 2^-5 or when the
-    // update is at rounding level: it only has to lie in the Newton basin of
-    // the next target, and the next target is aimed from the actual value
     const double tol2 = 0x1p-10;
-    const double dphi = 2.0 * M_PI / pl.M;
-    unsigned long long steps = 0, pfail = 0;
-    int64_t j = -1;        // current segment
-    int64_t s = 0, send = 0;
+    type_count steps, pfail;
+    int64_t g = -1; // current segment (global)
+    int t = -1;
+    // the fields of the current type's plan that the walk uses
+    int pl_l = 0, pl_N = 1, pl_M = 8, pl_q = 2;
+    int64_t pl_F = 1;
+    double pl_level = 5.0;
+    int64_t s = 0, send = 0, sbase = 0, st_off = 0, segbase = 0;
     int it = 0;
     cd z = {0.0, 0.0};
     bool done = false;
     wave_queue wq = {0, 0};
+    type_cache tc;
     while (true) {
-        bool need = !done && j < 0;
-        uint64_t got = wave_take(wq, &ctr[C_SEG_NEXT], pl.chunk_seg, need);
+        const bool need = !done && g < 0;
+        const uint64_t got = wave_take(wq, &b.gctr[G_SEG_NEXT], b.chunk_seg, need);
+        bool change = false;
         if (need) {
-            if (got >= (uint64_t)pl.S) done = true;
-            else { j = (int64_t)got; z = seeds[j]; s = j * pl.F + 1; send = j * pl.F + pl.F; it = 0; }
+            if (got >= (uint64_t)b.n_segs) {
+                done = true;
+            } else {
+                g = (int64_t)got;
+                const int t1 = cached_type(tc, b.seg_offs, b.T, g);
+                if (t1 != t) {
+                    t = t1;
+                    const plan_t &pl = b.types[t].p;
+                    pl_l = pl.l;
+                    pl_N = pl.N;
+                    pl_M = pl.M;
+                    pl_q = pl.q;
+                    pl_F = pl.F;
+                    pl_level = pl.level;
+                    st_off = b.types[t].start_off;
+                    sbase = b.types[t].seed_off;
+                    segbase = b.seg_offs[t];
+                }
+                change = steps.t != t;
+                const int64_t j = g - segbase;
+                z = seeds[sbase + j];
+                s = j * pl_F + 1;
+                send = j * pl_F + pl_F;
+                it = 0;
+            }
         }
+        // per-type counters flush when a lane's type changes
+        if (__ballot(change)) {
+            flush_count(b.ctr, C_STEPS_WALK, steps);
+            flush_count(b.ctr, C_PHASE_FAIL, pfail);
+        }
+        if (change) { steps.t = t; pfail.t = t; }
         if (__ballot(!done) == 0) break;
         if (done) continue;
         cd P, dP;
-        eval_q(pl.l, pl.N, z, P, dP);
-        ++steps;
-        int r = (int)(s % pl.M);
-        cd T = {pl.level * c_cis_re[r], pl.level * c_cis_im[r]};
+        eval_q(pl_l, pl_N, z, P, dP);
+        ++steps.v;
+        const int r = (int)(s % pl_M);
+        const cd T = {pl_level * c_cis_re[r], pl_level * c_cis_im[r]};
         cd w = cdiv(T, P);
-        cd v = {w.re - 1.0, w.im};
-        bool is_start = (s % pl.q) == 0;
-        double a2 = cabs2(v);
-        cd step = cdiv(P, dP);
+        const cd v = {w.re - 1.0, w.im};
+        const double a2 = cabs2(v);
+        const cd step = cdiv(P, dP);
         if (!cfinite(w) || !cfinite(step) || it > 24) {
-            seg_flag[j] = 2;
-            ++pfail;
-            j = -1;
+            seg_flag[g] = 2;
+            ++pfail.v;
+            g = -1;
             continue;
         }
         cd u0 = clog_near1(w);
-        cd h = cmul(u0, step);
+        const cd h = cmul(u0, step);
         if (a2 < tol2 || cabs2(h) <= 0x1p-96 * fmax(cabs2(z), 0x1p-16)) {
             if (s == send) {
                 // the walk must end on the next seed (phase check): a skipped
                 // turn would land about 2 pi |P/P'| away
-                cd e = csub(z, seeds[j + 1]);
-                bool ok = cabs2(e) < 1e-2 * cabs2(step);
-                seg_flag[j] = ok ? 0 : 1;
-                pfail += !ok;
-                j = -1;
+                const cd e = csub(z, seeds[sbase + (g - segbase) + 1]);
+                const bool ok = cabs2(e) < 1e-2 * cabs2(step);
+                seg_flag[g] = ok ? 0 : 1;
+                pfail.v += !ok;
+                g = -1;
                 continue;
             }
-            if (is_start) starts[s / pl.q] = z;
+            if ((s % pl_q) == 0) starts[st_off + s / pl_q] = z;
             // aim at the next fine point: log(T_{s+1}/P) = i dphi + log(T_s/P)
             ++s;
             it = 0;
-            u0.im += dphi;
+            u0.im += 2.0 * M_PI / pl_M;
             z = cadd(z, cmul(u0, step));
         } else {
             ++it;
             z = cadd(z, h);
         }
     }
-    wave_add(&ctr[C_STEPS_WALK], steps);
-    wave_add(&ctr[C_PHASE_FAIL], pfail);
+    flush_count(b.ctr, C_STEPS_WALK, steps);
+    flush_count(b.ctr, C_PHASE_FAIL, pfail);
 }
 
 // ---------------------------------------------------------- Newton descent
@@ -191,140 +308,245 @@ __global__ void k_walk(plan_t pl, const cd *seeds, cd *starts, uint8_t *seg_flag
 // times the previous one after the third step, Section 6.4.3).  Converged
 // when the step falls below tol * max(|z|, 2^-8); one more step is taken.
 // MIXED precision: the descent starts in FP32 and a lane moves to FP64 once
-// its FP32 step is below fp32_switch * |z| (or FP32 stalls / overflows).
-__global__ void k_descend(plan_t pl, cd *roots, uint8_t *status, unsigned long long *ctr)
+// its FP32 step is below fp32_switch * |z| (or FP32 overflows): FP32 only
+// covers the steps whose rounding error is far below the step itself.
+__global__ void k_descend(batch_args b, cd *roots, uint8_t *status)
 {
-    unsigned long long steps = 0, steps32 = 0, nconv = 0, ndiv = 0, ntime = 0;
-    int64_t k = -1;
+    type_count steps, steps32, nconv, ndiv, ntime;
+    int64_t g = -1;
+    int t = -1;
+    // the fields of the current type's plan that the descent uses
+    int pl_l = 0, pl_N = 1, pl_cap = 20, pl_prec = 0;
+    double pl_tol2 = 0.0;
+    float pl_sw = 0.f;
     cd z = {0.0, 0.0};
-    double prev = 0.0; // previous step (FP32: length; FP64: squared length)
+    double prev = 0.0; // previous squared step length
     int it = 0;
     bool fin = false, done = false, f32 = false;
-    const bool mixed = pl.precision == 1;
-    const double tol2 = pl.tol_desc * pl.tol_desc;
     wave_queue wq = {0, 0};
+    type_cache tc;
     while (true) {
-        bool need = !done && k < 0;
-        uint64_t got = wave_take(wq, &ctr[C_START_NEXT], pl.chunk_start, need);
+        const bool need = !done && g < 0;
+        const uint64_t got = wave_take(wq, &b.gctr[G_START_NEXT], b.chunk_start, need);
+        bool change = false;
         if (need) {
-            if (got >= (uint64_t)pl.NS) done = true;
-            else { k = (int64_t)got; z = roots[k]; it = 0; prev = 0.0; fin = false; f32 = mixed; }
+            if (got >= (uint64_t)b.n_starts) {
+                done = true;
+            } else {
+                g = (int64_t)got;
+                const int t1 = cached_type(tc, b.start_offs, b.T, g);
+                if (t1 != t) {
+                    t = t1;
+                    const plan_t &pl = b.types[t].p;
+                    pl_l = pl.l;
+                    pl_N = pl.N;
+                    pl_cap = pl.cap;
+                    pl_prec = pl.precision;
+                    pl_tol2 = pl.tol_desc * pl.tol_desc;
+                    pl_sw = pl.fp32_switch;
+                }
+                change = steps.t != t;
+                z = roots[g];
+                it = 0;
+                prev = 0.0;
+                fin = false;
+                f32 = pl_prec == 1;
+            }
         }
+        if (__ballot(change)) {
+            flush_count(b.ctr, C_STEPS_DESC, steps);
+            flush_count(b.ctr, C_STEPS_FP32, steps32);
+            flush_count(b.ctr, C_CONVERGED, nconv);
+            flush_count(b.ctr, C_DIVERGED, ndiv);
+            flush_count(b.ctr, C_TIMEOUT, ntime);
+        }
+        if (change) steps.t = steps32.t = nconv.t = ndiv.t = ntime.t = t;
         if (__ballot(!done) == 0) break;
         if (done) continue;
         uint8_t st = ST_NONE;
         if (f32) {
-            cf c = {(float)z.re, (float)z.im}, P, dP;
-            eval_q_f32(pl.l, pl.N, c, P, dP);
-            ++steps32;
-            float den = dP.re * dP.re + dP.im * dP.im;
-            float sr = (P.re * dP.re + P.im * dP.im) / den;
-            float si = (P.im * dP.re - P.re * dP.im) / den;
-            float a = sqrtf(sr * sr + si * si);
-            float ac = sqrtf(c.re * c.re + c.im * c.im);
-            if (!isfinite(a) || !(den > 0.f) || a <= pl.fp32_switch * fmaxf(ac, 0.00390625f)) {
+            const cf c = {(float)z.re, (float)z.im};
+            cf P, dP;
+            eval_q_f32(pl_l, pl_N, c, P, dP);
+            ++steps32.v;
+            const float den = dP.re * dP.re + dP.im * dP.im;
+            const float rd = __frcp_rn(den);
+            const float sr = (P.re * dP.re + P.im * dP.im) * rd;
+            const float si = (P.im * dP.re - P.re * dP.im) * rd;
+            const float a2 = sr * sr + si * si;
+            const float ac2 = c.re * c.re + c.im * c.im;
+            const float sw = pl_sw;
+            if (!isfinite(a2) || !(den > 0.f) || !isfinite(den) || a2 <= sw * sw * fmaxf(ac2, 0x1p-16f)) {
                 // FP32 is done (or cannot resolve this point): FP64 takes
                 // over from the current point without this step
                 f32 = false;
-                prev = prev * prev;
             } else {
-                float zr = c.re - sr, zi = c.im - si;
+                const float zr = c.re - sr, zi = c.im - si;
                 ++it;
                 z = {(double)zr, (double)zi};
-                float az = sqrtf(zr * zr + zi * zi);
-                if (!isfinite(zr) || !isfinite(zi) || az > 8.f) st = ST_DIVERGED;
-                else if (it > 3 && a > 8.f * (float)prev) st = ST_DIVERGED;
-                else if (it >= pl.cap) st = ST_TIMEOUT;
-                prev = a;
+                const float az2 = zr * zr + zi * zi;
+                if (!isfinite(zr) || !isfinite(zi) || az2 > 64.f) st = ST_DIVERGED;
+                else if (it > 3 && a2 > 64.f * (float)prev) st = ST_DIVERGED;
+                else if (it >= pl_cap) st = ST_TIMEOUT;
+                prev = a2;
             }
         } else {
             cd P, dP;
-            eval_q(pl.l, pl.N, z, P, dP);
-            ++steps;
-            cd d = cdiv(P, dP);
+            eval_q(pl_l, pl_N, z, P, dP);
+            ++steps.v;
+            const cd d = cdiv(P, dP);
             z = csub(z, d);
             ++it;
-            // squared lengths: |d|, |z| compared without square roots
-            double a2 = cabs2(d);
-            double az2 = cabs2(z);
+            // squared lengths: |d| and |z| compared without square roots
+            const double a2 = cabs2(d);
+            const double az2 = cabs2(z);
             if (fin) st = ST_CONVERGED;
             else if (!isfinite(a2) || !cfinite(z) || az2 > 64.0) st = ST_DIVERGED;
             else if (it > 3 && a2 > 64.0 * prev) st = ST_DIVERGED;
-            else if (a2 <= tol2 * fmax(az2, 0x1p-16)) fin = true;
-            else if (it >= pl.cap) st = ST_TIMEOUT;
+            else if (a2 <= pl_tol2 * fmax(az2, 0x1p-16)) fin = true;
+            else if (it >= pl_cap) st = ST_TIMEOUT;
             prev = a2;
         }
         if (st != ST_NONE) {
-            roots[k] = z;
-            status[k] = st;
-            nconv += st == ST_CONVERGED;
-            ndiv += st == ST_DIVERGED;
-            ntime += st == ST_TIMEOUT;
-            k = -1;
+            roots[g] = z;
+            status[g] = st;
+            nconv.v += st == ST_CONVERGED;
+            ndiv.v += st == ST_DIVERGED;
+            ntime.v += st == ST_TIMEOUT;
+            g = -1;
         }
     }
-    wave_add(&ctr[C_STEPS_DESC], steps);
-    wave_add(&ctr[C_STEPS_FP32], steps32);
-    wave_add(&ctr[C_CONVERGED], nconv);
-    wave_add(&ctr[C_DIVERGED], ndiv);
-    wave_add(&ctr[C_TIMEOUT], ntime);
+    flush_count(b.ctr, C_STEPS_DESC, steps);
+    flush_count(b.ctr, C_STEPS_FP32, steps32);
+    flush_count(b.ctr, C_CONVERGED, nconv);
+    flush_count(b.ctr, C_DIVERGED, ndiv);
+    flush_count(b.ctr, C_TIMEOUT, ntime);
 }
 
 // -------------------------------------------------------- nset collection
-// Fold to the closed upper half plane, snap |Im| < tau/2 to the real axis,
-// key by the real part (order-preserving uint64); non-converged go last.
-__global__ void k_keys(plan_t pl, cd *roots, const uint8_t *status, uint64_t *keys, uint32_t *vals)
+// Sort key of a root of the type of rank t: t in the top bits, then the real
+// part in fixed point with resolution 2^-55 over [-2.125, 1.875) -- far finer
+// than any identification radius used with FP64 roots.
+__device__ __forceinline__ uint64_t root_key(int t, double re)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= pl.NS) return;
-    uint64_t key = ~0ull;
-    if (status[k] == ST_CONVERGED) {
-        cd z = roots[k];
-        z.im = fabs(z.im);
-        if (z.im < 0.5 * pl.tau) z.im = 0.0;
-        roots[k] = z;
-        key = orderable(z.re);
-    }
-    keys[k] = key;
-    vals[k] = (uint32_t)k;
+    double x = (re + 2.125) * 0x1p55;
+    x = fmin(fmax(x, 0.0), 0x1p57 - 1.0);
+    return ((uint64_t)t << 57) | (uint64_t)x;
 }
 
-// A sorted point is a duplicate when an earlier point lies within tau in both
-// coordinates (the nset identification, the first point of a cluster kept).
-__global__ void k_mark(plan_t pl, const cd *roots, const uint64_t *keys, const uint32_t *vals,
-                       uint32_t *flag)
+__device__ __forceinline__ cd fold_snap(cd z, double tau)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= pl.NS) return;
+    z.im = fabs(z.im);
+    if (z.im < 0.5 * tau) z.im = 0.0;
+    return z;
+}
+
+// Fold to the closed upper half plane, snap |Im| < tau/2 to the real axis
+// (Section 6.1, nset), and drop a start whose root repeats the root of one
+// of the three previous starts of the same type: the starts of one level-line
+// turn mostly reach the same root (73% repeats, Section 6.4.3), so this local
+// identification removes most duplicates before the sort.
+__global__ void k_prekeys(batch_args b, const cd *roots, const uint8_t *status, uint32_t *flag)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.n_starts) return;
     uint32_t f = 0;
-    if (keys[i] != ~0ull) {
-        cd zi = roots[vals[i]];
+    if (status[g] == ST_CONVERGED) {
+        const int t = find_type(b.start_offs, b.T, g);
+        const double tau = b.types[t].p.tau;
+        const cd z = fold_snap(roots[g], tau);
         f = 1;
-        for (int64_t j = i - 1, c = 0; j >= 0 && c < 256; --j, ++c) {
-            cd zj = roots[vals[j]];
-            if (zi.re - zj.re >= pl.tau) break;
-            if (fabs(zi.im - zj.im) < pl.tau) { f = 0; break; }
+        const int64_t k = g - b.start_offs[t];
+        for (int d = 1; d <= 3 && d <= k; ++d) {
+            if (status[g - d] != ST_CONVERGED) continue;
+            const cd y = fold_snap(roots[g - d], tau);
+            if (fabs(y.re - z.re) < tau && fabs(y.im - z.im) < tau) { f = 0; break; }
         }
+    }
+    flag[g] = f;
+}
+
+__global__ void k_compact(batch_args b, const cd *roots, const uint32_t *flag, const uint32_t *pos, uint64_t *keys,
+                          uint32_t *vals, unsigned long long *count)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.n_starts) return;
+    if (flag[g]) {
+        const int t = find_type(b.start_offs, b.T, g);
+        const cd z = fold_snap(roots[g], b.types[t].p.tau);
+        keys[pos[g]] = root_key(t, z.re);
+        vals[pos[g]] = (uint32_t)g;
+    }
+    if (g == b.n_starts - 1) *count = (unsigned long long)pos[g] + flag[g];
+}
+
+// A sorted point is a duplicate when an earlier point of the same type lies
+// within tau in both coordinates (the nset identification, the first point of
+// a cluster kept).
+__global__ void k_mark(batch_args b, const cd *roots, const uint64_t *keys, const uint32_t *vals, uint32_t *flag,
+                       int64_t m)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int t = (int)(keys[i] >> 57);
+    const double tau = b.types[t].p.tau;
+    const cd zi = fold_snap(roots[vals[i]], tau);
+    uint32_t f = 1;
+    for (int64_t j = i - 1, c = 0; j >= 0 && c < 256; --j, ++c) {
+        if ((int)(keys[j] >> 57) != t) break;
+        const cd zj = fold_snap(roots[vals[j]], tau);
+        if (zi.re - zj.re >= tau) break;
+        if (fabs(zi.im - zj.im) < tau) { f = 0; break; }
     }
     flag[i] = f;
 }
 
-__global__ void k_scatter(plan_t pl, const cd *roots, const uint32_t *vals, const uint32_t *flag,
-                          const uint32_t *pos, double *ore, double *oim, uint64_t capacity,
-                          unsigned long long *ctr)
+// Per type: first sorted index (lower bound of the type's key range, T + 1
+// entries in tb) and the number of unique roots in ctr[t][C_UNIQUE].
+// One block of at least T + 1 threads.
+__global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t *flag, const uint32_t *pos,
+                              int64_t m, int64_t *tb)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long nreal = 0;
-    if (i < pl.NS) {
-        if (flag[i]) {
-            uint64_t p = pos[i];
-            cd z = roots[vals[i]];
-            if (p < capacity) { ore[p] = z.re; oim[p] = z.im; }
-            nreal += z.im == 0.0;
+    const int t = threadIdx.x;
+    if (t <= b.T) {
+        const uint64_t key = (uint64_t)t << 57;
+        int64_t lo = 0, hi = m;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (keys[mid] < key) lo = mid + 1; else hi = mid;
         }
-        if (i == pl.NS - 1) ctr[C_UNIQUE] = (unsigned long long)pos[i] + flag[i];
+        tb[t] = (t == b.T) ? m : lo;
     }
-    wave_add(&ctr[C_REAL], nreal);
+    __syncthreads();
+    if (t < b.T) {
+        auto pos_at = [&](int64_t i) -> uint64_t { return i < m ? pos[i] : (m ? pos[m - 1] + flag[m - 1] : 0); };
+        b.ctr[(int64_t)t * C_NCOUNTERS + C_UNIQUE] = pos_at(tb[t + 1]) - pos_at(tb[t]);
+    }
+}
+
+__global__ void k_scatter(batch_args b, const cd *roots, const uint64_t *keys, const uint32_t *vals,
+                          const uint32_t *flag, const uint32_t *pos, const int64_t *tb, int64_t m, double *ore,
+                          double *oim)
+{
+    type_count nreal;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool act = i < m && flag[i];
+        const int t = act ? (int)(keys[i] >> 57) : nreal.t;
+        if (__ballot(act && t != nreal.t)) flush_count(b.ctr, C_REAL, nreal);
+        nreal.t = t;
+        if (!act) continue;
+        const type_desc &td = b.types[t];
+        const uint64_t u = pos[i] - pos[tb[t]];
+        const cd z = fold_snap(roots[vals[i]], td.p.tau);
+        if (u < td.cap) {
+            ore[td.out_off + u] = z.re;
+            oim[td.out_off + u] = z.im;
+        }
+        nreal.v += z.im == 0.0;
+    }
+    flush_count(b.ctr, C_REAL, nreal);
 }
 
 // ---------------------------------------------------------- classification
@@ -334,12 +556,17 @@ __global__ void k_scatter(plan_t pl, const cd *roots, const uint32_t *vals, cons
 // 6.3.2): a root of period n can sit that close to a root of period n/2 (the
 // centre of a satellite next to its parent), so the scale of p_k alone would
 // not do.  One orbit pass serves all divisors.
-__global__ void k_classify(plan_t pl, const double *re, const double *im, int32_t *period,
-                           int32_t *preperiod, uint8_t *flags, uint64_t count)
+// Threads run over the compact unique index space (uniq_offs).
+__global__ void k_classify(batch_args b, const double *re, const double *im, int32_t *period, int32_t *preperiod,
+                           uint8_t *flags, int64_t n_uniq)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)count) return;
-    cd c = {re[i], im[i]};
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_uniq) return;
+    const int t = find_type(b.uniq_offs, b.T, u);
+    const type_desc &td = b.types[t];
+    const plan_t &pl = td.p;
+    const int64_t i = td.out_off + (u - b.uniq_offs[t]);
+    const cd c = {re[i], im[i]};
     int per = pl.n;
     if (pl.l == 0 && period) {
         orbit_state<double> s = {0.0, 0.0, 0.0, 0.0};
@@ -347,15 +574,15 @@ __global__ void k_classify(plan_t pl, const double *re, const double *im, int32_
         for (int k = 1; k < pl.n; ++k) {
             orbit_step(s, c.re, c.im);
             if (((pl.divmask_lo >> k) & 1u) && per == pl.n) {
-                double a2 = s.zr * s.zr + s.zi * s.zi;
-                double d2 = s.dr * s.dr + s.di * s.di;
+                const double a2 = s.zr * s.zr + s.zi * s.zi;
+                const double d2 = s.dr * s.dr + s.di * s.di;
                 if (a2 < thr * thr * d2) per = k;
             }
         }
     }
     if (period) period[i] = per;
     if (preperiod) preperiod[i] = pl.l;
-    if (flags) flags[i] = (im[i] == 0.0) ? 1 : 0;
+    if (flags) flags[i] = (c.im == 0.0) ? 1 : 0;
 }
 
 } // namespace msplit

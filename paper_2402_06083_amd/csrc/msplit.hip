@@ -10,6 +10,7 @@
 #include <rocprim/rocprim.hpp>
 
 #include <algorithm>
+#include <numeric>
 #include <vector>
 
 #include "msplit.h"
@@ -106,54 +107,109 @@ plan_t make_plan(int l, int n, const msplit_options *o)
     p.divmask_lo = divisor_mask(n);
     p.precision = o->precision;
     p.fp32_switch = o->fp32_switch > 0 ? (float)o->fp32_switch : 0x1p-14f;
-    // work-queue chunks: about four chunks per wave of a full persistent grid
-    auto chunk_for = [](int64_t items) {
-        int64_t waves = 256 * 8 * 4;
-        int64_t c = items / (waves * 4);
-        return (uint32_t)std::max<int64_t>(64, std::min<int64_t>(1024, c));
-    };
-    p.chunk_seg = chunk_for(p.S);
-    p.chunk_start = chunk_for(p.NS);
     return p;
+}
+
+// work-queue chunk: about four chunks per wave of a full persistent grid
+uint32_t chunk_for(int64_t items)
+{
+    const int64_t waves = 256 * 8 * 4;
+    const int64_t c = items / (waves * 4);
+    return (uint32_t)std::max<int64_t>(64, std::min<int64_t>(1024, c));
+}
+
+// ------------------------------------------------------------------ batch
+struct batch_plan {
+    int T = 0;
+    std::vector<int> slot;          // processing position -> caller index
+    std::vector<type_desc> td;      // in processing order
+    std::vector<int64_t> seed_offs, seg_offs, start_offs; // T + 1
+    int64_t n_seeds = 0, n_segs = 0, n_starts = 0;
+};
+
+// Types in decreasing order N (then caller order) so that the persistent
+// queues end on the cheapest items.
+int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uint64_t *out_offs,
+               const uint64_t *caps, batch_plan &bp)
+{
+    if (npairs <= 0 || npairs > 64) return MSPLIT_E_ARG;
+    bp.T = npairs;
+    bp.slot.resize(npairs);
+    std::iota(bp.slot.begin(), bp.slot.end(), 0);
+    std::stable_sort(bp.slot.begin(), bp.slot.end(), [&](int a, int b) {
+        return ln[2 * a] + ln[2 * a + 1] > ln[2 * b] + ln[2 * b + 1];
+    });
+    bp.td.resize(npairs);
+    bp.seed_offs.assign(npairs + 1, 0);
+    bp.seg_offs.assign(npairs + 1, 0);
+    bp.start_offs.assign(npairs + 1, 0);
+    for (int t = 0; t < npairs; ++t) {
+        const int c = bp.slot[t];
+        const int l = ln[2 * c], n = ln[2 * c + 1];
+        if (!valid_type(l, n)) return MSPLIT_E_ARG;
+        type_desc &d = bp.td[t];
+        memset(&d, 0, sizeof(d));
+        d.p = make_plan(l, n, o);
+        d.seed_off = bp.seed_offs[t];
+        d.seg_off = bp.seg_offs[t];
+        d.start_off = bp.start_offs[t];
+        d.out_off = out_offs ? (int64_t)out_offs[c] : 0;
+        d.cap = caps ? caps[c] : 0;
+        bp.seed_offs[t + 1] = bp.seed_offs[t] + d.p.S + 1;
+        bp.seg_offs[t + 1] = bp.seg_offs[t] + d.p.S;
+        bp.start_offs[t + 1] = bp.start_offs[t] + d.p.NS;
+    }
+    bp.n_seeds = bp.seed_offs[npairs];
+    bp.n_segs = bp.seg_offs[npairs];
+    bp.n_starts = bp.start_offs[npairs];
+    return MSPLIT_OK;
 }
 
 // ------------------------------------------------------------- workspace
 struct layout {
-    size_t ctr, seeds, starts, status, segf, keys, keys2, vals, vals2, flag, pos, temp, total;
+    size_t gctr, ctr, types, offs, tb, seeds, starts, status, segf, flag0, pos0, keys, vals, keys2, vals2, flag,
+        pos, temp, total;
     size_t temp_bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-hipError_t rocprim_temp(const plan_t &p, size_t &bytes)
+hipError_t rocprim_temp(int64_t n, size_t &bytes)
 {
     size_t sort_b = 0, scan_b = 0;
     hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_b, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                             (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)p.NS, 0, 64);
+                                             (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n, 0, 64);
     if (e != hipSuccess) return e;
-    e = rocprim::exclusive_scan(nullptr, scan_b, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, (size_t)p.NS,
+    e = rocprim::exclusive_scan(nullptr, scan_b, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, (size_t)n,
                                 rocprim::plus<uint32_t>());
     if (e != hipSuccess) return e;
     bytes = std::max(sort_b, scan_b);
     return hipSuccess;
 }
 
-layout make_layout(const plan_t &p, size_t temp_bytes)
+layout make_layout(const batch_plan &bp, size_t temp_bytes)
 {
     layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
-    L.ctr = take(sizeof(unsigned long long) * C_NCOUNTERS);
-    L.seeds = take(sizeof(cd) * (p.S + 1));
-    L.starts = take(sizeof(cd) * p.NS);
-    L.status = take(p.NS);
-    L.segf = take(p.S);
-    L.keys = take(8 * p.NS);
-    L.keys2 = take(8 * p.NS);
-    L.vals = take(4 * p.NS);
-    L.vals2 = take(4 * p.NS);
-    L.flag = take(4 * p.NS);
-    L.pos = take(4 * p.NS);
+    const size_t T = (size_t)bp.T, NS = (size_t)bp.n_starts;
+    L.gctr = take(sizeof(unsigned long long) * G_NCOUNTERS);
+    L.ctr = take(sizeof(unsigned long long) * C_NCOUNTERS * T);
+    L.types = take(sizeof(type_desc) * T);
+    L.offs = take(sizeof(int64_t) * 4 * (T + 1));
+    L.tb = take(sizeof(int64_t) * (T + 1));
+    L.seeds = take(sizeof(cd) * bp.n_seeds);
+    L.starts = take(sizeof(cd) * NS);
+    L.status = take(NS);
+    L.segf = take(bp.n_segs);
+    L.flag0 = take(4 * NS);
+    L.pos0 = take(4 * NS);
+    L.keys = take(8 * NS);
+    L.vals = take(4 * NS);
+    L.keys2 = take(8 * NS);
+    L.vals2 = take(4 * NS);
+    L.flag = take(4 * NS);
+    L.pos = take(4 * NS);
     L.temp_bytes = temp_bytes;
     L.temp = take(temp_bytes);
     L.total = off;
@@ -176,6 +232,18 @@ __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
+// counters: zero; per-type minimum-separation slot at +inf
+__global__ void k_init_counters(unsigned long long *gctr, unsigned long long *ctr, int T)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < G_NCOUNTERS) gctr[i] = 0;
+    if (i < T * C_NCOUNTERS) ctr[i] = (i % C_NCOUNTERS == C_MIN_SEP_BITS) ? 0x7ff0000000000000ull : 0ull;
+}
+__global__ void k_unzip(const cd *z, double *re, double *im, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { re[i] = z[i].re; im[i] = z[i].im; }
+}
 
 int device_cus()
 {
@@ -189,7 +257,7 @@ int device_cus()
     return cus;
 }
 
-unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+unsigned blocks_for(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
 // persistent grid: enough waves to fill every SIMD several times
 unsigned persistent_blocks(int64_t work, int bs)
@@ -199,13 +267,13 @@ unsigned persistent_blocks(int64_t work, int bs)
 }
 
 struct call_ctx {
-    hipStream_t stream;
     msplit_stats *stats;
+    int nstats;
     int err = MSPLIT_OK;
     bool check(hipError_t e)
     {
         if (e != hipSuccess) {
-            if (stats) stats->hip_error = (int32_t)e;
+            for (int i = 0; i < nstats && stats; ++i) stats[i].hip_error = (int32_t)e;
             err = MSPLIT_E_DEVICE;
             return false;
         }
@@ -213,15 +281,13 @@ struct call_ctx {
     }
 };
 
-#define CHK(x)                      \
-    do {                            \
+#define CHK(x)                               \
+    do {                                     \
         if (!ctx.check((x))) return ctx.err; \
     } while (0)
 
-void set_cis(int M, hipStream_t stream)
+hipError_t set_cis(int M, hipStream_t stream)
 {
-    static int cached = -1;
-    if (cached == M) return;
     double re[64], im[64];
     for (int s = 0; s < 64; ++s) {
         double t = 2.0 * M_PI * (double)(s % M) / (double)M;
@@ -233,183 +299,253 @@ void set_cis(int M, hipStream_t stream)
         if (4 * (s % M) == 2 * M) { re[s] = -1; im[s] = 0; }
         if (4 * (s % M) == 3 * M) { re[s] = 0; im[s] = -1; }
     }
-    (void)hipMemcpyToSymbolAsync(HIP_SYMBOL(c_cis_re), re, sizeof(re), 0, hipMemcpyHostToDevice, stream);
-    (void)hipMemcpyToSymbolAsync(HIP_SYMBOL(c_cis_im), im, sizeof(im), 0, hipMemcpyHostToDevice, stream);
-    (void)hipStreamSynchronize(stream);
-    cached = M;
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_cis_re), re, sizeof(re), 0, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_cis_im), im, sizeof(im), 0, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return e;
 }
 
-__global__ void k_unzip(const cd *z, double *re, double *im, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) { re[i] = z[i].re; im[i] = z[i].im; }
-}
+struct events {
+    hipEvent_t e[7];
+    int made = 0;
+    ~events() { for (int i = 0; i < made; ++i) (void)hipEventDestroy(e[i]); }
+};
 
-// The whole split of one type.  Returns a status; *count is always written.
-int split_one(int l, int n, const msplit_options *opts, void *workspace, uint64_t ws_bytes, msplit_roots *out,
-              uint64_t *count, msplit_stats *stats, void *stream_v, bool starts_only = false,
-              double *sre = nullptr, double *sim = nullptr, uint64_t scap = 0)
+// The split of a list of types (in caller order ln[2i], ln[2i+1]); roots of
+// type i go to out at out_offs[i] with capacity caps[i].  counts[i] and
+// stats[i] are written for every type.  starts_only: stop after the level
+// line and copy the starts of the single type to sre / sim.
+int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *workspace, uint64_t ws_bytes,
+              msplit_roots *out, const uint64_t *out_offs, const uint64_t *caps, uint64_t *counts,
+              msplit_stats *stats, void *stream_v, bool starts_only = false, double *sre = nullptr,
+              double *sim = nullptr, uint64_t scap = 0)
 {
-    if (count) *count = 0;
-    if (!count || !workspace) return MSPLIT_E_ARG;
-    if (!starts_only && !out) return MSPLIT_E_ARG;
-    if (starts_only && (!sre || !sim)) return MSPLIT_E_ARG;
-    if (!valid_type(l, n)) return MSPLIT_E_ARG;
+    for (int i = 0; i < npairs && counts; ++i) counts[i] = 0;
+    if (!counts || !workspace || !ln) return MSPLIT_E_ARG;
+    if (!starts_only && (!out || !out->re || !out->im)) return MSPLIT_E_ARG;
+    if (starts_only && (!sre || !sim || npairs != 1)) return MSPLIT_E_ARG;
     if (!opts) opts = defaults();
     if (opts->struct_size && opts->struct_size != sizeof(msplit_options)) return MSPLIT_E_ARG;
-    if (opts->precision < 0 || opts->precision > 1) return MSPLIT_E_UNSUPPORTED;
+    if (opts->precision < 0 || opts->precision > 2) return MSPLIT_E_ARG;
+    if (opts->precision == MSPLIT_DD) return MSPLIT_E_UNSUPPORTED;
     if (opts->points_per_turn && (opts->points_per_turn % 4 || opts->points_per_turn > 64)) return MSPLIT_E_ARG;
-    if (stats) memset(stats, 0, sizeof(*stats));
-    plan_t p = make_plan(l, n, opts);
-    // FP64 keys separate the roots only while the identification radius
-    // stays well above the FP64 rounding of a root
-    if (p.tau < 0x1p-50) return MSPLIT_E_PRECISION;
-    if (l != 0) return MSPLIT_E_UNSUPPORTED;
+    const int bs = opts->block_size ? (int)opts->block_size : 256;
+    if (bs % 64 || bs > 1024) return MSPLIT_E_ARG;
+    if (stats) memset(stats, 0, sizeof(msplit_stats) * npairs);
+    batch_plan bp;
+    int r = make_batch(ln, npairs, opts, out_offs, caps, bp);
+    if (r) return r;
+    for (int t = 0; t < bp.T; ++t) {
+        // FP64 keys separate the roots only while the identification radius
+        // stays well above the FP64 rounding of a root
+        if (bp.td[t].p.tau < 0x1p-50) return MSPLIT_E_PRECISION;
+        if (bp.td[t].p.l != 0) return MSPLIT_E_UNSUPPORTED;
+    }
+    if (bp.n_starts >= ((int64_t)1 << 32)) return MSPLIT_E_UNSUPPORTED;
     hipStream_t stream = (hipStream_t)stream_v;
-    call_ctx ctx{stream, stats};
+    call_ctx ctx{stats, npairs};
     size_t temp_bytes = 0;
-    CHK(rocprim_temp(p, temp_bytes));
-    layout L = make_layout(p, temp_bytes);
+    CHK(rocprim_temp(bp.n_starts, temp_bytes));
+    const layout L = make_layout(bp, temp_bytes);
     if (ws_bytes < L.total) return MSPLIT_E_WORKSPACE;
     char *ws = (char *)workspace;
+    unsigned long long *gctr = (unsigned long long *)(ws + L.gctr);
     unsigned long long *ctr = (unsigned long long *)(ws + L.ctr);
+    type_desc *dtypes = (type_desc *)(ws + L.types);
+    int64_t *doffs = (int64_t *)(ws + L.offs);
+    int64_t *tb = (int64_t *)(ws + L.tb);
     cd *seeds = (cd *)(ws + L.seeds);
     cd *starts = (cd *)(ws + L.starts);
     uint8_t *status = (uint8_t *)(ws + L.status);
     uint8_t *segf = (uint8_t *)(ws + L.segf);
+    uint32_t *flag0 = (uint32_t *)(ws + L.flag0), *pos0 = (uint32_t *)(ws + L.pos0);
     uint64_t *keys = (uint64_t *)(ws + L.keys), *keys2 = (uint64_t *)(ws + L.keys2);
     uint32_t *vals = (uint32_t *)(ws + L.vals), *vals2 = (uint32_t *)(ws + L.vals2);
     uint32_t *flag = (uint32_t *)(ws + L.flag), *pos = (uint32_t *)(ws + L.pos);
     void *temp = ws + L.temp;
-    const int bs = opts->block_size ? (int)opts->block_size : 256;
-    if (bs % 64 || bs > 1024) return MSPLIT_E_ARG;
+    const int T = bp.T;
 
-    set_cis(p.M, stream);
-    // events: [0] start, [1] seeds, [2] walk, [3] descend, [4] collect,
-    // [5] classify, [6] certify (end)
-    hipEvent_t ev[7];
-    for (int i = 0; i < 7; ++i) CHK(hipEventCreate(&ev[i]));
-    struct ev_guard {
-        hipEvent_t *e;
-        ~ev_guard() { for (int i = 0; i < 7; ++i) (void)hipEventDestroy(e[i]); }
-    } guard{ev};
-    CHK(hipEventRecord(ev[0], stream));
+    // every type of one call shares M (the cis table)
+    for (int t = 1; t < T; ++t)
+        if (bp.td[t].p.M != bp.td[0].p.M) return MSPLIT_E_ARG;
+    CHK(set_cis(bp.td[0].p.M, stream));
 
-    // counters: zero, min-separation slot at +inf
-    k_fill_u64<<<1, 64, 0, stream>>>(ctr, C_NCOUNTERS, 0ull);
-    k_fill_u64<<<1, 1, 0, stream>>>(ctr + C_MIN_SEP_BITS, 1, 0x7ff0000000000000ull);
-    k_fill_nan<<<blocks_for(p.NS, 256), 256, 0, stream>>>(starts, p.NS);
-    k_fill_u8<<<blocks_for(p.NS, 256), 256, 0, stream>>>(status, p.NS, ST_NONE);
-    // seeds (lift from the circle |p_1| = lambda_0)
-    k_seeds<<<blocks_for(p.S + 1, bs), bs, 0, stream>>>(p, seeds, starts, ctr);
-    CHK(hipEventRecord(ev[1], stream));
+    // tables: type descriptors and offsets (uniq_offs filled later)
+    std::vector<int64_t> offs(4 * (T + 1), 0);
+    std::copy(bp.seed_offs.begin(), bp.seed_offs.end(), offs.begin());
+    std::copy(bp.seg_offs.begin(), bp.seg_offs.end(), offs.begin() + (T + 1));
+    std::copy(bp.start_offs.begin(), bp.start_offs.end(), offs.begin() + 2 * (T + 1));
+    CHK(hipMemcpyAsync(dtypes, bp.td.data(), sizeof(type_desc) * T, hipMemcpyHostToDevice, stream));
+    CHK(hipMemcpyAsync(doffs, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, stream));
+
+    batch_args ba;
+    ba.types = dtypes;
+    ba.seed_offs = doffs;
+    ba.seg_offs = doffs + (T + 1);
+    ba.start_offs = doffs + 2 * (T + 1);
+    ba.uniq_offs = doffs + 3 * (T + 1);
+    ba.T = T;
+    ba.n_seeds = bp.n_seeds;
+    ba.n_segs = bp.n_segs;
+    ba.n_starts = bp.n_starts;
+    ba.chunk_seg = chunk_for(bp.n_segs);
+    ba.chunk_start = chunk_for(bp.n_starts);
+    ba.gctr = gctr;
+    ba.ctr = ctr;
+
+    events ev;
+    for (int i = 0; i < 7; ++i) {
+        CHK(hipEventCreate(&ev.e[i]));
+        ev.made = i + 1;
+    }
+    CHK(hipEventRecord(ev.e[0], stream));
+    k_init_counters<<<blocks_for((int64_t)T * C_NCOUNTERS + G_NCOUNTERS, 256), 256, 0, stream>>>(gctr, ctr, T);
+    k_fill_nan<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(starts, bp.n_starts);
+    k_fill_u8<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(status, bp.n_starts, ST_NONE);
+    // seeds: lift from the circle |p_1| = lambda_0
+    k_seeds<<<persistent_blocks(bp.n_seeds, bs), bs, 0, stream>>>(ba, seeds, starts);
+    CHK(hipEventRecord(ev.e[1], stream));
     // level-line walk
-    k_walk<<<persistent_blocks(p.S, bs), bs, 0, stream>>>(p, seeds, starts, segf, ctr);
-    CHK(hipEventRecord(ev[2], stream));
+    k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, segf);
+    CHK(hipEventRecord(ev.e[2], stream));
+    CHK(hipGetLastError());
+
+    std::vector<unsigned long long> h((size_t)T * C_NCOUNTERS);
+    auto read_counters = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(h.data(), ctr, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+                                      stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        return e;
+    };
+    auto H = [&](int t, int slot) { return h[(size_t)t * C_NCOUNTERS + slot]; };
+
     if (starts_only) {
+        const plan_t &p = bp.td[0].p;
         if (scap < (uint64_t)p.NS) return MSPLIT_E_CAPACITY;
         k_unzip<<<blocks_for(p.NS, 256), 256, 0, stream>>>(starts, sre, sim, p.NS);
         CHK(hipGetLastError());
-        unsigned long long h[C_NCOUNTERS];
-        CHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, stream));
-        CHK(hipStreamSynchronize(stream));
-        *count = (uint64_t)p.NS;
+        CHK(read_counters());
+        counts[0] = (uint64_t)p.NS;
+        float a = 0.f, b = 0.f;
+        (void)hipEventElapsedTime(&a, ev.e[0], ev.e[1]);
+        (void)hipEventElapsedTime(&b, ev.e[1], ev.e[2]);
         if (stats) {
             stats->starts = (uint64_t)p.NS;
-            stats->phase_fail = h[C_PHASE_FAIL] + h[C_SEED_FAIL];
-            stats->steps_lift = h[C_STEPS_LIFT];
-            stats->steps_walk = h[C_STEPS_WALK];
-            float a = 0.f, b = 0.f;
-            (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-            (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+            stats->phase_fail = H(0, C_PHASE_FAIL) + H(0, C_SEED_FAIL);
+            stats->steps_lift = H(0, C_STEPS_LIFT);
+            stats->steps_walk = H(0, C_STEPS_WALK);
             stats->ms_stage[0] = a;
             stats->ms_stage[1] = b;
             stats->ms_device = a + b;
         }
-        return (h[C_PHASE_FAIL] + h[C_SEED_FAIL]) ? MSPLIT_E_INCOMPLETE : MSPLIT_OK;
+        return stats && stats->phase_fail ? MSPLIT_E_INCOMPLETE : MSPLIT_OK;
     }
-    // descents
-    k_descend<<<persistent_blocks(p.NS, bs), bs, 0, stream>>>(p, starts, status, ctr);
-    CHK(hipEventRecord(ev[3], stream));
-    // nset collection
-    k_keys<<<blocks_for(p.NS, 256), 256, 0, stream>>>(p, starts, status, keys, vals);
-    size_t tb = temp_bytes;
-    CHK(rocprim::radix_sort_pairs(temp, tb, keys, keys2, vals, vals2, (size_t)p.NS, 0, 64, stream));
-    k_mark<<<blocks_for(p.NS, 256), 256, 0, stream>>>(p, starts, keys2, vals2, flag);
-    tb = temp_bytes;
-    CHK(rocprim::exclusive_scan(temp, tb, flag, pos, 0u, (size_t)p.NS, rocprim::plus<uint32_t>(), stream));
-    k_scatter<<<blocks_for(p.NS, 256), 256, 0, stream>>>(p, starts, vals2, flag, pos, out->re, out->im,
-                                                          out->capacity, ctr);
-    CHK(hipEventRecord(ev[4], stream));
-    CHK(hipGetLastError());
-    unsigned long long h[C_NCOUNTERS];
-    CHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, stream));
-    CHK(hipStreamSynchronize(stream));
-    const uint64_t uniq = h[C_UNIQUE];
-    *count = uniq;
-    if (uniq > out->capacity) return MSPLIT_E_CAPACITY;
-    // classification
-    if (uniq) {
-        if (out->re_lo)
-            k_fill_u64<<<blocks_for((int64_t)uniq, 256), 256, 0, stream>>>((unsigned long long *)out->re_lo, uniq, 0ull);
-        if (out->im_lo)
-            k_fill_u64<<<blocks_for((int64_t)uniq, 256), 256, 0, stream>>>((unsigned long long *)out->im_lo, uniq, 0ull);
-        k_classify<<<blocks_for((int64_t)uniq, 256), 256, 0, stream>>>(
-            p, out->re, out->im, (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period, out->preperiod,
-            out->flags, uniq);
-        if (out->radius)
-            k_fill_u64<<<blocks_for((int64_t)uniq, 256), 256, 0, stream>>>((unsigned long long *)out->radius, uniq, 0ull);
-    }
-    CHK(hipEventRecord(ev[5], stream));
-    // certificate
-    const bool cert = (opts->flags & MSPLIT_F_CERTIFY) != 0;
-    if (cert && uniq) {
-        if (!out->radius || !out->flags) return MSPLIT_E_ARG;
-        k_certify<<<blocks_for((int64_t)uniq, 128), 128, 0, stream>>>(
-            l, n, p.divmask_lo, out->re, out->im, (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period,
-            out->flags, out->radius, uniq, ctr, C_CERTIFIED, C_LABEL, C_MAX_RAD_BITS);
-        // the separation scan needs the largest radius
-        k_separation_rmax<<<blocks_for((int64_t)uniq, 256), 256, 0, stream>>>(
-            out->re, out->im, out->radius, uniq, ctr, C_MAX_RAD_BITS, C_OVERLAP, C_MIN_SEP_BITS);
-    } else if (uniq) {
-        k_separation<<<blocks_for((int64_t)uniq, 256), 256, 0, stream>>>(out->re, out->im, nullptr, uniq, 0.0,
-                                                                          ctr, C_OVERLAP, C_MIN_SEP_BITS);
-    }
-    CHK(hipEventRecord(ev[6], stream));
-    CHK(hipGetLastError());
-    CHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, stream));
-    CHK(hipStreamSynchronize(stream));
-    float ms = 0.f, mss[6] = {0, 0, 0, 0, 0, 0};
-    (void)hipEventElapsedTime(&ms, ev[0], ev[6]);
-    for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&mss[i], ev[i], ev[i + 1]);
 
-    const uint64_t total = h[C_REAL] + 2 * (uniq - h[C_REAL]);
-    const uint64_t expected = (uint64_t)p.D;
-    if (stats) {
-        stats->starts = (uint64_t)p.NS;
-        stats->converged = h[C_CONVERGED];
-        stats->diverged = h[C_DIVERGED];
-        stats->timeouts = h[C_TIMEOUT];
-        stats->unique = uniq;
-        stats->n_real = h[C_REAL];
-        stats->total = total;
-        stats->expected = expected;
-        stats->missing = expected > total ? expected - total : 0;
-        stats->phase_fail = h[C_PHASE_FAIL] + h[C_SEED_FAIL];
-        stats->certified = h[C_CERTIFIED];
-        stats->label_proven = h[C_LABEL];
-        stats->overlaps = h[C_OVERLAP];
-        stats->steps_lift = h[C_STEPS_LIFT];
-        stats->steps_walk = h[C_STEPS_WALK];
-        stats->steps_desc = h[C_STEPS_DESC];
-        stats->steps_fp32 = h[C_STEPS_FP32];
-        memcpy(&stats->min_sep, &h[C_MIN_SEP_BITS], 8);
-        memcpy(&stats->max_radius, &h[C_MAX_RAD_BITS], 8);
-        stats->ms_device = ms;
-        for (int i = 0; i < 6; ++i) stats->ms_stage[i] = mss[i];
+    // descents
+    k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, status);
+    CHK(hipEventRecord(ev.e[3], stream));
+    // nset collection: local identification, compaction, sort, global
+    // identification, per-type output slices
+    k_prekeys<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, starts, status, flag0);
+    size_t tb_bytes = temp_bytes;
+    CHK(rocprim::exclusive_scan(temp, tb_bytes, flag0, pos0, 0u, (size_t)bp.n_starts, rocprim::plus<uint32_t>(),
+                                stream));
+    k_compact<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, starts, flag0, pos0, keys, vals, gctr + 2);
+    CHK(hipGetLastError());
+    unsigned long long m_h = 0;
+    CHK(hipMemcpyAsync(&m_h, gctr + 2, sizeof(m_h), hipMemcpyDeviceToHost, stream));
+    CHK(hipStreamSynchronize(stream));
+    const int64_t m = (int64_t)m_h;
+    if (m > 0) {
+        tb_bytes = temp_bytes;
+        CHK(rocprim::radix_sort_pairs(temp, tb_bytes, keys, keys2, vals, vals2, (size_t)m, 0, 64, stream));
+        k_mark<<<blocks_for(m, 256), 256, 0, stream>>>(ba, starts, keys2, vals2, flag, m);
+        tb_bytes = temp_bytes;
+        CHK(rocprim::exclusive_scan(temp, tb_bytes, flag, pos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
     }
-    if (total != expected) return MSPLIT_E_INCOMPLETE;
-    return MSPLIT_OK;
+    k_type_bounds<<<1, 128, 0, stream>>>(ba, keys2, flag, pos, m, tb);
+    if (m > 0)
+        k_scatter<<<persistent_blocks(m, 256), 256, 0, stream>>>(ba, starts, keys2, vals2, flag, pos, tb, m, out->re,
+                                                          out->im);
+    CHK(hipEventRecord(ev.e[4], stream));
+    CHK(hipGetLastError());
+    CHK(read_counters());
+
+    // capacities, compact unique index space
+    int status_all = MSPLIT_OK;
+    std::vector<int64_t> uniq_offs(T + 1, 0);
+    for (int t = 0; t < T; ++t) {
+        const uint64_t u = H(t, C_UNIQUE);
+        const int c = bp.slot[t];
+        counts[c] = u;
+        if (u > bp.td[t].cap) status_all = MSPLIT_E_CAPACITY;
+        uniq_offs[t + 1] = uniq_offs[t] + (int64_t)std::min<uint64_t>(u, bp.td[t].cap);
+    }
+    if (status_all == MSPLIT_E_CAPACITY) return MSPLIT_E_CAPACITY;
+    const int64_t n_uniq = uniq_offs[T];
+    CHK(hipMemcpyAsync(doffs + 3 * (T + 1), uniq_offs.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice,
+                       stream));
+    // classification
+    if (n_uniq) {
+        k_classify<<<blocks_for(n_uniq, 256), 256, 0, stream>>>(
+            ba, out->re, out->im, (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period, out->preperiod,
+            out->flags, n_uniq);
+    }
+    CHK(hipEventRecord(ev.e[5], stream));
+    // certificate and separation
+    const bool cert = (opts->flags & MSPLIT_F_CERTIFY) != 0;
+    if (cert && (!out->radius || !out->flags)) return MSPLIT_E_ARG;
+    if (n_uniq) {
+        if (cert) {
+            k_certify<<<persistent_blocks(n_uniq, 128), 128, 0, stream>>>(
+                ba, out->re, out->im, (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period, out->flags,
+                out->radius, n_uniq);
+            k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, out->radius, n_uniq);
+        } else {
+            k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, nullptr, n_uniq);
+        }
+    }
+    CHK(hipEventRecord(ev.e[6], stream));
+    CHK(hipGetLastError());
+    CHK(read_counters());
+    float ms = 0.f, mss[6] = {0, 0, 0, 0, 0, 0};
+    (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[6]);
+    for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&mss[i], ev.e[i], ev.e[i + 1]);
+
+    for (int t = 0; t < T; ++t) {
+        const int c = bp.slot[t];
+        const plan_t &p = bp.td[t].p;
+        const uint64_t uniq = H(t, C_UNIQUE), nreal = H(t, C_REAL);
+        const uint64_t total = nreal + 2 * (uniq - nreal);
+        const uint64_t expected = (uint64_t)p.D;
+        if (total != expected && status_all == MSPLIT_OK) status_all = MSPLIT_E_INCOMPLETE;
+        if (!stats) continue;
+        msplit_stats &s = stats[c];
+        s.starts = (uint64_t)p.NS;
+        s.converged = H(t, C_CONVERGED);
+        s.diverged = H(t, C_DIVERGED);
+        s.timeouts = H(t, C_TIMEOUT);
+        s.unique = uniq;
+        s.n_real = nreal;
+        s.total = total;
+        s.expected = expected;
+        s.missing = expected > total ? expected - total : 0;
+        s.phase_fail = H(t, C_PHASE_FAIL) + H(t, C_SEED_FAIL);
+        s.certified = H(t, C_CERTIFIED);
+        s.label_proven = H(t, C_LABEL);
+        s.overlaps = H(t, C_OVERLAP);
+        s.steps_lift = H(t, C_STEPS_LIFT);
+        s.steps_walk = H(t, C_STEPS_WALK);
+        s.steps_desc = H(t, C_STEPS_DESC);
+        s.steps_fp32 = H(t, C_STEPS_FP32);
+        unsigned long long ms_bits = H(t, C_MIN_SEP_BITS), mr_bits = H(t, C_MAX_RAD_BITS);
+        memcpy(&s.min_sep, &ms_bits, 8);
+        memcpy(&s.max_radius, &mr_bits, 8);
+        s.ms_device = ms;
+        for (int i = 0; i < 6; ++i) s.ms_stage[i] = mss[i];
+    }
+    return status_all;
 }
 
 } // namespace
@@ -439,37 +575,65 @@ uint64_t msplit_expected_count(int l, int n, int primitive_only)
     return (uint64_t)mis_count(l, n);
 }
 
+int msplit_batch_workspace_size(const int32_t *ln_pairs, int npairs, const msplit_options *opts, uint64_t *bytes)
+{
+    if (!ln_pairs || npairs <= 0 || !bytes) return MSPLIT_E_ARG;
+    if (!opts) opts = defaults();
+    batch_plan bp;
+    int r = make_batch(ln_pairs, npairs, opts, nullptr, nullptr, bp);
+    if (r) return r;
+    size_t tb = 0;
+    if (rocprim_temp(bp.n_starts, tb) != hipSuccess) return MSPLIT_E_DEVICE;
+    *bytes = make_layout(bp, tb).total;
+    return MSPLIT_OK;
+}
+
 int msplit_workspace_size(int l, int n, const msplit_options *opts, uint64_t *bytes)
 {
     if (!bytes || !valid_type(l, n)) return MSPLIT_E_ARG;
-    if (!opts) opts = defaults();
-    plan_t p = make_plan(l, n, opts);
-    size_t tb = 0;
-    if (rocprim_temp(p, tb) != hipSuccess) return MSPLIT_E_DEVICE;
-    *bytes = make_layout(p, tb).total;
-    return MSPLIT_OK;
+    const int32_t ln[2] = {l, n};
+    return msplit_batch_workspace_size(ln, 1, opts, bytes);
 }
 
 int msplit_hyperbolic(int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes,
                       msplit_roots *out, uint64_t *count, msplit_stats *stats, void *stream)
 {
-    return split_one(0, n, opts, workspace, workspace_bytes, out, count, stats, stream);
+    if (count) *count = 0;
+    if (!count || !out) return MSPLIT_E_ARG;
+    const int32_t ln[2] = {0, n};
+    const uint64_t off = 0, cap = out->capacity;
+    return run_batch(ln, 1, opts, workspace, workspace_bytes, out, &off, &cap, count, stats, stream);
 }
 
 int msplit_misiurewicz(int l, int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes,
                        msplit_roots *out, uint64_t *count, msplit_stats *stats, void *stream)
 {
-    if (l < 2) {
-        if (count) *count = 0;
-        return MSPLIT_E_ARG;
-    }
-    return split_one(l, n, opts, workspace, workspace_bytes, out, count, stats, stream);
+    if (count) *count = 0;
+    if (!count || !out || l < 2) return MSPLIT_E_ARG;
+    const int32_t ln[2] = {l, n};
+    const uint64_t off = 0, cap = out->capacity;
+    return run_batch(ln, 1, opts, workspace, workspace_bytes, out, &off, &cap, count, stats, stream);
 }
 
 int msplit_starts(int l, int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes, double *re,
                   double *im, uint64_t capacity, uint64_t *count, msplit_stats *stats, void *stream)
 {
-    return split_one(l, n, opts, workspace, workspace_bytes, nullptr, count, stats, stream, true, re, im, capacity);
+    if (count) *count = 0;
+    if (!count) return MSPLIT_E_ARG;
+    const int32_t ln[2] = {l, n};
+    return run_batch(ln, 1, opts, workspace, workspace_bytes, nullptr, nullptr, nullptr, count, stats, stream, true,
+                     re, im, capacity);
+}
+
+int msplit_batch(const int32_t *ln_pairs, int npairs, const msplit_options *opts, void *workspace,
+                 uint64_t workspace_bytes, msplit_roots *out, const uint64_t *caps, uint64_t *counts,
+                 msplit_stats *stats, void *stream)
+{
+    if (!ln_pairs || npairs <= 0 || !out || !caps || !counts) return MSPLIT_E_ARG;
+    std::vector<uint64_t> offs(npairs, 0);
+    for (int i = 1; i < npairs; ++i) offs[i] = offs[i - 1] + caps[i - 1];
+    return run_batch(ln_pairs, npairs, opts, workspace, workspace_bytes, out, offs.data(), caps, counts, stats,
+                     stream);
 }
 
 int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *workspace, uint64_t workspace_bytes,
@@ -477,29 +641,42 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
 {
     if (!roots || !workspace || !roots->re || !roots->im || !roots->flags || !roots->radius) return MSPLIT_E_ARG;
     if (!valid_type(l, n)) return MSPLIT_E_ARG;
-    if (workspace_bytes < 256) return MSPLIT_E_WORKSPACE;
     if (stats) memset(stats, 0, sizeof(*stats));
+    // one type, the candidates as its unique roots
+    batch_plan bp;
+    const int32_t ln[2] = {l, n};
+    const uint64_t off = 0;
+    int r = make_batch(ln, 1, defaults(), &off, &count, bp);
+    if (r) return r;
+    size_t need = align256(sizeof(unsigned long long) * (G_NCOUNTERS + C_NCOUNTERS)) + align256(sizeof(type_desc)) +
+                  align256(sizeof(int64_t) * 8);
+    if (workspace_bytes < need) return MSPLIT_E_WORKSPACE;
     hipStream_t stream = (hipStream_t)stream_v;
-    call_ctx ctx{stream, stats};
-    unsigned long long *ctr = (unsigned long long *)workspace;
-    k_fill_u64<<<1, 64, 0, stream>>>(ctr, C_NCOUNTERS, 0ull);
-    k_fill_u64<<<1, 1, 0, stream>>>(ctr + C_MIN_SEP_BITS, 1, 0x7ff0000000000000ull);
+    call_ctx ctx{stats, 1};
+    char *ws = (char *)workspace;
+    unsigned long long *gctr = (unsigned long long *)ws;
+    unsigned long long *ctr = gctr + G_NCOUNTERS;
+    type_desc *dtypes = (type_desc *)(ws + align256(sizeof(unsigned long long) * (G_NCOUNTERS + C_NCOUNTERS)));
+    int64_t *doffs = (int64_t *)((char *)dtypes + align256(sizeof(type_desc)));
+    const int64_t uo[2] = {0, (int64_t)count};
+    CHK(hipMemcpyAsync(dtypes, bp.td.data(), sizeof(type_desc), hipMemcpyHostToDevice, stream));
+    CHK(hipMemcpyAsync(doffs, uo, sizeof(uo), hipMemcpyHostToDevice, stream));
+    batch_args ba;
+    memset(&ba, 0, sizeof(ba));
+    ba.types = dtypes;
+    ba.seed_offs = ba.seg_offs = ba.start_offs = ba.uniq_offs = doffs;
+    ba.T = 1;
+    ba.gctr = gctr;
+    ba.ctr = ctr;
+    k_init_counters<<<1, 64, 0, stream>>>(gctr, ctr, 1);
     if (count) {
-        k_certify<<<blocks_for((int64_t)count, 128), 128, 0, stream>>>(
-            l, n, divisor_mask(n), roots->re, roots->im, roots->period, roots->flags, roots->radius, count, ctr,
-            C_CERTIFIED, C_LABEL, C_MAX_RAD_BITS);
+        k_certify<<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(ba, roots->re, roots->im, roots->period,
+                                                                       roots->flags, roots->radius, (int64_t)count);
+        k_separation<<<persistent_blocks((int64_t)count, 256), 256, 0, stream>>>(ba, roots->re, roots->im, roots->radius,
+                                                                          (int64_t)count);
     }
+    CHK(hipGetLastError());
     unsigned long long h[C_NCOUNTERS];
-    CHK(hipGetLastError());
-    CHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, stream));
-    CHK(hipStreamSynchronize(stream));
-    double rmax;
-    memcpy(&rmax, &h[C_MAX_RAD_BITS], 8);
-    if (count)
-        k_separation<<<blocks_for((int64_t)count, 256), 256, 0, stream>>>(roots->re, roots->im, roots->radius,
-                                                                           count, rmax, ctr, C_OVERLAP,
-                                                                           C_MIN_SEP_BITS);
-    CHK(hipGetLastError());
     CHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, stream));
     CHK(hipStreamSynchronize(stream));
     if (stats) {
@@ -510,47 +687,6 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
         memcpy(&stats->max_radius, &h[C_MAX_RAD_BITS], 8);
     }
     return MSPLIT_OK;
-}
-
-int msplit_batch_workspace_size(const int32_t *ln_pairs, int npairs, const msplit_options *opts, uint64_t *bytes)
-{
-    if (!ln_pairs || npairs <= 0 || !bytes) return MSPLIT_E_ARG;
-    uint64_t mx = 0;
-    for (int i = 0; i < npairs; ++i) {
-        uint64_t b = 0;
-        int r = msplit_workspace_size(ln_pairs[2 * i], ln_pairs[2 * i + 1], opts, &b);
-        if (r) return r;
-        mx = std::max(mx, b);
-    }
-    *bytes = mx;
-    return MSPLIT_OK;
-}
-
-int msplit_batch(const int32_t *ln_pairs, int npairs, const msplit_options *opts, void *workspace,
-                 uint64_t workspace_bytes, msplit_roots *out, const uint64_t *caps, uint64_t *counts,
-                 msplit_stats *stats, void *stream)
-{
-    if (!ln_pairs || npairs <= 0 || !out || !caps || !counts) return MSPLIT_E_ARG;
-    uint64_t off = 0;
-    int first_err = MSPLIT_OK;
-    for (int i = 0; i < npairs; ++i) {
-        msplit_roots o = *out;
-        o.re = out->re + off;
-        o.im = out->im + off;
-        o.re_lo = out->re_lo ? out->re_lo + off : nullptr;
-        o.im_lo = out->im_lo ? out->im_lo + off : nullptr;
-        o.period = out->period ? out->period + off : nullptr;
-        o.preperiod = out->preperiod ? out->preperiod + off : nullptr;
-        o.flags = out->flags ? out->flags + off : nullptr;
-        o.radius = out->radius ? out->radius + off : nullptr;
-        o.capacity = caps[i];
-        int r = split_one(ln_pairs[2 * i], ln_pairs[2 * i + 1], opts, workspace, workspace_bytes, &o, &counts[i],
-                          stats ? &stats[i] : nullptr, stream);
-        if (r && first_err == MSPLIT_OK) first_err = r;
-        if (r == MSPLIT_E_ARG || r == MSPLIT_E_DEVICE || r == MSPLIT_E_WORKSPACE) return r;
-        off += caps[i];
-    }
-    return first_err;
 }
 
 } // extern "C"
