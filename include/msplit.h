@@ -75,6 +75,10 @@ enum msplit_root_flags {
     MSPLIT_R_LABEL = 4u      /* the period / type label is proven on that disk */
 };
 
+/* Device workspace, in bytes, that msplit_certify needs (counters and one
+ * type descriptor; independent of the number of candidates). */
+#define MSPLIT_CERTIFY_WORKSPACE 16384u
+
 /* Options.  Zero in any field selects the default shown. */
 typedef struct msplit_options {
     uint32_t struct_size;     /* sizeof(msplit_options) */
@@ -169,8 +173,9 @@ int msplit_misiurewicz(int l, int n, const msplit_options *opts, void *workspace
  * FP64 with round-to-nearest and explicit radius inflation).  Reads re, im
  * (and period for p_n labels); writes flags (MSPLIT_R_*) and radius.  The
  * list must be sorted by increasing real part for the separation check.
- * stats (nullable) receives certified, label_proven, overlaps, min_sep,
- * max_radius, n_real, total. */
+ * workspace: device memory of at least MSPLIT_CERTIFY_WORKSPACE bytes, else
+ * MSPLIT_E_WORKSPACE.  stats (nullable) receives certified, label_proven,
+ * overlaps, min_sep and max_radius. */
 int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *workspace,
                    uint64_t workspace_bytes, msplit_stats *stats, void *stream);
 

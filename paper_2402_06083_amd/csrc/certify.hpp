@@ -168,6 +168,7 @@ __device__ cert_result certify_root(int l, int n, int lab, uint32_t divmask_n, c
 __global__ void k_certify(batch_args b, const double *re, const double *im, const int32_t *period, uint8_t *flags,
                           double *radius, int64_t n_uniq)
 {
+    unsigned long long *const wc = wave_ctr(b);
     type_count nc, nl;
     type_cache tc;
     unsigned long long rbits = 0;
@@ -176,10 +177,10 @@ __global__ void k_certify(batch_args b, const double *re, const double *im, cons
         const int64_t u = u0 + threadIdx.x;
         const int t = u < n_uniq ? cached_type(tc, b.uniq_offs, b.T, u) : nc.t;
         if (__ballot(u < n_uniq && t != nc.t)) {
-            flush_count(b.ctr, C_CERTIFIED, nc);
-            flush_count(b.ctr, C_LABEL, nl);
+            flush_count(wc, C_CERTIFIED, nc);
+            flush_count(wc, C_LABEL, nl);
             // non-negative doubles order like their bit patterns
-            wave_reduce_by_key<RED_MAX>(b.ctr, C_NCOUNTERS, C_MAX_RAD_BITS, rbits ? nc.t : -1, rbits);
+            wave_reduce_by_key<RED_MAX>(wc, C_NCOUNTERS, C_MAX_RAD_BITS, rbits ? nc.t : -1, rbits);
             rbits = 0;
         }
         nc.t = nl.t = t;
@@ -198,9 +199,9 @@ __global__ void k_certify(batch_args b, const double *re, const double *im, cons
             rbits = bits > rbits ? bits : rbits;
         }
     }
-    flush_count(b.ctr, C_CERTIFIED, nc);
-    flush_count(b.ctr, C_LABEL, nl);
-    wave_reduce_by_key<RED_MAX>(b.ctr, C_NCOUNTERS, C_MAX_RAD_BITS, rbits ? nc.t : -1, rbits);
+    flush_count(wc, C_CERTIFIED, nc);
+    flush_count(wc, C_LABEL, nl);
+    wave_reduce_by_key<RED_MAX>(wc, C_NCOUNTERS, C_MAX_RAD_BITS, rbits ? nc.t : -1, rbits);
 }
 
 // Thm certif, global part, on each type's list (sorted by real part):
@@ -214,6 +215,7 @@ __global__ void k_certify(batch_args b, const double *re, const double *im, cons
 // roots, are adjacent in that order).  radius == nullptr: only the statistic.
 __global__ void k_separation(batch_args b, const double *re, const double *im, const double *radius, int64_t n_uniq)
 {
+    unsigned long long *const wc = wave_ctr(b);
     type_count bad;
     type_cache tc;
     unsigned long long sbits = ~0ull;
@@ -222,8 +224,8 @@ __global__ void k_separation(batch_args b, const double *re, const double *im, c
         const int64_t u = u0 + threadIdx.x;
         const int t = u < n_uniq ? cached_type(tc, b.uniq_offs, b.T, u) : bad.t;
         if (__ballot(u < n_uniq && t != bad.t)) {
-            flush_count(b.ctr, C_OVERLAP, bad);
-            wave_reduce_by_key<RED_MIN>(b.ctr, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);
+            flush_count(wc, C_OVERLAP, bad);
+            wave_reduce_by_key<RED_MIN>(wc, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);
             sbits = ~0ull;
         }
         bad.t = t;
@@ -255,8 +257,8 @@ __global__ void k_separation(batch_args b, const double *re, const double *im, c
             sbits = bits < sbits ? bits : sbits;
         }
     }
-    flush_count(b.ctr, C_OVERLAP, bad);
-    wave_reduce_by_key<RED_MIN>(b.ctr, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);
+    flush_count(wc, C_OVERLAP, bad);
+    wave_reduce_by_key<RED_MIN>(wc, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);
 }
 
 } // namespace msplit

@@ -30,6 +30,19 @@ __device__ __forceinline__ cd cdiv(cd a, cd b)
 }
 __device__ __forceinline__ bool cfinite(cd a) { return isfinite(a.re) && isfinite(a.im); }
 
+// a / b for the Newton updates: the hardware reciprocal of |b|^2 refined by
+// one Newton-Raphson step (relative error ~1e-16: the iteration needs no
+// correctly rounded quotient), with the power-of-two scaling of cdiv only
+// when |b|^2 leaves [2^-1000, 2^1000].
+__device__ __forceinline__ cd cdiv_fast(cd a, cd b)
+{
+    const double d2 = cabs2(b);
+    if (!(d2 >= 0x1p-1000 && d2 <= 0x1p1000)) return cdiv(a, b);
+    double r = __builtin_amdgcn_rcp(d2);
+    r = fma(fma(-d2, r, 1.0), r, r);
+    return {(a.re * b.re + a.im * b.im) * r, (a.im * b.re - a.re * b.im) * r};
+}
+
 // Approximation u(w) of log w for the Newton iteration on log P (the step
 // z += u(T/P) P/P').  It only has to be exact at the fixed point w = 1 and
 // close enough elsewhere to keep the iteration contracting, so no
@@ -97,6 +110,15 @@ __device__ __forceinline__ void eval_q(int l, int N, cd c, cd &P, cd &dP)
     for (; k < N; ++k) orbit_step(s, c.re, c.im);
     P = {s.zr - zl.re, s.zi - zl.im};
     dP = {s.dr - dzl.re, s.di - dzl.im};
+}
+
+// Same evaluation; when every active lane of the wave has the same (l, N)
+// the trip counts are made wave-uniform (scalar loop control).
+__device__ __forceinline__ void eval_q_wave(int l, int N, cd c, cd &P, cd &dP)
+{
+    const int l0 = __builtin_amdgcn_readfirstlane(l), N0 = __builtin_amdgcn_readfirstlane(N);
+    if (__ballot(l != l0 || N != N0) == 0) eval_q(l0, N0, c, P, dP);
+    else eval_q(l, N, c, P, dP);
 }
 
 __device__ __forceinline__ void eval_q_f32(int l, int N, cf c, cf &P, cf &dP)
@@ -191,4 +213,13 @@ __device__ __forceinline__ uint64_t orderable(double x)
     return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
 }
 
+} // namespace msplit
+
+namespace msplit {
+__device__ __forceinline__ void eval_q_f32_wave(int l, int N, cf c, cf &P, cf &dP)
+{
+    const int l0 = __builtin_amdgcn_readfirstlane(l), N0 = __builtin_amdgcn_readfirstlane(N);
+    if (__ballot(l != l0 || N != N0) == 0) eval_q_f32(l0, N0, c, P, dP);
+    else eval_q_f32(l, N, c, P, dP);
+}
 } // namespace msplit

@@ -32,7 +32,7 @@ namespace msplit {
 enum : uint8_t { ST_NONE = 0, ST_CONVERGED = 1, ST_DIVERGED = 2, ST_TIMEOUT = 3 };
 
 // global counters
-enum { G_SEG_NEXT = 0, G_START_NEXT, G_NCOUNTERS = 8 };
+enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_NCOUNTERS = 8 };
 // per-type counters (uint64 slots, C_NCOUNTERS per type)
 enum {
     C_CONVERGED = 0, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL, C_SEED_FAIL, C_STEPS_LIFT, C_STEPS_WALK,
@@ -71,9 +71,24 @@ struct batch_args {
     int T;
     int64_t n_seeds, n_segs, n_starts;
     uint32_t chunk_seg, chunk_start;
-    unsigned long long *gctr; // global counters
-    unsigned long long *ctr;  // T x C_NCOUNTERS
+    unsigned long long *gctr;   // global counters
+    unsigned long long *ctr;    // T x C_NCOUNTERS, folded from spread
+    unsigned long long *spread; // CTR_SPREAD copies of T x C_NCOUNTERS
 };
+
+// Waves add their per-type counts into one of CTR_SPREAD copies of the
+// counter table (chosen by wave index) and a fold kernel combines the copies.
+// With one table every wave of the grid flushes into the same few addresses
+// at the same moment (when the work queue crosses from one type to the next,
+// and at the end): those atomics serialise and stall every wave on its next
+// memory wait.
+constexpr int CTR_SPREAD = 64;
+
+__device__ __forceinline__ unsigned long long *wave_ctr(const batch_args &b)
+{
+    const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    return b.spread + (size_t)(w & (CTR_SPREAD - 1)) * (size_t)b.T * C_NCOUNTERS;
+}
 
 // cis(2 pi s / M) for s = 0..M-1, M <= 64, set by the host
 __constant__ double c_cis_re[64];
@@ -136,6 +151,7 @@ __device__ __forceinline__ int cached_type(type_cache &c, const int64_t *offs, i
 // lane's type changes and at the end (a few atomics per wave in all).
 __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
 {
+    unsigned long long *const wc = wave_ctr(b);
     type_count steps, fail;
     type_cache tc;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -143,8 +159,8 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
         const int64_t g = g0 + threadIdx.x;
         const int t = g < b.n_seeds ? cached_type(tc, b.seed_offs, b.T, g) : steps.t;
         if (__ballot(g < b.n_seeds && t != steps.t)) {
-            flush_count(b.ctr, C_STEPS_LIFT, steps);
-            flush_count(b.ctr, C_SEED_FAIL, fail);
+            flush_count(wc, C_STEPS_LIFT, steps);
+            flush_count(wc, C_SEED_FAIL, fail);
         }
         steps.t = fail.t = t;
         if (g >= b.n_seeds) continue;
@@ -190,8 +206,8 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
         seeds[g] = z;
         starts[b.types[t].start_off + j * (pl.F / pl.q)] = z;
     }
-    flush_count(b.ctr, C_STEPS_LIFT, steps);
-    flush_count(b.ctr, C_SEED_FAIL, fail);
+    flush_count(wc, C_STEPS_LIFT, steps);
+    flush_count(wc, C_SEED_FAIL, fail);
 }
 
 // --------------------------------------------------------- level-line walk
@@ -205,6 +221,7 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
 // target is aimed from the actual value, so no error accumulates.
 __global__ void k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag)
 {
+    unsigned long long *const wc = wave_ctr(b);
     const double tol2 = 0x1p-10;
     type_count steps, pfail;
     int64_t g = -1; // current segment (global)
@@ -252,21 +269,21 @@ __global__ void k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_f
         }
         // per-type counters flush when a lane's type changes
         if (__ballot(change)) {
-            flush_count(b.ctr, C_STEPS_WALK, steps);
-            flush_count(b.ctr, C_PHASE_FAIL, pfail);
+            flush_count(wc, C_STEPS_WALK, steps);
+            flush_count(wc, C_PHASE_FAIL, pfail);
         }
         if (change) { steps.t = t; pfail.t = t; }
         if (__ballot(!done) == 0) break;
         if (done) continue;
         cd P, dP;
-        eval_q(pl_l, pl_N, z, P, dP);
+        eval_q_wave(pl_l, pl_N, z, P, dP);
         ++steps.v;
         const int r = (int)(s % pl_M);
         const cd T = {pl_level * c_cis_re[r], pl_level * c_cis_im[r]};
-        cd w = cdiv(T, P);
+        cd w = cdiv_fast(T, P);
         const cd v = {w.re - 1.0, w.im};
         const double a2 = cabs2(v);
-        const cd step = cdiv(P, dP);
+        const cd step = cdiv_fast(P, dP);
         if (!cfinite(w) || !cfinite(step) || it > 24) {
             seg_flag[g] = 2;
             ++pfail.v;
@@ -297,8 +314,8 @@ __global__ void k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_f
             z = cadd(z, h);
         }
     }
-    flush_count(b.ctr, C_STEPS_WALK, steps);
-    flush_count(b.ctr, C_PHASE_FAIL, pfail);
+    flush_count(wc, C_STEPS_WALK, steps);
+    flush_count(wc, C_PHASE_FAIL, pfail);
 }
 
 // ---------------------------------------------------------- Newton descent
@@ -307,22 +324,28 @@ __global__ void k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_f
 // M, which lies in D(0,2) u {-2}), or a long-distance jump (step more than 8
 // times the previous one after the third step, Section 6.4.3).  Converged
 // when the step falls below tol * max(|z|, 2^-8); one more step is taken.
-// MIXED precision: the descent starts in FP32 and a lane moves to FP64 once
-// its FP32 step is below fp32_switch * |z| (or FP32 overflows): FP32 only
-// covers the steps whose rounding error is far below the step itself.
-__global__ void k_descend(batch_args b, cd *roots, uint8_t *status)
+//
+// MIXED precision runs k_descend32 first over all starts: FP32 Newton steps
+// while the step exceeds fp32_switch * max(|z|, 2^-8).  The rounding noise of
+// an FP32 Newton step of p_n is about 8 u |z| (the orbit's error grows like
+// its derivative), far below that threshold, so FP32 only takes the steps it
+// resolves.  A start whose first FP32 step is already below the threshold --
+// near the tip of M, where FP32 cannot even tell neighbouring starts apart --
+// keeps its FP64 value untouched.  The FP64 pass then continues every start
+// not discarded in FP32, counting the FP32 steps against the cap.  Each pass
+// is precision-uniform, so no wave runs both code paths.
+__global__ void k_descend32(batch_args b, cd *roots, uint8_t *status, uint8_t *iters)
 {
-    type_count steps, steps32, nconv, ndiv, ntime;
+    unsigned long long *const wc = wave_ctr(b);
+    type_count steps32, ndiv, ntime;
     int64_t g = -1;
     int t = -1;
-    // the fields of the current type's plan that the descent uses
-    int pl_l = 0, pl_N = 1, pl_cap = 20, pl_prec = 0;
-    double pl_tol2 = 0.0;
+    int pl_l = 0, pl_N = 1, pl_cap = 20;
     float pl_sw = 0.f;
-    cd z = {0.0, 0.0};
-    double prev = 0.0; // previous squared step length
+    cf z = {0.f, 0.f};
+    float prev = 0.f; // previous squared step length
     int it = 0;
-    bool fin = false, done = false, f32 = false;
+    bool done = false;
     wave_queue wq = {0, 0};
     type_cache tc;
     while (true) {
@@ -341,72 +364,141 @@ __global__ void k_descend(batch_args b, cd *roots, uint8_t *status)
                     pl_l = pl.l;
                     pl_N = pl.N;
                     pl_cap = pl.cap;
-                    pl_prec = pl.precision;
-                    pl_tol2 = pl.tol_desc * pl.tol_desc;
                     pl_sw = pl.fp32_switch;
                 }
-                change = steps.t != t;
-                z = roots[g];
+                change = steps32.t != t;
+                const cd zd = roots[g];
+                z = {(float)zd.re, (float)zd.im};
                 it = 0;
-                prev = 0.0;
-                fin = false;
-                f32 = pl_prec == 1;
+                prev = 0.f;
             }
         }
         if (__ballot(change)) {
-            flush_count(b.ctr, C_STEPS_DESC, steps);
-            flush_count(b.ctr, C_STEPS_FP32, steps32);
-            flush_count(b.ctr, C_CONVERGED, nconv);
-            flush_count(b.ctr, C_DIVERGED, ndiv);
-            flush_count(b.ctr, C_TIMEOUT, ntime);
+            flush_count(wc, C_STEPS_FP32, steps32);
+            flush_count(wc, C_DIVERGED, ndiv);
+            flush_count(wc, C_TIMEOUT, ntime);
         }
-        if (change) steps.t = steps32.t = nconv.t = ndiv.t = ntime.t = t;
+        if (change) steps32.t = ndiv.t = ntime.t = t;
         if (__ballot(!done) == 0) break;
         if (done) continue;
+        cf P, dP;
+        eval_q_f32_wave(pl_l, pl_N, z, P, dP);
+        ++steps32.v;
+        const float den = dP.re * dP.re + dP.im * dP.im;
+        const float rd = __builtin_amdgcn_rcpf(den);
+        const float sr = (P.re * dP.re + P.im * dP.im) * rd;
+        const float si = (P.im * dP.re - P.re * dP.im) * rd;
+        const float a2 = sr * sr + si * si;
+        const float az2 = z.re * z.re + z.im * z.im;
         uint8_t st = ST_NONE;
-        if (f32) {
-            const cf c = {(float)z.re, (float)z.im};
-            cf P, dP;
-            eval_q_f32(pl_l, pl_N, c, P, dP);
-            ++steps32.v;
-            const float den = dP.re * dP.re + dP.im * dP.im;
-            const float rd = __frcp_rn(den);
-            const float sr = (P.re * dP.re + P.im * dP.im) * rd;
-            const float si = (P.im * dP.re - P.re * dP.im) * rd;
-            const float a2 = sr * sr + si * si;
-            const float ac2 = c.re * c.re + c.im * c.im;
-            const float sw = pl_sw;
-            if (!isfinite(a2) || !(den > 0.f) || !isfinite(den) || a2 <= sw * sw * fmaxf(ac2, 0x1p-16f)) {
-                // FP32 is done (or cannot resolve this point): FP64 takes
-                // over from the current point without this step
-                f32 = false;
-            } else {
-                const float zr = c.re - sr, zi = c.im - si;
-                ++it;
-                z = {(double)zr, (double)zi};
-                const float az2 = zr * zr + zi * zi;
-                if (!isfinite(zr) || !isfinite(zi) || az2 > 64.f) st = ST_DIVERGED;
-                else if (it > 3 && a2 > 64.f * (float)prev) st = ST_DIVERGED;
-                else if (it >= pl_cap) st = ST_TIMEOUT;
-                prev = a2;
-            }
+        bool handoff = false;
+        if (!isfinite(a2) || !(den > 0.f) || !isfinite(den) || a2 <= pl_sw * pl_sw * fmaxf(az2, 0x1p-16f)) {
+            handoff = true; // FP64 continues from the last applied step
         } else {
-            cd P, dP;
-            eval_q(pl_l, pl_N, z, P, dP);
-            ++steps.v;
-            const cd d = cdiv(P, dP);
-            z = csub(z, d);
+            z = {z.re - sr, z.im - si};
             ++it;
-            // squared lengths: |d| and |z| compared without square roots
-            const double a2 = cabs2(d);
-            const double az2 = cabs2(z);
-            if (fin) st = ST_CONVERGED;
-            else if (!isfinite(a2) || !cfinite(z) || az2 > 64.0) st = ST_DIVERGED;
-            else if (it > 3 && a2 > 64.0 * prev) st = ST_DIVERGED;
-            else if (a2 <= pl_tol2 * fmax(az2, 0x1p-16)) fin = true;
+            const float zz = z.re * z.re + z.im * z.im;
+            if (!isfinite(zz) || zz > 64.f) st = ST_DIVERGED;
+            else if (it > 3 && a2 > 64.f * prev) st = ST_DIVERGED;
             else if (it >= pl_cap) st = ST_TIMEOUT;
             prev = a2;
         }
+        if (handoff || st != ST_NONE) {
+            if (it > 0) roots[g] = {(double)z.re, (double)z.im};
+            status[g] = st;
+            iters[g] = (uint8_t)it;
+            ndiv.v += st == ST_DIVERGED;
+            ntime.v += st == ST_TIMEOUT;
+            g = -1;
+        }
+    }
+    flush_count(wc, C_STEPS_FP32, steps32);
+    flush_count(wc, C_DIVERGED, ndiv);
+    flush_count(wc, C_TIMEOUT, ntime);
+}
+
+// iters == nullptr: FP64 from the start.  Otherwise the FP32 pass ran: starts
+// it discarded keep their status, the others resume with their step count.
+// Each lane keeps one start of lookahead (index and value loaded one
+// iteration ahead), so the load latency of the next start is hidden behind
+// the current Newton step instead of stalling the wave whenever one of its
+// lanes finishes.
+__global__ void k_descend(batch_args b, cd *roots, uint8_t *status, const uint8_t *iters)
+{
+    unsigned long long *const wc = wave_ctr(b);
+    type_count steps, nconv, ndiv, ntime;
+    int64_t g = -1, gn = -1; // current start, prefetched start
+    cd zn = {0.0, 0.0};
+    int itn = 0;
+    bool exhausted = false;
+    int t = -1;
+    int pl_l = 0, pl_N = 1, pl_cap = 20;
+    double pl_tol2 = 0.0;
+    cd z = {0.0, 0.0};
+    double prev = 0.0; // previous squared step length
+    int it = 0, it0 = 0;
+    bool fin = false;
+    wave_queue wq = {0, 0};
+    type_cache tc;
+    unsigned long long *counter = &b.gctr[iters ? G_START_NEXT2 : G_START_NEXT];
+    while (true) {
+        // refill the lookahead
+        const bool need = !exhausted && gn < 0;
+        const uint64_t got = wave_take(wq, counter, b.chunk_start, need);
+        if (need) {
+            if (got >= (uint64_t)b.n_starts) {
+                exhausted = true;
+            } else if (!(iters && status[got] != ST_NONE)) { // else: discarded by the FP32 pass
+                gn = (int64_t)got;
+                zn = roots[gn];
+                itn = iters ? iters[gn] : 0;
+            }
+        }
+        // an idle lane takes the prefetched start
+        bool change = false;
+        if (g < 0 && gn >= 0) {
+            g = gn;
+            gn = -1;
+            const int t1 = cached_type(tc, b.start_offs, b.T, g);
+            if (t1 != t) {
+                t = t1;
+                const plan_t &pl = b.types[t].p;
+                pl_l = pl.l;
+                pl_N = pl.N;
+                pl_cap = pl.cap;
+                pl_tol2 = pl.tol_desc * pl.tol_desc;
+            }
+            change = steps.t != t;
+            z = zn;
+            it0 = it = itn;
+            prev = 0.0;
+            fin = false;
+        }
+        if (__ballot(change)) {
+            flush_count(wc, C_STEPS_DESC, steps);
+            flush_count(wc, C_CONVERGED, nconv);
+            flush_count(wc, C_DIVERGED, ndiv);
+            flush_count(wc, C_TIMEOUT, ntime);
+        }
+        if (change) steps.t = nconv.t = ndiv.t = ntime.t = t;
+        if (__ballot(g >= 0 || !exhausted || gn >= 0) == 0) break;
+        if (g < 0) continue;
+        cd P, dP;
+        eval_q_wave(pl_l, pl_N, z, P, dP);
+        ++steps.v;
+        const cd d = cdiv_fast(P, dP);
+        z = csub(z, d);
+        ++it;
+        // squared lengths: |d| and |z| compared without square roots
+        const double a2 = cabs2(d);
+        const double az2 = cabs2(z);
+        uint8_t st = ST_NONE;
+        if (fin) st = ST_CONVERGED;
+        else if (!isfinite(a2) || !cfinite(z) || az2 > 64.0) st = ST_DIVERGED;
+        else if (it > it0 + 3 && a2 > 64.0 * prev) st = ST_DIVERGED;
+        else if (a2 <= pl_tol2 * fmax(az2, 0x1p-16)) fin = true;
+        else if (it >= pl_cap) st = ST_TIMEOUT;
+        prev = a2;
         if (st != ST_NONE) {
             roots[g] = z;
             status[g] = st;
@@ -416,11 +508,10 @@ __global__ void k_descend(batch_args b, cd *roots, uint8_t *status)
             g = -1;
         }
     }
-    flush_count(b.ctr, C_STEPS_DESC, steps);
-    flush_count(b.ctr, C_STEPS_FP32, steps32);
-    flush_count(b.ctr, C_CONVERGED, nconv);
-    flush_count(b.ctr, C_DIVERGED, ndiv);
-    flush_count(b.ctr, C_TIMEOUT, ntime);
+    flush_count(wc, C_STEPS_DESC, steps);
+    flush_count(wc, C_CONVERGED, nconv);
+    flush_count(wc, C_DIVERGED, ndiv);
+    flush_count(wc, C_TIMEOUT, ntime);
 }
 
 // -------------------------------------------------------- nset collection
@@ -502,7 +593,8 @@ __global__ void k_mark(batch_args b, const cd *roots, const uint64_t *keys, cons
 }
 
 // Per type: first sorted index (lower bound of the type's key range, T + 1
-// entries in tb) and the number of unique roots in ctr[t][C_UNIQUE].
+// entries in tb) and the number of unique roots in C_UNIQUE of the first
+// counter copy (the fold adds the copies).
 // One block of at least T + 1 threads.
 __global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t *flag, const uint32_t *pos,
                               int64_t m, int64_t *tb)
@@ -520,7 +612,7 @@ __global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t
     __syncthreads();
     if (t < b.T) {
         auto pos_at = [&](int64_t i) -> uint64_t { return i < m ? pos[i] : (m ? pos[m - 1] + flag[m - 1] : 0); };
-        b.ctr[(int64_t)t * C_NCOUNTERS + C_UNIQUE] = pos_at(tb[t + 1]) - pos_at(tb[t]);
+        b.spread[(int64_t)t * C_NCOUNTERS + C_UNIQUE] = pos_at(tb[t + 1]) - pos_at(tb[t]);
     }
 }
 
@@ -528,13 +620,14 @@ __global__ void k_scatter(batch_args b, const cd *roots, const uint64_t *keys, c
                           const uint32_t *flag, const uint32_t *pos, const int64_t *tb, int64_t m, double *ore,
                           double *oim)
 {
+    unsigned long long *const wc = wave_ctr(b);
     type_count nreal;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < m && flag[i];
         const int t = act ? (int)(keys[i] >> 57) : nreal.t;
-        if (__ballot(act && t != nreal.t)) flush_count(b.ctr, C_REAL, nreal);
+        if (__ballot(act && t != nreal.t)) flush_count(wc, C_REAL, nreal);
         nreal.t = t;
         if (!act) continue;
         const type_desc &td = b.types[t];
@@ -546,7 +639,7 @@ __global__ void k_scatter(batch_args b, const cd *roots, const uint64_t *keys, c
         }
         nreal.v += z.im == 0.0;
     }
-    flush_count(b.ctr, C_REAL, nreal);
+    flush_count(wc, C_REAL, nreal);
 }
 
 // ---------------------------------------------------------- classification

@@ -167,12 +167,12 @@ int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uin
 
 // ------------------------------------------------------------- workspace
 struct layout {
-    size_t gctr, ctr, types, offs, tb, seeds, starts, status, segf, flag0, pos0, keys, vals, keys2, vals2, flag,
-        pos, temp, total;
+    size_t gctr, ctr, spread, types, offs, tb, seeds, starts, status, iters, segf, flag0, pos0, keys, vals, keys2, vals2,
+        flag, pos, temp, total;
     size_t temp_bytes;
 };
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 hipError_t rocprim_temp(int64_t n, size_t &bytes)
 {
@@ -195,12 +195,14 @@ layout make_layout(const batch_plan &bp, size_t temp_bytes)
     const size_t T = (size_t)bp.T, NS = (size_t)bp.n_starts;
     L.gctr = take(sizeof(unsigned long long) * G_NCOUNTERS);
     L.ctr = take(sizeof(unsigned long long) * C_NCOUNTERS * T);
+    L.spread = take(sizeof(unsigned long long) * C_NCOUNTERS * T * CTR_SPREAD);
     L.types = take(sizeof(type_desc) * T);
     L.offs = take(sizeof(int64_t) * 4 * (T + 1));
     L.tb = take(sizeof(int64_t) * (T + 1));
     L.seeds = take(sizeof(cd) * bp.n_seeds);
     L.starts = take(sizeof(cd) * NS);
     L.status = take(NS);
+    L.iters = take(NS);
     L.segf = take(bp.n_segs);
     L.flag0 = take(4 * NS);
     L.pos0 = take(4 * NS);
@@ -232,12 +234,34 @@ __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
-// counters: zero; per-type minimum-separation slot at +inf
-__global__ void k_init_counters(unsigned long long *gctr, unsigned long long *ctr, int T)
+// counters: zero; per-type minimum-separation slot at +inf (every copy)
+__device__ __forceinline__ unsigned long long ctr_identity(int slot)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    return slot == C_MIN_SEP_BITS ? 0x7ff0000000000000ull : 0ull;
+}
+__global__ void k_init_counters(unsigned long long *gctr, unsigned long long *ctr, unsigned long long *spread, int T)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < G_NCOUNTERS) gctr[i] = 0;
-    if (i < T * C_NCOUNTERS) ctr[i] = (i % C_NCOUNTERS == C_MIN_SEP_BITS) ? 0x7ff0000000000000ull : 0ull;
+    if (i < T * C_NCOUNTERS) ctr[i] = ctr_identity(i % C_NCOUNTERS);
+    if (i < T * C_NCOUNTERS * CTR_SPREAD) spread[i] = ctr_identity(i % C_NCOUNTERS);
+}
+// ctr = the copies combined: sums, except the largest radius (max) and the
+// least separation (min); non-negative doubles order like their bit patterns
+__global__ void k_fold_counters(unsigned long long *ctr, const unsigned long long *spread, int T)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = T * C_NCOUNTERS;
+    if (i >= n) return;
+    const int slot = i % C_NCOUNTERS;
+    unsigned long long a = spread[i];
+    for (int k = 1; k < CTR_SPREAD; ++k) {
+        const unsigned long long v = spread[(size_t)k * n + i];
+        if (slot == C_MAX_RAD_BITS) a = v > a ? v : a;
+        else if (slot == C_MIN_SEP_BITS) a = v < a ? v : a;
+        else a += v;
+    }
+    ctr[i] = a;
 }
 __global__ void k_unzip(const cd *z, double *re, double *im, int64_t n)
 {
@@ -352,12 +376,14 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     char *ws = (char *)workspace;
     unsigned long long *gctr = (unsigned long long *)(ws + L.gctr);
     unsigned long long *ctr = (unsigned long long *)(ws + L.ctr);
+    unsigned long long *spread = (unsigned long long *)(ws + L.spread);
     type_desc *dtypes = (type_desc *)(ws + L.types);
     int64_t *doffs = (int64_t *)(ws + L.offs);
     int64_t *tb = (int64_t *)(ws + L.tb);
     cd *seeds = (cd *)(ws + L.seeds);
     cd *starts = (cd *)(ws + L.starts);
     uint8_t *status = (uint8_t *)(ws + L.status);
+    uint8_t *iters = (uint8_t *)(ws + L.iters);
     uint8_t *segf = (uint8_t *)(ws + L.segf);
     uint32_t *flag0 = (uint32_t *)(ws + L.flag0), *pos0 = (uint32_t *)(ws + L.pos0);
     uint64_t *keys = (uint64_t *)(ws + L.keys), *keys2 = (uint64_t *)(ws + L.keys2);
@@ -393,6 +419,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     ba.chunk_start = chunk_for(bp.n_starts);
     ba.gctr = gctr;
     ba.ctr = ctr;
+    ba.spread = spread;
 
     events ev;
     for (int i = 0; i < 7; ++i) {
@@ -400,7 +427,8 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         ev.made = i + 1;
     }
     CHK(hipEventRecord(ev.e[0], stream));
-    k_init_counters<<<blocks_for((int64_t)T * C_NCOUNTERS + G_NCOUNTERS, 256), 256, 0, stream>>>(gctr, ctr, T);
+    k_init_counters<<<blocks_for((int64_t)T * C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
+        gctr, ctr, spread, T);
     k_fill_nan<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(starts, bp.n_starts);
     k_fill_u8<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(status, bp.n_starts, ST_NONE);
     // seeds: lift from the circle |p_1| = lambda_0
@@ -413,7 +441,10 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
 
     std::vector<unsigned long long> h((size_t)T * C_NCOUNTERS);
     auto read_counters = [&]() -> hipError_t {
-        hipError_t e = hipMemcpyAsync(h.data(), ctr, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+        k_fold_counters<<<blocks_for((int64_t)T * C_NCOUNTERS, 256), 256, 0, stream>>>(ctr, spread, T);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h.data(), ctr, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
                                       stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         return e;
@@ -442,8 +473,13 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         return stats && stats->phase_fail ? MSPLIT_E_INCOMPLETE : MSPLIT_OK;
     }
 
-    // descents
-    k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, status);
+    // descents (MIXED: an FP32 pass first)
+    if (opts->precision == MSPLIT_MIXED) {
+        k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, status, iters);
+        k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, status, iters);
+    } else {
+        k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, status, nullptr);
+    }
     CHK(hipEventRecord(ev.e[3], stream));
     // nset collection: local identification, compaction, sort, global
     // identification, per-type output slices
@@ -451,10 +487,10 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     size_t tb_bytes = temp_bytes;
     CHK(rocprim::exclusive_scan(temp, tb_bytes, flag0, pos0, 0u, (size_t)bp.n_starts, rocprim::plus<uint32_t>(),
                                 stream));
-    k_compact<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, starts, flag0, pos0, keys, vals, gctr + 2);
+    k_compact<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, starts, flag0, pos0, keys, vals, gctr + G_COMPACT);
     CHK(hipGetLastError());
     unsigned long long m_h = 0;
-    CHK(hipMemcpyAsync(&m_h, gctr + 2, sizeof(m_h), hipMemcpyDeviceToHost, stream));
+    CHK(hipMemcpyAsync(&m_h, gctr + G_COMPACT, sizeof(m_h), hipMemcpyDeviceToHost, stream));
     CHK(hipStreamSynchronize(stream));
     const int64_t m = (int64_t)m_h;
     if (m > 0) {
@@ -501,6 +537,8 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
             k_certify<<<persistent_blocks(n_uniq, 128), 128, 0, stream>>>(
                 ba, out->re, out->im, (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period, out->flags,
                 out->radius, n_uniq);
+            // k_separation reads the largest radius of each type
+            k_fold_counters<<<blocks_for((int64_t)T * C_NCOUNTERS, 256), 256, 0, stream>>>(ctr, spread, T);
             k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, out->radius, n_uniq);
         } else {
             k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, nullptr, n_uniq);
@@ -648,15 +686,22 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
     const uint64_t off = 0;
     int r = make_batch(ln, 1, defaults(), &off, &count, bp);
     if (r) return r;
-    size_t need = align256(sizeof(unsigned long long) * (G_NCOUNTERS + C_NCOUNTERS)) + align256(sizeof(type_desc)) +
-                  align256(sizeof(int64_t) * 8);
+    const size_t ctr_bytes = align256(sizeof(unsigned long long) * (G_NCOUNTERS + C_NCOUNTERS));
+    const size_t spread_bytes = align256(sizeof(unsigned long long) * C_NCOUNTERS * CTR_SPREAD);
+    const size_t need = ctr_bytes + spread_bytes + align256(sizeof(type_desc)) + align256(sizeof(int64_t) * 8);
+    static_assert(align256(sizeof(unsigned long long) * (G_NCOUNTERS + C_NCOUNTERS)) +
+                          align256(sizeof(unsigned long long) * C_NCOUNTERS * CTR_SPREAD) +
+                          align256(sizeof(type_desc)) + align256(sizeof(int64_t) * 8) <=
+                      MSPLIT_CERTIFY_WORKSPACE,
+                  "certify workspace");
     if (workspace_bytes < need) return MSPLIT_E_WORKSPACE;
     hipStream_t stream = (hipStream_t)stream_v;
     call_ctx ctx{stats, 1};
     char *ws = (char *)workspace;
     unsigned long long *gctr = (unsigned long long *)ws;
     unsigned long long *ctr = gctr + G_NCOUNTERS;
-    type_desc *dtypes = (type_desc *)(ws + align256(sizeof(unsigned long long) * (G_NCOUNTERS + C_NCOUNTERS)));
+    unsigned long long *spread = (unsigned long long *)(ws + ctr_bytes);
+    type_desc *dtypes = (type_desc *)(ws + ctr_bytes + spread_bytes);
     int64_t *doffs = (int64_t *)((char *)dtypes + align256(sizeof(type_desc)));
     const int64_t uo[2] = {0, (int64_t)count};
     CHK(hipMemcpyAsync(dtypes, bp.td.data(), sizeof(type_desc), hipMemcpyHostToDevice, stream));
@@ -668,13 +713,17 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
     ba.T = 1;
     ba.gctr = gctr;
     ba.ctr = ctr;
-    k_init_counters<<<1, 64, 0, stream>>>(gctr, ctr, 1);
+    ba.spread = spread;
+    k_init_counters<<<blocks_for((int64_t)C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
+        gctr, ctr, spread, 1);
     if (count) {
         k_certify<<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(ba, roots->re, roots->im, roots->period,
                                                                        roots->flags, roots->radius, (int64_t)count);
+        k_fold_counters<<<1, 64, 0, stream>>>(ctr, spread, 1);
         k_separation<<<persistent_blocks((int64_t)count, 256), 256, 0, stream>>>(ba, roots->re, roots->im, roots->radius,
                                                                           (int64_t)count);
     }
+    k_fold_counters<<<1, 64, 0, stream>>>(ctr, spread, 1);
     CHK(hipGetLastError());
     unsigned long long h[C_NCOUNTERS];
     CHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, stream));

@@ -18,6 +18,7 @@ OK, E_ARG, E_CAPACITY, E_WORKSPACE, E_DEVICE, E_INCOMPLETE, E_PRECISION, E_UNSUP
 FP64, MIXED, DD = 0, 1, 2
 F_CERTIFY, F_NO_LABEL = 1, 2
 R_REAL, R_CERTIFIED, R_LABEL = 1, 2, 4
+CERTIFY_WORKSPACE = 16384  # MSPLIT_CERTIFY_WORKSPACE
 
 
 class Options(ctypes.Structure):
@@ -237,11 +238,11 @@ def certify(l: int, n: int, re: torch.Tensor, im: torch.Tensor, period: torch.Te
     flags = torch.zeros(m, dtype=torch.uint8, device=dev)
     radius = torch.zeros(m, dtype=torch.float64, device=dev)
     per = period.contiguous().to(torch.int32) if period is not None else None
-    ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+    ws = torch.empty(CERTIFY_WORKSPACE, dtype=torch.uint8, device=dev)
     rs = RootsC(re.data_ptr(), im.data_ptr(), None, None, per.data_ptr() if per is not None else None, None,
                 flags.data_ptr(), radius.data_ptr(), m)
     st = Stats()
-    r = lib().msplit_certify(l, n, ctypes.byref(rs), m, ctypes.c_void_p(ws.data_ptr()), 4096, ctypes.byref(st),
+    r = lib().msplit_certify(l, n, ctypes.byref(rs), m, ctypes.c_void_p(ws.data_ptr()), CERTIFY_WORKSPACE, ctypes.byref(st),
                              _stream_handle(stream))
     if r:
         raise MsplitError(r, "msplit_certify")

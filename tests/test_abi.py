@@ -44,6 +44,18 @@ def test_struct_sizes_match_binding(lib):
     assert ctypes.sizeof(msplit.Stats) == 17 * 8 + 3 * 8 + 6 * 8 + 8
 
 
+def test_header_constants_match_binding():
+    from paper_2402_06083_amd import msplit
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+MSPLIT_CERTIFY_WORKSPACE\s+(\d+)u?", text)
+    assert m and int(m.group(1)) == msplit.CERTIFY_WORKSPACE
+    for name, val in [("MSPLIT_R_REAL", msplit.R_REAL), ("MSPLIT_R_CERTIFIED", msplit.R_CERTIFIED),
+                      ("MSPLIT_R_LABEL", msplit.R_LABEL), ("MSPLIT_F_CERTIFY", msplit.F_CERTIFY),
+                      ("MSPLIT_F_NO_LABEL", msplit.F_NO_LABEL), ("MSPLIT_E_WORKSPACE", msplit.E_WORKSPACE)]:
+        m = re.search(name + r"\s*=\s*(-?\d+)u?", text)
+        assert m and int(m.group(1)) == val, name
+
+
 def test_expected_counts_match_oracle_counts(lib):
     from paper_2402_06083_amd import msplit
     for n in range(1, 31):
