@@ -100,17 +100,47 @@ __device__ __forceinline__ void orbit_step(orbit_state<T> &s, T cr, T ci)
     s.zi = ni;
 }
 
-// P = q_{l,n}(c), dP = q_{l,n}'(c), N = l + n (l = 0: p_N)
-__device__ __forceinline__ void eval_q(int l, int N, cd c, cd &P, cd &dP)
+// The evaluation runs the same recurrence on u_k = 2 p_k (a scaling by 2,
+// exact in binary floating point): u_{k+1} = u_k^2 / 2 + 2c and
+// p'_{k+1} = u_k p'_k + 1.  Written with fused multiply-adds, one step is 2
+// multiplications and 6 FMAs -- 8 vector instructions for the 16 real flops
+// of the plain step, the FMA peak rate -- against 11 for the plain form
+// (which needs 2 z and 2 (z dz) as separate doublings).
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename T>
+struct orbit2_state { T ur, ui, dr, di; }; // u = 2 p_k, d = p_k'
+
+template <typename T>
+__device__ __forceinline__ void orbit2_step(orbit2_state<T> &s, T c4r, T c2i)
 {
-    orbit_state<double> s = {0.0, 0.0, 0.0, 0.0};
-    int k = 0;
-    for (; k < l; ++k) orbit_step(s, c.re, c.im);
-    cd zl = {s.zr, s.zi}, dzl = {s.dr, s.di};
-    for (; k < N; ++k) orbit_step(s, c.re, c.im);
-    P = {s.zr - zl.re, s.zi - zl.im};
-    dP = {s.dr - dzl.re, s.di - dzl.im};
+    const T ur = T(0.5) * fmat(s.ur, s.ur, fmat(-s.ui, s.ui, c4r));
+    const T ui = fmat(s.ur, s.ui, c2i);
+    const T dr = fmat(s.ur, s.dr, fmat(-s.ui, s.di, T(1)));
+    const T di = fmat(s.ur, s.di, s.ui * s.dr);
+    s.ur = ur;
+    s.ui = ui;
+    s.dr = dr;
+    s.di = di;
 }
+
+// P = q_{l,n}(c), dP = q_{l,n}'(c), N = l + n (l = 0: p_N)
+template <typename T, typename C>
+__device__ __forceinline__ void eval_q_t(int l, int N, C c, C &P, C &dP)
+{
+    orbit2_state<T> s = {T(0), T(0), T(0), T(0)};
+    const T c4r = T(4) * c.re, c2i = T(2) * c.im;
+    int k = 0;
+    for (; k < l; ++k) orbit2_step(s, c4r, c2i);
+    const orbit2_state<T> sl = s;
+#pragma unroll 2
+    for (; k < N; ++k) orbit2_step(s, c4r, c2i);
+    P = {T(0.5) * (s.ur - sl.ur), T(0.5) * (s.ui - sl.ui)};
+    dP = {s.dr - sl.dr, s.di - sl.di};
+}
+
+__device__ __forceinline__ void eval_q(int l, int N, cd c, cd &P, cd &dP) { eval_q_t<double>(l, N, c, P, dP); }
 
 // Same evaluation; when every active lane of the wave has the same (l, N)
 // the trip counts are made wave-uniform (scalar loop control).
@@ -121,16 +151,7 @@ __device__ __forceinline__ void eval_q_wave(int l, int N, cd c, cd &P, cd &dP)
     else eval_q(l, N, c, P, dP);
 }
 
-__device__ __forceinline__ void eval_q_f32(int l, int N, cf c, cf &P, cf &dP)
-{
-    orbit_state<float> s = {0.f, 0.f, 0.f, 0.f};
-    int k = 0;
-    for (; k < l; ++k) orbit_step(s, c.re, c.im);
-    cf zl = {s.zr, s.zi}, dzl = {s.dr, s.di};
-    for (; k < N; ++k) orbit_step(s, c.re, c.im);
-    P = {s.zr - zl.re, s.zi - zl.im};
-    dP = {s.dr - dzl.re, s.di - dzl.im};
-}
+__device__ __forceinline__ void eval_q_f32(int l, int N, cf c, cf &P, cf &dP) { eval_q_t<float>(l, N, c, P, dP); }
 
 // ---------------------------------------------------------- wave helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
