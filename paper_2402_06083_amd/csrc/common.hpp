@@ -164,22 +164,31 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 // distinct indices (possibly >= the item count: no work left).  chunk >= 64.
 struct wave_queue { uint64_t next, end; };
 
+// value of `x` in lane `lane` as a wave-uniform (scalar) value
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t x, int lane)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t wave_take(wave_queue &q, unsigned long long *counter, uint64_t chunk, bool need)
 {
-    unsigned long long mask = __ballot(need);
+    const unsigned long long mask = __ballot(need);
     uint64_t idx = ~0ull;
     if (!mask) return idx;
     const uint32_t cnt = (uint32_t)__popcll(mask);
-    const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
     const uint64_t avail = q.end - q.next;
     if (avail < cnt) {
         const int leader = __ffsll((unsigned long long)mask) - 1;
         unsigned long long b = 0;
         if (lane_id() == leader) b = atomicAdd(counter, (unsigned long long)chunk);
-        b = __shfl(b, leader);
-        if (need) idx = rank < avail ? q.next + rank : b + (rank - avail);
-        q.next = b + (cnt - avail);
-        q.end = b + chunk;
+        const uint64_t base = read_lane_u64(b, leader);
+        if (need) idx = rank < avail ? q.next + rank : base + (rank - avail);
+        q.next = base + (cnt - avail);
+        q.end = base + chunk;
     } else {
         if (need) idx = q.next + rank;
         q.next += cnt;
@@ -222,6 +231,35 @@ __device__ __forceinline__ void wave_reduce_by_key(unsigned long long *base, int
             if (OP == RED_ADD) atomicAdd(dst, v);
             else if (OP == RED_MAX) atomicMax(dst, v);
             else atomicMin(dst, v);
+        }
+        if (mine) pending = false;
+    }
+}
+
+// Four sums under one key per lane (same contract as wave_reduce_by_key):
+// one butterfly pass per distinct key, four atomics by its first lane into
+// base[key * stride + slot_i].
+__device__ __forceinline__ void wave_add4_by_key(unsigned long long *base, int stride, int key, const int slot[4],
+                                                 const uint32_t v[4])
+{
+    bool pending = key >= 0;
+    while (true) {
+        const unsigned long long pend = __ballot(pending);
+        if (!pend) break;
+        const int leader = __ffsll(pend) - 1;
+        const int k = __builtin_amdgcn_readlane(key, leader);
+        const bool mine = pending && key == k;
+        unsigned long long a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            unsigned long long x = mine ? (unsigned long long)v[i] : 0ull;
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+            a[i] = x;
+        }
+        if (lane_id() == leader) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (a[i]) atomicAdd(base + (int64_t)k * stride + slot[i], a[i]);
         }
         if (mine) pending = false;
     }

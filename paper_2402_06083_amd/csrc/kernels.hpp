@@ -419,19 +419,23 @@ __global__ void k_descend32(batch_args b, cd *roots, uint8_t *status, uint8_t *i
 
 // iters == nullptr: FP64 from the start.  Otherwise the FP32 pass ran: starts
 // it discarded keep their status, the others resume with their step count.
-// Each lane keeps one start of lookahead (index and value loaded one
-// iteration ahead), so the load latency of the next start is hidden behind
-// the current Newton step instead of stalling the wave whenever one of its
-// lanes finishes.
-__global__ void k_descend(batch_args b, cd *roots, uint8_t *status, const uint8_t *iters)
+// The lane state is kept small (32-bit start indices and type bounds, one
+// type tag for the four 32-bit counts, branch-free status selection) so that
+// the kernel fits 64 VGPRs: 8 waves per SIMD hide the load of a new start
+// and the FP64 dependency latency of the orbit loop.
+__global__ void __launch_bounds__(256) k_descend(batch_args b, cd *roots, uint8_t *status, const uint8_t *iters)
 {
+    constexpr uint32_t NONE = 0xffffffffu;
     unsigned long long *const wc = wave_ctr(b);
-    type_count steps, nconv, ndiv, ntime;
-    int64_t g = -1, gn = -1; // current start, prefetched start
-    cd zn = {0.0, 0.0};
-    int itn = 0;
+    const uint32_t n_starts = (uint32_t)b.n_starts;
+    // per-lane counts of type ct: steps, converged, diverged, timeouts
+    int ct = -1;
+    uint32_t cnt[4] = {0u, 0u, 0u, 0u};
+    const int slots[4] = {C_STEPS_DESC, C_CONVERGED, C_DIVERGED, C_TIMEOUT};
+    uint32_t g = NONE;
     bool exhausted = false;
     int t = -1;
+    uint32_t t_lo = 0, t_hi = 0;
     int pl_l = 0, pl_N = 1, pl_cap = 20;
     double pl_tol2 = 0.0;
     cd z = {0.0, 0.0};
@@ -439,79 +443,65 @@ __global__ void k_descend(batch_args b, cd *roots, uint8_t *status, const uint8_
     int it = 0, it0 = 0;
     bool fin = false;
     wave_queue wq = {0, 0};
-    type_cache tc;
     unsigned long long *counter = &b.gctr[iters ? G_START_NEXT2 : G_START_NEXT];
     while (true) {
-        // refill the lookahead
-        const bool need = !exhausted && gn < 0;
+        const bool need = !exhausted && g == NONE;
         const uint64_t got = wave_take(wq, counter, b.chunk_start, need);
         if (need) {
-            if (got >= (uint64_t)b.n_starts) {
+            if (got >= n_starts) {
                 exhausted = true;
             } else if (!(iters && status[got] != ST_NONE)) { // else: discarded by the FP32 pass
-                gn = (int64_t)got;
-                zn = roots[gn];
-                itn = iters ? iters[gn] : 0;
+                g = (uint32_t)got;
+                if (g < t_lo || g >= t_hi) {
+                    t = find_type(b.start_offs, b.T, g);
+                    t_lo = (uint32_t)b.start_offs[t];
+                    t_hi = (uint32_t)b.start_offs[t + 1];
+                    const plan_t &pl = b.types[t].p;
+                    pl_l = pl.l;
+                    pl_N = pl.N;
+                    pl_cap = pl.cap;
+                    pl_tol2 = pl.tol_desc * pl.tol_desc;
+                }
+                z = roots[g];
+                it0 = it = iters ? iters[g] : 0;
+                prev = 0.0;
+                fin = false;
             }
         }
-        // an idle lane takes the prefetched start
-        bool change = false;
-        if (g < 0 && gn >= 0) {
-            g = gn;
-            gn = -1;
-            const int t1 = cached_type(tc, b.start_offs, b.T, g);
-            if (t1 != t) {
-                t = t1;
-                const plan_t &pl = b.types[t].p;
-                pl_l = pl.l;
-                pl_N = pl.N;
-                pl_cap = pl.cap;
-                pl_tol2 = pl.tol_desc * pl.tol_desc;
-            }
-            change = steps.t != t;
-            z = zn;
-            it0 = it = itn;
-            prev = 0.0;
-            fin = false;
-        }
+        const bool change = g != NONE && t != ct;
         if (__ballot(change)) {
-            flush_count(wc, C_STEPS_DESC, steps);
-            flush_count(wc, C_CONVERGED, nconv);
-            flush_count(wc, C_DIVERGED, ndiv);
-            flush_count(wc, C_TIMEOUT, ntime);
+            // every lane flushes (and restarts) its counts
+            wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
+            cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0u;
+            if (change) ct = t;
         }
-        if (change) steps.t = nconv.t = ndiv.t = ntime.t = t;
-        if (__ballot(g >= 0 || !exhausted || gn >= 0) == 0) break;
-        if (g < 0) continue;
+        if (__ballot(g != NONE || !exhausted) == 0) break;
+        if (g == NONE) continue;
         cd P, dP;
         eval_q_wave(pl_l, pl_N, z, P, dP);
-        ++steps.v;
         const cd d = cdiv_fast(P, dP);
         z = csub(z, d);
         ++it;
-        // squared lengths: |d| and |z| compared without square roots
+        // squared lengths: |d| and |z| compared without square roots;
+        // a NaN or infinite value fails the <= tests
         const double a2 = cabs2(d);
         const double az2 = cabs2(z);
-        uint8_t st = ST_NONE;
-        if (fin) st = ST_CONVERGED;
-        else if (!isfinite(a2) || !cfinite(z) || az2 > 64.0) st = ST_DIVERGED;
-        else if (it > it0 + 3 && a2 > 64.0 * prev) st = ST_DIVERGED;
-        else if (a2 <= pl_tol2 * fmax(az2, 0x1p-16)) fin = true;
-        else if (it >= pl_cap) st = ST_TIMEOUT;
+        const bool bad = !(a2 <= 0x1p1000) || !(az2 <= 64.0) || (it > it0 + 3 && a2 > 64.0 * prev);
+        const bool small = a2 <= pl_tol2 * fmax(az2, 0x1p-16);
+        const uint8_t st = fin ? ST_CONVERGED : bad ? ST_DIVERGED : (!small && it >= pl_cap) ? ST_TIMEOUT : ST_NONE;
+        fin = small;
         prev = a2;
+        cnt[0] += 1u;
         if (st != ST_NONE) {
             roots[g] = z;
             status[g] = st;
-            nconv.v += st == ST_CONVERGED;
-            ndiv.v += st == ST_DIVERGED;
-            ntime.v += st == ST_TIMEOUT;
-            g = -1;
+            cnt[1] += st == ST_CONVERGED;
+            cnt[2] += st == ST_DIVERGED;
+            cnt[3] += st == ST_TIMEOUT;
+            g = NONE;
         }
     }
-    flush_count(wc, C_STEPS_DESC, steps);
-    flush_count(wc, C_CONVERGED, nconv);
-    flush_count(wc, C_DIVERGED, ndiv);
-    flush_count(wc, C_TIMEOUT, ntime);
+    wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
 }
 
 // -------------------------------------------------------- nset collection
