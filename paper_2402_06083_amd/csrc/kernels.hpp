@@ -215,70 +215,77 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
 // one update, so lanes never wait for each other inside a segment.  Fine point
 // s targets T_s = lambda_0 e^{2 i pi s / M}; the step towards it is Newton on
 // log P, z += log(T_s / P) P / P' (an Euler step of the level-line flow
-// lambda' = i P / P' of Section 4.1 with its correction).  A fine point is
-// accepted at |T_s / P - 1| < 2^-5, or when the update is at rounding level:
-// it only has to lie in the Newton basin of the next target, and the next
-// target is aimed from the actual value, so no error accumulates.
-__global__ void k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag)
+// lambda' = i P / P' of Section 4.1 with its correction).  A fine point that
+// becomes a start (every q-th) is accepted once |P / T_s - 1| < 2^-5, the
+// others at |T_s / P - 1| < 2^-2, or when the update is at rounding level:
+// an intermediate point only has to lie in the Newton basin of the next
+// target, and the next target is aimed from the actual value, so no error
+// accumulates.  Lane state is 32-bit (segment index, fine point within the
+// segment) to keep the kernel within 64 VGPRs.
+__global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag)
 {
+    constexpr uint32_t NONE = 0xffffffffu;
+    // |T/P - 1| < 2^-5 sqrt(0.9) keeps |P/T - 1| = |v| / |1 + v| below 2^-5
+    const double tol2_start = 0.9 * 0x1p-10, tol2_mid = 0x1p-4;
     unsigned long long *const wc = wave_ctr(b);
-    const double tol2 = 0x1p-10;
-    type_count steps, pfail;
-    int64_t g = -1; // current segment (global)
+    const uint32_t n_segs = (uint32_t)b.n_segs;
+    int ct = -1;
+    uint32_t cnt[4] = {0u, 0u, 0u, 0u}; // steps, phase failures
+    const int slots[4] = {C_STEPS_WALK, C_PHASE_FAIL, C_STEPS_WALK, C_STEPS_WALK};
+    uint32_t g = NONE; // current segment (global)
+    bool exhausted = false;
     int t = -1;
+    uint32_t t_lo = 0, t_hi = 0;
     // the fields of the current type's plan that the walk uses
-    int pl_l = 0, pl_N = 1, pl_M = 8, pl_q = 2;
-    int64_t pl_F = 1;
+    int pl_l = 0, pl_N = 1, pl_M = 8, pl_q = 2, pl_F = 1;
     double pl_level = 5.0;
-    int64_t s = 0, send = 0, sbase = 0, st_off = 0, segbase = 0;
+    uint32_t seed_j = 0;  // global index of the segment's first seed
+    uint32_t start0 = 0;  // global start index of fine point j F of the segment
+    int s = 0, r0 = 0;    // fine point within the segment (1..F); (j F) mod M
     int it = 0;
     cd z = {0.0, 0.0};
-    bool done = false;
     wave_queue wq = {0, 0};
-    type_cache tc;
     while (true) {
-        const bool need = !done && g < 0;
+        const bool need = !exhausted && g == NONE;
         const uint64_t got = wave_take(wq, &b.gctr[G_SEG_NEXT], b.chunk_seg, need);
-        bool change = false;
         if (need) {
-            if (got >= (uint64_t)b.n_segs) {
-                done = true;
+            if (got >= n_segs) {
+                exhausted = true;
             } else {
-                g = (int64_t)got;
-                const int t1 = cached_type(tc, b.seg_offs, b.T, g);
-                if (t1 != t) {
-                    t = t1;
+                g = (uint32_t)got;
+                if (g < t_lo || g >= t_hi) {
+                    t = find_type(b.seg_offs, b.T, g);
+                    t_lo = (uint32_t)b.seg_offs[t];
+                    t_hi = (uint32_t)b.seg_offs[t + 1];
                     const plan_t &pl = b.types[t].p;
                     pl_l = pl.l;
                     pl_N = pl.N;
                     pl_M = pl.M;
                     pl_q = pl.q;
-                    pl_F = pl.F;
+                    pl_F = (int)pl.F;
                     pl_level = pl.level;
-                    st_off = b.types[t].start_off;
-                    sbase = b.types[t].seed_off;
-                    segbase = b.seg_offs[t];
                 }
-                change = steps.t != t;
-                const int64_t j = g - segbase;
-                z = seeds[sbase + j];
-                s = j * pl_F + 1;
-                send = j * pl_F + pl_F;
+                const uint32_t j = g - t_lo;
+                seed_j = (uint32_t)b.types[t].seed_off + j;
+                start0 = (uint32_t)b.types[t].start_off + j * (uint32_t)(pl_F / pl_q);
+                r0 = (int)(((uint64_t)j * (uint64_t)pl_F) % (uint64_t)pl_M);
+                z = seeds[seed_j];
+                s = 1;
                 it = 0;
             }
         }
-        // per-type counters flush when a lane's type changes
+        const bool change = g != NONE && t != ct;
         if (__ballot(change)) {
-            flush_count(wc, C_STEPS_WALK, steps);
-            flush_count(wc, C_PHASE_FAIL, pfail);
+            wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
+            cnt[0] = cnt[1] = 0u;
+            if (change) ct = t;
         }
-        if (change) { steps.t = t; pfail.t = t; }
-        if (__ballot(!done) == 0) break;
-        if (done) continue;
+        if (__ballot(g != NONE || !exhausted) == 0) break;
+        if (g == NONE) continue;
         cd P, dP;
         eval_q_wave(pl_l, pl_N, z, P, dP);
-        ++steps.v;
-        const int r = (int)(s % pl_M);
+        cnt[0] += 1u;
+        const int r = (r0 + s) % pl_M;
         const cd T = {pl_level * c_cis_re[r], pl_level * c_cis_im[r]};
         cd w = cdiv_fast(T, P);
         const cd v = {w.re - 1.0, w.im};
@@ -286,24 +293,26 @@ __global__ void k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_f
         const cd step = cdiv_fast(P, dP);
         if (!cfinite(w) || !cfinite(step) || it > 24) {
             seg_flag[g] = 2;
-            ++pfail.v;
-            g = -1;
+            cnt[1] += 1u;
+            g = NONE;
             continue;
         }
         cd u0 = clog_near1(w);
         const cd h = cmul(u0, step);
-        if (a2 < tol2 || cabs2(h) <= 0x1p-96 * fmax(cabs2(z), 0x1p-16)) {
-            if (s == send) {
+        const bool is_start = (s % pl_q) == 0;
+        if (a2 < (is_start || s == pl_F ? tol2_start : tol2_mid) ||
+            cabs2(h) <= 0x1p-96 * fmax(cabs2(z), 0x1p-16)) {
+            if (s == pl_F) {
                 // the walk must end on the next seed (phase check): a skipped
                 // turn would land about 2 pi |P/P'| away
-                const cd e = csub(z, seeds[sbase + (g - segbase) + 1]);
+                const cd e = csub(z, seeds[seed_j + 1]);
                 const bool ok = cabs2(e) < 1e-2 * cabs2(step);
                 seg_flag[g] = ok ? 0 : 1;
-                pfail.v += !ok;
-                g = -1;
+                cnt[1] += !ok;
+                g = NONE;
                 continue;
             }
-            if ((s % pl_q) == 0) starts[st_off + s / pl_q] = z;
+            if (is_start) starts[start0 + (uint32_t)(s / pl_q)] = z;
             // aim at the next fine point: log(T_{s+1}/P) = i dphi + log(T_s/P)
             ++s;
             it = 0;
@@ -314,8 +323,7 @@ __global__ void k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_f
             z = cadd(z, h);
         }
     }
-    flush_count(wc, C_STEPS_WALK, steps);
-    flush_count(wc, C_PHASE_FAIL, pfail);
+    wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
 }
 
 // ---------------------------------------------------------- Newton descent
