@@ -123,6 +123,8 @@ typedef struct msplit_stats {
     uint64_t steps_walk;    /* ... in the level-line walk */
     uint64_t steps_desc;    /* ... in the descents */
     uint64_t steps_fp32;    /* ... of which in FP32 (MIXED) */
+    uint64_t sorted;        /* converged starts left after the local identification of
+                               consecutive starts: the entries of the global sort */
     double min_sep;         /* least distance found between a root and its conjugate or one
                                of the next 8 roots in real order (upper bound of the least
                                distance; the closest pairs are adjacent in that order) */

@@ -513,15 +513,25 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, cd *roots, uint8_
 }
 
 // -------------------------------------------------------- nset collection
-// Sort key of a root of the type of rank t: t in the top bits, then the real
-// part in fixed point with resolution 2^-55 over [-2.125, 1.875) -- far finer
-// than any identification radius used with FP64 roots.
+// Sort key of a root of the type of rank t: t above bit KEY_TYPE_SHIFT, then
+// q = floor((re + 2.125) 2^48), an exact integer (re 2^48 is exact, so is
+// its floor) over [-2.125, 1.875).  Keys order the roots of a type by real
+// part up to the resolution 2^-48; the identification below reasons on key
+// differences, so equal keys are harmless.  T <= 64 types need 56 key bits.
+constexpr int KEY_TYPE_SHIFT = 50;
+constexpr int MAX_TYPES = 64;
+
 __device__ __forceinline__ uint64_t root_key(int t, double re)
 {
-    double x = (re + 2.125) * 0x1p55;
-    x = fmin(fmax(x, 0.0), 0x1p57 - 1.0);
-    return ((uint64_t)t << 57) | (uint64_t)x;
+    const double x = fmin(fmax(re, -2.125), 1.875 - 0x1p-48);
+    const int64_t q = (int64_t)floor(x * 0x1p48) + (int64_t)(17ll << 45); // 2.125 2^48
+    return ((uint64_t)t << KEY_TYPE_SHIFT) | (uint64_t)q;
 }
+__device__ __forceinline__ int key_type(uint64_t key) { return (int)(key >> KEY_TYPE_SHIFT); }
+
+// Keys i > j of one type with key_i - key_j >= key_window(tau) have
+// re_i - re_j > (key_i - key_j - 1) 2^-48 >= tau, and so have all earlier j.
+__device__ __forceinline__ uint64_t key_window(double tau) { return 1ull + (uint64_t)ceil(tau * 0x1p48); }
 
 __device__ __forceinline__ cd fold_snap(cd z, double tau)
 {
@@ -530,38 +540,80 @@ __device__ __forceinline__ cd fold_snap(cd z, double tau)
     return z;
 }
 
+// Type of item g from a copy of the offsets in LDS (T + 1 entries).
+__device__ __forceinline__ int find_type_lds(const int64_t *offs, int T, int64_t g)
+{
+    int lo = 0, hi = T;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (offs[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void load_offsets_lds(int64_t *dst, const int64_t *offs, int T)
+{
+    for (int i = threadIdx.x; i <= T; i += blockDim.x) dst[i] = offs[i];
+    __syncthreads();
+}
+
 // Fold to the closed upper half plane, snap |Im| < tau/2 to the real axis
 // (Section 6.1, nset), and drop a start whose root repeats the root of one
-// of the three previous starts of the same type: the starts of one level-line
-// turn mostly reach the same root (73% repeats, Section 6.4.3), so this local
-// identification removes most duplicates before the sort.
-__global__ void k_prekeys(batch_args b, const cd *roots, const uint8_t *status, uint32_t *flag)
+// of the PREKEY_WINDOW previous converged starts of the same type: the starts
+// of one level-line turn mostly reach the same root (73% repeats, Section
+// 6.4.3), so this local identification removes most duplicates before the
+// sort.  A block stages its starts and the window before them in LDS.
+constexpr int PREKEY_WINDOW = 8;
+constexpr int COLLECT_BLOCK = 256;
+
+__global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const cd *roots, const uint8_t *status,
+                                                           uint32_t *flag)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int64_t offs[MAX_TYPES + 1];
+    __shared__ cd zs[COLLECT_BLOCK + PREKEY_WINDOW];
+    __shared__ int ts[COLLECT_BLOCK + PREKEY_WINDOW]; // type, or -1: not converged
+    load_offsets_lds(offs, b.start_offs, b.T);
+    const int64_t base = (int64_t)blockIdx.x * COLLECT_BLOCK - PREKEY_WINDOW;
+    for (int i = threadIdx.x; i < COLLECT_BLOCK + PREKEY_WINDOW; i += COLLECT_BLOCK) {
+        const int64_t g = base + i;
+        int t = -1;
+        cd z = {0.0, 0.0};
+        if (g >= 0 && g < b.n_starts && status[g] == ST_CONVERGED) {
+            t = find_type_lds(offs, b.T, g);
+            z = fold_snap(roots[g], b.types[t].p.tau);
+        }
+        ts[i] = t;
+        zs[i] = z;
+    }
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * COLLECT_BLOCK + threadIdx.x;
     if (g >= b.n_starts) return;
+    const int i = threadIdx.x + PREKEY_WINDOW;
+    const int t = ts[i];
     uint32_t f = 0;
-    if (status[g] == ST_CONVERGED) {
-        const int t = find_type(b.start_offs, b.T, g);
+    if (t >= 0) {
         const double tau = b.types[t].p.tau;
-        const cd z = fold_snap(roots[g], tau);
+        const cd z = zs[i];
         f = 1;
-        const int64_t k = g - b.start_offs[t];
-        for (int d = 1; d <= 3 && d <= k; ++d) {
-            if (status[g - d] != ST_CONVERGED) continue;
-            const cd y = fold_snap(roots[g - d], tau);
+        for (int d = 1; d <= PREKEY_WINDOW; ++d) {
+            if (ts[i - d] != t) continue;
+            const cd y = zs[i - d];
             if (fabs(y.re - z.re) < tau && fabs(y.im - z.im) < tau) { f = 0; break; }
         }
     }
     flag[g] = f;
 }
 
-__global__ void k_compact(batch_args b, const cd *roots, const uint32_t *flag, const uint32_t *pos, uint64_t *keys,
-                          uint32_t *vals, unsigned long long *count)
+__global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const cd *roots, const uint32_t *flag,
+                                                           const uint32_t *pos, uint64_t *keys, uint32_t *vals,
+                                                           unsigned long long *count)
 {
+    __shared__ int64_t offs[MAX_TYPES + 1];
+    load_offsets_lds(offs, b.start_offs, b.T);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= b.n_starts) return;
     if (flag[g]) {
-        const int t = find_type(b.start_offs, b.T, g);
+        const int t = find_type_lds(offs, b.T, g);
         const cd z = fold_snap(roots[g], b.types[t].p.tau);
         keys[pos[g]] = root_key(t, z.re);
         vals[pos[g]] = (uint32_t)g;
@@ -569,37 +621,49 @@ __global__ void k_compact(batch_args b, const cd *roots, const uint32_t *flag, c
     if (g == b.n_starts - 1) *count = (unsigned long long)pos[g] + flag[g];
 }
 
-// A sorted point is a duplicate when an earlier point of the same type lies
-// within tau in both coordinates (the nset identification, the first point of
-// a cluster kept).
-__global__ void k_mark(batch_args b, const cd *roots, const uint64_t *keys, const uint32_t *vals, uint32_t *flag,
-                       int64_t m)
+// The sorted candidates, folded and snapped, in sort order: one gather, so
+// that the identification and the output pass read them in sequence.
+__global__ void k_gather(batch_args b, const cd *roots, const uint64_t *keys, const uint32_t *vals, cd *zs,
+                         int64_t m)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    const int t = (int)(keys[i] >> 57);
+    zs[i] = fold_snap(roots[vals[i]], b.types[key_type(keys[i])].p.tau);
+}
+
+// A sorted point is a duplicate when an earlier point of the same type lies
+// within tau in both coordinates (the nset identification, the first point of
+// a cluster kept).  The backward scan stops at the key window (real parts
+// tau apart) or after 256 points.
+__global__ void k_mark(batch_args b, const uint64_t *keys, const cd *zs, uint32_t *flag, int64_t m)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t ki = keys[i];
+    const int t = key_type(ki);
     const double tau = b.types[t].p.tau;
-    const cd zi = fold_snap(roots[vals[i]], tau);
+    const uint64_t win = key_window(tau);
+    const cd zi = zs[i];
     uint32_t f = 1;
     for (int64_t j = i - 1, c = 0; j >= 0 && c < 256; --j, ++c) {
-        if ((int)(keys[j] >> 57) != t) break;
-        const cd zj = fold_snap(roots[vals[j]], tau);
-        if (zi.re - zj.re >= tau) break;
-        if (fabs(zi.im - zj.im) < tau) { f = 0; break; }
+        const uint64_t kj = keys[j];
+        if (key_type(kj) != t || ki - kj >= win) break;
+        const cd zj = zs[j];
+        if (fabs(zi.re - zj.re) < tau && fabs(zi.im - zj.im) < tau) { f = 0; break; }
     }
     flag[i] = f;
 }
 
 // Per type: first sorted index (lower bound of the type's key range, T + 1
-// entries in tb) and the number of unique roots in C_UNIQUE of the first
-// counter copy (the fold adds the copies).
-// One block of at least T + 1 threads.
+// entries in tb), the number of unique roots (C_UNIQUE) and of sorted
+// candidates (C_SURVIVORS), both in the first counter copy (the fold adds the
+// copies).  One block of at least T + 1 threads.
 __global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t *flag, const uint32_t *pos,
                               int64_t m, int64_t *tb)
 {
     const int t = threadIdx.x;
     if (t <= b.T) {
-        const uint64_t key = (uint64_t)t << 57;
+        const uint64_t key = (uint64_t)t << KEY_TYPE_SHIFT;
         int64_t lo = 0, hi = m;
         while (lo < hi) {
             int64_t mid = (lo + hi) / 2;
@@ -611,12 +675,12 @@ __global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t
     if (t < b.T) {
         auto pos_at = [&](int64_t i) -> uint64_t { return i < m ? pos[i] : (m ? pos[m - 1] + flag[m - 1] : 0); };
         b.spread[(int64_t)t * C_NCOUNTERS + C_UNIQUE] = pos_at(tb[t + 1]) - pos_at(tb[t]);
+        b.spread[(int64_t)t * C_NCOUNTERS + C_SURVIVORS] = (uint64_t)(tb[t + 1] - tb[t]);
     }
 }
 
-__global__ void k_scatter(batch_args b, const cd *roots, const uint64_t *keys, const uint32_t *vals,
-                          const uint32_t *flag, const uint32_t *pos, const int64_t *tb, int64_t m, double *ore,
-                          double *oim)
+__global__ void k_scatter(batch_args b, const uint64_t *keys, const cd *zs, const uint32_t *flag, const uint32_t *pos,
+                          const int64_t *tb, int64_t m, double *ore, double *oim)
 {
     unsigned long long *const wc = wave_ctr(b);
     type_count nreal;
@@ -624,13 +688,13 @@ __global__ void k_scatter(batch_args b, const cd *roots, const uint64_t *keys, c
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < m && flag[i];
-        const int t = act ? (int)(keys[i] >> 57) : nreal.t;
+        const int t = act ? key_type(keys[i]) : nreal.t;
         if (__ballot(act && t != nreal.t)) flush_count(wc, C_REAL, nreal);
         nreal.t = t;
         if (!act) continue;
         const type_desc &td = b.types[t];
         const uint64_t u = pos[i] - pos[tb[t]];
-        const cd z = fold_snap(roots[vals[i]], td.p.tau);
+        const cd z = zs[i];
         if (u < td.cap) {
             ore[td.out_off + u] = z.re;
             oim[td.out_off + u] = z.im;

@@ -167,18 +167,27 @@ int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uin
 
 // ------------------------------------------------------------- workspace
 struct layout {
-    size_t gctr, ctr, spread, types, offs, tb, seeds, starts, status, iters, segf, flag0, pos0, keys, vals, keys2, vals2,
+    size_t gctr, ctr, spread, zs, types, offs, tb, seeds, starts, status, iters, segf, flag0, pos0, keys, vals, keys2, vals2,
         flag, pos, temp, total;
     size_t temp_bytes;
 };
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-hipError_t rocprim_temp(int64_t n, size_t &bytes)
+// key bits of a call with T types: the fixed-point real part and the type
+int key_end_bit(int T)
+{
+    int tb = 0;
+    while ((1 << tb) < T) ++tb;
+    return KEY_TYPE_SHIFT + tb;
+}
+
+hipError_t rocprim_temp(int64_t n, int T, size_t &bytes)
 {
     size_t sort_b = 0, scan_b = 0;
     hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_b, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                             (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n, 0, 64);
+                                             (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n, 0,
+                                             key_end_bit(T));
     if (e != hipSuccess) return e;
     e = rocprim::exclusive_scan(nullptr, scan_b, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, (size_t)n,
                                 rocprim::plus<uint32_t>());
@@ -209,6 +218,7 @@ layout make_layout(const batch_plan &bp, size_t temp_bytes)
     L.keys = take(8 * NS);
     L.vals = take(4 * NS);
     L.keys2 = take(8 * NS);
+    L.zs = take(sizeof(cd) * NS);
     L.vals2 = take(4 * NS);
     L.flag = take(4 * NS);
     L.pos = take(4 * NS);
@@ -370,7 +380,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     hipStream_t stream = (hipStream_t)stream_v;
     call_ctx ctx{stats, npairs};
     size_t temp_bytes = 0;
-    CHK(rocprim_temp(bp.n_starts, temp_bytes));
+    CHK(rocprim_temp(bp.n_starts, bp.T, temp_bytes));
     const layout L = make_layout(bp, temp_bytes);
     if (ws_bytes < L.total) return MSPLIT_E_WORKSPACE;
     char *ws = (char *)workspace;
@@ -387,6 +397,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     uint8_t *segf = (uint8_t *)(ws + L.segf);
     uint32_t *flag0 = (uint32_t *)(ws + L.flag0), *pos0 = (uint32_t *)(ws + L.pos0);
     uint64_t *keys = (uint64_t *)(ws + L.keys), *keys2 = (uint64_t *)(ws + L.keys2);
+    cd *zs = (cd *)(ws + L.zs);
     uint32_t *vals = (uint32_t *)(ws + L.vals), *vals2 = (uint32_t *)(ws + L.vals2);
     uint32_t *flag = (uint32_t *)(ws + L.flag), *pos = (uint32_t *)(ws + L.pos);
     void *temp = ws + L.temp;
@@ -483,11 +494,12 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     CHK(hipEventRecord(ev.e[3], stream));
     // nset collection: local identification, compaction, sort, global
     // identification, per-type output slices
-    k_prekeys<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, starts, status, flag0);
+    k_prekeys<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, starts, status, flag0);
     size_t tb_bytes = temp_bytes;
     CHK(rocprim::exclusive_scan(temp, tb_bytes, flag0, pos0, 0u, (size_t)bp.n_starts, rocprim::plus<uint32_t>(),
                                 stream));
-    k_compact<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, starts, flag0, pos0, keys, vals, gctr + G_COMPACT);
+    k_compact<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, starts, flag0, pos0, keys, vals,
+                                                                                    gctr + G_COMPACT);
     CHK(hipGetLastError());
     unsigned long long m_h = 0;
     CHK(hipMemcpyAsync(&m_h, gctr + G_COMPACT, sizeof(m_h), hipMemcpyDeviceToHost, stream));
@@ -495,14 +507,16 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     const int64_t m = (int64_t)m_h;
     if (m > 0) {
         tb_bytes = temp_bytes;
-        CHK(rocprim::radix_sort_pairs(temp, tb_bytes, keys, keys2, vals, vals2, (size_t)m, 0, 64, stream));
-        k_mark<<<blocks_for(m, 256), 256, 0, stream>>>(ba, starts, keys2, vals2, flag, m);
+        CHK(rocprim::radix_sort_pairs(temp, tb_bytes, keys, keys2, vals, vals2, (size_t)m, 0, key_end_bit(T),
+                                      stream));
+        k_gather<<<blocks_for(m, 256), 256, 0, stream>>>(ba, starts, keys2, vals2, zs, m);
+        k_mark<<<blocks_for(m, 256), 256, 0, stream>>>(ba, keys2, zs, flag, m);
         tb_bytes = temp_bytes;
         CHK(rocprim::exclusive_scan(temp, tb_bytes, flag, pos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
     }
     k_type_bounds<<<1, 128, 0, stream>>>(ba, keys2, flag, pos, m, tb);
     if (m > 0)
-        k_scatter<<<persistent_blocks(m, 256), 256, 0, stream>>>(ba, starts, keys2, vals2, flag, pos, tb, m, out->re,
+        k_scatter<<<persistent_blocks(m, 256), 256, 0, stream>>>(ba, keys2, zs, flag, pos, tb, m, out->re,
                                                           out->im);
     CHK(hipEventRecord(ev.e[4], stream));
     CHK(hipGetLastError());
@@ -577,6 +591,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         s.steps_walk = H(t, C_STEPS_WALK);
         s.steps_desc = H(t, C_STEPS_DESC);
         s.steps_fp32 = H(t, C_STEPS_FP32);
+        s.sorted = H(t, C_SURVIVORS);
         unsigned long long ms_bits = H(t, C_MIN_SEP_BITS), mr_bits = H(t, C_MAX_RAD_BITS);
         memcpy(&s.min_sep, &ms_bits, 8);
         memcpy(&s.max_radius, &mr_bits, 8);
@@ -621,7 +636,7 @@ int msplit_batch_workspace_size(const int32_t *ln_pairs, int npairs, const mspli
     int r = make_batch(ln_pairs, npairs, opts, nullptr, nullptr, bp);
     if (r) return r;
     size_t tb = 0;
-    if (rocprim_temp(bp.n_starts, tb) != hipSuccess) return MSPLIT_E_DEVICE;
+    if (rocprim_temp(bp.n_starts, bp.T, tb) != hipSuccess) return MSPLIT_E_DEVICE;
     *bytes = make_layout(bp, tb).total;
     return MSPLIT_OK;
 }

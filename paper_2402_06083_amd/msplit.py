@@ -48,7 +48,7 @@ class RootsC(ctypes.Structure):
 
 _STAT_U64 = ["starts", "converged", "diverged", "timeouts", "unique", "n_real", "total", "expected",
              "missing", "phase_fail", "certified", "label_proven", "overlaps", "steps_lift",
-             "steps_walk", "steps_desc", "steps_fp32"]
+             "steps_walk", "steps_desc", "steps_fp32", "sorted"]
 
 
 class Stats(ctypes.Structure):
