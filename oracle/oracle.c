@@ -282,18 +282,24 @@ static int walk_segment(const method_t *m, cld z, int64_t s0, int64_t F, cld *st
 /* Left:  P(-2) <= 2 < level, and P grows without bound to the left of -2.    */
 /* For P = p_1 = z the curve is the circle |z| = level.                       */
 /* ------------------------------------------------------------------------- */
+/* P above the level on the real axis.  Outside [-2, 1/4] the orbit grows
+ * without bound; when p_{l+n} overflows, q = p_{l+n} - p_l evaluates to NaN
+ * (inf - inf) although its true value is far above the level, so a value
+ * that is not <= level counts as above. */
+static int above_level(const method_t *m, cld P) { return !(creall(P) <= m->level); }
+
 static ld bisect_real(const method_t *m, ld a, ld b)
 {
     /* invariant: P(a) - level and P(b) - level have opposite signs */
     cld Pa, dPa;
     eval_q(m->l, m->n, a, &Pa, &dPa);
-    int sa = creall(Pa) > m->level;
+    int sa = above_level(m, Pa);
     for (int it = 0; it < 200; it++) {
         ld c = 0.5L * (a + b);
         if (c == a || c == b) break;
         cld Pc, dPc;
         eval_q(m->l, m->n, c, &Pc, &dPc);
-        if ((creall(Pc) > m->level) == sa) a = c; else b = c;
+        if (above_level(m, Pc) == sa) a = c; else b = c;
     }
     return 0.5L * (a + b);
 }
@@ -307,7 +313,7 @@ static void endpoints(const method_t *m, ld *xl, ld *xr)
     for (int it = 0; it < 16; it++) {
         cld Pb, dPb;
         eval_q(m->l, m->n, b, &Pb, &dPb);
-        if (creall(Pb) > m->level) break;
+        if (above_level(m, Pb)) break;
         b = -2.0L + 2 * (b + 2.0L);
     }
     *xl = bisect_real(m, b, -2.0L);

@@ -367,6 +367,35 @@ def test_mis_counts(order):
         assert total_count(r) == counts.mis_count(l, n), (l, n)
 
 
+@pytest.mark.parametrize("ln", [(13, 1), (14, 2), (15, 1), (20, 2)])
+def test_mis_endpoints_large_preperiod(ln):
+    """Real end points of |q_{l,n}| = 100 (Section 6.3.1) where the far end of
+    the bisection bracket overflows: checked against the orbit in mpmath (no
+    overflow there) -- q crosses the level inside a 1e-12 bracket of each."""
+    l, n = ln
+    xl, xr = oracle.endpoints(l, n)
+
+    def q(x):
+        z, zl = mpmath.mpf(0), None
+        for k in range(1, l + n + 1):
+            z = z * z + x
+            if k == l:
+                zl = z
+        return z - zl - 100
+
+    for x in (xl, xr):
+        a, b = mpmath.mpf(float(x)) - mpmath.mpf(1e-12), mpmath.mpf(float(x)) + mpmath.mpf(1e-12)
+        assert (q(a) > 0) != (q(b) > 0), (ln, float(x))
+    assert 0.25 < float(xr) < 1.0 and float(xl) < -2.0
+
+
+@pytest.mark.parametrize("ln", [(13, 1), (13, 2), (14, 1), (14, 2), (15, 1)])
+def test_mis_counts_large_preperiod(ln):
+    l, n = ln
+    r = oracle.split(l, n)
+    assert total_count(r) == counts.mis_count(l, n), ln
+
+
 def test_mis_certificates_prove_the_type():
     for (l, n) in [(2, 4), (3, 3), (4, 6)]:
         r = oracle.split(l, n)
