@@ -582,10 +582,33 @@ static int newton_zero(int l, int n, cdd c)
     return !(a >= TAU_ZERO); /* also true for an exact zero (0/0 -> NaN) */
 }
 
-/* Membership in Mis(l,n) from eq. def:mis: not a root of q_{l-1,n}, and not a
- * root of q_{l,k} for a strict divisor k of n. */
+/* At (or next to) a centre of Hyp(k), k | n?  By Thm fact_mis such a centre
+ * is a root of q_{l,n} of multiplicity eta_l(k) >= 2, so at distance d from
+ * it the Newton step of q is about d / eta, while the Newton distance of p_k
+ * (a simple root of p_k) is about d: their ratio is at most eta (<= 64 for
+ * l <= 62).  At a simple root of q the step is at the rounding of c and the
+ * centre lies a root separation away.  A point that has been polished to the
+ * noise floor of a multiple root sits far below any fixed zero threshold, so
+ * the test is this ratio, in double-double. */
+static int at_multiple_root(const method_t *m, cdd c)
+{
+    cdd s = dd_newton_step(m->l, m->n, c);
+    double a = hypot(s.re.hi + s.re.lo, s.im.hi + s.im.lo);
+    for (int k = 1; k <= m->n; k++) {
+        if (m->n % k) continue;
+        cdd h = dd_newton_step(0, k, c);
+        double hk = hypot(h.re.hi + h.re.lo, h.im.hi + h.im.lo);
+        if (!(hk >= 1e-6) && !(64.0 * a < hk)) return 1; /* also an exact zero of p_k */
+    }
+    return 0;
+}
+
+/* Membership in Mis(l,n) from eq. def:mis: not a centre of Hyp(k) for k | n
+ * (preperiod 0), not a root of q_{l-1,n}, and not a root of q_{l,k} for a
+ * strict divisor k of n. */
 static int is_mis_type(const method_t *m, cdd c)
 {
+    if (at_multiple_root(m, c)) return 0;
     if (newton_zero(m->l - 1, m->n, c)) return 0;
     for (int k = 1; k < m->n; k++)
         if (m->n % k == 0 && newton_zero(m->l, k, c)) return 0;

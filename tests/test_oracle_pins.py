@@ -389,6 +389,18 @@ def test_mis_endpoints_large_preperiod(ln):
     assert 0.25 < float(xr) < 1.0 and float(xl) < -2.0
 
 
+@pytest.mark.parametrize("ln", [(3, 15), (6, 13), (2, 16), (4, 14)])
+def test_mis_counts_order_18_19(ln):
+    """Orders where descents settle on the multiple roots of q_{l,n} (the
+    centres Hyp(k), k | n, Thm fact_mis) closely enough to pass any fixed
+    zero threshold: the count must still be exactly |Mis(l,n)| (eq. MisCount)
+    and no returned point may be a centre."""
+    l, n = ln
+    r = oracle.split(l, n)
+    assert total_count(r) == counts.mis_count(l, n), ln
+    assert not np.any((r.im_hi > 0) & (r.im_hi < 1e-14))
+
+
 @pytest.mark.parametrize("ln", [(13, 1), (13, 2), (14, 1), (14, 2), (15, 1)])
 def test_mis_counts_large_preperiod(ln):
     l, n = ln
