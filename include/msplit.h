@@ -125,6 +125,9 @@ typedef struct msplit_stats {
     uint64_t steps_fp32;    /* ... of which in FP32 (MIXED) */
     uint64_t sorted;        /* converged starts left after the local identification of
                                consecutive starts: the entries of the global sort */
+    uint64_t discarded;     /* identified roots of a lower type dropped by the
+                               classification (q_{l,n}: Hyp(k), Mis(j,k) with j < l or
+                               k < n; zero for p_n) */
     double min_sep;         /* least distance found between a root and its conjugate or one
                                of the next 8 roots in real order (upper bound of the least
                                distance; the closest pairs are adjacent in that order) */

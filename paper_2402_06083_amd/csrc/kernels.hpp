@@ -25,6 +25,7 @@
 // objection to GPUs).
 #pragma once
 #include "common.hpp"
+#include "dd.hpp"
 
 namespace msplit {
 
@@ -37,7 +38,7 @@ enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_NCOUNTERS = 8 }
 enum {
     C_CONVERGED = 0, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL, C_SEED_FAIL, C_STEPS_LIFT, C_STEPS_WALK,
     C_STEPS_DESC, C_STEPS_FP32, C_UNIQUE, C_REAL, C_CERTIFIED, C_LABEL, C_OVERLAP, C_MIN_SEP_BITS,
-    C_MAX_RAD_BITS, C_SURVIVORS, C_NCOUNTERS = 20
+    C_MAX_RAD_BITS, C_SURVIVORS, C_KEPT, C_NCOUNTERS = 20
 };
 
 struct plan_t {
@@ -67,7 +68,10 @@ struct type_desc {
 
 struct batch_args {
     const type_desc *types;
-    const int64_t *seed_offs, *seg_offs, *start_offs, *uniq_offs; // T + 1 entries each
+    const int64_t *seed_offs, *seg_offs, *start_offs; // T + 1 entries each
+    const int64_t *uniq_offs; // output index space: min(kept, capacity) roots per type
+    int64_t *coll_offs;       // collected (identified) roots per type, set on the device
+    int64_t *kept_offs;       // roots kept by the classification per type, set on the device
     int T;
     int64_t n_seeds, n_segs, n_starts;
     uint32_t chunk_seg, chunk_start;
@@ -519,7 +523,7 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, cd *roots, uint8_
 // part up to the resolution 2^-48; the identification below reasons on key
 // differences, so equal keys are harmless.  T <= 64 types need 56 key bits.
 constexpr int KEY_TYPE_SHIFT = 50;
-constexpr int MAX_TYPES = 64;
+constexpr int MAX_TYPES = 256;
 
 __device__ __forceinline__ uint64_t root_key(int t, double re)
 {
@@ -533,10 +537,14 @@ __device__ __forceinline__ int key_type(uint64_t key) { return (int)(key >> KEY_
 // re_i - re_j > (key_i - key_j - 1) 2^-48 >= tau, and so have all earlier j.
 __device__ __forceinline__ uint64_t key_window(double tau) { return 1ull + (uint64_t)ceil(tau * 0x1p48); }
 
+// Fold to the closed upper half plane and snap to the real axis when the
+// imaginary part is below both tau/2 and the rounding level of a converged
+// descent (2^-46 |z|): q_{l,n} has genuine non-real roots next to -2 whose
+// imaginary part (about 4^-(l+n)) falls below tau/2.
 __device__ __forceinline__ cd fold_snap(cd z, double tau)
 {
     z.im = fabs(z.im);
-    if (z.im < 0.5 * tau) z.im = 0.0;
+    if (z.im < fmin(0.5 * tau, 0x1p-46 * fmax(fabs(z.re), 0x1p-8))) z.im = 0.0;
     return z;
 }
 
@@ -551,10 +559,18 @@ __device__ __forceinline__ int find_type_lds(const int64_t *offs, int T, int64_t
     return lo;
 }
 
-__device__ __forceinline__ void load_offsets_lds(int64_t *dst, const int64_t *offs, int T)
+// LDS copies of the start offsets and of each type's identification radius
+struct collect_tables {
+    int64_t offs[MAX_TYPES + 1];
+    double tau[MAX_TYPES];
+};
+
+__device__ __forceinline__ void load_tables_lds(collect_tables &c, const batch_args &b)
 {
-    for (int i = threadIdx.x; i <= T; i += blockDim.x) dst[i] = offs[i];
-    __syncthreads();
+    for (int i = threadIdx.x; i <= b.T; i += blockDim.x) {
+        c.offs[i] = b.start_offs[i];
+        if (i < b.T) c.tau[i] = b.types[i].p.tau;
+    }
 }
 
 // Fold to the closed upper half plane, snap |Im| < tau/2 to the real axis
@@ -562,28 +578,34 @@ __device__ __forceinline__ void load_offsets_lds(int64_t *dst, const int64_t *of
 // of the PREKEY_WINDOW previous converged starts of the same type: the starts
 // of one level-line turn mostly reach the same root (73% repeats, Section
 // 6.4.3), so this local identification removes most duplicates before the
-// sort.  A block stages its starts and the window before them in LDS.
+// sort.  A block stages its starts and the window before them in LDS; every
+// global load is issued before the first wait.
 constexpr int PREKEY_WINDOW = 8;
 constexpr int COLLECT_BLOCK = 256;
 
 __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const cd *roots, const uint8_t *status,
                                                            uint32_t *flag)
 {
-    __shared__ int64_t offs[MAX_TYPES + 1];
+    __shared__ collect_tables tabs;
     __shared__ cd zs[COLLECT_BLOCK + PREKEY_WINDOW];
     __shared__ int ts[COLLECT_BLOCK + PREKEY_WINDOW]; // type, or -1: not converged
-    load_offsets_lds(offs, b.start_offs, b.T);
     const int64_t base = (int64_t)blockIdx.x * COLLECT_BLOCK - PREKEY_WINDOW;
-    for (int i = threadIdx.x; i < COLLECT_BLOCK + PREKEY_WINDOW; i += COLLECT_BLOCK) {
-        const int64_t g = base + i;
-        int t = -1;
-        cd z = {0.0, 0.0};
-        if (g >= 0 && g < b.n_starts && status[g] == ST_CONVERGED) {
-            t = find_type_lds(offs, b.T, g);
-            z = fold_snap(roots[g], b.types[t].p.tau);
-        }
-        ts[i] = t;
-        zs[i] = z;
+    const int64_t g0 = base + threadIdx.x, g1 = base + COLLECT_BLOCK + threadIdx.x;
+    const bool has1 = threadIdx.x < PREKEY_WINDOW;
+    const bool v0 = g0 >= 0 && g0 < b.n_starts, v1 = has1 && g1 < b.n_starts;
+    const uint8_t s0 = v0 ? status[g0] : ST_NONE, s1 = v1 ? status[g1] : ST_NONE;
+    const cd z0 = v0 ? roots[g0] : cd{0.0, 0.0}, z1 = v1 ? roots[g1] : cd{0.0, 0.0};
+    load_tables_lds(tabs, b);
+    __syncthreads();
+    {
+        const int t = s0 == ST_CONVERGED ? find_type_lds(tabs.offs, b.T, g0) : -1;
+        ts[threadIdx.x] = t;
+        zs[threadIdx.x] = t >= 0 ? fold_snap(z0, tabs.tau[t]) : z0;
+    }
+    if (has1) {
+        const int t = s1 == ST_CONVERGED ? find_type_lds(tabs.offs, b.T, g1) : -1;
+        ts[COLLECT_BLOCK + threadIdx.x] = t;
+        zs[COLLECT_BLOCK + threadIdx.x] = t >= 0 ? fold_snap(z1, tabs.tau[t]) : z1;
     }
     __syncthreads();
     const int64_t g = (int64_t)blockIdx.x * COLLECT_BLOCK + threadIdx.x;
@@ -592,7 +614,7 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
     const int t = ts[i];
     uint32_t f = 0;
     if (t >= 0) {
-        const double tau = b.types[t].p.tau;
+        const double tau = tabs.tau[t];
         const cd z = zs[i];
         f = 1;
         for (int d = 1; d <= PREKEY_WINDOW; ++d) {
@@ -608,17 +630,20 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const c
                                                            const uint32_t *pos, uint64_t *keys, uint32_t *vals,
                                                            unsigned long long *count)
 {
-    __shared__ int64_t offs[MAX_TYPES + 1];
-    load_offsets_lds(offs, b.start_offs, b.T);
+    __shared__ collect_tables tabs;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= b.n_starts) return;
-    if (flag[g]) {
-        const int t = find_type_lds(offs, b.T, g);
-        const cd z = fold_snap(roots[g], b.types[t].p.tau);
-        keys[pos[g]] = root_key(t, z.re);
-        vals[pos[g]] = (uint32_t)g;
+    const bool v = g < b.n_starts;
+    const uint32_t f = v ? flag[g] : 0u;
+    const uint32_t p = v ? pos[g] : 0u;
+    const cd z = v ? roots[g] : cd{0.0, 0.0};
+    load_tables_lds(tabs, b);
+    __syncthreads();
+    if (f) {
+        const int t = find_type_lds(tabs.offs, b.T, g);
+        keys[p] = root_key(t, fold_snap(z, tabs.tau[t]).re);
+        vals[p] = (uint32_t)g;
     }
-    if (g == b.n_starts - 1) *count = (unsigned long long)pos[g] + flag[g];
+    if (g == b.n_starts - 1) *count = (unsigned long long)p + f;
 }
 
 // The sorted candidates, folded and snapped, in sort order: one gather, so
@@ -655,14 +680,14 @@ __global__ void k_mark(batch_args b, const uint64_t *keys, const cd *zs, uint32_
 }
 
 // Per type: first sorted index (lower bound of the type's key range, T + 1
-// entries in tb), the number of unique roots (C_UNIQUE) and of sorted
-// candidates (C_SURVIVORS), both in the first counter copy (the fold adds the
-// copies).  One block of at least T + 1 threads.
+// entries in tb) and first index in the collected index space (coll_offs);
+// the number of collected roots (C_UNIQUE) and of sorted candidates
+// (C_SURVIVORS) go to the first counter copy (the fold adds the copies).
+// One block.
 __global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t *flag, const uint32_t *pos,
                               int64_t m, int64_t *tb)
 {
-    const int t = threadIdx.x;
-    if (t <= b.T) {
+    for (int t = threadIdx.x; t <= b.T; t += blockDim.x) {
         const uint64_t key = (uint64_t)t << KEY_TYPE_SHIFT;
         int64_t lo = 0, hi = m;
         while (lo < hi) {
@@ -672,36 +697,22 @@ __global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t
         tb[t] = (t == b.T) ? m : lo;
     }
     __syncthreads();
-    if (t < b.T) {
-        auto pos_at = [&](int64_t i) -> uint64_t { return i < m ? pos[i] : (m ? pos[m - 1] + flag[m - 1] : 0); };
-        b.spread[(int64_t)t * C_NCOUNTERS + C_UNIQUE] = pos_at(tb[t + 1]) - pos_at(tb[t]);
-        b.spread[(int64_t)t * C_NCOUNTERS + C_SURVIVORS] = (uint64_t)(tb[t + 1] - tb[t]);
+    auto pos_at = [&](int64_t i) -> int64_t { return i < m ? pos[i] : (m ? pos[m - 1] + flag[m - 1] : 0); };
+    for (int t = threadIdx.x; t <= b.T; t += blockDim.x) {
+        b.coll_offs[t] = pos_at(tb[t]);
+        if (t < b.T) {
+            b.spread[(int64_t)t * C_NCOUNTERS + C_UNIQUE] = (uint64_t)(pos_at(tb[t + 1]) - pos_at(tb[t]));
+            b.spread[(int64_t)t * C_NCOUNTERS + C_SURVIVORS] = (uint64_t)(tb[t + 1] - tb[t]);
+        }
     }
 }
 
-__global__ void k_scatter(batch_args b, const uint64_t *keys, const cd *zs, const uint32_t *flag, const uint32_t *pos,
-                          const int64_t *tb, int64_t m, double *ore, double *oim)
+// The identified roots into the collected index space (type-major, by real
+// part within a type).
+__global__ void k_scatter(const uint32_t *flag, const uint32_t *pos, const cd *zs, int64_t m, cd *uz)
 {
-    unsigned long long *const wc = wave_ctr(b);
-    type_count nreal;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
-        const int64_t i = i0 + threadIdx.x;
-        const bool act = i < m && flag[i];
-        const int t = act ? key_type(keys[i]) : nreal.t;
-        if (__ballot(act && t != nreal.t)) flush_count(wc, C_REAL, nreal);
-        nreal.t = t;
-        if (!act) continue;
-        const type_desc &td = b.types[t];
-        const uint64_t u = pos[i] - pos[tb[t]];
-        const cd z = zs[i];
-        if (u < td.cap) {
-            ore[td.out_off + u] = z.re;
-            oim[td.out_off + u] = z.im;
-        }
-        nreal.v += z.im == 0.0;
-    }
-    flush_count(wc, C_REAL, nreal);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m && flag[i]) uz[pos[i]] = zs[i];
 }
 
 // ---------------------------------------------------------- classification
@@ -711,33 +722,159 @@ __global__ void k_scatter(batch_args b, const uint64_t *keys, const cd *zs, cons
 // 6.3.2): a root of period n can sit that close to a root of period n/2 (the
 // centre of a satellite next to its parent), so the scale of p_k alone would
 // not do.  One orbit pass serves all divisors.
-// Threads run over the compact unique index space (uniq_offs).
-__global__ void k_classify(batch_args b, const double *re, const double *im, int32_t *period, int32_t *preperiod,
-                           uint8_t *flags, int64_t n_uniq)
+__device__ __forceinline__ int classify_p(int n, uint32_t divmask, double tau, cd c)
 {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_uniq) return;
-    const int t = find_type(b.uniq_offs, b.T, u);
-    const type_desc &td = b.types[t];
-    const plan_t &pl = td.p;
-    const int64_t i = td.out_off + (u - b.uniq_offs[t]);
-    const cd c = {re[i], im[i]};
-    int per = pl.n;
-    if (pl.l == 0 && period) {
-        orbit_state<double> s = {0.0, 0.0, 0.0, 0.0};
-        const double thr = pl.tau;
-        for (int k = 1; k < pl.n; ++k) {
-            orbit_step(s, c.re, c.im);
-            if (((pl.divmask_lo >> k) & 1u) && per == pl.n) {
-                const double a2 = s.zr * s.zr + s.zi * s.zi;
-                const double d2 = s.dr * s.dr + s.di * s.di;
-                if (a2 < thr * thr * d2) per = k;
-            }
+    orbit_state<double> s = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 1; k < n; ++k) {
+        orbit_step(s, c.re, c.im);
+        if ((divmask >> k) & 1u) {
+            const double a2 = s.zr * s.zr + s.zi * s.zi;
+            const double d2 = s.dr * s.dr + s.di * s.di;
+            if (a2 < tau * tau * d2) return k;
         }
     }
-    if (period) period[i] = per;
-    if (preperiod) preperiod[i] = pl.l;
-    if (flags) flags[i] = (c.im == 0.0) ? 1 : 0;
+    return n;
+}
+
+// q_{l,n}, l >= 2: keep c when it is a root of type Mis(l,n) (eq. def:mis).
+// By Thm fact_mis the roots of q_{l,n} are the centres Hyp(k), k | n, with
+// multiplicity eta_l(k) >= 2, and the simple roots Mis(j,k), 2 <= j <= l,
+// k | n.  The lower types are recognised by a vanishing Newton distance
+// (< tau):
+//   Hyp(k):        p_k,          k | n;
+//   Mis(j,n), j<l: q_{l-1,n} = z_{l-1+n} - z_{l-1};
+//   Mis(j,k), k<n: q_{l,k}   = z_{l+k} - z_l,  k | n, k < n.
+// A descent can also stop next to a multiple root, where FP64 evaluates q at
+// noise level: at distance d from Hyp(k) the exact Newton step of q is
+// d / eta and the Newton distance of p_k (a simple root there) is d, so their
+// ratio is at most eta <= 64, while at a genuine simple root of q the step is
+// at the rounding of c and p_k is a root separation away.  Near a centre
+// (p_k Newton distance < 1e-6) both are taken from a double-double orbit and
+// the point is kept only when 64 |step| < |p_k / p_k'|.
+__device__ __forceinline__ bool newton_dist_below(double ar, double ai, double br, double bi, double tau)
+{
+    return ar * ar + ai * ai < tau * tau * (br * br + bi * bi);
+}
+
+__device__ __noinline__ bool stalled_at_multiple_root(int l, int n, int k, cd c)
+{
+    const cdd cc = {{c.re, 0.0}, {c.im, 0.0}};
+    cdd z = {{0.0, 0.0}, {0.0, 0.0}}, zl = z, zk = z;
+    double dr = 0.0, di = 0.0, dlr = 0.0, dli = 0.0, dkr = 0.0, dki = 0.0;
+    for (int i = 1; i <= l + n; ++i) {
+        // dz <- 2 z dz + 1 (FP64 scale), z <- z^2 + c (double-double)
+        const double tr = z.re.hi * dr - z.im.hi * di, ti = z.re.hi * di + z.im.hi * dr;
+        dr = 2.0 * tr + 1.0;
+        di = 2.0 * ti;
+        z = cdd_sqr_add(z, cc);
+        if (i == k) { zk = z; dkr = dr; dki = di; }
+        if (i == l) { zl = z; dlr = dr; dli = di; }
+    }
+    const cdd q = cdd_sub(z, zl);
+    const double s2 = cdd_abs2_hi(q) / ((dr - dlr) * (dr - dlr) + (di - dli) * (di - dli));
+    const double h2 = cdd_abs2_hi(zk) / (dkr * dkr + dki * dki);
+    return !(64.0 * 64.0 * s2 < h2);
+}
+
+__device__ __forceinline__ bool classify_q(int l, int n, uint32_t divmask, double tau, cd c)
+{
+    orbit_state<double> s = {0.0, 0.0, 0.0, 0.0};
+    double zlm_r = 0.0, zlm_i = 0.0, dlm_r = 0.0, dlm_i = 0.0; // z_{l-1}, dz_{l-1}
+    double zl_r = 0.0, zl_i = 0.0, dl_r = 0.0, dl_i = 0.0;     // z_l, dz_l
+    bool keep = true;
+    double hmin2 = INFINITY; // least squared Newton distance of p_k, k | n
+    int kmin = 0;
+    const int N = l + n;
+    for (int i = 1; i <= N; ++i) {
+        orbit_step(s, c.re, c.im);
+        if (i <= n && (i == n || ((divmask >> i) & 1u))) {
+            const double h2 = (s.zr * s.zr + s.zi * s.zi) / (s.dr * s.dr + s.di * s.di);
+            if (h2 < hmin2) { hmin2 = h2; kmin = i; }
+            if (newton_dist_below(s.zr, s.zi, s.dr, s.di, tau)) keep = false; // Hyp(i), i | n
+        }
+        if (i == l - 1) { zlm_r = s.zr; zlm_i = s.zi; dlm_r = s.dr; dlm_i = s.di; }
+        if (i == l) { zl_r = s.zr; zl_i = s.zi; dl_r = s.dr; dl_i = s.di; }
+        const int k = i - l;
+        if (k >= 1 && k < n && ((divmask >> k) & 1u) &&
+            newton_dist_below(s.zr - zl_r, s.zi - zl_i, s.dr - dl_r, s.di - dl_i, tau))
+            keep = false; // Mis(j,k), k < n
+        if (i == l - 1 + n && newton_dist_below(s.zr - zlm_r, s.zi - zlm_i, s.dr - dlm_r, s.di - dlm_i, tau))
+            keep = false; // Mis(j,n), j < l
+    }
+    if (keep && hmin2 < 1e-12 && stalled_at_multiple_root(l, n, kmin, c)) keep = false;
+    return keep;
+}
+
+// Threads run over the collected index space (bounded by m on the host; the
+// count itself, coll_offs[T], is read on the device).  keep[u] selects the
+// roots of the output set, cls[u] is the period (p_n) or n (q_{l,n}).
+__global__ void __launch_bounds__(256) k_classify(batch_args b, const cd *uz, uint32_t *keep, int32_t *cls,
+                                                  int64_t m, int labels)
+{
+    __shared__ int64_t offs[MAX_TYPES + 1];
+    for (int i = threadIdx.x; i <= b.T; i += blockDim.x) offs[i] = b.coll_offs[i];
+    __syncthreads();
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= m) return;
+    if (u >= offs[b.T]) { keep[u] = 0; return; }
+    const int t = find_type_lds(offs, b.T, u);
+    const plan_t &pl = b.types[t].p;
+    const cd c = uz[u];
+    uint32_t k = 1;
+    int per = pl.n;
+    if (pl.l == 0) {
+        if (labels) per = classify_p(pl.n, pl.divmask_lo, pl.tau, c);
+    } else {
+        k = classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c) ? 1u : 0u;
+    }
+    keep[u] = k;
+    cls[u] = per;
+}
+
+// Per type: first index in the kept index space; kept count in C_KEPT.
+// One block.
+__global__ void k_kept_bounds(batch_args b, const uint32_t *keep, const uint32_t *kpos)
+{
+    const int64_t n = b.coll_offs[b.T];
+    auto kpos_at = [&](int64_t u) -> int64_t { return u < n ? kpos[u] : (n ? kpos[n - 1] + keep[n - 1] : 0); };
+    for (int t = threadIdx.x; t <= b.T; t += blockDim.x) {
+        b.kept_offs[t] = kpos_at(b.coll_offs[t]);
+        if (t < b.T)
+            b.spread[(int64_t)t * C_NCOUNTERS + C_KEPT] =
+                (uint64_t)(kpos_at(b.coll_offs[t + 1]) - kpos_at(b.coll_offs[t]));
+    }
+}
+
+// Kept roots to the caller's output slices (at most the capacity of each),
+// with period, preperiod and the real flag; real roots counted per type.
+__global__ void __launch_bounds__(256) k_emit(batch_args b, const cd *uz, const uint32_t *keep, const uint32_t *kpos,
+                                              const int32_t *cls, int64_t m, double *ore, double *oim,
+                                              int32_t *period, int32_t *preperiod, uint8_t *flags)
+{
+    __shared__ int64_t offs[MAX_TYPES + 1];
+    for (int i = threadIdx.x; i <= b.T; i += blockDim.x) offs[i] = b.coll_offs[i];
+    __syncthreads();
+    unsigned long long *const wc = wave_ctr(b);
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = u < m && u < offs[b.T] && keep[u];
+    const int t = act ? find_type_lds(offs, b.T, u) : -1;
+    type_count nreal;
+    nreal.t = t;
+    if (act) {
+        const type_desc &td = b.types[t];
+        const int64_t rank = (int64_t)kpos[u] - b.kept_offs[t];
+        const cd z = uz[u];
+        if ((uint64_t)rank < td.cap) {
+            const int64_t i = td.out_off + rank;
+            ore[i] = z.re;
+            oim[i] = z.im;
+            if (period) period[i] = cls[u];
+            if (preperiod) preperiod[i] = td.p.l;
+            if (flags) flags[i] = z.im == 0.0 ? 1 : 0;
+        }
+        nreal.v = z.im == 0.0;
+    }
+    flush_count(wc, C_REAL, nreal);
 }
 
 } // namespace msplit

@@ -132,7 +132,7 @@ struct batch_plan {
 int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uint64_t *out_offs,
                const uint64_t *caps, batch_plan &bp)
 {
-    if (npairs <= 0 || npairs > 64) return MSPLIT_E_ARG;
+    if (npairs <= 0 || npairs > MAX_TYPES) return MSPLIT_E_ARG;
     bp.T = npairs;
     bp.slot.resize(npairs);
     std::iota(bp.slot.begin(), bp.slot.end(), 0);
@@ -206,7 +206,7 @@ layout make_layout(const batch_plan &bp, size_t temp_bytes)
     L.ctr = take(sizeof(unsigned long long) * C_NCOUNTERS * T);
     L.spread = take(sizeof(unsigned long long) * C_NCOUNTERS * T * CTR_SPREAD);
     L.types = take(sizeof(type_desc) * T);
-    L.offs = take(sizeof(int64_t) * 4 * (T + 1));
+    L.offs = take(sizeof(int64_t) * 6 * (T + 1));
     L.tb = take(sizeof(int64_t) * (T + 1));
     L.seeds = take(sizeof(cd) * bp.n_seeds);
     L.starts = take(sizeof(cd) * NS);
@@ -374,7 +374,6 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         // FP64 keys separate the roots only while the identification radius
         // stays well above the FP64 rounding of a root
         if (bp.td[t].p.tau < 0x1p-50) return MSPLIT_E_PRECISION;
-        if (bp.td[t].p.l != 0) return MSPLIT_E_UNSUPPORTED;
     }
     if (bp.n_starts >= ((int64_t)1 << 32)) return MSPLIT_E_UNSUPPORTED;
     hipStream_t stream = (hipStream_t)stream_v;
@@ -409,7 +408,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     CHK(set_cis(bp.td[0].p.M, stream));
 
     // tables: type descriptors and offsets (uniq_offs filled later)
-    std::vector<int64_t> offs(4 * (T + 1), 0);
+    std::vector<int64_t> offs(6 * (T + 1), 0);
     std::copy(bp.seed_offs.begin(), bp.seed_offs.end(), offs.begin());
     std::copy(bp.seg_offs.begin(), bp.seg_offs.end(), offs.begin() + (T + 1));
     std::copy(bp.start_offs.begin(), bp.start_offs.end(), offs.begin() + 2 * (T + 1));
@@ -422,6 +421,8 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     ba.seg_offs = doffs + (T + 1);
     ba.start_offs = doffs + 2 * (T + 1);
     ba.uniq_offs = doffs + 3 * (T + 1);
+    ba.coll_offs = doffs + 4 * (T + 1);
+    ba.kept_offs = doffs + 5 * (T + 1);
     ba.T = T;
     ba.n_seeds = bp.n_seeds;
     ba.n_segs = bp.n_segs;
@@ -514,19 +515,36 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         tb_bytes = temp_bytes;
         CHK(rocprim::exclusive_scan(temp, tb_bytes, flag, pos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
     }
-    k_type_bounds<<<1, 128, 0, stream>>>(ba, keys2, flag, pos, m, tb);
-    if (m > 0)
-        k_scatter<<<persistent_blocks(m, 256), 256, 0, stream>>>(ba, keys2, zs, flag, pos, tb, m, out->re,
-                                                          out->im);
+    k_type_bounds<<<1, 256, 0, stream>>>(ba, keys2, flag, pos, m, tb);
+    // the identified roots into the collected index space; the descent
+    // results (starts) are no longer needed once gathered
+    cd *uz = starts;
+    if (m > 0) k_scatter<<<blocks_for(m, 256), 256, 0, stream>>>(flag, pos, zs, m, uz);
     CHK(hipEventRecord(ev.e[4], stream));
+    CHK(hipGetLastError());
+
+    // classification: period labels (p_n), type Mis(l,n) (q_{l,n}); the kept
+    // roots go to the caller's slices.  flag0/pos0 and vals2 are free here.
+    uint32_t *keep = flag0, *kpos = pos0;
+    int32_t *cls = (int32_t *)vals2;
+    const bool labels = !(opts->flags & MSPLIT_F_NO_LABEL);
+    if (m > 0) {
+        k_classify<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, keep, cls, m, labels ? 1 : 0);
+        tb_bytes = temp_bytes;
+        CHK(rocprim::exclusive_scan(temp, tb_bytes, keep, kpos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
+    }
+    k_kept_bounds<<<1, 256, 0, stream>>>(ba, keep, kpos);
+    if (m > 0)
+        k_emit<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, keep, kpos, cls, m, out->re, out->im,
+                                                      labels ? out->period : nullptr, out->preperiod, out->flags);
     CHK(hipGetLastError());
     CHK(read_counters());
 
-    // capacities, compact unique index space
+    // capacities; the certificate runs over the output index space
     int status_all = MSPLIT_OK;
     std::vector<int64_t> uniq_offs(T + 1, 0);
     for (int t = 0; t < T; ++t) {
-        const uint64_t u = H(t, C_UNIQUE);
+        const uint64_t u = H(t, C_KEPT);
         const int c = bp.slot[t];
         counts[c] = u;
         if (u > bp.td[t].cap) status_all = MSPLIT_E_CAPACITY;
@@ -536,12 +554,6 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     const int64_t n_uniq = uniq_offs[T];
     CHK(hipMemcpyAsync(doffs + 3 * (T + 1), uniq_offs.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice,
                        stream));
-    // classification
-    if (n_uniq) {
-        k_classify<<<blocks_for(n_uniq, 256), 256, 0, stream>>>(
-            ba, out->re, out->im, (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period, out->preperiod,
-            out->flags, n_uniq);
-    }
     CHK(hipEventRecord(ev.e[5], stream));
     // certificate and separation
     const bool cert = (opts->flags & MSPLIT_F_CERTIFY) != 0;
@@ -568,9 +580,10 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     for (int t = 0; t < T; ++t) {
         const int c = bp.slot[t];
         const plan_t &p = bp.td[t].p;
-        const uint64_t uniq = H(t, C_UNIQUE), nreal = H(t, C_REAL);
+        const uint64_t uniq = H(t, C_KEPT), nreal = H(t, C_REAL);
         const uint64_t total = nreal + 2 * (uniq - nreal);
-        const uint64_t expected = (uint64_t)p.D;
+        // p_n: all 2^(n-1) roots; q_{l,n}: |Mis(l,n)| (eq. MisCount)
+        const uint64_t expected = p.l == 0 ? (uint64_t)p.D : (uint64_t)mis_count(p.l, p.n);
         if (total != expected && status_all == MSPLIT_OK) status_all = MSPLIT_E_INCOMPLETE;
         if (!stats) continue;
         msplit_stats &s = stats[c];
@@ -592,6 +605,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         s.steps_desc = H(t, C_STEPS_DESC);
         s.steps_fp32 = H(t, C_STEPS_FP32);
         s.sorted = H(t, C_SURVIVORS);
+        s.discarded = H(t, C_UNIQUE) - uniq;
         unsigned long long ms_bits = H(t, C_MIN_SEP_BITS), mr_bits = H(t, C_MAX_RAD_BITS);
         memcpy(&s.min_sep, &ms_bits, 8);
         memcpy(&s.max_radius, &mr_bits, 8);

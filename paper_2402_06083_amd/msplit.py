@@ -48,7 +48,7 @@ class RootsC(ctypes.Structure):
 
 _STAT_U64 = ["starts", "converged", "diverged", "timeouts", "unique", "n_real", "total", "expected",
              "missing", "phase_fail", "certified", "label_proven", "overlaps", "steps_lift",
-             "steps_walk", "steps_desc", "steps_fp32", "sorted"]
+             "steps_walk", "steps_desc", "steps_fp32", "sorted", "discarded"]
 
 
 class Stats(ctypes.Structure):
@@ -146,9 +146,10 @@ def _stream_handle(stream):
 class Result:
     """Roots of one split (device tensors trimmed to the count)."""
 
-    def __init__(self, l, n, re, im, period, flags, radius, count, stats, status):
+    def __init__(self, l, n, re, im, period, flags, radius, count, stats, status, preperiod=None):
         self.l, self.n = l, n
         self.re, self.im, self.period, self.flags, self.radius = re, im, period, flags, radius
+        self.preperiod = preperiod
         self.count = count
         self.stats = stats
         self.status = status
@@ -159,7 +160,7 @@ class Result:
     def cpu(self):
         import numpy as np
         d = {"re": self.re.cpu().numpy(), "im": self.im.cpu().numpy()}
-        for k in ("period", "flags", "radius"):
+        for k in ("period", "preperiod", "flags", "radius"):
             t = getattr(self, k)
             d[k] = t.cpu().numpy() if t is not None else None
         d["stats"] = self.stats
@@ -215,7 +216,7 @@ def split(l: int, n: int, opts: Options = None, buffers: Buffers = None, stream=
         raise MsplitError(r, f"split({l},{n})")
     certified = bool(opts.flags & F_CERTIFY)
     return Result(l, n, b.re[:c], b.im[:c], b.period[:c], b.flags[:c], b.radius[:c] if certified else None, c,
-                  st.as_dict(), r)
+                  st.as_dict(), r, preperiod=b.preperiod[:c])
 
 
 def hyperbolic(n: int, **kw) -> Result:

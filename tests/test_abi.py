@@ -41,7 +41,7 @@ def test_struct_sizes_match_binding(lib):
     # msplit_options: 4+4+8+4+4+4(pad)+8+4+4+8 = 56 bytes on x86-64 SysV
     assert ctypes.sizeof(msplit.Options) == 56
     assert ctypes.sizeof(msplit.RootsC) == 8 * 8 + 8
-    assert ctypes.sizeof(msplit.Stats) == 18 * 8 + 3 * 8 + 6 * 8 + 8
+    assert ctypes.sizeof(msplit.Stats) == 19 * 8 + 3 * 8 + 6 * 8 + 8
 
 
 def test_header_constants_match_binding():

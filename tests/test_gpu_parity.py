@@ -151,6 +151,75 @@ def test_batch_periods_1_to_24():
         assert st["total"] == 2 ** (n - 1) and st["certified"] == count and st["overlaps"] == 0, (n, st)
 
 
+# q_{l,n}: preperiods 2..15, periods 1..13, orders 3..16
+MIS_SMALL = [(2, 1), (2, 2), (3, 1), (2, 3), (3, 2), (4, 2), (2, 5), (3, 4), (5, 3), (2, 8), (4, 6), (8, 4),
+             (12, 2), (2, 12), (6, 8), (13, 1), (10, 6), (3, 13), (15, 1), (7, 7)]
+
+
+@pytest.mark.parametrize("ln", MIS_SMALL)
+def test_misiurewicz_parity_small(ln):
+    """Mis(l,n) (eq. def:mis): the same set as the oracle, exact count
+    (eq. MisCount), period n and preperiod l on every root."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    r, g = gpu_split(l, n)
+    assert r.status == msplit.OK, (r.status, r.stats)
+    st = r.stats
+    assert st["phase_fail"] == 0 and st["missing"] == 0 and st["total"] == counts.mis_count(l, n), st
+    o = oracle_split(l, n)
+    compare_sets(g, o)
+    assert np.all(g.period == n) and np.all(g.preperiod == l)
+    assert np.all(np.diff(g.re) >= 0)
+
+
+@pytest.mark.parametrize("ln", [(2, 10), (5, 7), (11, 3)])
+def test_misiurewicz_certificate(ln):
+    """Every returned root certified with its type proven on the disk (no
+    root of q_{l-1,n} or of q_{l,k}, k | n, k < n); the oracle's long-double
+    certificate accepts the same disks' centres."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    r, g = gpu_split(l, n, certify=True)
+    assert r.status == msplit.OK, (r.status, r.stats)
+    st = r.stats
+    assert st["certified"] == len(g) and st["label_proven"] == len(g) and st["overlaps"] == 0, st
+    assert g.radius.max() <= 1e-10
+    ok, rad = oracle.certify(l, n, g.re, g.im)
+    assert np.all(ok == 3)
+
+
+def mis_pairs(max_order):
+    return [(l, s - l) for s in range(3, max_order + 1) for l in range(2, s)]
+
+
+def test_batch_misiurewicz_all_pairs():
+    """Every q_{l,n} with l >= 2, n >= 1, l + n <= 15 (91 pairs) in one
+    batch, certified: exact counts |Mis(l,n)| (eq. MisCount) per pair, every
+    root certified with its type proven, quarter-separated; a sample of each of
+    the largest pairs certified again by the oracle."""
+    from paper_2402_06083_amd import batch
+    pairs = mis_pairs(15)
+    assert len(pairs) == 91
+    say("[gpu] batch of all q_{l,n}, l + n <= 15")
+    res = batch.run_batch(pairs, certify=True)
+    tot = 0
+    for i, ((l, n), (count, st, status)) in enumerate(zip(res.pairs, res.per_pair)):
+        assert status == 0, ((l, n), status, st)
+        assert st["total"] == counts.mis_count(l, n), ((l, n), st)
+        assert st["certified"] == count and st["label_proven"] == count and st["overlaps"] == 0, ((l, n), st)
+        tot += st["total"]
+    say(f"[gpu] C4: {tot} roots, stage ms {res.per_pair[0][1]['ms_stage']}")
+    b = res.bufs
+    rng = np.random.default_rng(22)
+    for (l, n) in [(2, 13), (7, 8), (13, 2)]:
+        sl = b.slices(res.pairs.index((l, n)))
+        re = b.re[sl].cpu().numpy()
+        im = b.im[sl].cpu().numpy()
+        idx = np.sort(rng.choice(len(re), size=min(4000, len(re)), replace=False))
+        ok, rad = oracle.certify(l, n, re[idx], im[idx])
+        assert np.all(ok == 3) and rad.max() <= 1e-10, (l, n)
+
+
 def test_certify_api_and_rejection():
     from paper_2402_06083_amd import msplit
     o = oracle_split(0, 12)
