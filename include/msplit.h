@@ -30,7 +30,12 @@
  * - Roots are returned in the closed upper half plane (Section 6.1: only
  *   Im >= 0 is stored; p_n and q_{l,n} have integer coefficients): a real
  *   root appears once with im == 0 exactly, a non-real root stands for
- *   itself and its conjugate.  Order: increasing real part.
+ *   itself and its conjugate.  Order: increasing real part, to 2^-48 (roots
+ *   closer than that -- only double-double ones next to -2 -- come in start
+ *   order).  Where FP64 cannot separate the roots (next to c = -2) a root is
+ *   a double-double value re + re_lo, im + im_lo (flag MSPLIT_R_DD); give
+ *   re_lo and im_lo to receive the low parts (otherwise such roots are
+ *   returned to FP64 only).
  * - Return value: MSPLIT_OK (0) or a negative msplit_status.  No C++
  *   exception crosses the ABI.
  */
@@ -72,7 +77,9 @@ enum msplit_flags {
 enum msplit_root_flags {
     MSPLIT_R_REAL = 1u,      /* im == 0: the root is real (proven when certified) */
     MSPLIT_R_CERTIFIED = 2u, /* D(root, radius) holds exactly one root of P */
-    MSPLIT_R_LABEL = 4u      /* the period / type label is proven on that disk */
+    MSPLIT_R_LABEL = 4u,     /* the period / type label is proven on that disk */
+    MSPLIT_R_DD = 8u         /* double-double root: the value is re + re_lo, im + im_lo (roots
+                                next to -2 that FP64 cannot separate); certified in double-double */
 };
 
 /* Device workspace, in bytes, that msplit_certify needs (counters and one
@@ -128,6 +135,8 @@ typedef struct msplit_stats {
     uint64_t discarded;     /* identified roots of a lower type dropped by the
                                classification (q_{l,n}: Hyp(k), Mis(j,k) with j < l or
                                k < n; zero for p_n) */
+    uint64_t dd_routed;     /* descents redone in double-double next to -2 */
+    uint64_t steps_dd;      /* polynomial evaluations of those descents */
     double min_sep;         /* least distance found between a root and its conjugate or one
                                of the next 8 roots in real order (upper bound of the least
                                distance; the closest pairs are adjacent in that order) */

@@ -37,6 +37,8 @@ class BatchRunner:
         tot = sum(self.caps)
         self.re = torch.empty(tot, dtype=torch.float64, device=device)
         self.im = torch.empty(tot, dtype=torch.float64, device=device)
+        self.re_lo = torch.empty(tot, dtype=torch.float64, device=device)
+        self.im_lo = torch.empty(tot, dtype=torch.float64, device=device)
         self.period = torch.empty(tot, dtype=torch.int32, device=device)
         self.preperiod = torch.empty(tot, dtype=torch.int32, device=device)
         self.flags = torch.empty(tot, dtype=torch.uint8, device=device)
@@ -44,7 +46,8 @@ class BatchRunner:
         self.caps_arr = (ctypes.c_uint64 * len(self.pairs))(*self.caps)
         self.counts = (ctypes.c_uint64 * len(self.pairs))()
         self.stats = (msplit.Stats * len(self.pairs))()
-        self.roots = msplit.RootsC(self.re.data_ptr(), self.im.data_ptr(), None, None, self.period.data_ptr(),
+        self.roots = msplit.RootsC(self.re.data_ptr(), self.im.data_ptr(), self.re_lo.data_ptr(),
+                                   self.im_lo.data_ptr(), self.period.data_ptr(),
                                    self.preperiod.data_ptr(), self.flags.data_ptr(), self.radius.data_ptr(), tot)
 
     def run(self, stream=None):

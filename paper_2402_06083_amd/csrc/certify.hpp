@@ -24,9 +24,13 @@
 #pragma once
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tip.hpp"
 
 namespace msplit {
 
+// Contraction is switched off in every routine below (DD_EXACT): the
+// rounding bounds count one rounding per written operation.
+//
 // Rounding bound used below: a double r^ = fl(r) rounded to nearest obeys
 // |r^ - r| <= ulp(r^)/2 <= u |r^| + eta with u = 2^-53 (normal results) and
 // eta = 2^-1074 (covers a subnormal result), so the R* term of Thm
@@ -37,20 +41,20 @@ constexpr double ETA = 0x1p-1074;
 
 // x (1 + 2^-47) + 2^-1000: upper bound of a radius expression of at most a
 // few dozen non-negative round-to-nearest operations
-__device__ __forceinline__ double up(double x) { return __dadd_rn(__dmul_rn(x, 1.0 + 0x1p-47), 0x1p-1000); }
-__device__ __forceinline__ double dn(double x) { return __dsub_rn(__dmul_rn(x, 1.0 - 0x1p-47), 0x1p-1000); }
+__device__ __forceinline__ double up(double x) { DD_EXACT return __dadd_rn(__dmul_rn(x, 1.0 + 0x1p-47), 0x1p-1000); }
+__device__ __forceinline__ double dn(double x) { DD_EXACT return __dsub_rn(__dmul_rn(x, 1.0 - 0x1p-47), 0x1p-1000); }
 // upper bound of |a|
 __device__ __forceinline__ double abs_up(cd a)
-{
+{ DD_EXACT
     return up(sqrt(up(__dadd_rn(__dmul_rn(a.re, a.re), __dmul_rn(a.im, a.im)))));
 }
 // lower bound of |a|^2
 __device__ __forceinline__ double abs2_dn(cd a)
-{
+{ DD_EXACT
     return dn(__dadd_rn(__dmul_rn(a.re, a.re), __dmul_rn(a.im, a.im)));
 }
 // bound of the rounding of a complex result a^ (both components)
-__device__ __forceinline__ double rnd(cd a) { return U53 * (fabs(a.re) + fabs(a.im)) + 2.0 * ETA; }
+__device__ __forceinline__ double rnd(cd a) { DD_EXACT return U53 * (fabs(a.re) + fabs(a.im)) + 2.0 * ETA; }
 
 struct disk_step {
     cd Z, DZ;        // centres
@@ -61,7 +65,7 @@ struct disk_step {
 // One step of the orbit over disks: z <- z^2 + c, dz <- 2 z dz + 1, the centres
 // computed with separate IEEE products and sums (no fused multiply-add).
 __device__ __forceinline__ void disk_orbit_step(disk_step &s, cd c, double R)
-{
+{ DD_EXACT
     const double x = s.Z.re, y = s.Z.im, u = s.DZ.re, v = s.DZ.im;
     const double xx = __dmul_rn(x, x), yy = __dmul_rn(y, y), xy = __dmul_rn(x, y);
     const cd sq = {__dsub_rn(xx, yy), __dadd_rn(xy, xy)}; // doubling is exact
@@ -96,7 +100,7 @@ struct cert_result { uint8_t flags; double R; };
 // carries the centres, the point radii e and the disk radii rho, sigma.
 // If the test fails, R grows by 16 (two more attempts).
 __device__ cert_result certify_root(int l, int n, int lab, uint32_t divmask_n, cd c)
-{
+{ DD_EXACT
     const int N = l + n;
     cd P0, dP0;
     eval_q(l, N, c, P0, dP0);
@@ -162,11 +166,126 @@ __device__ cert_result certify_root(int l, int n, int lab, uint32_t divmask_n, c
     return res;
 }
 
+// ------------------------------------------------- double-double centres
+// The same certificate for a double-double candidate c = hi + lo: the centres
+// z_k run in double-double, the derivative centres and every radius in FP64.
+// Each double-double operation on the centres (TwoSum / TwoProd based, with
+// the final renormalisation) is within 2^-100 of the exact result relative to
+// the magnitudes of its operands and result, so the R* term of the squaring
+// step is bounded by U_DD (2|Z|^2 + |c| + |Z^2 + c|); the derivative
+// recurrence uses Z.hi, and the neglected 2 |Z.lo| |DZ| joins its rounding.
+constexpr double U_DD = 0x1p-100;
+
+__device__ __forceinline__ double cdd_abs_up(cdd a)
+{ DD_EXACT
+    return up(abs_up({a.re.hi, a.im.hi}) + up(fabs(a.re.lo) + fabs(a.im.lo)));
+}
+// lower bound of |a| (0 when the bound is not positive)
+__device__ __forceinline__ double cdd_abs_dn(cdd a)
+{ DD_EXACT
+    const double h = dn(sqrt(abs2_dn({a.re.hi, a.im.hi})));
+    return fmax(0.0, dn(h - up(fabs(a.re.lo) + fabs(a.im.lo))));
+}
+
+struct disk_step_dd {
+    cdd Z;
+    cd DZ;
+    double e, rho, sig;
+};
+
+__device__ __forceinline__ void disk_orbit_step_dd(disk_step_dd &s, cdd c, double aC, double R)
+{ DD_EXACT
+    const double aZ = cdd_abs_up(s.Z);
+    const cdd Z1 = cdd_sqr_add(s.Z, c);
+    const double Rsq = up(U_DD * up(2.0 * aZ * aZ + aC + cdd_abs_up(Z1)) + 8.0 * ETA);
+    const double x = s.Z.re.hi, y = s.Z.im.hi, u = s.DZ.re, v = s.DZ.im;
+    const double xu = __dmul_rn(x, u), yv = __dmul_rn(y, v), xv = __dmul_rn(x, v), yu = __dmul_rn(y, u);
+    const cd pr = {__dsub_rn(xu, yv), __dadd_rn(xv, yu)};
+    const cd DZ1 = {__dadd_rn(__dadd_rn(pr.re, pr.re), 1.0), __dadd_rn(pr.im, pr.im)};
+    const double aDZ = abs_up(s.DZ);
+    const double Rpr = up(2.0 * (U53 * (fabs(xu) + fabs(yv) + fabs(xv) + fabs(yu)) + rnd(pr) + 4.0 * ETA) +
+                          U53 * fabs(DZ1.re) + ETA + 2.0 * up(fabs(s.Z.re.lo) + fabs(s.Z.im.lo)) * aDZ);
+    const double e1 = up(s.e * s.e + 2.0 * s.e * aZ + Rsq);
+    const double rho1 = up(s.rho * s.rho + 2.0 * s.rho * aZ + R + Rsq);
+    const double sig1 = up(2.0 * (s.rho * s.sig + s.rho * aDZ + s.sig * aZ) + Rpr);
+    s.Z = Z1;
+    s.DZ = DZ1;
+    s.e = e1;
+    s.rho = rho1;
+    s.sig = sig1;
+}
+
+// rounding bound of a double-double difference (relative U_DD)
+__device__ __forceinline__ double rnd_dd(cdd a) { DD_EXACT return U_DD * cdd_abs_up(a) + 4.0 * ETA; }
+
+__device__ cert_result certify_root_dd(int l, int n, int lab, uint32_t divmask_n, cdd c)
+{ DD_EXACT
+    const int N = l + n;
+    cert_result res = {0, 0.0};
+    const dd_step ns = dd_newton_step(l, N, c);
+    const double s = sqrt(cdd_abs2_hi(ns.s));
+    const double ac = sqrt(c.re.hi * c.re.hi + c.im.hi * c.im.hi);
+    if (!isfinite(s) || !(ns.d2 > 0.0)) return res;
+    double R0 = 4.0 * s + 64.0 * 0x1p-104 * fmax(ac, 0x1p-8);
+    if (!(R0 > 0x1p-1000)) R0 = 0x1p-1000;
+    double R = ldexp(1.0, ilogb(R0) + 1);
+    const double aC = cdd_abs_up(c);
+    const cdd zero = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int attempt = 0; attempt < 3; ++attempt, R *= 16.0) {
+        disk_step_dd t = {zero, {0.0, 0.0}, 0.0, 0.0, 0.0};
+        cdd Zl = zero, Zlm = zero, Zk = zero;
+        cd DZl = {0, 0}, DZk = {0, 0};
+        double el = 0.0, rl = 0.0, sl = 0.0, rlm = 0.0, ek = 0.0, sk = 0.0;
+        bool label_ok = true;
+        for (int k = 0; k < N; ++k) {
+            disk_orbit_step_dd(t, c, aC, R);
+            const int kk = k + 1;
+            if (kk == l - 1) { Zlm = t.Z; rlm = t.rho; }
+            if (kk == l) { Zl = t.Z; DZl = t.DZ; el = t.e; rl = t.rho; sl = t.sig; }
+            if (l == 0) {
+                if (kk == lab) { Zk = t.Z; DZk = t.DZ; ek = t.e; sk = t.sig; }
+                if (kk < lab && lab % kk == 0 && !(cdd_abs_dn(t.Z) > t.rho)) label_ok = false;
+            } else {
+                const int kd = kk - l;
+                if (kd >= 1 && kd < n && ((divmask_n >> kd) & 1u)) {
+                    const cdd d = cdd_sub(t.Z, Zl);
+                    if (!(cdd_abs_dn(d) > up(t.rho + rl + rnd_dd(d)))) label_ok = false;
+                }
+                if (kk == l - 1 + n) {
+                    const cdd d = cdd_sub(t.Z, Zlm);
+                    if (!(cdd_abs_dn(d) > up(t.rho + rlm + rnd_dd(d)))) label_ok = false;
+                }
+            }
+        }
+        const cdd P = cdd_sub(t.Z, Zl);
+        const cd dP = {__dsub_rn(t.DZ.re, DZl.re), __dsub_rn(t.DZ.im, DZl.im)};
+        const double Pup = up(cdd_abs_up(P) + up(t.e + el + rnd_dd(P)));
+        const double sP = up(t.sig + sl + rnd(dP));
+        const double need = up(up(Pup / R) + sP);
+        if (abs2_dn(dP) > up(need * need)) {
+            res.flags = 2;
+            res.R = R;
+            if (l == 0 && lab != n) {
+                const double Pk = up(cdd_abs_up(Zk) + up(ek + rnd_dd(Zk)));
+                const double nk = up(up(Pk / R) + up(sk + rnd(DZk)));
+                if (!(abs2_dn(DZk) > up(nk * nk))) label_ok = false;
+            }
+            if (l > 0 && lab != n) label_ok = false;
+            if (label_ok) res.flags |= 4;
+            return res;
+        }
+    }
+    return res;
+}
+
 // Grid-stride loop over the unique roots (compact index space of
 // batch_args.uniq_offs); counts and the largest radius stay in registers per
 // type and are reduced once per wave at type changes and at the end.
-__global__ void k_certify(batch_args b, const double *re, const double *im, const int32_t *period, uint8_t *flags,
-                          double *radius, int64_t n_uniq)
+// With low parts (re_lo, im_lo non-null) a candidate with a non-zero low
+// part, or one the FP64 certificate cannot settle, gets the double-double
+// certificate; MSPLIT_R_DD marks it.
+__global__ void k_certify(batch_args b, const double *re, const double *im, const double *re_lo,
+                          const double *im_lo, const int32_t *period, uint8_t *flags, double *radius, int64_t n_uniq)
 {
     unsigned long long *const wc = wave_ctr(b);
     type_count nc, nl;
@@ -189,8 +308,13 @@ __global__ void k_certify(batch_args b, const double *re, const double *im, cons
         const int64_t i = td.out_off + (u - b.uniq_offs[t]);
         const cd c = {re[i], im[i]};
         const int lab = period ? period[i] : td.p.n;
-        const cert_result r = certify_root(td.p.l, td.p.n, lab, td.p.divmask_lo, c);
-        flags[i] = (c.im == 0.0 ? 1 : 0) | r.flags;
+        const cd lo = re_lo && im_lo ? cd{re_lo[i], im_lo[i]} : cd{0.0, 0.0};
+        const bool has_lo = lo.re != 0.0 || lo.im != 0.0;
+        cert_result r = {0, 0.0};
+        if (!has_lo) r = certify_root(td.p.l, td.p.n, lab, td.p.divmask_lo, c);
+        const bool use_dd = re_lo && im_lo && (has_lo || !(r.flags & 2));
+        if (use_dd) r = certify_root_dd(td.p.l, td.p.n, lab, td.p.divmask_lo, {{c.re, lo.re}, {c.im, lo.im}});
+        flags[i] = (c.im == 0.0 && lo.im == 0.0 ? 1 : 0) | r.flags | (use_dd ? 8 : 0);
         radius[i] = r.R;
         nc.v += (r.flags & 2) != 0;
         nl.v += (r.flags & 4) != 0;
@@ -213,7 +337,10 @@ __global__ void k_certify(batch_args b, const double *re, const double *im, cons
 // root and its conjugate or one of the next 8 roots in real order (an upper
 // bound of the least distance; the closest pairs of p_n, the leftmost real
 // roots, are adjacent in that order).  radius == nullptr: only the statistic.
-__global__ void k_separation(batch_args b, const double *re, const double *im, const double *radius, int64_t n_uniq)
+// With low parts the distances are taken on hi + lo (the list is ordered by
+// the real part to 2^-48, so closer roots may come in either order).
+__global__ void k_separation(batch_args b, const double *re, const double *im, const double *re_lo,
+                             const double *im_lo, const double *radius, int64_t n_uniq)
 {
     unsigned long long *const wc = wave_ctr(b);
     type_count bad;
@@ -235,15 +362,18 @@ __global__ void k_separation(batch_args b, const double *re, const double *im, c
         const int64_t end = td.out_off + (b.uniq_offs[t + 1] - b.uniq_offs[t]);
         const double rmax =
             radius ? __longlong_as_double((long long)b.ctr[(int64_t)t * C_NCOUNTERS + C_MAX_RAD_BITS]) : 0.0;
+        const bool lo = re_lo && im_lo;
         const double xi = re[i], yi = im[i], Ri = radius ? radius[i] : 0.0;
-        double best = yi > 0.0 ? 2.0 * yi : INFINITY;
-        if (radius && yi != 0.0 && !(yi >= 2.0 * Ri)) bad.v += 1;
+        const double xl = lo ? re_lo[i] : 0.0, yl = lo ? im_lo[i] : 0.0;
+        const double yt = yi + yl;
+        double best = yt > 0.0 ? 2.0 * yt : INFINITY;
+        if (radius && (yi != 0.0 || yl != 0.0) && !(yt >= 2.0 * Ri)) bad.v += 1;
         bool pair_bad = false;
         for (int64_t j = i + 1, c = 0; j < end; ++j, ++c) {
-            const double dx = re[j] - xi;
+            const double dx = (re[j] - xi) + (lo ? re_lo[j] - xl : 0.0);
             const bool need_pair = radius && dx <= 4.0 * (Ri + rmax);
             if (!need_pair && (dx > best || c >= 8)) break;
-            const double dy = im[j] - yi;
+            const double dy = (im[j] - yi) + (lo ? im_lo[j] - yl : 0.0);
             const double d = sqrt(dx * dx + dy * dy);
             best = fmin(best, d);
             if (radius) {
@@ -259,6 +389,62 @@ __global__ void k_separation(batch_args b, const double *re, const double *im, c
     }
     flush_count(wc, C_OVERLAP, bad);
     wave_reduce_by_key<RED_MIN>(wc, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);
+}
+
+// ---------------------------------------------------------- classification
+// Threads run over the collected index space (bounded by m on the host; the
+// count itself, coll_offs[T], is read on the device).  keep[u] selects the
+// roots of the output set, cls[u] is the period (p_n) or n (q_{l,n}).
+//
+// q_{l,n}: a candidate near a centre Hyp(k), k | n, may be a descent stalled
+// inside the rounding-noise ball of that multiple root (Thm fact_mis), where
+// q evaluates to noise -- even to an exact zero, which passes as converged --
+// and neither the step ratio nor any fixed distance tells it from a genuine
+// root.  q ~ C d^eta at distance d from a root of multiplicity
+// eta = eta_l(k) = floor((l-1)/k) + 2, so the ball has radius about
+// eps^(1/eta): 1e-4 in FP64 for eta = 4, 0.2 for the centre 0 of q_{20,2}
+// (eta = 21).  Thm proofRoots settles it: it certifies exactly one root
+// counted with multiplicity, which a multiple root never passes, so a
+// candidate within max(NEAR_CENTRE, 2^(-50/eta)) of a centre is kept only
+// when the certificate (FP64, else double-double) holds on it.
+constexpr double NEAR_CENTRE = 1e-3;
+
+__global__ void __launch_bounds__(256) k_classify(batch_args b, const cd *uz, const cd *uz_lo, const uint8_t *uz_dd,
+                                                  uint32_t *keep, int32_t *cls, int64_t m, int labels)
+{
+    __shared__ int64_t offs[MAX_TYPES + 1];
+    for (int i = threadIdx.x; i <= b.T; i += blockDim.x) offs[i] = b.coll_offs[i];
+    __syncthreads();
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= m) return;
+    if (u >= offs[b.T]) { keep[u] = 0; return; }
+    const int t = find_type_lds(offs, b.T, u);
+    const plan_t &pl = b.types[t].p;
+    const cd c = uz[u];
+    const bool dd = uz_dd[u];
+    const cd lo = dd ? uz_lo[u] : cd{0.0, 0.0};
+    const cdd cc = {{c.re, lo.re}, {c.im, lo.im}};
+    uint32_t k = 1;
+    int per = pl.n;
+    if (pl.l == 0) {
+        if (labels) per = dd ? classify_p_dd(pl.n, pl.divmask_lo, pl.tau_dd, cc) : classify_p(pl.n, pl.divmask_lo, pl.tau, c);
+    } else {
+        double hmin2 = INFINITY;
+        int kmin = pl.n;
+        bool kq = dd ? classify_q_dd(pl.l, pl.n, pl.divmask_lo, pl.tau_dd, cc, hmin2, kmin)
+                     : classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c, hmin2, kmin);
+        const int eta = (pl.l - 1) / kmin + 2;
+        const double w = fmax(NEAR_CENTRE, exp2(-50.0 / eta));
+        if (kq && hmin2 < w * w) {
+            cert_result r = {0, 0.0};
+            if (!dd) r = certify_root(pl.l, pl.n, pl.n, pl.divmask_lo, c);
+            if (!(r.flags & 2)) r = certify_root_dd(pl.l, pl.n, pl.n, pl.divmask_lo, cc);
+            kq = (r.flags & 2) != 0;
+        }
+        k = kq ? 1u : 0u;
+    }
+    keep[u] = k;
+    cls[u] = per;
 }
 
 } // namespace msplit

@@ -30,15 +30,17 @@
 namespace msplit {
 
 // status of a descent
-enum : uint8_t { ST_NONE = 0, ST_CONVERGED = 1, ST_DIVERGED = 2, ST_TIMEOUT = 3 };
+// ST_DD: converged in double-double (the low parts are in roots_lo)
+enum : uint8_t { ST_NONE = 0, ST_CONVERGED = 1, ST_DIVERGED = 2, ST_TIMEOUT = 3, ST_DD = 4 };
+__device__ __forceinline__ bool st_converged(uint8_t s) { return s == ST_CONVERGED || s == ST_DD; }
 
 // global counters
-enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_NCOUNTERS = 8 };
+enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_DD_COUNT, G_DD_NEXT, G_NCOUNTERS = 8 };
 // per-type counters (uint64 slots, C_NCOUNTERS per type)
 enum {
     C_CONVERGED = 0, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL, C_SEED_FAIL, C_STEPS_LIFT, C_STEPS_WALK,
     C_STEPS_DESC, C_STEPS_FP32, C_UNIQUE, C_REAL, C_CERTIFIED, C_LABEL, C_OVERLAP, C_MIN_SEP_BITS,
-    C_MAX_RAD_BITS, C_SURVIVORS, C_KEPT, C_NCOUNTERS = 20
+    C_MAX_RAD_BITS, C_SURVIVORS, C_KEPT, C_DD_ROUTED, C_STEPS_DD, C_NCOUNTERS = 20
 };
 
 struct plan_t {
@@ -53,6 +55,8 @@ struct plan_t {
     double level;         // lambda_0
     double tau;           // nset identification radius
     double tol_desc;      // relative step of a converged descent
+    double x_tip;         // |c + 2| below which descents are redone in double-double (0: none)
+    double tau_dd;        // identification radius between double-double roots
     uint32_t divmask_lo;  // bit k set when k | n, k < n (k < 32)
     int precision;
     float fp32_switch;
@@ -346,7 +350,7 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
 // keeps its FP64 value untouched.  The FP64 pass then continues every start
 // not discarded in FP32, counting the FP32 steps against the cap.  Each pass
 // is precision-uniform, so no wave runs both code paths.
-__global__ void k_descend32(batch_args b, cd *roots, uint8_t *status, uint8_t *iters)
+__global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *status, uint8_t *iters)
 {
     unsigned long long *const wc = wave_ctr(b);
     type_count steps32, ndiv, ntime;
@@ -379,7 +383,7 @@ __global__ void k_descend32(batch_args b, cd *roots, uint8_t *status, uint8_t *i
                     pl_sw = pl.fp32_switch;
                 }
                 change = steps32.t != t;
-                const cd zd = roots[g];
+                const cd zd = starts[g];
                 z = {(float)zd.re, (float)zd.im};
                 it = 0;
                 prev = 0.f;
@@ -416,7 +420,7 @@ __global__ void k_descend32(batch_args b, cd *roots, uint8_t *status, uint8_t *i
             prev = a2;
         }
         if (handoff || st != ST_NONE) {
-            if (it > 0) roots[g] = {(double)z.re, (double)z.im};
+            roots[g] = it > 0 ? cd{(double)z.re, (double)z.im} : starts[g];
             status[g] = st;
             iters[g] = (uint8_t)it;
             ndiv.v += st == ST_DIVERGED;
@@ -435,7 +439,8 @@ __global__ void k_descend32(batch_args b, cd *roots, uint8_t *status, uint8_t *i
 // type tag for the four 32-bit counts, branch-free status selection) so that
 // the kernel fits 64 VGPRs: 8 waves per SIMD hide the load of a new start
 // and the FP64 dependency latency of the orbit loop.
-__global__ void __launch_bounds__(256) k_descend(batch_args b, cd *roots, uint8_t *status, const uint8_t *iters)
+__global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd *roots, uint8_t *status,
+                                                 const uint8_t *iters)
 {
     constexpr uint32_t NONE = 0xffffffffu;
     unsigned long long *const wc = wave_ctr(b);
@@ -474,7 +479,7 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, cd *roots, uint8_
                     pl_cap = pl.cap;
                     pl_tol2 = pl.tol_desc * pl.tol_desc;
                 }
-                z = roots[g];
+                z = src[g];
                 it0 = it = iters ? iters[g] : 0;
                 prev = 0.0;
                 fin = false;
@@ -548,6 +553,33 @@ __device__ __forceinline__ cd fold_snap(cd z, double tau)
     return z;
 }
 
+// The same for a double-double root (hi, lo): the sign of the imaginary part
+// is that of hi + lo; snapped below the double-double rounding level.
+__device__ __forceinline__ void fold_snap_dd(cd &hi, cd &lo, double tau_dd)
+{
+    if (hi.im < 0.0 || (hi.im == 0.0 && lo.im < 0.0)) {
+        hi.im = -hi.im;
+        lo.im = -lo.im;
+    }
+    if (hi.im + lo.im < fmin(0.5 * tau_dd, 0x1p-96 * fmax(fabs(hi.re), 0x1p-8))) {
+        hi.im = 0.0;
+        lo.im = 0.0;
+    }
+}
+
+// nset identification of two folded roots: within tau_dd in both coordinates
+// when both are double-double (differences of hi parts are exact for close
+// values), else within tau on the FP64 parts.
+__device__ __forceinline__ bool same_root(cd a, cd alo, bool add, cd b, cd blo, bool bdd, double tau, double tau_dd)
+{
+    if (add && bdd) {
+        const double dr = (a.re - b.re) + (alo.re - blo.re);
+        const double di = (a.im - b.im) + (alo.im - blo.im);
+        return fabs(dr) < tau_dd && fabs(di) < tau_dd;
+    }
+    return fabs(a.re - b.re) < tau && fabs(a.im - b.im) < tau;
+}
+
 // Type of item g from a copy of the offsets in LDS (T + 1 entries).
 __device__ __forceinline__ int find_type_lds(const int64_t *offs, int T, int64_t g)
 {
@@ -562,14 +594,17 @@ __device__ __forceinline__ int find_type_lds(const int64_t *offs, int T, int64_t
 // LDS copies of the start offsets and of each type's identification radius
 struct collect_tables {
     int64_t offs[MAX_TYPES + 1];
-    double tau[MAX_TYPES];
+    double tau[MAX_TYPES], tau_dd[MAX_TYPES];
 };
 
 __device__ __forceinline__ void load_tables_lds(collect_tables &c, const batch_args &b)
 {
     for (int i = threadIdx.x; i <= b.T; i += blockDim.x) {
         c.offs[i] = b.start_offs[i];
-        if (i < b.T) c.tau[i] = b.types[i].p.tau;
+        if (i < b.T) {
+            c.tau[i] = b.types[i].p.tau;
+            c.tau_dd[i] = b.types[i].p.tau_dd;
+        }
     }
 }
 
@@ -583,12 +618,13 @@ __device__ __forceinline__ void load_tables_lds(collect_tables &c, const batch_a
 constexpr int PREKEY_WINDOW = 8;
 constexpr int COLLECT_BLOCK = 256;
 
-__global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const cd *roots, const uint8_t *status,
-                                                           uint32_t *flag)
+__global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const cd *roots, const cd *roots_lo,
+                                                           const uint8_t *status, uint32_t *flag)
 {
     __shared__ collect_tables tabs;
-    __shared__ cd zs[COLLECT_BLOCK + PREKEY_WINDOW];
+    __shared__ cd zs[COLLECT_BLOCK + PREKEY_WINDOW], zl[COLLECT_BLOCK + PREKEY_WINDOW];
     __shared__ int ts[COLLECT_BLOCK + PREKEY_WINDOW]; // type, or -1: not converged
+    __shared__ uint8_t dds[COLLECT_BLOCK + PREKEY_WINDOW];
     const int64_t base = (int64_t)blockIdx.x * COLLECT_BLOCK - PREKEY_WINDOW;
     const int64_t g0 = base + threadIdx.x, g1 = base + COLLECT_BLOCK + threadIdx.x;
     const bool has1 = threadIdx.x < PREKEY_WINDOW;
@@ -597,16 +633,24 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
     const cd z0 = v0 ? roots[g0] : cd{0.0, 0.0}, z1 = v1 ? roots[g1] : cd{0.0, 0.0};
     load_tables_lds(tabs, b);
     __syncthreads();
-    {
-        const int t = s0 == ST_CONVERGED ? find_type_lds(tabs.offs, b.T, g0) : -1;
-        ts[threadIdx.x] = t;
-        zs[threadIdx.x] = t >= 0 ? fold_snap(z0, tabs.tau[t]) : z0;
-    }
-    if (has1) {
-        const int t = s1 == ST_CONVERGED ? find_type_lds(tabs.offs, b.T, g1) : -1;
-        ts[COLLECT_BLOCK + threadIdx.x] = t;
-        zs[COLLECT_BLOCK + threadIdx.x] = t >= 0 ? fold_snap(z1, tabs.tau[t]) : z1;
-    }
+    auto stage = [&](int i, int64_t g, uint8_t st, cd z) {
+        const int t = st_converged(st) ? find_type_lds(tabs.offs, b.T, g) : -1;
+        cd lo = {0.0, 0.0};
+        if (t >= 0) {
+            if (st == ST_DD) {
+                lo = roots_lo[g];
+                fold_snap_dd(z, lo, tabs.tau_dd[t]);
+            } else {
+                z = fold_snap(z, tabs.tau[t]);
+            }
+        }
+        ts[i] = t;
+        zs[i] = z;
+        zl[i] = lo;
+        dds[i] = st == ST_DD;
+    };
+    stage(threadIdx.x, g0, s0, z0);
+    if (has1) stage(COLLECT_BLOCK + threadIdx.x, g1, s1, z1);
     __syncthreads();
     const int64_t g = (int64_t)blockIdx.x * COLLECT_BLOCK + threadIdx.x;
     if (g >= b.n_starts) return;
@@ -614,13 +658,13 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
     const int t = ts[i];
     uint32_t f = 0;
     if (t >= 0) {
-        const double tau = tabs.tau[t];
-        const cd z = zs[i];
+        const double tau = tabs.tau[t], tdd = tabs.tau_dd[t];
+        const cd z = zs[i], lo = zl[i];
+        const bool dd = dds[i];
         f = 1;
         for (int d = 1; d <= PREKEY_WINDOW; ++d) {
             if (ts[i - d] != t) continue;
-            const cd y = zs[i - d];
-            if (fabs(y.re - z.re) < tau && fabs(y.im - z.im) < tau) { f = 0; break; }
+            if (same_root(z, lo, dd, zs[i - d], zl[i - d], dds[i - d], tau, tdd)) { f = 0; break; }
         }
     }
     flag[g] = f;
@@ -648,33 +692,46 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const c
 
 // The sorted candidates, folded and snapped, in sort order: one gather, so
 // that the identification and the output pass read them in sequence.
-__global__ void k_gather(batch_args b, const cd *roots, const uint64_t *keys, const uint32_t *vals, cd *zs,
-                         int64_t m)
+__global__ void k_gather(batch_args b, const cd *roots, const cd *roots_lo, const uint8_t *status,
+                         const uint64_t *keys, const uint32_t *vals, cd *zs, cd *zs_lo, uint8_t *zs_dd, int64_t m)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    zs[i] = fold_snap(roots[vals[i]], b.types[key_type(keys[i])].p.tau);
+    const uint32_t v = vals[i];
+    const plan_t &pl = b.types[key_type(keys[i])].p;
+    cd z = roots[v], lo = {0.0, 0.0};
+    const bool dd = status[v] == ST_DD;
+    if (dd) {
+        lo = roots_lo[v];
+        fold_snap_dd(z, lo, pl.tau_dd);
+    } else {
+        z = fold_snap(z, pl.tau);
+    }
+    zs[i] = z;
+    zs_lo[i] = lo;
+    zs_dd[i] = dd;
 }
 
-// A sorted point is a duplicate when an earlier point of the same type lies
-// within tau in both coordinates (the nset identification, the first point of
-// a cluster kept).  The backward scan stops at the key window (real parts
-// tau apart) or after 256 points.
-__global__ void k_mark(batch_args b, const uint64_t *keys, const cd *zs, uint32_t *flag, int64_t m)
+// A sorted point is a duplicate when an earlier point of the same type is the
+// same root (same_root: the nset identification, the first point of a
+// cluster kept).  The backward scan stops at the key window (real parts tau
+// apart) or after 256 points.
+__global__ void k_mark(batch_args b, const uint64_t *keys, const cd *zs, const cd *zs_lo, const uint8_t *zs_dd,
+                       uint32_t *flag, int64_t m)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const uint64_t ki = keys[i];
     const int t = key_type(ki);
-    const double tau = b.types[t].p.tau;
+    const double tau = b.types[t].p.tau, tdd = b.types[t].p.tau_dd;
     const uint64_t win = key_window(tau);
-    const cd zi = zs[i];
+    const cd zi = zs[i], li = zs_lo[i];
+    const bool di = zs_dd[i];
     uint32_t f = 1;
     for (int64_t j = i - 1, c = 0; j >= 0 && c < 256; --j, ++c) {
         const uint64_t kj = keys[j];
         if (key_type(kj) != t || ki - kj >= win) break;
-        const cd zj = zs[j];
-        if (fabs(zi.re - zj.re) < tau && fabs(zi.im - zj.im) < tau) { f = 0; break; }
+        if (same_root(zi, li, di, zs[j], zs_lo[j], zs_dd[j], tau, tdd)) { f = 0; break; }
     }
     flag[i] = f;
 }
@@ -709,10 +766,16 @@ __global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t
 
 // The identified roots into the collected index space (type-major, by real
 // part within a type).
-__global__ void k_scatter(const uint32_t *flag, const uint32_t *pos, const cd *zs, int64_t m, cd *uz)
+__global__ void k_scatter(const uint32_t *flag, const uint32_t *pos, const cd *zs, const cd *zs_lo,
+                          const uint8_t *zs_dd, int64_t m, cd *uz, cd *uz_lo, uint8_t *uz_dd)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m && flag[i]) uz[pos[i]] = zs[i];
+    if (i < m && flag[i]) {
+        const uint32_t u = pos[i];
+        uz[u] = zs[i];
+        uz_lo[u] = zs_lo[i];
+        uz_dd[u] = zs_dd[i];
+    }
 }
 
 // ---------------------------------------------------------- classification
@@ -776,7 +839,8 @@ __device__ __noinline__ bool stalled_at_multiple_root(int l, int n, int k, cd c)
     return !(64.0 * 64.0 * s2 < h2);
 }
 
-__device__ __forceinline__ bool classify_q(int l, int n, uint32_t divmask, double tau, cd c)
+__device__ __forceinline__ bool classify_q(int l, int n, uint32_t divmask, double tau, cd c, double &hmin2_out,
+                                           int &kmin_out)
 {
     orbit_state<double> s = {0.0, 0.0, 0.0, 0.0};
     double zlm_r = 0.0, zlm_i = 0.0, dlm_r = 0.0, dlm_i = 0.0; // z_{l-1}, dz_{l-1}
@@ -802,33 +866,70 @@ __device__ __forceinline__ bool classify_q(int l, int n, uint32_t divmask, doubl
             keep = false; // Mis(j,n), j < l
     }
     if (keep && hmin2 < 1e-12 && stalled_at_multiple_root(l, n, kmin, c)) keep = false;
+    hmin2_out = hmin2;
+    kmin_out = kmin;
     return keep;
 }
 
-// Threads run over the collected index space (bounded by m on the host; the
-// count itself, coll_offs[T], is read on the device).  keep[u] selects the
-// roots of the output set, cls[u] is the period (p_n) or n (q_{l,n}).
-__global__ void __launch_bounds__(256) k_classify(batch_args b, const cd *uz, uint32_t *keep, int32_t *cls,
-                                                  int64_t m, int labels)
+// The same classifications for a double-double root: the orbit z_k in
+// double-double, its derivative in FP64 (a Newton distance |A / B| only needs
+// B to FP64 accuracy), identification radius tau_dd.
+__device__ __forceinline__ bool dd_dist_below(cdd a, double br, double bi, double tau)
 {
-    __shared__ int64_t offs[MAX_TYPES + 1];
-    for (int i = threadIdx.x; i <= b.T; i += blockDim.x) offs[i] = b.coll_offs[i];
-    __syncthreads();
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= m) return;
-    if (u >= offs[b.T]) { keep[u] = 0; return; }
-    const int t = find_type_lds(offs, b.T, u);
-    const plan_t &pl = b.types[t].p;
-    const cd c = uz[u];
-    uint32_t k = 1;
-    int per = pl.n;
-    if (pl.l == 0) {
-        if (labels) per = classify_p(pl.n, pl.divmask_lo, pl.tau, c);
-    } else {
-        k = classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c) ? 1u : 0u;
+    return cdd_abs2_hi(a) < tau * tau * (br * br + bi * bi);
+}
+
+__device__ int classify_p_dd(int n, uint32_t divmask, double tau, cdd c)
+{
+    cdd z = {{0.0, 0.0}, {0.0, 0.0}};
+    double dr = 0.0, di = 0.0;
+    for (int k = 1; k < n; ++k) {
+        const double tr = z.re.hi * dr - z.im.hi * di, ti = z.re.hi * di + z.im.hi * dr;
+        dr = 2.0 * tr + 1.0;
+        di = 2.0 * ti;
+        z = cdd_sqr_add(z, c);
+        if (((divmask >> k) & 1u) && dd_dist_below(z, dr, di, tau)) return k;
     }
-    keep[u] = k;
-    cls[u] = per;
+    return n;
+}
+
+// Inside the rounding-noise ball of a multiple root q evaluates to noise
+// (even to exactly 0), so the step ratio can miss a point stalled there; the
+// caller settles every candidate near a centre with the certificate.
+__device__ bool classify_q_dd(int l, int n, uint32_t divmask, double tau, cdd c, double &hmin2_out, int &kmin_out)
+{
+    const cdd zero = {{0.0, 0.0}, {0.0, 0.0}};
+    cdd z = zero, zlm = zero, zl = zero;
+    double dr = 0.0, di = 0.0, dlm_r = 0.0, dlm_i = 0.0, dl_r = 0.0, dl_i = 0.0;
+    bool keep = true;
+    double hmin2 = INFINITY;
+    int kmin = n;
+    const int N = l + n;
+    for (int i = 1; i <= N; ++i) {
+        const double tr = z.re.hi * dr - z.im.hi * di, ti = z.re.hi * di + z.im.hi * dr;
+        dr = 2.0 * tr + 1.0;
+        di = 2.0 * ti;
+        z = cdd_sqr_add(z, c);
+        if (i <= n && (i == n || ((divmask >> i) & 1u))) {
+            const double h2 = cdd_abs2_hi(z) / (dr * dr + di * di);
+            if (h2 < hmin2) { hmin2 = h2; kmin = i; }
+            if (dd_dist_below(z, dr, di, tau)) keep = false; // Hyp(i)
+        }
+        if (i == l - 1) { zlm = z; dlm_r = dr; dlm_i = di; }
+        if (i == l) { zl = z; dl_r = dr; dl_i = di; }
+        const int k = i - l;
+        if (k >= 1 && k < n && ((divmask >> k) & 1u) && dd_dist_below(cdd_sub(z, zl), dr - dl_r, di - dl_i, tau))
+            keep = false; // Mis(j,k), k < n
+        if (i == l - 1 + n && dd_dist_below(cdd_sub(z, zlm), dr - dlm_r, di - dlm_i, tau))
+            keep = false; // Mis(j,n), j < l
+    }
+    // next to a multiple root (Hyp(k)): step of q within 64 times the p_k distance
+    const cdd q = cdd_sub(z, zl);
+    const double s2 = cdd_abs2_hi(q) / ((dr - dl_r) * (dr - dl_r) + (di - dl_i) * (di - dl_i));
+    if (keep && hmin2 < 1e-12 && !(64.0 * 64.0 * s2 < hmin2)) keep = false;
+    hmin2_out = hmin2;
+    kmin_out = kmin;
+    return keep;
 }
 
 // Per type: first index in the kept index space; kept count in C_KEPT.
@@ -847,8 +948,9 @@ __global__ void k_kept_bounds(batch_args b, const uint32_t *keep, const uint32_t
 
 // Kept roots to the caller's output slices (at most the capacity of each),
 // with period, preperiod and the real flag; real roots counted per type.
-__global__ void __launch_bounds__(256) k_emit(batch_args b, const cd *uz, const uint32_t *keep, const uint32_t *kpos,
-                                              const int32_t *cls, int64_t m, double *ore, double *oim,
+__global__ void __launch_bounds__(256) k_emit(batch_args b, const cd *uz, const cd *uz_lo, const uint8_t *uz_dd,
+                                              const uint32_t *keep, const uint32_t *kpos, const int32_t *cls,
+                                              int64_t m, double *ore, double *oim, double *ore_lo, double *oim_lo,
                                               int32_t *period, int32_t *preperiod, uint8_t *flags)
 {
     __shared__ int64_t offs[MAX_TYPES + 1];
@@ -866,11 +968,15 @@ __global__ void __launch_bounds__(256) k_emit(batch_args b, const cd *uz, const 
         const cd z = uz[u];
         if ((uint64_t)rank < td.cap) {
             const int64_t i = td.out_off + rank;
+            const bool dd = uz_dd[u];
+            const cd lo = dd ? uz_lo[u] : cd{0.0, 0.0};
             ore[i] = z.re;
             oim[i] = z.im;
+            if (ore_lo) ore_lo[i] = lo.re;
+            if (oim_lo) oim_lo[i] = lo.im;
             if (period) period[i] = cls[u];
             if (preperiod) preperiod[i] = td.p.l;
-            if (flags) flags[i] = z.im == 0.0 ? 1 : 0;
+            if (flags) flags[i] = (z.im == 0.0 ? 1 : 0) | (dd ? 8 : 0); // MSPLIT_R_REAL, MSPLIT_R_DD
         }
         nreal.v = z.im == 0.0;
     }

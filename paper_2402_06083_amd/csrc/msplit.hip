@@ -104,6 +104,12 @@ plan_t make_plan(int l, int n, const msplit_options *o)
     double sep = 118.4 * pow(4.0, -(double)p.N);
     p.tau = std::min(1e-12, sep / 32.0);
     p.tol_desc = 0x1p-46;
+    // double-double route next to -2 (Section 6.3.2): the real Misiurewicz
+    // parameters at the left end of M pair up closer than FP64 resolves from
+    // order about 18 on (their gap shrinks like 8^-N); a generous tip radius
+    // keeps every FP64 root outside it far from its neighbours
+    p.x_tip = (l >= 2 && p.N >= 14) ? 0x1p-14 : 0.0;
+    p.tau_dd = 0x1p-90;
     p.divmask_lo = divisor_mask(n);
     p.precision = o->precision;
     p.fp32_switch = o->fp32_switch > 0 ? (float)o->fp32_switch : 0x1p-14f;
@@ -167,7 +173,7 @@ int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uin
 
 // ------------------------------------------------------------- workspace
 struct layout {
-    size_t gctr, ctr, spread, zs, types, offs, tb, seeds, starts, status, iters, segf, flag0, pos0, keys, vals, keys2, vals2,
+    size_t gctr, ctr, spread, zs, zs_lo, roots, roots_lo, types, offs, tb, seeds, starts, status, iters, segf, flag0, pos0, keys, vals, keys2, vals2,
         flag, pos, temp, total;
     size_t temp_bytes;
 };
@@ -219,6 +225,9 @@ layout make_layout(const batch_plan &bp, size_t temp_bytes)
     L.vals = take(4 * NS);
     L.keys2 = take(8 * NS);
     L.zs = take(sizeof(cd) * NS);
+    L.zs_lo = take(sizeof(cd) * NS);
+    L.roots = take(sizeof(cd) * NS);
+    L.roots_lo = take(sizeof(cd) * NS);
     L.vals2 = take(4 * NS);
     L.flag = take(4 * NS);
     L.pos = take(4 * NS);
@@ -396,7 +405,8 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     uint8_t *segf = (uint8_t *)(ws + L.segf);
     uint32_t *flag0 = (uint32_t *)(ws + L.flag0), *pos0 = (uint32_t *)(ws + L.pos0);
     uint64_t *keys = (uint64_t *)(ws + L.keys), *keys2 = (uint64_t *)(ws + L.keys2);
-    cd *zs = (cd *)(ws + L.zs);
+    cd *zs = (cd *)(ws + L.zs), *zs_lo = (cd *)(ws + L.zs_lo);
+    cd *roots = (cd *)(ws + L.roots), *roots_lo = (cd *)(ws + L.roots_lo);
     uint32_t *vals = (uint32_t *)(ws + L.vals), *vals2 = (uint32_t *)(ws + L.vals2);
     uint32_t *flag = (uint32_t *)(ws + L.flag), *pos = (uint32_t *)(ws + L.pos);
     void *temp = ws + L.temp;
@@ -487,19 +497,28 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
 
     // descents (MIXED: an FP32 pass first)
     if (opts->precision == MSPLIT_MIXED) {
-        k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, status, iters);
-        k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, status, iters);
+        k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, roots, status, iters);
+        k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, roots, roots, status, iters);
     } else {
-        k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, status, nullptr);
+        k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, roots, status, nullptr);
+    }
+    // double-double route next to -2: the routed starts descend again from
+    // their starting points (the list lives in flag0 until the collection)
+    bool any_tip = false;
+    for (int t = 0; t < T; ++t) any_tip = any_tip || bp.td[t].p.x_tip > 0.0;
+    if (any_tip) {
+        k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, roots, status, flag0);
+        k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, flag0, starts, roots, roots_lo, status);
     }
     CHK(hipEventRecord(ev.e[3], stream));
     // nset collection: local identification, compaction, sort, global
     // identification, per-type output slices
-    k_prekeys<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, starts, status, flag0);
+    k_prekeys<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, roots, roots_lo, status,
+                                                                                    flag0);
     size_t tb_bytes = temp_bytes;
     CHK(rocprim::exclusive_scan(temp, tb_bytes, flag0, pos0, 0u, (size_t)bp.n_starts, rocprim::plus<uint32_t>(),
                                 stream));
-    k_compact<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, starts, flag0, pos0, keys, vals,
+    k_compact<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, roots, flag0, pos0, keys, vals,
                                                                                     gctr + G_COMPACT);
     CHK(hipGetLastError());
     unsigned long long m_h = 0;
@@ -510,16 +529,18 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         tb_bytes = temp_bytes;
         CHK(rocprim::radix_sort_pairs(temp, tb_bytes, keys, keys2, vals, vals2, (size_t)m, 0, key_end_bit(T),
                                       stream));
-        k_gather<<<blocks_for(m, 256), 256, 0, stream>>>(ba, starts, keys2, vals2, zs, m);
-        k_mark<<<blocks_for(m, 256), 256, 0, stream>>>(ba, keys2, zs, flag, m);
+        k_gather<<<blocks_for(m, 256), 256, 0, stream>>>(ba, roots, roots_lo, status, keys2, vals2, zs, zs_lo, iters,
+                                                         m);
+        k_mark<<<blocks_for(m, 256), 256, 0, stream>>>(ba, keys2, zs, zs_lo, iters, flag, m);
         tb_bytes = temp_bytes;
         CHK(rocprim::exclusive_scan(temp, tb_bytes, flag, pos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
     }
     k_type_bounds<<<1, 256, 0, stream>>>(ba, keys2, flag, pos, m, tb);
-    // the identified roots into the collected index space; the descent
-    // results (starts) are no longer needed once gathered
-    cd *uz = starts;
-    if (m > 0) k_scatter<<<blocks_for(m, 256), 256, 0, stream>>>(flag, pos, zs, m, uz);
+    // the identified roots into the collected index space; the starts, the
+    // descent results and their status are no longer needed once gathered
+    cd *uz = starts, *uz_lo = roots_lo;
+    uint8_t *uz_dd = status;
+    if (m > 0) k_scatter<<<blocks_for(m, 256), 256, 0, stream>>>(flag, pos, zs, zs_lo, iters, m, uz, uz_lo, uz_dd);
     CHK(hipEventRecord(ev.e[4], stream));
     CHK(hipGetLastError());
 
@@ -529,14 +550,15 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     int32_t *cls = (int32_t *)vals2;
     const bool labels = !(opts->flags & MSPLIT_F_NO_LABEL);
     if (m > 0) {
-        k_classify<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, keep, cls, m, labels ? 1 : 0);
+        k_classify<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, cls, m, labels ? 1 : 0);
         tb_bytes = temp_bytes;
         CHK(rocprim::exclusive_scan(temp, tb_bytes, keep, kpos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
     }
     k_kept_bounds<<<1, 256, 0, stream>>>(ba, keep, kpos);
     if (m > 0)
-        k_emit<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, keep, kpos, cls, m, out->re, out->im,
-                                                      labels ? out->period : nullptr, out->preperiod, out->flags);
+        k_emit<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, kpos, cls, m, out->re, out->im,
+                                                      out->re_lo, out->im_lo, labels ? out->period : nullptr,
+                                                      out->preperiod, out->flags);
     CHK(hipGetLastError());
     CHK(read_counters());
 
@@ -561,13 +583,15 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     if (n_uniq) {
         if (cert) {
             k_certify<<<persistent_blocks(n_uniq, 128), 128, 0, stream>>>(
-                ba, out->re, out->im, (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period, out->flags,
-                out->radius, n_uniq);
+                ba, out->re, out->im, out->re_lo, out->im_lo,
+                (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period, out->flags, out->radius, n_uniq);
             // k_separation reads the largest radius of each type
             k_fold_counters<<<blocks_for((int64_t)T * C_NCOUNTERS, 256), 256, 0, stream>>>(ctr, spread, T);
-            k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, out->radius, n_uniq);
+            k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, out->re_lo,
+                                                                             out->im_lo, out->radius, n_uniq);
         } else {
-            k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, nullptr, n_uniq);
+            k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, out->re_lo,
+                                                                             out->im_lo, nullptr, n_uniq);
         }
     }
     CHK(hipEventRecord(ev.e[6], stream));
@@ -606,6 +630,8 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         s.steps_fp32 = H(t, C_STEPS_FP32);
         s.sorted = H(t, C_SURVIVORS);
         s.discarded = H(t, C_UNIQUE) - uniq;
+        s.dd_routed = H(t, C_DD_ROUTED);
+        s.steps_dd = H(t, C_STEPS_DD);
         unsigned long long ms_bits = H(t, C_MIN_SEP_BITS), mr_bits = H(t, C_MAX_RAD_BITS);
         memcpy(&s.min_sep, &ms_bits, 8);
         memcpy(&s.max_radius, &mr_bits, 8);
@@ -746,11 +772,12 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
     k_init_counters<<<blocks_for((int64_t)C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
         gctr, ctr, spread, 1);
     if (count) {
-        k_certify<<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(ba, roots->re, roots->im, roots->period,
-                                                                       roots->flags, roots->radius, (int64_t)count);
+        k_certify<<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(
+            ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->period, roots->flags, roots->radius,
+            (int64_t)count);
         k_fold_counters<<<1, 64, 0, stream>>>(ctr, spread, 1);
-        k_separation<<<persistent_blocks((int64_t)count, 256), 256, 0, stream>>>(ba, roots->re, roots->im, roots->radius,
-                                                                          (int64_t)count);
+        k_separation<<<persistent_blocks((int64_t)count, 256), 256, 0, stream>>>(
+            ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->radius, (int64_t)count);
     }
     k_fold_counters<<<1, 64, 0, stream>>>(ctr, spread, 1);
     CHK(hipGetLastError());

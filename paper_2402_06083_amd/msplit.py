@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmsplit.so")
 OK, E_ARG, E_CAPACITY, E_WORKSPACE, E_DEVICE, E_INCOMPLETE, E_PRECISION, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED, DD = 0, 1, 2
 F_CERTIFY, F_NO_LABEL = 1, 2
-R_REAL, R_CERTIFIED, R_LABEL = 1, 2, 4
+R_REAL, R_CERTIFIED, R_LABEL, R_DD = 1, 2, 4, 8
 CERTIFY_WORKSPACE = 16384  # MSPLIT_CERTIFY_WORKSPACE
 
 
@@ -48,7 +48,8 @@ class RootsC(ctypes.Structure):
 
 _STAT_U64 = ["starts", "converged", "diverged", "timeouts", "unique", "n_real", "total", "expected",
              "missing", "phase_fail", "certified", "label_proven", "overlaps", "steps_lift",
-             "steps_walk", "steps_desc", "steps_fp32", "sorted", "discarded"]
+             "steps_walk", "steps_desc", "steps_fp32", "sorted", "discarded", "dd_routed",
+             "steps_dd"]
 
 
 class Stats(ctypes.Structure):
@@ -146,10 +147,12 @@ def _stream_handle(stream):
 class Result:
     """Roots of one split (device tensors trimmed to the count)."""
 
-    def __init__(self, l, n, re, im, period, flags, radius, count, stats, status, preperiod=None):
+    def __init__(self, l, n, re, im, period, flags, radius, count, stats, status, preperiod=None, re_lo=None,
+                 im_lo=None):
         self.l, self.n = l, n
         self.re, self.im, self.period, self.flags, self.radius = re, im, period, flags, radius
         self.preperiod = preperiod
+        self.re_lo, self.im_lo = re_lo, im_lo
         self.count = count
         self.stats = stats
         self.status = status
@@ -160,7 +163,7 @@ class Result:
     def cpu(self):
         import numpy as np
         d = {"re": self.re.cpu().numpy(), "im": self.im.cpu().numpy()}
-        for k in ("period", "preperiod", "flags", "radius"):
+        for k in ("period", "preperiod", "flags", "radius", "re_lo", "im_lo"):
             t = getattr(self, k)
             d[k] = t.cpu().numpy() if t is not None else None
         d["stats"] = self.stats
@@ -187,14 +190,17 @@ class Buffers:
         self.cap = cap
         self.re = torch.empty(cap, dtype=torch.float64, device=device)
         self.im = torch.empty(cap, dtype=torch.float64, device=device)
+        self.re_lo = torch.empty(cap, dtype=torch.float64, device=device)
+        self.im_lo = torch.empty(cap, dtype=torch.float64, device=device)
         self.period = torch.empty(cap, dtype=torch.int32, device=device)
         self.preperiod = torch.empty(cap, dtype=torch.int32, device=device)
         self.flags = torch.empty(cap, dtype=torch.uint8, device=device)
         self.radius = torch.empty(cap, dtype=torch.float64, device=device)
 
     def roots_struct(self):
-        return RootsC(self.re.data_ptr(), self.im.data_ptr(), None, None, self.period.data_ptr(),
-                      self.preperiod.data_ptr(), self.flags.data_ptr(), self.radius.data_ptr(), self.cap)
+        return RootsC(self.re.data_ptr(), self.im.data_ptr(), self.re_lo.data_ptr(), self.im_lo.data_ptr(),
+                      self.period.data_ptr(), self.preperiod.data_ptr(), self.flags.data_ptr(),
+                      self.radius.data_ptr(), self.cap)
 
 
 def split(l: int, n: int, opts: Options = None, buffers: Buffers = None, stream=None, check=True) -> Result:
@@ -216,7 +222,7 @@ def split(l: int, n: int, opts: Options = None, buffers: Buffers = None, stream=
         raise MsplitError(r, f"split({l},{n})")
     certified = bool(opts.flags & F_CERTIFY)
     return Result(l, n, b.re[:c], b.im[:c], b.period[:c], b.flags[:c], b.radius[:c] if certified else None, c,
-                  st.as_dict(), r, preperiod=b.preperiod[:c])
+                  st.as_dict(), r, preperiod=b.preperiod[:c], re_lo=b.re_lo[:c], im_lo=b.im_lo[:c])
 
 
 def hyperbolic(n: int, **kw) -> Result:
@@ -229,9 +235,11 @@ def misiurewicz(l: int, n: int, **kw) -> Result:
     return split(l, n, opts, stream=kw.get("stream"), check=kw.get("check", True))
 
 
-def certify(l: int, n: int, re: torch.Tensor, im: torch.Tensor, period: torch.Tensor = None, stream=None):
-    """Certify candidates (device tensors, sorted by real part).  Returns
-    (flags uint8 tensor, radius float64 tensor, stats dict)."""
+def certify(l: int, n: int, re: torch.Tensor, im: torch.Tensor, period: torch.Tensor = None, stream=None,
+            re_lo: torch.Tensor = None, im_lo: torch.Tensor = None):
+    """Certify candidates (device tensors, sorted by real part; optional
+    double-double low parts).  Returns (flags uint8 tensor, radius float64
+    tensor, stats dict)."""
     m = re.numel()
     dev = re.device
     re = re.contiguous().to(torch.float64)
@@ -239,9 +247,12 @@ def certify(l: int, n: int, re: torch.Tensor, im: torch.Tensor, period: torch.Te
     flags = torch.zeros(m, dtype=torch.uint8, device=dev)
     radius = torch.zeros(m, dtype=torch.float64, device=dev)
     per = period.contiguous().to(torch.int32) if period is not None else None
+    lo = None
+    if re_lo is not None and im_lo is not None:
+        lo = (re_lo.contiguous().to(torch.float64), im_lo.contiguous().to(torch.float64))
     ws = torch.empty(CERTIFY_WORKSPACE, dtype=torch.uint8, device=dev)
-    rs = RootsC(re.data_ptr(), im.data_ptr(), None, None, per.data_ptr() if per is not None else None, None,
-                flags.data_ptr(), radius.data_ptr(), m)
+    rs = RootsC(re.data_ptr(), im.data_ptr(), lo[0].data_ptr() if lo else None, lo[1].data_ptr() if lo else None,
+                per.data_ptr() if per is not None else None, None, flags.data_ptr(), radius.data_ptr(), m)
     st = Stats()
     r = lib().msplit_certify(l, n, ctypes.byref(rs), m, ctypes.c_void_p(ws.data_ptr()), CERTIFY_WORKSPACE, ctypes.byref(st),
                              _stream_handle(stream))

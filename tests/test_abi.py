@@ -41,7 +41,7 @@ def test_struct_sizes_match_binding(lib):
     # msplit_options: 4+4+8+4+4+4(pad)+8+4+4+8 = 56 bytes on x86-64 SysV
     assert ctypes.sizeof(msplit.Options) == 56
     assert ctypes.sizeof(msplit.RootsC) == 8 * 8 + 8
-    assert ctypes.sizeof(msplit.Stats) == 19 * 8 + 3 * 8 + 6 * 8 + 8
+    assert ctypes.sizeof(msplit.Stats) == 21 * 8 + 3 * 8 + 6 * 8 + 8
 
 
 def test_header_constants_match_binding():
@@ -50,7 +50,7 @@ def test_header_constants_match_binding():
     m = re.search(r"#define\s+MSPLIT_CERTIFY_WORKSPACE\s+(\d+)u?", text)
     assert m and int(m.group(1)) == msplit.CERTIFY_WORKSPACE
     for name, val in [("MSPLIT_R_REAL", msplit.R_REAL), ("MSPLIT_R_CERTIFIED", msplit.R_CERTIFIED),
-                      ("MSPLIT_R_LABEL", msplit.R_LABEL), ("MSPLIT_F_CERTIFY", msplit.F_CERTIFY),
+                      ("MSPLIT_R_LABEL", msplit.R_LABEL), ("MSPLIT_R_DD", msplit.R_DD), ("MSPLIT_F_CERTIFY", msplit.F_CERTIFY),
                       ("MSPLIT_F_NO_LABEL", msplit.F_NO_LABEL), ("MSPLIT_E_WORKSPACE", msplit.E_WORKSPACE)]:
         m = re.search(name + r"\s*=\s*(-?\d+)u?", text)
         assert m and int(m.group(1)) == val, name

@@ -192,15 +192,37 @@ def mis_pairs(max_order):
     return [(l, s - l) for s in range(3, max_order + 1) for l in range(2, s)]
 
 
+@pytest.mark.parametrize("ln", [(3, 15), (6, 13), (2, 16), (4, 14)])
+def test_misiurewicz_parity_tip(ln):
+    """Orders 18 and 19: real Misiurewicz parameters next to -2 pair up below
+    1e-12 and q_{l,n} has centres of high multiplicity (Thm fact_mis) that
+    stall descents.  Same set as the oracle, exact count; the double-double
+    roots (MSPLIT_R_DD) agree with the oracle's to 1e-25."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    r, g = gpu_split(l, n, certify=True)
+    st = r.stats
+    assert r.status == msplit.OK, (r.status, st)
+    assert st["total"] == counts.mis_count(l, n) and st["certified"] == len(g) and st["overlaps"] == 0, st
+    assert st["dd_routed"] > 0
+    o = oracle_split(l, n)
+    _, idx = compare_sets(g, o)
+    dd = (g.flags & msplit.R_DD) != 0
+    assert dd.any()
+    ere = (g.re[dd] - o.re_hi[idx[dd]]) + (g.re_lo[dd] - o.re_lo[idx[dd]])
+    eim = (g.im[dd] - o.im_hi[idx[dd]]) + (g.im_lo[dd] - o.im_lo[idx[dd]])
+    assert np.max(np.abs(ere)) < 1e-25 and np.max(np.abs(eim)) < 1e-25
+
+
 def test_batch_misiurewicz_all_pairs():
-    """Every q_{l,n} with l >= 2, n >= 1, l + n <= 15 (91 pairs) in one
+    """Every q_{l,n} with l >= 2, n >= 1, l + n <= 22 (210 pairs) in one
     batch, certified: exact counts |Mis(l,n)| (eq. MisCount) per pair, every
     root certified with its type proven, quarter-separated; a sample of each of
-    the largest pairs certified again by the oracle."""
+    three of the largest pairs certified again by the oracle."""
     from paper_2402_06083_amd import batch
-    pairs = mis_pairs(15)
-    assert len(pairs) == 91
-    say("[gpu] batch of all q_{l,n}, l + n <= 15")
+    pairs = mis_pairs(22)
+    assert len(pairs) == 210
+    say("[gpu] batch of all q_{l,n}, l + n <= 22")
     res = batch.run_batch(pairs, certify=True)
     tot = 0
     for i, ((l, n), (count, st, status)) in enumerate(zip(res.pairs, res.per_pair)):
@@ -211,12 +233,12 @@ def test_batch_misiurewicz_all_pairs():
     say(f"[gpu] C4: {tot} roots, stage ms {res.per_pair[0][1]['ms_stage']}")
     b = res.bufs
     rng = np.random.default_rng(22)
-    for (l, n) in [(2, 13), (7, 8), (13, 2)]:
+    for (l, n) in [(2, 20), (11, 11), (20, 2)]:
         sl = b.slices(res.pairs.index((l, n)))
-        re = b.re[sl].cpu().numpy()
-        im = b.im[sl].cpu().numpy()
+        re, im = b.re[sl].cpu().numpy(), b.im[sl].cpu().numpy()
+        rl, il = b.re_lo[sl].cpu().numpy(), b.im_lo[sl].cpu().numpy()
         idx = np.sort(rng.choice(len(re), size=min(4000, len(re)), replace=False))
-        ok, rad = oracle.certify(l, n, re[idx], im[idx])
+        ok, rad = oracle.certify(l, n, re[idx], im[idx], rl[idx], il[idx])
         assert np.all(ok == 3) and rad.max() <= 1e-10, (l, n)
 
 
