@@ -30,8 +30,10 @@
 namespace msplit {
 
 // status of a descent
-// ST_DD: converged in double-double (the low parts are in roots_lo)
-enum : uint8_t { ST_NONE = 0, ST_CONVERGED = 1, ST_DIVERGED = 2, ST_TIMEOUT = 3, ST_DD = 4 };
+// ST_DD: converged in double-double (the low parts are in roots_lo);
+// ST_STALL: the FP64 descent met its step test without the quadratic
+// convergence of a simple root (redone in double-double)
+enum : uint8_t { ST_NONE = 0, ST_CONVERGED = 1, ST_DIVERGED = 2, ST_TIMEOUT = 3, ST_DD = 4, ST_STALL = 5 };
 __device__ __forceinline__ bool st_converged(uint8_t s) { return s == ST_CONVERGED || s == ST_DD; }
 
 // global counters
@@ -57,6 +59,7 @@ struct plan_t {
     double tol_desc;      // relative step of a converged descent
     double x_tip;         // |c + 2| below which descents are redone in double-double (0: none)
     double tau_dd;        // identification radius between double-double roots
+    int tip_starts;       // last starts of the type re-solved in double-double (left tip)
     uint32_t divmask_lo;  // bit k set when k | n, k < n (k < 32)
     int precision;
     float fp32_switch;
@@ -68,6 +71,7 @@ struct type_desc {
     int64_t out_off;                      // first output slot
     uint64_t cap;                         // output capacity
     int64_t uniq_off;                     // offset in the compact unique index space
+    int64_t tip_lo_off;                   // first slot of this type in the tip-start low parts
 };
 
 struct batch_args {
@@ -439,6 +443,15 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
 // type tag for the four 32-bit counts, branch-free status selection) so that
 // the kernel fits 64 VGPRs: 8 waves per SIMD hide the load of a new start
 // and the FP64 dependency latency of the orbit loop.
+//
+// ROUTE (some type of the call has a double-double route): a converged
+// descent is marked ST_STALL, to be redone in double-double, when its last
+// step did not show the quadratic convergence of a simple root, or when the
+// root is too ill-conditioned for an FP64 centre: the certificate needs the
+// image of D(c, R) under the orbit to stay small, R |P'| << 1, and an FP64
+// centre leaves R ~ 2^-46 |z|, so |P'| 2^-46 |z| > 1/16 asks for a
+// double-double centre.
+template <bool ROUTE>
 __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd *roots, uint8_t *status,
                                                  const uint8_t *iters)
 {
@@ -455,10 +468,11 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
     uint32_t t_lo = 0, t_hi = 0;
     int pl_l = 0, pl_N = 1, pl_cap = 20;
     double pl_tol2 = 0.0;
+    bool pl_route = false; // the type has a double-double route
     cd z = {0.0, 0.0};
     double prev = 0.0; // previous squared step length
     int it = 0, it0 = 0;
-    bool fin = false;
+    bool fin = false, stall = false;
     wave_queue wq = {0, 0};
     unsigned long long *counter = &b.gctr[iters ? G_START_NEXT2 : G_START_NEXT];
     while (true) {
@@ -478,11 +492,12 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
                     pl_N = pl.N;
                     pl_cap = pl.cap;
                     pl_tol2 = pl.tol_desc * pl.tol_desc;
+                    if (ROUTE) pl_route = pl.x_tip > 0.0;
                 }
                 z = src[g];
                 it0 = it = iters ? iters[g] : 0;
                 prev = 0.0;
-                fin = false;
+                fin = stall = false;
             }
         }
         const bool change = g != NONE && t != ct;
@@ -505,14 +520,24 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
         const double az2 = cabs2(z);
         const bool bad = !(a2 <= 0x1p1000) || !(az2 <= 64.0) || (it > it0 + 3 && a2 > 64.0 * prev);
         const bool small = a2 <= pl_tol2 * fmax(az2, 0x1p-16);
-        const uint8_t st = fin ? ST_CONVERGED : bad ? ST_DIVERGED : (!small && it >= pl_cap) ? ST_TIMEOUT : ST_NONE;
+        const uint8_t st = fin ? (stall ? ST_STALL : ST_CONVERGED)
+                               : bad ? ST_DIVERGED : (!small && it >= pl_cap) ? ST_TIMEOUT : ST_NONE;
+        // a simple root is met by a step far below the one before (quadratic
+        // convergence); a descent that creeps onto close roots or meets the
+        // test on rounding noise does not, and is redone in double-double
+        // (precision routing: progress stalled at the precision floor)
+        if (ROUTE && small && !fin) {
+            const bool slow = it > it0 + 1 && 64.0 * a2 > prev;
+            const bool ill = cabs2(dP) * fmax(az2, 0x1p-16) > 0x1p84;
+            stall = pl_route && (slow || ill);
+        }
         fin = small;
         prev = a2;
         cnt[0] += 1u;
         if (st != ST_NONE) {
             roots[g] = z;
             status[g] = st;
-            cnt[1] += st == ST_CONVERGED;
+            cnt[1] += st == ST_CONVERGED || st == ST_STALL;
             cnt[2] += st == ST_DIVERGED;
             cnt[3] += st == ST_TIMEOUT;
             g = NONE;

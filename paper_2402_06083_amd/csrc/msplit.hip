@@ -109,6 +109,24 @@ plan_t make_plan(int l, int n, const msplit_options *o)
     // order about 18 on (their gap shrinks like 8^-N); a generous tip radius
     // keeps every FP64 root outside it far from its neighbours
     p.x_tip = (l >= 2 && p.N >= 14) ? 0x1p-14 : 0.0;
+    if (l == 0 && p.N >= 25) {
+        // p_n beyond FP64 separation (118.4 / 4^n, Section 6.3.2, nears the
+        // FP64 spacing at n = 25): FP64 keeps tau = 2^-44 away from -2 and
+        // the tip goes to double-double.  The closest pairs there are a
+        // centre of period n/2 and its satellite of period n (Section 6.3.2),
+        // whose gap grows about linearly with the distance x to -2, measured
+        // at 6e-8 x for n = 26 and halving with each further order; the tip
+        // covers every x where that gap is below 128 tau, and at least the
+        // region where the spacing of the real roots, about
+        // 4 pi sqrt(x / 2) / 2^n, is below 128 tau.
+        p.tau = 0x1p-44;
+        // from order 28 the left end of the level line (about -2 - 14.7 / 4^n)
+        // is closer to -2 than the FP64 spacing: re-solve the starts there
+        if (p.N >= 28) p.tip_starts = (int)std::min<int64_t>(p.NS, 4096);
+        const double a = 128.0 * p.tau * ldexp(1.0, p.N) / (4.0 * M_PI);
+        const double x_sat = 128.0 * p.tau / (6e-8 * ldexp(1.0, 26 - p.N));
+        p.x_tip = std::max(2.0 * a * a, x_sat);
+    }
     p.tau_dd = 0x1p-90;
     p.divmask_lo = divisor_mask(n);
     p.precision = o->precision;
@@ -131,6 +149,7 @@ struct batch_plan {
     std::vector<type_desc> td;      // in processing order
     std::vector<int64_t> seed_offs, seg_offs, start_offs; // T + 1
     int64_t n_seeds = 0, n_segs = 0, n_starts = 0;
+    int64_t n_tip = 0; // starts re-solved in double-double, all types
 };
 
 // Types in decreasing order N (then caller order) so that the persistent
@@ -160,6 +179,8 @@ int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uin
         d.seg_off = bp.seg_offs[t];
         d.start_off = bp.start_offs[t];
         d.out_off = out_offs ? (int64_t)out_offs[c] : 0;
+        d.tip_lo_off = bp.n_tip;
+        bp.n_tip += d.p.tip_starts;
         d.cap = caps ? caps[c] : 0;
         bp.seed_offs[t + 1] = bp.seed_offs[t] + d.p.S + 1;
         bp.seg_offs[t + 1] = bp.seg_offs[t] + d.p.S;
@@ -173,7 +194,7 @@ int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uin
 
 // ------------------------------------------------------------- workspace
 struct layout {
-    size_t gctr, ctr, spread, zs, zs_lo, roots, roots_lo, types, offs, tb, seeds, starts, status, iters, segf, flag0, pos0, keys, vals, keys2, vals2,
+    size_t gctr, ctr, spread, zs, zs_lo, roots, roots_lo, tip_lo, types, offs, tb, seeds, starts, status, iters, segf, flag0, pos0, keys, vals, keys2, vals2,
         flag, pos, temp, total;
     size_t temp_bytes;
 };
@@ -228,6 +249,7 @@ layout make_layout(const batch_plan &bp, size_t temp_bytes)
     L.zs_lo = take(sizeof(cd) * NS);
     L.roots = take(sizeof(cd) * NS);
     L.roots_lo = take(sizeof(cd) * NS);
+    L.tip_lo = take(sizeof(cd) * (size_t)std::max<int64_t>(bp.n_tip, 1));
     L.vals2 = take(4 * NS);
     L.flag = take(4 * NS);
     L.pos = take(4 * NS);
@@ -406,7 +428,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     uint32_t *flag0 = (uint32_t *)(ws + L.flag0), *pos0 = (uint32_t *)(ws + L.pos0);
     uint64_t *keys = (uint64_t *)(ws + L.keys), *keys2 = (uint64_t *)(ws + L.keys2);
     cd *zs = (cd *)(ws + L.zs), *zs_lo = (cd *)(ws + L.zs_lo);
-    cd *roots = (cd *)(ws + L.roots), *roots_lo = (cd *)(ws + L.roots_lo);
+    cd *roots = (cd *)(ws + L.roots), *roots_lo = (cd *)(ws + L.roots_lo), *tip_lo = (cd *)(ws + L.tip_lo);
     uint32_t *vals = (uint32_t *)(ws + L.vals), *vals2 = (uint32_t *)(ws + L.vals2);
     uint32_t *flag = (uint32_t *)(ws + L.flag), *pos = (uint32_t *)(ws + L.pos);
     void *temp = ws + L.temp;
@@ -458,6 +480,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     CHK(hipEventRecord(ev.e[1], stream));
     // level-line walk
     k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, segf);
+    if (bp.n_tip > 0) k_refine_tip_starts<<<blocks_for(bp.n_tip, 256), 256, 0, stream>>>(ba, starts, tip_lo, bp.n_tip);
     CHK(hipEventRecord(ev.e[2], stream));
     CHK(hipGetLastError());
 
@@ -496,19 +519,26 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     }
 
     // descents (MIXED: an FP32 pass first)
-    if (opts->precision == MSPLIT_MIXED) {
-        k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, roots, status, iters);
-        k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, roots, roots, status, iters);
-    } else {
-        k_descend<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, roots, status, nullptr);
-    }
-    // double-double route next to -2: the routed starts descend again from
-    // their starting points (the list lives in flag0 until the collection)
     bool any_tip = false;
     for (int t = 0; t < T; ++t) any_tip = any_tip || bp.td[t].p.x_tip > 0.0;
+    auto descend64 = [&](const cd *src, const uint8_t *it) {
+        if (any_tip)
+            k_descend<true><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, roots, status, it);
+        else
+            k_descend<false><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, roots, status, it);
+    };
+    if (opts->precision == MSPLIT_MIXED) {
+        k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, roots, status, iters);
+        descend64(roots, iters);
+    } else {
+        descend64(starts, nullptr);
+    }
+    // double-double route: the routed starts (next to -2, or stalled at the
+    // FP64 precision floor) descend again from their starting points (the
+    // list lives in flag0 until the collection)
     if (any_tip) {
         k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, roots, status, flag0);
-        k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, flag0, starts, roots, roots_lo, status);
+        k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, flag0, starts, tip_lo, roots, roots_lo, status);
     }
     CHK(hipEventRecord(ev.e[3], stream));
     // nset collection: local identification, compaction, sort, global

@@ -50,9 +50,61 @@ __device__ dd_step dd_newton_step(int l, int N, cdd c)
     return {{dd_div_by(nr, d2), dd_div_by(ni, d2)}, d2};
 }
 
+// Starts at the left tip.  From order about 28 on the level line passes
+// -2 closer than the FP64 spacing there (its left end lies near
+// -2 - 14.7 / 4^n): the last starts of the upper half plane, start k with
+// P = lambda_0 i^k, collapse onto the same FP64 values.  Each of the last
+// tip_starts starts is re-solved in double-double, Newton on P(z) = T_k with
+// the exact target T_k = lambda_0 i^k from its FP64 value: the high part
+// replaces the start, the low part goes to tip_lo (read by the
+// double-double descent).
+__global__ void k_refine_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t n_tip)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tip) return;
+    int t = 0; // type owning slot i (few types carry tip starts)
+    while (t + 1 < b.T && b.types[t + 1].tip_lo_off <= i) ++t;
+    const type_desc &td = b.types[t];
+    const plan_t &pl = td.p;
+    const int64_t j = i - td.tip_lo_off;
+    if (j >= pl.tip_starts) return;
+    const int64_t k = pl.NS - pl.tip_starts + j; // start index within the type
+    const int64_t g = td.start_off + k;
+    const double tr[4] = {pl.level, 0.0, -pl.level, 0.0}, ti[4] = {0.0, pl.level, 0.0, -pl.level};
+    const double Tr = tr[k & 3], Ti = ti[k & 3];
+    const cd s0 = starts[g];
+    cdd z = {{s0.re, 0.0}, {s0.im, 0.0}};
+    for (int it = 0; it < 16; ++it) {
+        // P - T in double-double, P' in FP64 (dd_newton_step of P - T)
+        cdd w = {{0.0, 0.0}, {0.0, 0.0}}, wl = w;
+        double dr = 0.0, di = 0.0, dlr = 0.0, dli = 0.0;
+        for (int m = 1; m <= pl.N; ++m) {
+            const double a = w.re.hi * dr - w.im.hi * di, c = w.re.hi * di + w.im.hi * dr;
+            dr = 2.0 * a + 1.0;
+            di = 2.0 * c;
+            w = cdd_sqr_add(w, z);
+            if (m == pl.l) { wl = w; dlr = dr; dli = di; }
+        }
+        cdd P = cdd_sub(w, wl);
+        P.re = dd_add_d(P.re, -Tr);
+        P.im = dd_add_d(P.im, -Ti);
+        const double pr = dr - dlr, pi = di - dli, d2 = pr * pr + pi * pi;
+        if (!(d2 > 0.0) || !isfinite(d2)) break;
+        const dd nr = dd_add(dd_mul_d(P.re, pr), dd_mul_d(P.im, pi));
+        const dd ni = dd_sub(dd_mul_d(P.im, pr), dd_mul_d(P.re, pi));
+        const cdd st = {dd_div_by(nr, d2), dd_div_by(ni, d2)};
+        z = cdd_sub(z, st);
+        if (k == 0 || k == pl.NS - 1) z.im = {0.0, 0.0}; // the real end points
+        if (cdd_abs2_hi(st) <= 0x1p-200 * fmax(cdd_abs2_hi(z), 0x1p-16)) break;
+    }
+    starts[g] = {z.re.hi, z.im.hi};
+    tip_lo[i] = {z.re.lo, z.im.lo};
+}
+
 // Routing: starts whose FP64 descent ended within x_tip of -2 (any status:
-// a descent the FP64 rounding derailed there is retried) go to a list; one
-// atomic per wave.
+// a descent the FP64 rounding derailed there is retried), and descents that
+// stalled at the FP64 precision floor anywhere, go to a list; one atomic per
+// wave.
 __global__ void k_route_tip(batch_args b, const cd *roots, const uint8_t *status, uint32_t *list)
 {
     __shared__ int64_t offs[MAX_TYPES + 1];
@@ -68,7 +120,7 @@ __global__ void k_route_tip(batch_args b, const cd *roots, const uint8_t *status
         const int t = find_type_lds(offs, b.T, g);
         const cd z = roots[g];
         const double x = xt[t];
-        take = x > 0.0 && fabs(z.re + 2.0) < x && fabs(z.im) < x;
+        take = status[g] == ST_STALL || (x > 0.0 && fabs(z.re + 2.0) < x && fabs(z.im) < x);
     }
     const unsigned long long mask = __ballot(take);
     if (!mask) return;
@@ -92,8 +144,8 @@ __global__ void k_route_tip(batch_args b, const cd *roots, const uint8_t *status
 // few routed starts make cheap.  Work list length read on the device.
 constexpr int DD_CAP = 256;
 
-__global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t *list, const cd *starts, cd *roots,
-                                                    cd *roots_lo, uint8_t *status)
+__global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t *list, const cd *starts,
+                                                    const cd *tip_lo, cd *roots, cd *roots_lo, uint8_t *status)
 {
     unsigned long long *const wc = wave_ctr(b);
     const uint64_t n = b.gctr[G_DD_COUNT];
@@ -114,6 +166,12 @@ __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t
         const plan_t &pl = b.types[t].p;
         const cd s0 = starts[g];
         cdd z = {{s0.re, 0.0}, {s0.im, 0.0}};
+        const int64_t k = g - b.types[t].start_off;
+        if (k >= pl.NS - pl.tip_starts) { // a start re-solved in double-double
+            const cd lo = tip_lo[b.types[t].tip_lo_off + (k - (pl.NS - pl.tip_starts))];
+            z.re.lo = lo.re;
+            z.im.lo = lo.im;
+        }
         const int cap = DD_CAP;
         double prev = 0.0;
         bool fin = false;

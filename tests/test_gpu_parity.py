@@ -113,6 +113,54 @@ def test_certificate_on_split(n):
     assert np.all(ok == 3)
 
 
+def check_full_period(n, sample=4000, seed=0):
+    """p_n at full size: exact counts per period class (eq. HypCount) taken on
+    the device, every root certified with its period proven, no overlap, and a
+    random sample -- with the double-double roots next to -2 -- certified again
+    by the oracle from the double-double values."""
+    from paper_2402_06083_amd import msplit
+    opts = msplit.make_options(certify=True)
+    b = msplit.Buffers(0, n, opts)
+    r = msplit.split(0, n, opts, buffers=b, check=False)
+    torch.cuda.synchronize()
+    st = r.stats
+    say(f"[gpu] p_{n}: status {r.status} stages {st['ms_stage']} dd_routed {st['dd_routed']}")
+    assert r.status == msplit.OK, (r.status, st)
+    assert st["total"] == 2 ** (n - 1) and st["certified"] == len(r) and st["label_proven"] == len(r), st
+    assert st["overlaps"] == 0
+    for k in counts.divisors(n):
+        sel = r.period == k
+        cnt = int((r.im[sel] == 0).sum().item()) + 2 * int((r.im[sel] > 0).sum().item())
+        assert cnt == counts.hyp_count(k), (k, cnt)
+    dd = torch.nonzero((r.flags & msplit.R_DD) != 0).flatten()
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(r), size=sample, replace=False))
+    idx = np.union1d(idx, dd[: min(len(dd), 200)].cpu().numpy())
+    t = torch.as_tensor(idx, device=r.re.device)
+    ok, rad = oracle.certify(0, n, r.re[t].cpu().numpy(), r.im[t].cpu().numpy(), r.re_lo[t].cpu().numpy(),
+                             r.im_lo[t].cpu().numpy(), label=r.period[t].cpu().numpy())
+    assert np.all(ok == 3)
+    del b, r
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [25, 26])
+def test_full_size_beyond_fp64(n):
+    """p_25, p_26: past the FP64 separation of the roots next to -2
+    (118.4 / 4^n, Section 6.3.2); the tip goes through double-double."""
+    check_full_period(n, seed=n)
+
+
+def test_full_size_period_28():
+    check_full_period(28, seed=28)
+
+
+def test_full_size_period_30():
+    """p_30 (536 870 912 roots), the double-double storage configuration:
+    the starts at the left tip are re-solved in double-double."""
+    check_full_period(30, sample=2000, seed=30)
+
+
 def test_full_size_period_24():
     """Period 24 at full size (8 388 608 roots): exact counts per period class,
     every root certified by the GPU, a random sample certified one by one by
@@ -287,8 +335,9 @@ def test_error_paths():
     r = L.msplit_hyperbolic(10, ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ws_bytes - 4096,
                             ctypes.byref(rs), ctypes.byref(cnt), ctypes.byref(st), sh)
     assert r == msplit.E_WORKSPACE
-    r = L.msplit_hyperbolic(28, ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ws_bytes, ctypes.byref(rs),
-                            ctypes.byref(cnt), ctypes.byref(st), sh)
+    # q_{4,22}: tau of order 26 is below the FP64 floor (no double-double route for q there)
+    r = L.msplit_misiurewicz(4, 22, ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), ws_bytes,
+                             ctypes.byref(rs), ctypes.byref(cnt), ctypes.byref(st), sh)
     assert r == msplit.E_PRECISION
 
 
