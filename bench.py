@@ -1,13 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark: certified roots per second of the level-line splitter on one GPU.
 
-Workload (default ``batch24``): every p_n, n = 1..24, split in one batch --
-16 777 215 roots of degree 1 to 8 388 608 -- and every returned root certified
-by the disk-arithmetic certificate (Thm proofRoots), in FP64 and in mixed
-FP32 -> FP64 precision.  A step is one pass of the whole hot path over that
-batch: seeds, level-line walk, descents, collection, classification,
-certificate.  The inputs are the integers n themselves (no dataset exists for
-this problem); nothing is cached between steps.
+The metric is quoted on two workloads, both measured here:
+- ``batch24`` (the headline ``value``): every p_n, n = 1..24, split in one
+  batch -- 16 777 215 roots of degree 1 to 8 388 608 -- every returned root
+  certified by the disk-arithmetic certificate (Thm proofRoots);
+- ``p30``: p_30, 536 870 912 roots, the tip next to -2 in double-double.
+Each runs in FP64 and in mixed FP32 -> FP64 precision.  A step is one pass
+of the whole hot path over the workload: seeds, level-line walk, descents
+(with the double-double route), collection, classification, certificate.
+The inputs are the integers n themselves (no dataset exists for this
+problem); nothing is cached between steps.  ``mis22`` (every q_{l,n},
+l + n <= 22) is available with --workload.
 
 Prints one JSON line (metric, value, roofline of the dominant kernel, CPU
 oracle baseline).
@@ -35,12 +39,16 @@ WORKLOADS = {
     "batch24": ("p_1..p_24 batched, all roots certified", [(0, n) for n in range(1, 25)]),
     "p20": ("p_20, all roots certified", [(0, 20)]),
     "p24": ("p_24, all roots certified", [(0, 24)]),
+    "p30": ("p_30, all roots certified, tip next to -2 in double-double", [(0, 30)]),
+    "mis22": ("all q_{l,n}, l >= 2, l + n <= 22, Mis(l,n) kept, all roots certified",
+              [(l, s - l) for s in range(3, 23) for l in range(2, s)]),
 }
 
 
 def certified_roots(stats_list):
-    """Roots counted as roots of P: a certified non-real root in the upper
-    half plane stands for itself and its conjugate."""
+    """Roots counted as roots of P (p_n: all 2^(n-1); q_{l,n}: |Mis(l,n)|):
+    a certified non-real root in the upper half plane stands for itself and
+    its conjugate."""
     tot = 0
     for st in stats_list:
         if st["certified"] == st["unique"]:
@@ -70,6 +78,15 @@ def run_gpu(pairs, precision, steps, warmup):
     from paper_2402_06083_amd import batch, msplit
     opts = msplit.make_options(precision=precision, certify=True)
     runner = batch.BatchRunner(pairs, opts)
+    agg = _time_runner(runner, pairs, steps, warmup)
+    del runner
+    torch.cuda.empty_cache()
+    return agg
+
+
+def _time_runner(runner, pairs, steps, warmup):
+    import torch
+    from paper_2402_06083_amd import msplit
     for _ in range(warmup):
         r = runner.run()
     torch.cuda.synchronize()
@@ -128,6 +145,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-compare", action="store_true", help="skip the second precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-p30", action="store_true", help="skip the period-30 measurement")
+    ap.add_argument("--p30-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (scale of the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -151,7 +172,7 @@ def main():
         kname, flops, tms = "k_walk", res["walk"], res["t_walk"]
     achieved = flops / (tms * 1e-3) / 1e12 if tms > 0 else 0.0
     out = {
-        "metric": "certified roots/sec (all periods 1..24 batched; FP64 vs mixed precision)",
+        "metric": "certified roots/sec at period 24 batched & period 30; plain FP64 vs mixed precision",
         "value": value,
         "unit": "certified roots/s",
         "n_gpus": 1,
@@ -162,8 +183,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f32+f64",
-        "data": "synthetic: the integers n = 1..24 (no dataset exists for this problem)",
-        "config": {"workload": desc, "periods": [p[1] for p in pairs], "roots_per_step": res["roots"] // args.steps,
+        "data": "synthetic: the integers n themselves (no dataset exists for this problem)",
+        "config": {"workload": desc, "pairs": len(pairs), "roots_per_step": res["roots"] // args.steps,
                    "precision": main_prec, "certified": True, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
@@ -174,6 +195,20 @@ def main():
         r2 = run_gpu(pairs, other, args.steps, args.warmup)
         out[other] = {"value": r2["roots"] / r2["wall"], "ms_per_step": 1e3 * r2["wall"] / args.steps,
                       "stage_ms_per_step": {k: v / args.steps for k, v in r2["stages"].items()}}
+    if not args.no_p30 and args.workload != "p30":
+        p30 = {}
+        for prec in ([main_prec] if args.no_compare else [main_prec, other]):
+            r3 = run_gpu(WORKLOADS["p30"][1], prec, args.p30_steps, 1)
+            p30[prec] = {"value": r3["roots"] / r3["wall"], "ms_per_step": 1e3 * r3["wall"] / args.p30_steps,
+                         "roots_per_step": r3["roots"] // args.p30_steps,
+                         "stage_ms_per_step": {k: v / args.p30_steps for k, v in r3["stages"].items()}}
+        out["p30"] = {"workload": WORKLOADS["p30"][0], "unit": "certified roots/s", **p30}
+    if args.copy_probe:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

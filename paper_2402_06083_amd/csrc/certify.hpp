@@ -218,7 +218,7 @@ __device__ __forceinline__ void disk_orbit_step_dd(disk_step_dd &s, cdd c, doubl
 // rounding bound of a double-double difference (relative U_DD)
 __device__ __forceinline__ double rnd_dd(cdd a) { DD_EXACT return U_DD * cdd_abs_up(a) + 4.0 * ETA; }
 
-__device__ cert_result certify_root_dd(int l, int n, int lab, uint32_t divmask_n, cdd c)
+__device__ __noinline__ cert_result certify_root_dd(int l, int n, int lab, uint32_t divmask_n, cdd c)
 { DD_EXACT
     const int N = l + n;
     cert_result res = {0, 0.0};
@@ -283,9 +283,13 @@ __device__ cert_result certify_root_dd(int l, int n, int lab, uint32_t divmask_n
 // type and are reduced once per wave at type changes and at the end.
 // With low parts (re_lo, im_lo non-null) a candidate with a non-zero low
 // part, or one the FP64 certificate cannot settle, gets the double-double
-// certificate; MSPLIT_R_DD marks it.
+// certificate; MSPLIT_R_DD marks it.  With a hard list (list non-null)
+// those candidates are appended to it for k_certify_dd instead, so that
+// this kernel keeps the registers of the FP64 certificate alone.
+template <bool HARD_LIST>
 __global__ void k_certify(batch_args b, const double *re, const double *im, const double *re_lo,
-                          const double *im_lo, const int32_t *period, uint8_t *flags, double *radius, int64_t n_uniq)
+                          const double *im_lo, const int32_t *period, uint8_t *flags, double *radius, int64_t n_uniq,
+                          uint32_t *list)
 {
     unsigned long long *const wc = wave_ctr(b);
     type_count nc, nl;
@@ -303,18 +307,66 @@ __global__ void k_certify(batch_args b, const double *re, const double *im, cons
             rbits = 0;
         }
         nc.t = nl.t = t;
-        if (u >= n_uniq) continue;
+        bool hard = false;
+        if (u < n_uniq) {
+            const type_desc &td = b.types[t];
+            const int64_t i = td.out_off + (u - b.uniq_offs[t]);
+            const cd c = {re[i], im[i]};
+            const int lab = period ? period[i] : td.p.n;
+            const cd lo = re_lo && im_lo ? cd{re_lo[i], im_lo[i]} : cd{0.0, 0.0};
+            const bool has_lo = lo.re != 0.0 || lo.im != 0.0;
+            cert_result r = {0, 0.0};
+            if (!has_lo) r = certify_root(td.p.l, td.p.n, lab, td.p.divmask_lo, c);
+            const bool use_dd = re_lo && im_lo && (has_lo || !(r.flags & 2));
+            hard = HARD_LIST && use_dd;
+            if (!hard) {
+                if (use_dd) r = certify_root_dd(td.p.l, td.p.n, lab, td.p.divmask_lo, {{c.re, lo.re}, {c.im, lo.im}});
+                flags[i] = (c.im == 0.0 && lo.im == 0.0 ? 1 : 0) | r.flags | (use_dd ? 8 : 0);
+                radius[i] = r.R;
+                nc.v += (r.flags & 2) != 0;
+                nl.v += (r.flags & 4) != 0;
+                if (r.flags & 2) {
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(r.R);
+                    rbits = bits > rbits ? bits : rbits;
+                }
+            }
+        }
+        if (HARD_LIST) wave_append(list, &b.gctr[G_HARD_CERT], hard, (uint32_t)u);
+    }
+    flush_count(wc, C_CERTIFIED, nc);
+    flush_count(wc, C_LABEL, nl);
+    wave_reduce_by_key<RED_MAX>(wc, C_NCOUNTERS, C_MAX_RAD_BITS, rbits ? nc.t : -1, rbits);
+}
+
+// The double-double certificates of the hard list of k_certify<true>.
+__global__ void k_certify_dd(batch_args b, const double *re, const double *im, const double *re_lo,
+                             const double *im_lo, const int32_t *period, uint8_t *flags, double *radius,
+                             const uint32_t *list)
+{
+    unsigned long long *const wc = wave_ctr(b);
+    const int64_t n = (int64_t)b.gctr[G_HARD_CERT];
+    type_count nc, nl;
+    type_cache tc;
+    unsigned long long rbits = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x; k0 < n; k0 += stride) {
+        const int64_t k = k0 + threadIdx.x;
+        const int64_t u = k < n ? (int64_t)list[k] : -1;
+        const int t = u >= 0 ? cached_type(tc, b.uniq_offs, b.T, u) : nc.t;
+        if (__ballot(u >= 0 && t != nc.t)) {
+            flush_count(wc, C_CERTIFIED, nc);
+            flush_count(wc, C_LABEL, nl);
+            wave_reduce_by_key<RED_MAX>(wc, C_NCOUNTERS, C_MAX_RAD_BITS, rbits ? nc.t : -1, rbits);
+            rbits = 0;
+        }
+        nc.t = nl.t = t;
+        if (u < 0) continue;
         const type_desc &td = b.types[t];
         const int64_t i = td.out_off + (u - b.uniq_offs[t]);
-        const cd c = {re[i], im[i]};
+        const cd c = {re[i], im[i]}, lo = {re_lo[i], im_lo[i]};
         const int lab = period ? period[i] : td.p.n;
-        const cd lo = re_lo && im_lo ? cd{re_lo[i], im_lo[i]} : cd{0.0, 0.0};
-        const bool has_lo = lo.re != 0.0 || lo.im != 0.0;
-        cert_result r = {0, 0.0};
-        if (!has_lo) r = certify_root(td.p.l, td.p.n, lab, td.p.divmask_lo, c);
-        const bool use_dd = re_lo && im_lo && (has_lo || !(r.flags & 2));
-        if (use_dd) r = certify_root_dd(td.p.l, td.p.n, lab, td.p.divmask_lo, {{c.re, lo.re}, {c.im, lo.im}});
-        flags[i] = (c.im == 0.0 && lo.im == 0.0 ? 1 : 0) | r.flags | (use_dd ? 8 : 0);
+        const cert_result r = certify_root_dd(td.p.l, td.p.n, lab, td.p.divmask_lo, {{c.re, lo.re}, {c.im, lo.im}});
+        flags[i] = (c.im == 0.0 && lo.im == 0.0 ? 1 : 0) | r.flags | 8;
         radius[i] = r.R;
         nc.v += (r.flags & 2) != 0;
         nl.v += (r.flags & 4) != 0;
@@ -409,42 +461,94 @@ __global__ void k_separation(batch_args b, const double *re, const double *im, c
 // when the certificate (FP64, else double-double) holds on it.
 constexpr double NEAR_CENTRE = 1e-3;
 
-__global__ void __launch_bounds__(256) k_classify(batch_args b, const cd *uz, const cd *uz_lo, const uint8_t *uz_dd,
-                                                  uint32_t *keep, int32_t *cls, int64_t m, int labels)
+
+
+__device__ __forceinline__ double near_centre_radius(int l, int kmin)
+{
+    const int eta = (l - 1) / kmin + 2;
+    return fmax(NEAR_CENTRE, exp2(-50.0 / eta));
+}
+
+// FP64 pass: every FP64 candidate whose classification FP64 settles; the
+// double-double candidates and the q candidates near a centre go to a hard
+// list for k_classify_hard (their certificates and double-double orbits kept
+// out of this kernel's registers).
+__global__ void __launch_bounds__(256) k_classify(batch_args b, const cd *uz, const uint8_t *uz_dd, uint32_t *keep,
+                                                  int32_t *cls, int64_t m, int labels, uint32_t *list)
 {
     __shared__ int64_t offs[MAX_TYPES + 1];
     for (int i = threadIdx.x; i <= b.T; i += blockDim.x) offs[i] = b.coll_offs[i];
     __syncthreads();
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= m) return;
-    if (u >= offs[b.T]) { keep[u] = 0; return; }
-    const int t = find_type_lds(offs, b.T, u);
-    const plan_t &pl = b.types[t].p;
-    const cd c = uz[u];
-    const bool dd = uz_dd[u];
-    const cd lo = dd ? uz_lo[u] : cd{0.0, 0.0};
-    const cdd cc = {{c.re, lo.re}, {c.im, lo.im}};
-    uint32_t k = 1;
-    int per = pl.n;
-    if (pl.l == 0) {
-        if (labels) per = dd ? classify_p_dd(pl.n, pl.divmask_lo, pl.tau_dd, cc) : classify_p(pl.n, pl.divmask_lo, pl.tau, c);
-    } else {
-        double hmin2 = INFINITY;
-        int kmin = pl.n;
-        bool kq = dd ? classify_q_dd(pl.l, pl.n, pl.divmask_lo, pl.tau_dd, cc, hmin2, kmin)
-                     : classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c, hmin2, kmin);
-        const int eta = (pl.l - 1) / kmin + 2;
-        const double w = fmax(NEAR_CENTRE, exp2(-50.0 / eta));
-        if (kq && hmin2 < w * w) {
-            cert_result r = {0, 0.0};
-            if (!dd) r = certify_root(pl.l, pl.n, pl.n, pl.divmask_lo, c);
-            if (!(r.flags & 2)) r = certify_root_dd(pl.l, pl.n, pl.n, pl.divmask_lo, cc);
-            kq = (r.flags & 2) != 0;
+    bool hard = false;
+    if (u < m) {
+        if (u >= offs[b.T]) {
+            keep[u] = 0;
+        } else {
+            const int t = find_type_lds(offs, b.T, u);
+            const plan_t &pl = b.types[t].p;
+            const cd c = uz[u];
+            const bool dd = uz_dd[u];
+            uint32_t k = 1;
+            int per = pl.n;
+            if (pl.l == 0) {
+                if (dd) hard = labels != 0;
+                else if (labels) per = classify_p(pl.n, pl.divmask_lo, pl.tau, c);
+            } else if (dd) {
+                hard = true;
+            } else {
+                double hmin2 = INFINITY;
+                int kmin = pl.n;
+                const bool kq = classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c, hmin2, kmin);
+                const double w = near_centre_radius(pl.l, kmin);
+                hard = kq && hmin2 < w * w;
+                k = kq ? 1u : 0u;
+            }
+            if (!hard) {
+                keep[u] = k;
+                cls[u] = per;
+            }
         }
-        k = kq ? 1u : 0u;
     }
-    keep[u] = k;
-    cls[u] = per;
+    wave_append(list, &b.gctr[G_HARD_CLS], hard, (uint32_t)u);
+}
+
+__global__ void k_classify_hard(batch_args b, const cd *uz, const cd *uz_lo, const uint8_t *uz_dd, uint32_t *keep,
+                                int32_t *cls, const uint32_t *list)
+{
+    const int64_t n = (int64_t)b.gctr[G_HARD_CLS];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const int64_t u = list[j];
+        const int t = find_type(b.coll_offs, b.T, u);
+        const plan_t &pl = b.types[t].p;
+        const cd c = uz[u];
+        const bool dd = uz_dd[u];
+        const cd lo = dd ? uz_lo[u] : cd{0.0, 0.0};
+        const cdd cc = {{c.re, lo.re}, {c.im, lo.im}};
+        uint32_t k = 1;
+        int per = pl.n;
+        if (pl.l == 0) {
+            per = classify_p_dd(pl.n, pl.divmask_lo, pl.tau_dd, cc);
+        } else {
+            double hmin2 = INFINITY;
+            int kmin = pl.n;
+            bool kq = dd ? classify_q_dd(pl.l, pl.n, pl.divmask_lo, pl.tau_dd, cc, hmin2, kmin)
+                         : classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c, hmin2, kmin);
+            // cheap first: the step ratio of Thm fact_mis in double-double
+            if (kq && !dd && hmin2 < 1e-12 && stalled_at_multiple_root(pl.l, pl.n, kmin, c)) kq = false;
+            const double w = near_centre_radius(pl.l, kmin);
+            if (kq && hmin2 < w * w) {
+                cert_result r = {0, 0.0};
+                if (!dd) r = certify_root(pl.l, pl.n, pl.n, pl.divmask_lo, c);
+                if (!(r.flags & 2)) r = certify_root_dd(pl.l, pl.n, pl.n, pl.divmask_lo, cc);
+                kq = (r.flags & 2) != 0;
+            }
+            k = kq ? 1u : 0u;
+        }
+        keep[u] = k;
+        cls[u] = per;
+    }
 }
 
 } // namespace msplit

@@ -265,6 +265,23 @@ __device__ __forceinline__ void wave_add4_by_key(unsigned long long *base, int s
     }
 }
 
+// Append value to list for every lane with take: one atomic per wave on the
+// length counter, lanes in lane order.  All lanes of the wave must call it.
+__device__ __forceinline__ void wave_append(uint32_t *list, unsigned long long *count, bool take, uint32_t value)
+{
+    const unsigned long long mask = __ballot(take);
+    if (!mask) return;
+    const int leader = __ffsll(mask) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    base = read_lane_u64(base, leader);
+    if (take) {
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        list[base + rank] = value;
+    }
+}
+
 // Order-preserving map of a double onto uint64 (sort key).
 __device__ __forceinline__ uint64_t orderable(double x)
 {

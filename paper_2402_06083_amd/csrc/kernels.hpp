@@ -37,7 +37,9 @@ enum : uint8_t { ST_NONE = 0, ST_CONVERGED = 1, ST_DIVERGED = 2, ST_TIMEOUT = 3,
 __device__ __forceinline__ bool st_converged(uint8_t s) { return s == ST_CONVERGED || s == ST_DD; }
 
 // global counters
-enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_DD_COUNT, G_DD_NEXT, G_NCOUNTERS = 8 };
+// G_HARD_CLS / G_HARD_CERT: lengths of the lists of hard cases of the
+// classification and of the certificate (handled by kernels of their own)
+enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_DD_COUNT, G_HARD_CLS, G_HARD_CERT, G_NCOUNTERS = 8 };
 // per-type counters (uint64 slots, C_NCOUNTERS per type)
 enum {
     C_CONVERGED = 0, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL, C_SEED_FAIL, C_STEPS_LIFT, C_STEPS_WALK,
@@ -354,6 +356,11 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
 // keeps its FP64 value untouched.  The FP64 pass then continues every start
 // not discarded in FP32, counting the FP32 steps against the cap.  Each pass
 // is precision-uniform, so no wave runs both code paths.
+// Rounding in the orbit is amplified by up to about 2^N, so an FP32
+// evaluation of an order-N polynomial has a relative error near 2^(N-24):
+// FP32 steps are taken only up to order FP32_MAX_ORDER (error below 2^-4).
+constexpr int FP32_MAX_ORDER = 20;
+
 __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *status, uint8_t *iters)
 {
     unsigned long long *const wc = wave_ctr(b);
@@ -402,6 +409,12 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
         if (__ballot(!done) == 0) break;
         if (done) continue;
         cf P, dP;
+        if (pl_N > FP32_MAX_ORDER) { // FP32 carries no information: FP64 from the start
+            roots[g] = starts[g];
+            iters[g] = 0;
+            g = -1;
+            continue;
+        }
         eval_q_f32_wave(pl_l, pl_N, z, P, dP);
         ++steps32.v;
         const float den = dP.re * dP.re + dP.im * dP.im;
@@ -417,10 +430,12 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
         } else {
             z = {z.re - sr, z.im - si};
             ++it;
+            // FP32 only discards what is far outside M (|z| > 8); a long jump
+            // or the cap hands the start to FP64, which decides (next to -2
+            // FP32 evaluates P to rounding noise, and its steps mean nothing)
             const float zz = z.re * z.re + z.im * z.im;
-            if (!isfinite(zz) || zz > 64.f) st = ST_DIVERGED;
-            else if (it > 3 && a2 > 64.f * prev) st = ST_DIVERGED;
-            else if (it >= pl_cap) st = ST_TIMEOUT;
+            if (!(zz <= 64.f)) st = ST_DIVERGED;
+            else if ((it > 3 && a2 > 64.f * prev) || it >= pl_cap) handoff = true;
             prev = a2;
         }
         if (handoff || st != ST_NONE) {
@@ -890,7 +905,6 @@ __device__ __forceinline__ bool classify_q(int l, int n, uint32_t divmask, doubl
         if (i == l - 1 + n && newton_dist_below(s.zr - zlm_r, s.zi - zlm_i, s.dr - dlm_r, s.di - dlm_i, tau))
             keep = false; // Mis(j,n), j < l
     }
-    if (keep && hmin2 < 1e-12 && stalled_at_multiple_root(l, n, kmin, c)) keep = false;
     hmin2_out = hmin2;
     kmin_out = kmin;
     return keep;
@@ -904,7 +918,7 @@ __device__ __forceinline__ bool dd_dist_below(cdd a, double br, double bi, doubl
     return cdd_abs2_hi(a) < tau * tau * (br * br + bi * bi);
 }
 
-__device__ int classify_p_dd(int n, uint32_t divmask, double tau, cdd c)
+__device__ __noinline__ int classify_p_dd(int n, uint32_t divmask, double tau, cdd c)
 {
     cdd z = {{0.0, 0.0}, {0.0, 0.0}};
     double dr = 0.0, di = 0.0;
@@ -921,7 +935,8 @@ __device__ int classify_p_dd(int n, uint32_t divmask, double tau, cdd c)
 // Inside the rounding-noise ball of a multiple root q evaluates to noise
 // (even to exactly 0), so the step ratio can miss a point stalled there; the
 // caller settles every candidate near a centre with the certificate.
-__device__ bool classify_q_dd(int l, int n, uint32_t divmask, double tau, cdd c, double &hmin2_out, int &kmin_out)
+__device__ __noinline__ bool classify_q_dd(int l, int n, uint32_t divmask, double tau, cdd c, double &hmin2_out,
+                                           int &kmin_out)
 {
     const cdd zero = {{0.0, 0.0}, {0.0, 0.0}};
     cdd z = zero, zlm = zero, zl = zero;

@@ -580,7 +580,9 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     int32_t *cls = (int32_t *)vals2;
     const bool labels = !(opts->flags & MSPLIT_F_NO_LABEL);
     if (m > 0) {
-        k_classify<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, cls, m, labels ? 1 : 0);
+        uint32_t *hard = vals; // free once sorted
+        k_classify<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, uz_dd, keep, cls, m, labels ? 1 : 0, hard);
+        k_classify_hard<<<device_cus() * 4, 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, cls, hard);
         tb_bytes = temp_bytes;
         CHK(rocprim::exclusive_scan(temp, tb_bytes, keep, kpos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
     }
@@ -612,9 +614,17 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     if (cert && (!out->radius || !out->flags)) return MSPLIT_E_ARG;
     if (n_uniq) {
         if (cert) {
-            k_certify<<<persistent_blocks(n_uniq, 128), 128, 0, stream>>>(
-                ba, out->re, out->im, out->re_lo, out->im_lo,
-                (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period, out->flags, out->radius, n_uniq);
+            const int32_t *lab = (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period;
+            uint32_t *hard = (uint32_t *)keys; // free once sorted
+            if (out->re_lo && out->im_lo) {
+                k_certify<true><<<persistent_blocks(n_uniq, 128), 128, 0, stream>>>(
+                    ba, out->re, out->im, out->re_lo, out->im_lo, lab, out->flags, out->radius, n_uniq, hard);
+                k_certify_dd<<<device_cus() * 2, 128, 0, stream>>>(ba, out->re, out->im, out->re_lo, out->im_lo, lab,
+                                                                   out->flags, out->radius, hard);
+            } else {
+                k_certify<false><<<persistent_blocks(n_uniq, 128), 128, 0, stream>>>(
+                    ba, out->re, out->im, nullptr, nullptr, lab, out->flags, out->radius, n_uniq, nullptr);
+            }
             // k_separation reads the largest radius of each type
             k_fold_counters<<<blocks_for((int64_t)T * C_NCOUNTERS, 256), 256, 0, stream>>>(ctr, spread, T);
             k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, out->re_lo,
@@ -802,9 +812,9 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
     k_init_counters<<<blocks_for((int64_t)C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
         gctr, ctr, spread, 1);
     if (count) {
-        k_certify<<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(
+        k_certify<false><<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(
             ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->period, roots->flags, roots->radius,
-            (int64_t)count);
+            (int64_t)count, nullptr);
         k_fold_counters<<<1, 64, 0, stream>>>(ctr, spread, 1);
         k_separation<<<persistent_blocks((int64_t)count, 256), 256, 0, stream>>>(
             ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->radius, (int64_t)count);
