@@ -73,27 +73,36 @@ def kernel_flops(pairs, stats_list):
     return desc, t_desc, walk, t_walk
 
 
-def run_gpu(pairs, precision, steps, warmup):
+def run_gpu(pairs, precision, steps, warmup, launch="eager"):
+    """eager: every call enqueued by msplit_batch (stage times from HIP
+    events on the call's stream); graph: the call captured once as a
+    hipGraph and replayed (msplit_graph_launch: total device time only)."""
     import torch
     from paper_2402_06083_amd import batch, msplit
     opts = msplit.make_options(precision=precision, certify=True)
     runner = batch.BatchRunner(pairs, opts)
-    agg = _time_runner(runner, pairs, steps, warmup)
+    mode = launch
+    if mode == "graph":
+        runner.capture()
+    agg = _time_runner(runner, pairs, steps, warmup, mode)
+    agg["launch"] = mode
+    runner.close()
     del runner
     torch.cuda.empty_cache()
     return agg
 
 
-def _time_runner(runner, pairs, steps, warmup):
+def _time_runner(runner, pairs, steps, warmup, mode):
     import torch
     from paper_2402_06083_amd import msplit
+    call = runner.launch if mode == "graph" else runner.run
     for _ in range(warmup):
-        r = runner.run()
+        r = call()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     agg = None
     for _ in range(steps):
-        r = runner.run()
+        r = call()
         if r not in (0,):
             raise RuntimeError(f"msplit_batch failed: {msplit.strerror(r)}")
         res = runner.result(r)
@@ -147,6 +156,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-p30", action="store_true", help="skip the period-30 measurement")
     ap.add_argument("--p30-steps", type=int, default=2)
+    ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (scale of the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -162,7 +172,7 @@ def main():
     desc, pairs = WORKLOADS[args.workload]
     main_prec = args.precision
     other = "mixed" if main_prec == "fp64" else "fp64"
-    res = run_gpu(pairs, main_prec, args.steps, args.warmup)
+    res = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager")
     value = res["roots"] / res["wall"]
     ms_per_step = 1e3 * res["wall"] / args.steps
     # dominant kernel: the stage with the larger device time
@@ -185,20 +195,26 @@ def main():
         "dtype": "f64" if main_prec == "fp64" else "f32+f64",
         "data": "synthetic: the integers n themselves (no dataset exists for this problem)",
         "config": {"workload": desc, "pairs": len(pairs), "roots_per_step": res["roots"] // args.steps,
-                   "precision": main_prec, "certified": True, "parallelism": "single GPU"},
+                   "precision": main_prec, "certified": True, "parallelism": "single GPU",
+                   "launch": "eager: msplit_batch per step, one host synchronisation per call"},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "kernel_ms_per_step": tms / args.steps},
         "stage_ms_per_step": {k: v / args.steps for k, v in res["stages"].items()},
     }
+    if not args.no_graph:
+        rg = run_gpu(pairs, main_prec, args.steps, args.warmup, "graph")
+        out["graph"] = {"value": rg["roots"] / rg["wall"], "ms_per_step": 1e3 * rg["wall"] / args.steps,
+                        "device_ms_per_step": rg["ms_device"] / args.steps,
+                        "launch": "whole call captured once as a hipGraph, replayed each step"}
     if not args.no_compare:
-        r2 = run_gpu(pairs, other, args.steps, args.warmup)
+        r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager")
         out[other] = {"value": r2["roots"] / r2["wall"], "ms_per_step": 1e3 * r2["wall"] / args.steps,
                       "stage_ms_per_step": {k: v / args.steps for k, v in r2["stages"].items()}}
     if not args.no_p30 and args.workload != "p30":
         p30 = {}
         for prec in ([main_prec] if args.no_compare else [main_prec, other]):
-            r3 = run_gpu(WORKLOADS["p30"][1], prec, args.p30_steps, 1)
+            r3 = run_gpu(WORKLOADS["p30"][1], prec, args.p30_steps, 1, "eager")
             p30[prec] = {"value": r3["roots"] / r3["wall"], "ms_per_step": 1e3 * r3["wall"] / args.p30_steps,
                          "roots_per_step": r3["roots"] // args.p30_steps,
                          "stage_ms_per_step": {k: v / args.p30_steps for k, v in r3["stages"].items()}}

@@ -30,9 +30,8 @@
  * - Roots are returned in the closed upper half plane (Section 6.1: only
  *   Im >= 0 is stored; p_n and q_{l,n} have integer coefficients): a real
  *   root appears once with im == 0 exactly, a non-real root stands for
- *   itself and its conjugate.  Order: increasing real part, to 2^-48 (roots
- *   closer than that -- only double-double ones next to -2 -- come in start
- *   order).  Where FP64 cannot separate the roots (next to c = -2) a root is
+ *   itself and its conjugate.  Order: increasing real part, to 2^-46 (roots
+ *   whose real parts are closer than that come in start order).  Where FP64 cannot separate the roots (next to c = -2) a root is
  *   a double-double value re + re_lo, im + im_lo (flag MSPLIT_R_DD); give
  *   re_lo and im_lo to receive the low parts (otherwise such roots are
  *   returned to FP64 only).
@@ -204,10 +203,12 @@ int msplit_starts(int l, int n, const msplit_options *opts, void *workspace, uin
                   double *re, double *im, uint64_t capacity, uint64_t *count, msplit_stats *stats, void *stream);
 
 /* Split a list of types in one call: ln_pairs holds npairs (l, n) pairs
- * (l = 0 for p_n).  Roots of pair i are written at out[offsets[i] ..
- * offsets[i] + counts[i]) where offsets[i] is the running sum of the
- * capacities caps[i] (host array).  counts (host, npairs) receives the
- * counts; stats (host, npairs, nullable) the per-pair statistics. */
+ * (l = 0 for p_n), 1 <= npairs <= 256; all types share one launch per
+ * stage and the host synchronises once, at the end.  Roots of pair i are
+ * written at out[offsets[i] .. offsets[i] + counts[i]) where offsets[i] is
+ * the running sum of the capacities caps[i] (host array).  counts (host,
+ * npairs) receives the counts; stats (host, npairs, nullable) the per-pair
+ * statistics. */
 int msplit_batch(const int32_t *ln_pairs, int npairs, const msplit_options *opts, void *workspace,
                  uint64_t workspace_bytes, msplit_roots *out, const uint64_t *caps, uint64_t *counts,
                  msplit_stats *stats, void *stream);
@@ -215,6 +216,30 @@ int msplit_batch(const int32_t *ln_pairs, int npairs, const msplit_options *opts
 /* Workspace bytes for msplit_batch over these pairs. */
 int msplit_batch_workspace_size(const int32_t *ln_pairs, int npairs, const msplit_options *opts,
                                 uint64_t *bytes);
+
+/* A batch captured once as a hipGraph and replayed (the batch scheduling of
+ * the paper's job runs, Section 6.4.1, as one device graph): every kernel of
+ * an msplit_batch call -- seeds, walk, descents, collection, classification,
+ * certificate -- in one graph launch, since every size the kernels need is
+ * computed on the device.  Arguments as msplit_batch; stream must be a
+ * created stream (not NULL: the null stream cannot be captured).  The graph
+ * keeps the workspace and output pointers: they must stay allocated, and no
+ * other call may use that workspace while a launch runs.  *graph receives
+ * the handle (host object owned by the caller, freed by
+ * msplit_graph_destroy).  Errors as msplit_batch, MSPLIT_E_DEVICE when the
+ * capture fails. */
+typedef struct msplit_graph msplit_graph;
+int msplit_batch_graph(const int32_t *ln_pairs, int npairs, const msplit_options *opts, void *workspace,
+                       uint64_t workspace_bytes, msplit_roots *out, const uint64_t *caps, void *stream,
+                       msplit_graph **graph);
+
+/* One replay of the graph on stream (uploads the type tables, launches the
+ * graph, waits for it): counts and stats as msplit_batch, except that the
+ * stage times ms_stage stay 0 (ms_device is the launch's device time). */
+int msplit_graph_launch(msplit_graph *graph, uint64_t *counts, msplit_stats *stats, void *stream);
+
+/* Release the graph (host and runtime objects; not the workspace). */
+void msplit_graph_destroy(msplit_graph *graph);
 
 #ifdef __cplusplus
 }

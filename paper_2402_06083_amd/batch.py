@@ -50,12 +50,49 @@ class BatchRunner:
                                    self.im_lo.data_ptr(), self.period.data_ptr(),
                                    self.preperiod.data_ptr(), self.flags.data_ptr(), self.radius.data_ptr(), tot)
 
+        self._graph = None
+        self._gstream = None
+
     def run(self, stream=None):
         L = msplit.lib()
         sh = msplit._stream_handle(stream)
         r = L.msplit_batch(self.arr, len(self.pairs), ctypes.byref(self.opts), ctypes.c_void_p(self.ws.data_ptr()),
                            self.ws_bytes, ctypes.byref(self.roots), self.caps_arr, self.counts, self.stats, sh)
         return r
+
+    def capture(self):
+        """Capture the batch as one hipGraph (msplit_batch_graph) on a stream of
+        its own (the null stream cannot be captured)."""
+        if self._graph is not None:
+            return
+        L = msplit.lib()
+        self._gstream = torch.cuda.Stream(device=self.ws.device)
+        torch.cuda.synchronize()
+        g = ctypes.c_void_p()
+        r = L.msplit_batch_graph(self.arr, len(self.pairs), ctypes.byref(self.opts),
+                                 ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.byref(self.roots),
+                                 self.caps_arr, ctypes.c_void_p(self._gstream.cuda_stream), ctypes.byref(g))
+        if r:
+            raise msplit.MsplitError(r, "msplit_batch_graph")
+        self._graph = g
+
+    def launch(self):
+        """One replay of the captured graph; returns the status like run()."""
+        if self._graph is None:
+            self.capture()
+        return msplit.lib().msplit_graph_launch(self._graph, self.counts, self.stats,
+                                                ctypes.c_void_p(self._gstream.cuda_stream))
+
+    def close(self):
+        if self._graph is not None:
+            msplit.lib().msplit_graph_destroy(self._graph)
+            self._graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def result(self, status):
         counts = [int(c) for c in self.counts]

@@ -279,8 +279,9 @@ __device__ __noinline__ cert_result certify_root_dd(int l, int n, int lab, uint3
 }
 
 // Grid-stride loop over the unique roots (compact index space of
-// batch_args.uniq_offs); counts and the largest radius stay in registers per
-// type and are reduced once per wave at type changes and at the end.
+// batch_args.uniq_offs, uniq_offs[T] roots, read on the device); counts and
+// the largest radius stay in registers per type and are reduced once per
+// wave at type changes and at the end.
 // With low parts (re_lo, im_lo non-null) a candidate with a non-zero low
 // part, or one the FP64 certificate cannot settle, gets the double-double
 // certificate; MSPLIT_R_DD marks it.  With a hard list (list non-null)
@@ -288,9 +289,9 @@ __device__ __noinline__ cert_result certify_root_dd(int l, int n, int lab, uint3
 // this kernel keeps the registers of the FP64 certificate alone.
 template <bool HARD_LIST>
 __global__ void k_certify(batch_args b, const double *re, const double *im, const double *re_lo,
-                          const double *im_lo, const int32_t *period, uint8_t *flags, double *radius, int64_t n_uniq,
-                          uint32_t *list)
+                          const double *im_lo, const int32_t *period, uint8_t *flags, double *radius, uint32_t *list)
 {
+    const int64_t n_uniq = b.uniq_offs[b.T];
     unsigned long long *const wc = wave_ctr(b);
     type_count nc, nl;
     type_cache tc;
@@ -390,10 +391,11 @@ __global__ void k_certify_dd(batch_args b, const double *re, const double *im, c
 // bound of the least distance; the closest pairs of p_n, the leftmost real
 // roots, are adjacent in that order).  radius == nullptr: only the statistic.
 // With low parts the distances are taken on hi + lo (the list is ordered by
-// the real part to 2^-48, so closer roots may come in either order).
+// the real part to 2^-46, so closer roots may come in either order).
 __global__ void k_separation(batch_args b, const double *re, const double *im, const double *re_lo,
-                             const double *im_lo, const double *radius, int64_t n_uniq)
+                             const double *im_lo, const double *radius)
 {
+    const int64_t n_uniq = b.uniq_offs[b.T];
     unsigned long long *const wc = wave_ctr(b);
     type_count bad;
     type_cache tc;
@@ -444,8 +446,8 @@ __global__ void k_separation(batch_args b, const double *re, const double *im, c
 }
 
 // ---------------------------------------------------------- classification
-// Threads run over the collected index space (bounded by m on the host; the
-// count itself, coll_offs[T], is read on the device).  keep[u] selects the
+// Threads run over the collected index space (coll_offs[T] roots, read on
+// the device).  keep[u] selects the
 // roots of the output set, cls[u] is the period (p_n) or n (q_{l,n}).
 //
 // q_{l,n}: a candidate near a centre Hyp(k), k | n, may be a descent stalled
@@ -473,41 +475,41 @@ __device__ __forceinline__ double near_centre_radius(int l, int kmin)
 // double-double candidates and the q candidates near a centre go to a hard
 // list for k_classify_hard (their certificates and double-double orbits kept
 // out of this kernel's registers).
+// One thread per collected root; the grid covers an upper bound of their
+// number (blocks past it return at once).
 __global__ void __launch_bounds__(256) k_classify(batch_args b, const cd *uz, const uint8_t *uz_dd, uint32_t *keep,
-                                                  int32_t *cls, int64_t m, int labels, uint32_t *list)
+                                                  int32_t *cls, int labels, uint32_t *list)
 {
     __shared__ int64_t offs[MAX_TYPES + 1];
+    const int64_t n = b.coll_offs[b.T];
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)blockIdx.x * blockDim.x >= n) return; // whole blocks
     for (int i = threadIdx.x; i <= b.T; i += blockDim.x) offs[i] = b.coll_offs[i];
     __syncthreads();
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool hard = false;
-    if (u < m) {
-        if (u >= offs[b.T]) {
-            keep[u] = 0;
+    if (u < n) {
+        const int t = find_type_lds(offs, b.T, u);
+        const plan_t &pl = b.types[t].p;
+        const cd c = uz[u];
+        const bool dd = uz_dd[u];
+        uint32_t k = 1;
+        int per = pl.n;
+        if (pl.l == 0) {
+            if (dd) hard = labels != 0;
+            else if (labels) per = classify_p(pl.n, pl.divmask_lo, pl.tau, c);
+        } else if (dd) {
+            hard = true;
         } else {
-            const int t = find_type_lds(offs, b.T, u);
-            const plan_t &pl = b.types[t].p;
-            const cd c = uz[u];
-            const bool dd = uz_dd[u];
-            uint32_t k = 1;
-            int per = pl.n;
-            if (pl.l == 0) {
-                if (dd) hard = labels != 0;
-                else if (labels) per = classify_p(pl.n, pl.divmask_lo, pl.tau, c);
-            } else if (dd) {
-                hard = true;
-            } else {
-                double hmin2 = INFINITY;
-                int kmin = pl.n;
-                const bool kq = classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c, hmin2, kmin);
-                const double w = near_centre_radius(pl.l, kmin);
-                hard = kq && hmin2 < w * w;
-                k = kq ? 1u : 0u;
-            }
-            if (!hard) {
-                keep[u] = k;
-                cls[u] = per;
-            }
+            double hmin2 = INFINITY;
+            int kmin = pl.n;
+            const bool kq = classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c, hmin2, kmin);
+            const double w = near_centre_radius(pl.l, kmin);
+            hard = kq && hmin2 < w * w;
+            k = kq ? 1u : 0u;
+        }
+        if (!hard) {
+            keep[u] = k;
+            cls[u] = per;
         }
     }
     wave_append(list, &b.gctr[G_HARD_CLS], hard, (uint32_t)u);

@@ -79,9 +79,11 @@ struct type_desc {
 struct batch_args {
     const type_desc *types;
     const int64_t *seed_offs, *seg_offs, *start_offs; // T + 1 entries each
-    const int64_t *uniq_offs; // output index space: min(kept, capacity) roots per type
+    int64_t *uniq_offs;       // output index space: min(kept, capacity) roots per type, set on the device
     int64_t *coll_offs;       // collected (identified) roots per type, set on the device
     int64_t *kept_offs;       // roots kept by the classification per type, set on the device
+    int64_t *surv_offs;       // sorted candidates per type, set on the device
+    const double *cis;        // cos, then sin, of 2 pi s / M, s < 64 (k_cis)
     int T;
     int64_t n_seeds, n_segs, n_starts;
     uint32_t chunk_seg, chunk_start;
@@ -104,9 +106,22 @@ __device__ __forceinline__ unsigned long long *wave_ctr(const batch_args &b)
     return b.spread + (size_t)(w & (CTR_SPREAD - 1)) * (size_t)b.T * C_NCOUNTERS;
 }
 
-// cis(2 pi s / M) for s = 0..M-1, M <= 64, set by the host
-__constant__ double c_cis_re[64];
-__constant__ double c_cis_im[64];
+// cis(2 pi s / M) for s = 0..63 (s taken mod M), M <= 64, exact at the
+// quarter turns; one thread per entry
+__global__ void k_cis(int M, double *cis)
+{
+    const int s = threadIdx.x;
+    if (s >= 64) return;
+    const int r = s % M;
+    double sn, cs;
+    sincospi(2.0 * (double)r / (double)M, &sn, &cs);
+    if (4 * r == 0) { cs = 1.0; sn = 0.0; }
+    if (4 * r == M) { cs = 0.0; sn = 1.0; }
+    if (4 * r == 2 * M) { cs = -1.0; sn = 0.0; }
+    if (4 * r == 3 * M) { cs = 0.0; sn = -1.0; }
+    cis[s] = cs;
+    cis[64 + s] = sn;
+}
 
 // index of the type owning global item g: offs is non-decreasing, T + 1
 // entries, offs[0] = 0 <= g < offs[T]
@@ -300,12 +315,17 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
         eval_q_wave(pl_l, pl_N, z, P, dP);
         cnt[0] += 1u;
         const int r = (r0 + s) % pl_M;
-        const cd T = {pl_level * c_cis_re[r], pl_level * c_cis_im[r]};
+        const cd T = {pl_level * b.cis[r], pl_level * b.cis[64 + r]};
         cd w = cdiv_fast(T, P);
         const cd v = {w.re - 1.0, w.im};
         const double a2 = cabs2(v);
         const cd step = cdiv_fast(P, dP);
         if (!cfinite(w) || !cfinite(step) || it > 24) {
+            // the starts of the segment not reached yet get no value (NaN:
+            // their descents end as divergent)
+            const double nan = __longlong_as_double(0x7ff8000000000000ll);
+            for (int s2 = (s + pl_q - 1) / pl_q * pl_q; s2 < pl_F; s2 += pl_q)
+                starts[start0 + (uint32_t)(s2 / pl_q)] = {nan, nan};
             seg_flag[g] = 2;
             cnt[1] += 1u;
             g = NONE;
@@ -411,6 +431,7 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
         cf P, dP;
         if (pl_N > FP32_MAX_ORDER) { // FP32 carries no information: FP64 from the start
             roots[g] = starts[g];
+            status[g] = ST_NONE;
             iters[g] = 0;
             g = -1;
             continue;
@@ -563,24 +584,29 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
 
 // -------------------------------------------------------- nset collection
 // Sort key of a root of the type of rank t: t above bit KEY_TYPE_SHIFT, then
-// q = floor((re + 2.125) 2^48), an exact integer (re 2^48 is exact, so is
-// its floor) over [-2.125, 1.875).  Keys order the roots of a type by real
-// part up to the resolution 2^-48; the identification below reasons on key
-// differences, so equal keys are harmless.  T <= 64 types need 56 key bits.
+// q = floor((re + 2.125) 2^KEY_RES), an exact integer below 2^KEY_BITS over
+// re in [-2.125, 1.875).  Keys order the roots of a type by real part up to
+// the resolution 2^-KEY_RES; the identification below reasons on key
+// differences, so equal keys are harmless.  The candidates reach the sort
+// grouped by type (start order), and the sort keeps that grouping, so only
+// the KEY_BITS of the real part are sorted.
 constexpr int KEY_TYPE_SHIFT = 50;
+constexpr int KEY_RES = 46;
+constexpr int KEY_BITS = KEY_RES + 2;
 constexpr int MAX_TYPES = 256;
 
 __device__ __forceinline__ uint64_t root_key(int t, double re)
 {
-    const double x = fmin(fmax(re, -2.125), 1.875 - 0x1p-48);
-    const int64_t q = (int64_t)floor(x * 0x1p48) + (int64_t)(17ll << 45); // 2.125 2^48
+    const double x = fmin(fmax(re, -2.125), 1.875 - 0x1p-46);
+    const int64_t q = (int64_t)floor(x * 0x1p46) + (int64_t)(17ll << 43); // 2.125 2^46
     return ((uint64_t)t << KEY_TYPE_SHIFT) | (uint64_t)q;
 }
 __device__ __forceinline__ int key_type(uint64_t key) { return (int)(key >> KEY_TYPE_SHIFT); }
 
 // Keys i > j of one type with key_i - key_j >= key_window(tau) have
-// re_i - re_j > (key_i - key_j - 1) 2^-48 >= tau, and so have all earlier j.
-__device__ __forceinline__ uint64_t key_window(double tau) { return 1ull + (uint64_t)ceil(tau * 0x1p48); }
+// re_i - re_j > (key_i - key_j - 1) 2^-KEY_RES >= tau, and so have all
+// earlier j.
+__device__ __forceinline__ uint64_t key_window(double tau) { return 1ull + (uint64_t)ceil(tau * 0x1p46); }
 
 // Fold to the closed upper half plane and snap to the real axis when the
 // imaginary part is below both tau/2 and the rounding level of a converged
@@ -710,46 +736,61 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
     flag[g] = f;
 }
 
+// Survivors (flag) to their scanned positions as (key, start index) pairs,
+// grouped by type in start order; surv_offs[t] = the first position of type
+// t, surv_offs[T] = the number of survivors.
 __global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const cd *roots, const uint32_t *flag,
-                                                           const uint32_t *pos, uint64_t *keys, uint32_t *vals,
-                                                           unsigned long long *count)
+                                                           const uint32_t *pos, uint64_t *keys, uint32_t *vals)
 {
     __shared__ collect_tables tabs;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool v = g < b.n_starts;
     const uint32_t f = v ? flag[g] : 0u;
     const uint32_t p = v ? pos[g] : 0u;
-    const cd z = v ? roots[g] : cd{0.0, 0.0};
+    const cd z = v && f ? roots[g] : cd{0.0, 0.0};
     load_tables_lds(tabs, b);
     __syncthreads();
+    if (!v) return;
+    const int t = find_type_lds(tabs.offs, b.T, g);
     if (f) {
-        const int t = find_type_lds(tabs.offs, b.T, g);
         keys[p] = root_key(t, fold_snap(z, tabs.tau[t]).re);
         vals[p] = (uint32_t)g;
     }
-    if (g == b.n_starts - 1) *count = (unsigned long long)p + f;
+    if (g == tabs.offs[t]) b.surv_offs[t] = (int64_t)p;
+    if (g == b.n_starts - 1) b.surv_offs[b.T] = (int64_t)p + f;
 }
 
 // The sorted candidates, folded and snapped, in sort order: one gather, so
 // that the identification and the output pass read them in sequence.
+// Grid-stride over the m = surv_offs[T] candidates.
 __global__ void k_gather(batch_args b, const cd *roots, const cd *roots_lo, const uint8_t *status,
-                         const uint64_t *keys, const uint32_t *vals, cd *zs, cd *zs_lo, uint8_t *zs_dd, int64_t m)
+                         const uint64_t *keys, const uint32_t *vals, cd *zs, cd *zs_lo, uint8_t *zs_dd)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const uint32_t v = vals[i];
-    const plan_t &pl = b.types[key_type(keys[i])].p;
-    cd z = roots[v], lo = {0.0, 0.0};
-    const bool dd = status[v] == ST_DD;
-    if (dd) {
-        lo = roots_lo[v];
-        fold_snap_dd(z, lo, pl.tau_dd);
-    } else {
-        z = fold_snap(z, pl.tau);
+    const int64_t m = b.surv_offs[b.T];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const uint32_t v = vals[i];
+        const int t = key_type(keys[i]);
+        if (v >= b.n_starts || t >= b.T) { // not a sorted candidate: never matches
+            const double nan = __longlong_as_double(0x7ff8000000000000ll);
+            zs[i] = {nan, nan};
+            zs_lo[i] = {0.0, 0.0};
+            zs_dd[i] = 0;
+            continue;
+        }
+        const plan_t &pl = b.types[t].p;
+        cd z = roots[v], lo = {0.0, 0.0};
+        const bool dd = status[v] == ST_DD;
+        if (dd) {
+            lo = roots_lo[v];
+            fold_snap_dd(z, lo, pl.tau_dd);
+        } else {
+            z = fold_snap(z, pl.tau);
+        }
+        zs[i] = z;
+        zs_lo[i] = lo;
+        zs_dd[i] = dd;
     }
-    zs[i] = z;
-    zs_lo[i] = lo;
-    zs_dd[i] = dd;
 }
 
 // A sorted point is a duplicate when an earlier point of the same type is the
@@ -757,61 +798,58 @@ __global__ void k_gather(batch_args b, const cd *roots, const cd *roots_lo, cons
 // cluster kept).  The backward scan stops at the key window (real parts tau
 // apart) or after 256 points.
 __global__ void k_mark(batch_args b, const uint64_t *keys, const cd *zs, const cd *zs_lo, const uint8_t *zs_dd,
-                       uint32_t *flag, int64_t m)
+                       uint32_t *flag)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const uint64_t ki = keys[i];
-    const int t = key_type(ki);
-    const double tau = b.types[t].p.tau, tdd = b.types[t].p.tau_dd;
-    const uint64_t win = key_window(tau);
-    const cd zi = zs[i], li = zs_lo[i];
-    const bool di = zs_dd[i];
-    uint32_t f = 1;
-    for (int64_t j = i - 1, c = 0; j >= 0 && c < 256; --j, ++c) {
-        const uint64_t kj = keys[j];
-        if (key_type(kj) != t || ki - kj >= win) break;
-        if (same_root(zi, li, di, zs[j], zs_lo[j], zs_dd[j], tau, tdd)) { f = 0; break; }
+    const int64_t m = b.surv_offs[b.T];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const uint64_t ki = keys[i];
+        const int t = key_type(ki);
+        if (t >= b.T) {
+            flag[i] = 1;
+            continue;
+        }
+        const double tau = b.types[t].p.tau, tdd = b.types[t].p.tau_dd;
+        const uint64_t win = key_window(tau);
+        const cd zi = zs[i], li = zs_lo[i];
+        const bool di = zs_dd[i];
+        uint32_t f = 1;
+        for (int64_t j = i - 1, c = 0; j >= 0 && c < 256; --j, ++c) {
+            const uint64_t kj = keys[j];
+            if (key_type(kj) != t || ki - kj >= win) break;
+            if (same_root(zi, li, di, zs[j], zs_lo[j], zs_dd[j], tau, tdd)) { f = 0; break; }
+        }
+        flag[i] = f;
     }
-    flag[i] = f;
 }
 
-// Per type: first sorted index (lower bound of the type's key range, T + 1
-// entries in tb) and first index in the collected index space (coll_offs);
-// the number of collected roots (C_UNIQUE) and of sorted candidates
-// (C_SURVIVORS) go to the first counter copy (the fold adds the copies).
-// One block.
-__global__ void k_type_bounds(batch_args b, const uint64_t *keys, const uint32_t *flag, const uint32_t *pos,
-                              int64_t m, int64_t *tb)
+// Per type: first index in the collected index space (coll_offs, from the
+// scanned marks at the type's first sorted index); the number of collected
+// roots (C_UNIQUE) and of sorted candidates (C_SURVIVORS) go to the first
+// counter copy (the fold adds the copies).  One block.
+__global__ void k_type_bounds(batch_args b, const uint32_t *flag, const uint32_t *pos)
 {
-    for (int t = threadIdx.x; t <= b.T; t += blockDim.x) {
-        const uint64_t key = (uint64_t)t << KEY_TYPE_SHIFT;
-        int64_t lo = 0, hi = m;
-        while (lo < hi) {
-            int64_t mid = (lo + hi) / 2;
-            if (keys[mid] < key) lo = mid + 1; else hi = mid;
-        }
-        tb[t] = (t == b.T) ? m : lo;
-    }
-    __syncthreads();
+    const int64_t m = b.surv_offs[b.T];
     auto pos_at = [&](int64_t i) -> int64_t { return i < m ? pos[i] : (m ? pos[m - 1] + flag[m - 1] : 0); };
-    for (int t = threadIdx.x; t <= b.T; t += blockDim.x) {
-        b.coll_offs[t] = pos_at(tb[t]);
-        if (t < b.T) {
-            b.spread[(int64_t)t * C_NCOUNTERS + C_UNIQUE] = (uint64_t)(pos_at(tb[t + 1]) - pos_at(tb[t]));
-            b.spread[(int64_t)t * C_NCOUNTERS + C_SURVIVORS] = (uint64_t)(tb[t + 1] - tb[t]);
-        }
+    for (int t = threadIdx.x; t <= b.T; t += blockDim.x) b.coll_offs[t] = pos_at(b.surv_offs[t]);
+    __syncthreads();
+    for (int t = threadIdx.x; t < b.T; t += blockDim.x) {
+        b.spread[(int64_t)t * C_NCOUNTERS + C_UNIQUE] = (uint64_t)(b.coll_offs[t + 1] - b.coll_offs[t]);
+        b.spread[(int64_t)t * C_NCOUNTERS + C_SURVIVORS] = (uint64_t)(b.surv_offs[t + 1] - b.surv_offs[t]);
     }
 }
 
 // The identified roots into the collected index space (type-major, by real
 // part within a type).
-__global__ void k_scatter(const uint32_t *flag, const uint32_t *pos, const cd *zs, const cd *zs_lo,
-                          const uint8_t *zs_dd, int64_t m, cd *uz, cd *uz_lo, uint8_t *uz_dd)
+__global__ void k_scatter(batch_args b, const uint32_t *flag, const uint32_t *pos, const cd *zs, const cd *zs_lo,
+                          const uint8_t *zs_dd, cd *uz, cd *uz_lo, uint8_t *uz_dd)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m && flag[i]) {
+    const int64_t m = b.surv_offs[b.T];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        if (!flag[i]) continue;
         const uint32_t u = pos[i];
+        if (u >= b.n_starts) continue;
         uz[u] = zs[i];
         uz_lo[u] = zs_lo[i];
         uz_dd[u] = zs_dd[i];
@@ -972,8 +1010,9 @@ __device__ __noinline__ bool classify_q_dd(int l, int n, uint32_t divmask, doubl
     return keep;
 }
 
-// Per type: first index in the kept index space; kept count in C_KEPT.
-// One block.
+// Per type: first index in the kept index space; kept count in C_KEPT; the
+// output index space of the certificate, uniq_offs, with min(kept, capacity)
+// roots per type.  One block.
 __global__ void k_kept_bounds(batch_args b, const uint32_t *keep, const uint32_t *kpos)
 {
     const int64_t n = b.coll_offs[b.T];
@@ -984,25 +1023,40 @@ __global__ void k_kept_bounds(batch_args b, const uint32_t *keep, const uint32_t
             b.spread[(int64_t)t * C_NCOUNTERS + C_KEPT] =
                 (uint64_t)(kpos_at(b.coll_offs[t + 1]) - kpos_at(b.coll_offs[t]));
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t a = 0;
+        b.uniq_offs[0] = 0;
+        for (int t = 0; t < b.T; ++t) {
+            const int64_t k = b.kept_offs[t + 1] - b.kept_offs[t];
+            a += (uint64_t)k < b.types[t].cap ? k : (int64_t)b.types[t].cap;
+            b.uniq_offs[t + 1] = a;
+        }
+    }
 }
 
 // Kept roots to the caller's output slices (at most the capacity of each),
 // with period, preperiod and the real flag; real roots counted per type.
+// Grid-stride over the collected index space.
 __global__ void __launch_bounds__(256) k_emit(batch_args b, const cd *uz, const cd *uz_lo, const uint8_t *uz_dd,
                                               const uint32_t *keep, const uint32_t *kpos, const int32_t *cls,
-                                              int64_t m, double *ore, double *oim, double *ore_lo, double *oim_lo,
+                                              double *ore, double *oim, double *ore_lo, double *oim_lo,
                                               int32_t *period, int32_t *preperiod, uint8_t *flags)
 {
     __shared__ int64_t offs[MAX_TYPES + 1];
     for (int i = threadIdx.x; i <= b.T; i += blockDim.x) offs[i] = b.coll_offs[i];
     __syncthreads();
     unsigned long long *const wc = wave_ctr(b);
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool act = u < m && u < offs[b.T] && keep[u];
-    const int t = act ? find_type_lds(offs, b.T, u) : -1;
+    const int64_t n = offs[b.T];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     type_count nreal;
-    nreal.t = t;
-    if (act) {
+    for (int64_t u0 = (int64_t)blockIdx.x * blockDim.x; u0 < n; u0 += stride) {
+        const int64_t u = u0 + threadIdx.x;
+        const bool act = u < n && keep[u];
+        const int t = act ? find_type_lds(offs, b.T, u) : nreal.t;
+        if (__ballot(act && t != nreal.t)) flush_count(wc, C_REAL, nreal);
+        nreal.t = t;
+        if (!act) continue;
         const type_desc &td = b.types[t];
         const int64_t rank = (int64_t)kpos[u] - b.kept_offs[t];
         const cd z = uz[u];
@@ -1018,7 +1072,7 @@ __global__ void __launch_bounds__(256) k_emit(batch_args b, const cd *uz, const 
             if (preperiod) preperiod[i] = td.p.l;
             if (flags) flags[i] = (z.im == 0.0 ? 1 : 0) | (dd ? 8 : 0); // MSPLIT_R_REAL, MSPLIT_R_DD
         }
-        nreal.v = z.im == 0.0;
+        nreal.v += z.im == 0.0;
     }
     flush_count(wc, C_REAL, nreal);
 }

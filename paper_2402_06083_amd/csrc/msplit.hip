@@ -7,15 +7,16 @@
 #include <cstring>
 
 #include <hip/hip_runtime.h>
-#include <rocprim/rocprim.hpp>
 
 #include <algorithm>
+#include <new>
 #include <numeric>
 #include <vector>
 
 #include "msplit.h"
 #include "kernels.hpp"
 #include "certify.hpp"
+#include "sort.hpp"
 
 using namespace msplit;
 
@@ -194,47 +195,35 @@ int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uin
 
 // ------------------------------------------------------------- workspace
 struct layout {
-    size_t gctr, ctr, spread, zs, zs_lo, roots, roots_lo, tip_lo, types, offs, tb, seeds, starts, status, iters, segf, flag0, pos0, keys, vals, keys2, vals2,
-        flag, pos, temp, total;
-    size_t temp_bytes;
+    size_t gctr, ctr, spread, isz, cis, types, offs, rtile, seeds, starts, status, iters, segf, flag0, pos0, keys,
+        vals, keys2, vals2, zs, zs_lo, roots, roots_lo, tip_lo, flag, pos, counts, part, total;
 };
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// key bits of a call with T types: the fixed-point real part and the type
-int key_end_bit(int T)
-{
-    int tb = 0;
-    while ((1 << tb) < T) ++tb;
-    return KEY_TYPE_SHIFT + tb;
-}
+// device sizes (int64 slots): the scan of the prekey flags runs over all
+// starts, the scan between the sweeps of the sort over the digit counts
+enum { SZ_STARTS = 0, SZ_COUNTS, SZ_N = 4 };
 
-hipError_t rocprim_temp(int64_t n, int T, size_t &bytes)
-{
-    size_t sort_b = 0, scan_b = 0;
-    hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_b, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                             (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n, 0,
-                                             key_end_bit(T));
-    if (e != hipSuccess) return e;
-    e = rocprim::exclusive_scan(nullptr, scan_b, (uint32_t *)nullptr, (uint32_t *)nullptr, 0u, (size_t)n,
-                                rocprim::plus<uint32_t>());
-    if (e != hipSuccess) return e;
-    bytes = std::max(sort_b, scan_b);
-    return hipSuccess;
-}
+// tiles of the sort: every segment (type) rounds up to whole tiles
+int64_t sort_tiles_max(int64_t n, int T) { return n / RS_TILE + T + 1; }
 
-layout make_layout(const batch_plan &bp, size_t temp_bytes)
+layout make_layout(const batch_plan &bp)
 {
     layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     const size_t T = (size_t)bp.T, NS = (size_t)bp.n_starts;
+    const int64_t n_counts = sort_tiles_max(bp.n_starts, bp.T) * RS_BINS;
+    const int64_t n_part = std::max<int64_t>(bp.n_starts, n_counts) / SC_TILE + 2;
     L.gctr = take(sizeof(unsigned long long) * G_NCOUNTERS);
     L.ctr = take(sizeof(unsigned long long) * C_NCOUNTERS * T);
     L.spread = take(sizeof(unsigned long long) * C_NCOUNTERS * T * CTR_SPREAD);
+    L.isz = take(sizeof(int64_t) * SZ_N);
+    L.cis = take(sizeof(double) * 128);
     L.types = take(sizeof(type_desc) * T);
-    L.offs = take(sizeof(int64_t) * 6 * (T + 1));
-    L.tb = take(sizeof(int64_t) * (T + 1));
+    L.offs = take(sizeof(int64_t) * 7 * (T + 1));
+    L.rtile = take(sizeof(int64_t) * (T + 1));
     L.seeds = take(sizeof(cd) * bp.n_seeds);
     L.starts = take(sizeof(cd) * NS);
     L.status = take(NS);
@@ -253,57 +242,50 @@ layout make_layout(const batch_plan &bp, size_t temp_bytes)
     L.vals2 = take(4 * NS);
     L.flag = take(4 * NS);
     L.pos = take(4 * NS);
-    L.temp_bytes = temp_bytes;
-    L.temp = take(temp_bytes);
+    L.counts = take(4 * (size_t)n_counts);
+    L.part = take(4 * (size_t)n_part);
     L.total = off;
     return L;
 }
 
 // -------------------------------------------------------------- launches
-__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-__global__ void k_fill_nan(cd *p, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = {__longlong_as_double(0x7ff8000000000000ll), __longlong_as_double(0x7ff8000000000000ll)};
-}
-__global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-// counters: zero; per-type minimum-separation slot at +inf (every copy)
+// counters: zero; per-type minimum-separation slot at +inf (every copy);
+// the device sizes that are known before the call
 __device__ __forceinline__ unsigned long long ctr_identity(int slot)
 {
     return slot == C_MIN_SEP_BITS ? 0x7ff0000000000000ull : 0ull;
 }
-__global__ void k_init_counters(unsigned long long *gctr, unsigned long long *ctr, unsigned long long *spread, int T)
+__global__ void k_init_counters(unsigned long long *gctr, unsigned long long *ctr, unsigned long long *spread, int T,
+                                int64_t *isz, int64_t n_starts)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < G_NCOUNTERS) gctr[i] = 0;
     if (i < T * C_NCOUNTERS) ctr[i] = ctr_identity(i % C_NCOUNTERS);
     if (i < T * C_NCOUNTERS * CTR_SPREAD) spread[i] = ctr_identity(i % C_NCOUNTERS);
+    if (isz && i < SZ_N) isz[i] = i == SZ_STARTS ? n_starts : 0;
 }
 // ctr = the copies combined: sums, except the largest radius (max) and the
-// least separation (min); non-negative doubles order like their bit patterns
+// least separation (min); non-negative doubles order like their bit
+// patterns.  One wave per counter, lane k reading copy k.
+static_assert(CTR_SPREAD == 64, "one lane per counter copy");
 __global__ void k_fold_counters(unsigned long long *ctr, const unsigned long long *spread, int T)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = T * C_NCOUNTERS;
-    if (i >= n) return;
+    const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return; // whole waves
     const int slot = i % C_NCOUNTERS;
-    unsigned long long a = spread[i];
-    for (int k = 1; k < CTR_SPREAD; ++k) {
-        const unsigned long long v = spread[(size_t)k * n + i];
-        if (slot == C_MAX_RAD_BITS) a = v > a ? v : a;
-        else if (slot == C_MIN_SEP_BITS) a = v < a ? v : a;
-        else a += v;
+    unsigned long long a = spread[(size_t)lane * n + i];
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(a, d, 64);
+        if (slot == C_MAX_RAD_BITS) a = o > a ? o : a;
+        else if (slot == C_MIN_SEP_BITS) a = o < a ? o : a;
+        else a += o;
     }
-    ctr[i] = a;
+    if (lane == 0) ctr[i] = a;
 }
+unsigned fold_blocks(int T) { return (unsigned)((T * C_NCOUNTERS + 3) / 4); }
+
 __global__ void k_unzip(const cd *z, double *re, double *im, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -331,6 +313,39 @@ unsigned persistent_blocks(int64_t work, int bs)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, (work + bs - 1) / bs));
 }
 
+// exclusive scan of *n_dev (at most n_max) u32 values, in == out allowed
+void scan_u32(const uint32_t *in, uint32_t *out, const int64_t *n_dev, int64_t n_max, uint32_t *part,
+              hipStream_t st)
+{
+    const int64_t tiles = std::max<int64_t>(1, (n_max + SC_TILE - 1) / SC_TILE);
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, (int64_t)device_cus() * 8);
+    k_scan_reduce<<<grid, SC_BLOCK, 0, st>>>(in, n_dev, part);
+    k_scan_parts<<<1, SC_BLOCK, 0, st>>>(part, n_dev, nullptr);
+    k_scan_down<<<grid, SC_BLOCK, 0, st>>>(in, out, n_dev, part);
+}
+
+// segmented sort (segments seg[0..T], on the device, seg[0] = 0) of at most
+// n_max pairs on key bits [0, bits); the sorted pairs end in (*k, *v)
+void sort_pairs(uint64_t **k, uint32_t **v, uint64_t *k2, uint32_t *v2, const int64_t *seg, int64_t *tile, int T,
+                int bits, int64_t n_max, uint32_t *counts, int64_t *n_counts, uint32_t *part, hipStream_t st)
+{
+    k_rs_tiles<<<1, 64, 0, st>>>(seg, T, tile, n_counts);
+    const int64_t tmax = sort_tiles_max(n_max, T);
+    const unsigned grid = (unsigned)std::min<int64_t>(tmax, (int64_t)device_cus() * 4);
+    const rs_segs s = {seg, tile, T};
+    uint64_t *ka = *k, *kb = k2;
+    uint32_t *va = *v, *vb = v2;
+    for (int shift = 0; shift < bits; shift += 8) {
+        k_rs_upsweep<<<grid, SC_BLOCK, 0, st>>>(ka, s, shift, counts);
+        scan_u32(counts, counts, n_counts, tmax * RS_BINS, part, st);
+        k_rs_downsweep<<<grid, SC_BLOCK, 0, st>>>(ka, va, kb, vb, s, shift, counts);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    *k = ka;
+    *v = va;
+}
+
 struct call_ctx {
     msplit_stats *stats;
     int nstats;
@@ -351,183 +366,161 @@ struct call_ctx {
         if (!ctx.check((x))) return ctx.err; \
     } while (0)
 
-hipError_t set_cis(int M, hipStream_t stream)
-{
-    double re[64], im[64];
-    for (int s = 0; s < 64; ++s) {
-        double t = 2.0 * M_PI * (double)(s % M) / (double)M;
-        re[s] = cos(t);
-        im[s] = sin(t);
-        // exact values at the quarter turns
-        if (4 * (s % M) == 0) { re[s] = 1; im[s] = 0; }
-        if (4 * (s % M) == M) { re[s] = 0; im[s] = 1; }
-        if (4 * (s % M) == 2 * M) { re[s] = -1; im[s] = 0; }
-        if (4 * (s % M) == 3 * M) { re[s] = 0; im[s] = -1; }
-    }
-    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_cis_re), re, sizeof(re), 0, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_cis_im), im, sizeof(im), 0, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    return e;
-}
-
 struct events {
     hipEvent_t e[7];
     int made = 0;
     ~events() { for (int i = 0; i < made; ++i) (void)hipEventDestroy(e[i]); }
 };
 
-// The split of a list of types (in caller order ln[2i], ln[2i+1]); roots of
-// type i go to out at out_offs[i] with capacity caps[i].  counts[i] and
-// stats[i] are written for every type.  starts_only: stop after the level
-// line and copy the starts of the single type to sre / sim.
-int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *workspace, uint64_t ws_bytes,
-              msplit_roots *out, const uint64_t *out_offs, const uint64_t *caps, uint64_t *counts,
-              msplit_stats *stats, void *stream_v, bool starts_only = false, double *sre = nullptr,
-              double *sim = nullptr, uint64_t scap = 0)
+// One call of the pipeline: the plan, the workspace carve-up and the kernel
+// arguments, all prepared on the host before anything is enqueued.
+struct batch_call {
+    batch_plan bp;
+    layout L;
+    msplit_options o;
+    msplit_roots out;
+    int bs = 256;
+    bool cert = false, labels = true, any_tip = false;
+    batch_args ba;
+    char *ws = nullptr;
+    int64_t out_max = 0;
+    std::vector<int64_t> offs; // host copy of the item offsets (uploaded once)
+    std::vector<unsigned long long> h;
+};
+
+template <typename P>
+P *ws_at(const batch_call &c, size_t off) { return (P *)(c.ws + off); }
+
+// Validation, plan and layout; no device work.
+int prepare(batch_call &c, const int32_t *ln, int npairs, const msplit_options *opts, void *workspace,
+            uint64_t ws_bytes, const msplit_roots *out, const uint64_t *out_offs, const uint64_t *caps,
+            bool starts_only)
 {
-    for (int i = 0; i < npairs && counts; ++i) counts[i] = 0;
-    if (!counts || !workspace || !ln) return MSPLIT_E_ARG;
+    if (!workspace || !ln) return MSPLIT_E_ARG;
     if (!starts_only && (!out || !out->re || !out->im)) return MSPLIT_E_ARG;
-    if (starts_only && (!sre || !sim || npairs != 1)) return MSPLIT_E_ARG;
     if (!opts) opts = defaults();
     if (opts->struct_size && opts->struct_size != sizeof(msplit_options)) return MSPLIT_E_ARG;
     if (opts->precision < 0 || opts->precision > 2) return MSPLIT_E_ARG;
     if (opts->precision == MSPLIT_DD) return MSPLIT_E_UNSUPPORTED;
     if (opts->points_per_turn && (opts->points_per_turn % 4 || opts->points_per_turn > 64)) return MSPLIT_E_ARG;
-    const int bs = opts->block_size ? (int)opts->block_size : 256;
-    if (bs % 64 || bs > 1024) return MSPLIT_E_ARG;
-    if (stats) memset(stats, 0, sizeof(msplit_stats) * npairs);
-    batch_plan bp;
-    int r = make_batch(ln, npairs, opts, out_offs, caps, bp);
+    c.bs = opts->block_size ? (int)opts->block_size : 256;
+    if (c.bs % 64 || c.bs > 256) return MSPLIT_E_ARG;
+    c.o = *opts;
+    if (out) c.out = *out; else memset(&c.out, 0, sizeof(c.out));
+    int r = make_batch(ln, npairs, opts, out_offs, caps, c.bp);
     if (r) return r;
+    const batch_plan &bp = c.bp;
     for (int t = 0; t < bp.T; ++t) {
         // FP64 keys separate the roots only while the identification radius
         // stays well above the FP64 rounding of a root
         if (bp.td[t].p.tau < 0x1p-50) return MSPLIT_E_PRECISION;
     }
     if (bp.n_starts >= ((int64_t)1 << 32)) return MSPLIT_E_UNSUPPORTED;
-    hipStream_t stream = (hipStream_t)stream_v;
-    call_ctx ctx{stats, npairs};
-    size_t temp_bytes = 0;
-    CHK(rocprim_temp(bp.n_starts, bp.T, temp_bytes));
-    const layout L = make_layout(bp, temp_bytes);
-    if (ws_bytes < L.total) return MSPLIT_E_WORKSPACE;
-    char *ws = (char *)workspace;
-    unsigned long long *gctr = (unsigned long long *)(ws + L.gctr);
-    unsigned long long *ctr = (unsigned long long *)(ws + L.ctr);
-    unsigned long long *spread = (unsigned long long *)(ws + L.spread);
-    type_desc *dtypes = (type_desc *)(ws + L.types);
-    int64_t *doffs = (int64_t *)(ws + L.offs);
-    int64_t *tb = (int64_t *)(ws + L.tb);
-    cd *seeds = (cd *)(ws + L.seeds);
-    cd *starts = (cd *)(ws + L.starts);
-    uint8_t *status = (uint8_t *)(ws + L.status);
-    uint8_t *iters = (uint8_t *)(ws + L.iters);
-    uint8_t *segf = (uint8_t *)(ws + L.segf);
-    uint32_t *flag0 = (uint32_t *)(ws + L.flag0), *pos0 = (uint32_t *)(ws + L.pos0);
-    uint64_t *keys = (uint64_t *)(ws + L.keys), *keys2 = (uint64_t *)(ws + L.keys2);
-    cd *zs = (cd *)(ws + L.zs), *zs_lo = (cd *)(ws + L.zs_lo);
-    cd *roots = (cd *)(ws + L.roots), *roots_lo = (cd *)(ws + L.roots_lo), *tip_lo = (cd *)(ws + L.tip_lo);
-    uint32_t *vals = (uint32_t *)(ws + L.vals), *vals2 = (uint32_t *)(ws + L.vals2);
-    uint32_t *flag = (uint32_t *)(ws + L.flag), *pos = (uint32_t *)(ws + L.pos);
-    void *temp = ws + L.temp;
-    const int T = bp.T;
-
     // every type of one call shares M (the cis table)
-    for (int t = 1; t < T; ++t)
+    for (int t = 1; t < bp.T; ++t)
         if (bp.td[t].p.M != bp.td[0].p.M) return MSPLIT_E_ARG;
-    CHK(set_cis(bp.td[0].p.M, stream));
-
-    // tables: type descriptors and offsets (uniq_offs filled later)
-    std::vector<int64_t> offs(6 * (T + 1), 0);
-    std::copy(bp.seed_offs.begin(), bp.seed_offs.end(), offs.begin());
-    std::copy(bp.seg_offs.begin(), bp.seg_offs.end(), offs.begin() + (T + 1));
-    std::copy(bp.start_offs.begin(), bp.start_offs.end(), offs.begin() + 2 * (T + 1));
-    CHK(hipMemcpyAsync(dtypes, bp.td.data(), sizeof(type_desc) * T, hipMemcpyHostToDevice, stream));
-    CHK(hipMemcpyAsync(doffs, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, stream));
-
-    batch_args ba;
-    ba.types = dtypes;
+    c.cert = !starts_only && (opts->flags & MSPLIT_F_CERTIFY) != 0;
+    if (c.cert && (!out->radius || !out->flags)) return MSPLIT_E_ARG;
+    c.labels = !(opts->flags & MSPLIT_F_NO_LABEL);
+    c.L = make_layout(bp);
+    if (ws_bytes < c.L.total) return MSPLIT_E_WORKSPACE;
+    c.ws = (char *)workspace;
+    const int T = bp.T;
+    c.offs.assign(7 * (T + 1), 0);
+    std::copy(bp.seed_offs.begin(), bp.seed_offs.end(), c.offs.begin());
+    std::copy(bp.seg_offs.begin(), bp.seg_offs.end(), c.offs.begin() + (T + 1));
+    std::copy(bp.start_offs.begin(), bp.start_offs.end(), c.offs.begin() + 2 * (T + 1));
+    int64_t *doffs = ws_at<int64_t>(c, c.L.offs);
+    batch_args &ba = c.ba;
+    ba.types = ws_at<type_desc>(c, c.L.types);
     ba.seed_offs = doffs;
     ba.seg_offs = doffs + (T + 1);
     ba.start_offs = doffs + 2 * (T + 1);
     ba.uniq_offs = doffs + 3 * (T + 1);
     ba.coll_offs = doffs + 4 * (T + 1);
     ba.kept_offs = doffs + 5 * (T + 1);
+    ba.surv_offs = doffs + 6 * (T + 1);
+    ba.cis = ws_at<double>(c, c.L.cis);
     ba.T = T;
     ba.n_seeds = bp.n_seeds;
     ba.n_segs = bp.n_segs;
     ba.n_starts = bp.n_starts;
     ba.chunk_seg = chunk_for(bp.n_segs);
     ba.chunk_start = chunk_for(bp.n_starts);
-    ba.gctr = gctr;
-    ba.ctr = ctr;
-    ba.spread = spread;
+    ba.gctr = ws_at<unsigned long long>(c, c.L.gctr);
+    ba.ctr = ws_at<unsigned long long>(c, c.L.ctr);
+    ba.spread = ws_at<unsigned long long>(c, c.L.spread);
+    c.any_tip = false;
+    for (int t = 0; t < T; ++t) c.any_tip = c.any_tip || bp.td[t].p.x_tip > 0.0;
+    c.out_max = 0;
+    for (int t = 0; t < T; ++t) c.out_max += (int64_t)std::min<uint64_t>(bp.td[t].cap, (uint64_t)bp.td[t].p.D);
+    c.h.assign((size_t)T * C_NCOUNTERS, 0ull);
+    return MSPLIT_OK;
+}
 
-    events ev;
-    for (int i = 0; i < 7; ++i) {
-        CHK(hipEventCreate(&ev.e[i]));
-        ev.made = i + 1;
-    }
-    CHK(hipEventRecord(ev.e[0], stream));
+// Type descriptors and item offsets to the workspace (the other offset
+// tables are set on the device by every call).
+hipError_t upload_tables(const batch_call &c, hipStream_t stream)
+{
+    hipError_t e = hipMemcpyAsync((void *)c.ba.types, c.bp.td.data(), sizeof(type_desc) * c.bp.T,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void *)c.ba.seed_offs, c.offs.data(), sizeof(int64_t) * c.offs.size(),
+                           hipMemcpyHostToDevice, stream);
+    return e;
+}
+
+// The level line: counters, seeds, walk (events ev[0..2] when non-null).
+void enqueue_level_line(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
+{
+    const batch_plan &bp = c.bp;
+    const batch_args &ba = c.ba;
+    const int T = bp.T, bs = c.bs;
+    cd *seeds = ws_at<cd>(c, c.L.seeds), *starts = ws_at<cd>(c, c.L.starts);
+    cd *tip_lo = ws_at<cd>(c, c.L.tip_lo);
+    if (ev) (void)hipEventRecord(ev[0], stream);
     k_init_counters<<<blocks_for((int64_t)T * C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
-        gctr, ctr, spread, T);
-    k_fill_nan<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(starts, bp.n_starts);
-    k_fill_u8<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(status, bp.n_starts, ST_NONE);
+        ba.gctr, ba.ctr, ba.spread, T, ws_at<int64_t>(c, c.L.isz), bp.n_starts);
+    k_cis<<<1, 64, 0, stream>>>(bp.td[0].p.M, (double *)ba.cis);
     // seeds: lift from the circle |p_1| = lambda_0
     k_seeds<<<persistent_blocks(bp.n_seeds, bs), bs, 0, stream>>>(ba, seeds, starts);
-    CHK(hipEventRecord(ev.e[1], stream));
+    if (ev) (void)hipEventRecord(ev[1], stream);
     // level-line walk
-    k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, segf);
+    k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, ws_at<uint8_t>(c, c.L.segf));
     if (bp.n_tip > 0) k_refine_tip_starts<<<blocks_for(bp.n_tip, 256), 256, 0, stream>>>(ba, starts, tip_lo, bp.n_tip);
-    CHK(hipEventRecord(ev.e[2], stream));
-    CHK(hipGetLastError());
+    if (ev) (void)hipEventRecord(ev[2], stream);
+}
 
-    std::vector<unsigned long long> h((size_t)T * C_NCOUNTERS);
-    auto read_counters = [&]() -> hipError_t {
-        k_fold_counters<<<blocks_for((int64_t)T * C_NCOUNTERS, 256), 256, 0, stream>>>(ctr, spread, T);
-        hipError_t e = hipGetLastError();
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h.data(), ctr, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
-                                      stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        return e;
-    };
-    auto H = [&](int t, int slot) { return h[(size_t)t * C_NCOUNTERS + slot]; };
-
-    if (starts_only) {
-        const plan_t &p = bp.td[0].p;
-        if (scap < (uint64_t)p.NS) return MSPLIT_E_CAPACITY;
-        k_unzip<<<blocks_for(p.NS, 256), 256, 0, stream>>>(starts, sre, sim, p.NS);
-        CHK(hipGetLastError());
-        CHK(read_counters());
-        counts[0] = (uint64_t)p.NS;
-        float a = 0.f, b = 0.f;
-        (void)hipEventElapsedTime(&a, ev.e[0], ev.e[1]);
-        (void)hipEventElapsedTime(&b, ev.e[1], ev.e[2]);
-        if (stats) {
-            stats->starts = (uint64_t)p.NS;
-            stats->phase_fail = H(0, C_PHASE_FAIL) + H(0, C_SEED_FAIL);
-            stats->steps_lift = H(0, C_STEPS_LIFT);
-            stats->steps_walk = H(0, C_STEPS_WALK);
-            stats->ms_stage[0] = a;
-            stats->ms_stage[1] = b;
-            stats->ms_device = a + b;
-        }
-        return stats && stats->phase_fail ? MSPLIT_E_INCOMPLETE : MSPLIT_OK;
-    }
+// Descents, collection, classification, certificate (events ev[3..6]).
+// Every size after the level line is computed and read on the device.
+void enqueue_roots(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
+{
+    const batch_plan &bp = c.bp;
+    const batch_args &ba = c.ba;
+    const msplit_roots &out = c.out;
+    const int T = bp.T, bs = c.bs;
+    int64_t *isz = ws_at<int64_t>(c, c.L.isz);
+    int64_t *rtile = ws_at<int64_t>(c, c.L.rtile);
+    cd *starts = ws_at<cd>(c, c.L.starts);
+    uint8_t *status = ws_at<uint8_t>(c, c.L.status);
+    uint8_t *iters = ws_at<uint8_t>(c, c.L.iters);
+    uint32_t *flag0 = ws_at<uint32_t>(c, c.L.flag0), *pos0 = ws_at<uint32_t>(c, c.L.pos0);
+    uint64_t *keys = ws_at<uint64_t>(c, c.L.keys), *keys2 = ws_at<uint64_t>(c, c.L.keys2);
+    cd *zs = ws_at<cd>(c, c.L.zs), *zs_lo = ws_at<cd>(c, c.L.zs_lo);
+    cd *roots = ws_at<cd>(c, c.L.roots), *roots_lo = ws_at<cd>(c, c.L.roots_lo);
+    cd *tip_lo = ws_at<cd>(c, c.L.tip_lo);
+    uint32_t *vals = ws_at<uint32_t>(c, c.L.vals), *vals2 = ws_at<uint32_t>(c, c.L.vals2);
+    uint32_t *flag = ws_at<uint32_t>(c, c.L.flag), *pos = ws_at<uint32_t>(c, c.L.pos);
+    uint32_t *rcounts = ws_at<uint32_t>(c, c.L.counts), *part = ws_at<uint32_t>(c, c.L.part);
 
     // descents (MIXED: an FP32 pass first)
-    bool any_tip = false;
-    for (int t = 0; t < T; ++t) any_tip = any_tip || bp.td[t].p.x_tip > 0.0;
     auto descend64 = [&](const cd *src, const uint8_t *it) {
-        if (any_tip)
+        if (c.any_tip)
             k_descend<true><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, roots, status, it);
         else
             k_descend<false><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, roots, status, it);
     };
-    if (opts->precision == MSPLIT_MIXED) {
+    if (c.o.precision == MSPLIT_MIXED) {
         k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, roots, status, iters);
         descend64(roots, iters);
     } else {
@@ -536,113 +529,97 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     // double-double route: the routed starts (next to -2, or stalled at the
     // FP64 precision floor) descend again from their starting points (the
     // list lives in flag0 until the collection)
-    if (any_tip) {
+    if (c.any_tip) {
         k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, roots, status, flag0);
         k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, flag0, starts, tip_lo, roots, roots_lo, status);
     }
-    CHK(hipEventRecord(ev.e[3], stream));
+    if (ev) (void)hipEventRecord(ev[3], stream);
     // nset collection: local identification, compaction, sort, global
     // identification, per-type output slices
+    const unsigned gs = persistent_blocks(bp.n_starts, 256);
     k_prekeys<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, roots, roots_lo, status,
                                                                                     flag0);
-    size_t tb_bytes = temp_bytes;
-    CHK(rocprim::exclusive_scan(temp, tb_bytes, flag0, pos0, 0u, (size_t)bp.n_starts, rocprim::plus<uint32_t>(),
-                                stream));
-    k_compact<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, roots, flag0, pos0, keys, vals,
-                                                                                    gctr + G_COMPACT);
-    CHK(hipGetLastError());
-    unsigned long long m_h = 0;
-    CHK(hipMemcpyAsync(&m_h, gctr + G_COMPACT, sizeof(m_h), hipMemcpyDeviceToHost, stream));
-    CHK(hipStreamSynchronize(stream));
-    const int64_t m = (int64_t)m_h;
-    if (m > 0) {
-        tb_bytes = temp_bytes;
-        CHK(rocprim::radix_sort_pairs(temp, tb_bytes, keys, keys2, vals, vals2, (size_t)m, 0, key_end_bit(T),
-                                      stream));
-        k_gather<<<blocks_for(m, 256), 256, 0, stream>>>(ba, roots, roots_lo, status, keys2, vals2, zs, zs_lo, iters,
-                                                         m);
-        k_mark<<<blocks_for(m, 256), 256, 0, stream>>>(ba, keys2, zs, zs_lo, iters, flag, m);
-        tb_bytes = temp_bytes;
-        CHK(rocprim::exclusive_scan(temp, tb_bytes, flag, pos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
-    }
-    k_type_bounds<<<1, 256, 0, stream>>>(ba, keys2, flag, pos, m, tb);
+    scan_u32(flag0, pos0, isz + SZ_STARTS, bp.n_starts, part, stream);
+    k_compact<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, roots, flag0, pos0, keys,
+                                                                                    vals);
+    uint64_t *skeys = keys;
+    uint32_t *svals = vals;
+    sort_pairs(&skeys, &svals, keys2, vals2, ba.surv_offs, rtile, T, KEY_BITS, bp.n_starts, rcounts,
+               isz + SZ_COUNTS, part, stream);
+    uint64_t *fkeys = skeys == keys ? keys2 : keys; // the sort's other buffers, free now
+    uint32_t *fvals = svals == vals ? vals2 : vals;
+    k_gather<<<gs, 256, 0, stream>>>(ba, roots, roots_lo, status, skeys, svals, zs, zs_lo, iters);
+    k_mark<<<gs, 256, 0, stream>>>(ba, skeys, zs, zs_lo, iters, flag);
+    scan_u32(flag, pos, ba.surv_offs + T, bp.n_starts, part, stream);
+    k_type_bounds<<<1, 256, 0, stream>>>(ba, flag, pos);
     // the identified roots into the collected index space; the starts, the
     // descent results and their status are no longer needed once gathered
     cd *uz = starts, *uz_lo = roots_lo;
     uint8_t *uz_dd = status;
-    if (m > 0) k_scatter<<<blocks_for(m, 256), 256, 0, stream>>>(flag, pos, zs, zs_lo, iters, m, uz, uz_lo, uz_dd);
-    CHK(hipEventRecord(ev.e[4], stream));
-    CHK(hipGetLastError());
+    k_scatter<<<gs, 256, 0, stream>>>(ba, flag, pos, zs, zs_lo, iters, uz, uz_lo, uz_dd);
+    if (ev) (void)hipEventRecord(ev[4], stream);
 
     // classification: period labels (p_n), type Mis(l,n) (q_{l,n}); the kept
-    // roots go to the caller's slices.  flag0/pos0 and vals2 are free here.
+    // roots go to the caller's slices.  flag0/pos0 and the sort's spare
+    // buffers are free here.
     uint32_t *keep = flag0, *kpos = pos0;
-    int32_t *cls = (int32_t *)vals2;
-    const bool labels = !(opts->flags & MSPLIT_F_NO_LABEL);
-    if (m > 0) {
-        uint32_t *hard = vals; // free once sorted
-        k_classify<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, uz_dd, keep, cls, m, labels ? 1 : 0, hard);
-        k_classify_hard<<<device_cus() * 4, 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, cls, hard);
-        tb_bytes = temp_bytes;
-        CHK(rocprim::exclusive_scan(temp, tb_bytes, keep, kpos, 0u, (size_t)m, rocprim::plus<uint32_t>(), stream));
-    }
+    int32_t *cls = (int32_t *)fvals;
+    uint32_t *hard = svals; // free once gathered
+    k_classify<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, uz, uz_dd, keep, cls, c.labels ? 1 : 0, hard);
+    k_classify_hard<<<device_cus() * 4, 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, cls, hard);
+    scan_u32(keep, kpos, ba.coll_offs + T, bp.n_starts, part, stream);
     k_kept_bounds<<<1, 256, 0, stream>>>(ba, keep, kpos);
-    if (m > 0)
-        k_emit<<<blocks_for(m, 256), 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, kpos, cls, m, out->re, out->im,
-                                                      out->re_lo, out->im_lo, labels ? out->period : nullptr,
-                                                      out->preperiod, out->flags);
-    CHK(hipGetLastError());
-    CHK(read_counters());
+    k_emit<<<gs, 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, kpos, cls, out.re, out.im, out.re_lo, out.im_lo,
+                                   c.labels ? out.period : nullptr, out.preperiod, out.flags);
+    if (ev) (void)hipEventRecord(ev[5], stream);
 
-    // capacities; the certificate runs over the output index space
-    int status_all = MSPLIT_OK;
-    std::vector<int64_t> uniq_offs(T + 1, 0);
-    for (int t = 0; t < T; ++t) {
-        const uint64_t u = H(t, C_KEPT);
-        const int c = bp.slot[t];
-        counts[c] = u;
-        if (u > bp.td[t].cap) status_all = MSPLIT_E_CAPACITY;
-        uniq_offs[t + 1] = uniq_offs[t] + (int64_t)std::min<uint64_t>(u, bp.td[t].cap);
-    }
-    if (status_all == MSPLIT_E_CAPACITY) return MSPLIT_E_CAPACITY;
-    const int64_t n_uniq = uniq_offs[T];
-    CHK(hipMemcpyAsync(doffs + 3 * (T + 1), uniq_offs.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice,
-                       stream));
-    CHK(hipEventRecord(ev.e[5], stream));
-    // certificate and separation
-    const bool cert = (opts->flags & MSPLIT_F_CERTIFY) != 0;
-    if (cert && (!out->radius || !out->flags)) return MSPLIT_E_ARG;
-    if (n_uniq) {
-        if (cert) {
-            const int32_t *lab = (opts->flags & MSPLIT_F_NO_LABEL) ? nullptr : out->period;
-            uint32_t *hard = (uint32_t *)keys; // free once sorted
-            if (out->re_lo && out->im_lo) {
-                k_certify<true><<<persistent_blocks(n_uniq, 128), 128, 0, stream>>>(
-                    ba, out->re, out->im, out->re_lo, out->im_lo, lab, out->flags, out->radius, n_uniq, hard);
-                k_certify_dd<<<device_cus() * 2, 128, 0, stream>>>(ba, out->re, out->im, out->re_lo, out->im_lo, lab,
-                                                                   out->flags, out->radius, hard);
+    // certificate and separation over the output index space (uniq_offs,
+    // min(kept, capacity) roots per type, on the device)
+    if (c.out_max > 0) {
+        if (c.cert) {
+            const int32_t *lab = c.labels ? out.period : nullptr;
+            uint32_t *hard_c = (uint32_t *)fkeys;
+            if (out.re_lo && out.im_lo) {
+                k_certify<true><<<persistent_blocks(c.out_max, 128), 128, 0, stream>>>(
+                    ba, out.re, out.im, out.re_lo, out.im_lo, lab, out.flags, out.radius, hard_c);
+                k_certify_dd<<<device_cus() * 2, 128, 0, stream>>>(ba, out.re, out.im, out.re_lo, out.im_lo, lab,
+                                                                   out.flags, out.radius, hard_c);
             } else {
-                k_certify<false><<<persistent_blocks(n_uniq, 128), 128, 0, stream>>>(
-                    ba, out->re, out->im, nullptr, nullptr, lab, out->flags, out->radius, n_uniq, nullptr);
+                k_certify<false><<<persistent_blocks(c.out_max, 128), 128, 0, stream>>>(
+                    ba, out.re, out.im, nullptr, nullptr, lab, out.flags, out.radius, nullptr);
             }
             // k_separation reads the largest radius of each type
-            k_fold_counters<<<blocks_for((int64_t)T * C_NCOUNTERS, 256), 256, 0, stream>>>(ctr, spread, T);
-            k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, out->re_lo,
-                                                                             out->im_lo, out->radius, n_uniq);
+            k_fold_counters<<<fold_blocks(T), 256, 0, stream>>>(ba.ctr, ba.spread, T);
+            k_separation<<<persistent_blocks(c.out_max, 256), 256, 0, stream>>>(ba, out.re, out.im, out.re_lo,
+                                                                                out.im_lo, out.radius);
         } else {
-            k_separation<<<persistent_blocks(n_uniq, 256), 256, 0, stream>>>(ba, out->re, out->im, out->re_lo,
-                                                                             out->im_lo, nullptr, n_uniq);
+            k_separation<<<persistent_blocks(c.out_max, 256), 256, 0, stream>>>(ba, out.re, out.im, out.re_lo,
+                                                                                out.im_lo, nullptr);
         }
     }
-    CHK(hipEventRecord(ev.e[6], stream));
-    CHK(hipGetLastError());
-    CHK(read_counters());
-    float ms = 0.f, mss[6] = {0, 0, 0, 0, 0, 0};
-    (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[6]);
-    for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&mss[i], ev.e[i], ev.e[i + 1]);
+    k_fold_counters<<<fold_blocks(T), 256, 0, stream>>>(ba.ctr, ba.spread, T);
+    if (ev) (void)hipEventRecord(ev[6], stream);
+}
 
+// Counters to the host (one synchronisation), per-type counts and stats.
+int finish(batch_call &c, hipStream_t stream, uint64_t *counts, msplit_stats *stats, call_ctx &ctx, float ms,
+           const float *mss)
+{
+    CHK(hipMemcpyAsync(c.h.data(), c.ba.ctr, sizeof(unsigned long long) * c.h.size(), hipMemcpyDeviceToHost,
+                       stream));
+    CHK(hipStreamSynchronize(stream));
+    const batch_plan &bp = c.bp;
+    const int T = bp.T;
+    auto H = [&](int t, int slot) { return c.h[(size_t)t * C_NCOUNTERS + slot]; };
+    int status_all = MSPLIT_OK;
     for (int t = 0; t < T; ++t) {
-        const int c = bp.slot[t];
+        const uint64_t u = H(t, C_KEPT);
+        counts[bp.slot[t]] = u;
+        if (u > bp.td[t].cap) status_all = MSPLIT_E_CAPACITY;
+    }
+    if (stats) memset(stats, 0, sizeof(msplit_stats) * T);
+    for (int t = 0; t < T; ++t) {
+        const int ci = bp.slot[t];
         const plan_t &p = bp.td[t].p;
         const uint64_t uniq = H(t, C_KEPT), nreal = H(t, C_REAL);
         const uint64_t total = nreal + 2 * (uniq - nreal);
@@ -650,7 +627,7 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         const uint64_t expected = p.l == 0 ? (uint64_t)p.D : (uint64_t)mis_count(p.l, p.n);
         if (total != expected && status_all == MSPLIT_OK) status_all = MSPLIT_E_INCOMPLETE;
         if (!stats) continue;
-        msplit_stats &s = stats[c];
+        msplit_stats &s = stats[ci];
         s.starts = (uint64_t)p.NS;
         s.converged = H(t, C_CONVERGED);
         s.diverged = H(t, C_DIVERGED);
@@ -676,9 +653,113 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         memcpy(&s.min_sep, &ms_bits, 8);
         memcpy(&s.max_radius, &mr_bits, 8);
         s.ms_device = ms;
-        for (int i = 0; i < 6; ++i) s.ms_stage[i] = mss[i];
+        for (int i = 0; i < 6; ++i) s.ms_stage[i] = mss ? mss[i] : 0.f;
     }
     return status_all;
+}
+
+// The split of a list of types (in caller order ln[2i], ln[2i+1]); roots of
+// type i go to out at out_offs[i] with capacity caps[i].  counts[i] and
+// stats[i] are written for every type.  starts_only: stop after the level
+// line and copy the starts of the single type to sre / sim.
+int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *workspace, uint64_t ws_bytes,
+              msplit_roots *out, const uint64_t *out_offs, const uint64_t *caps, uint64_t *counts,
+              msplit_stats *stats, void *stream_v, bool starts_only = false, double *sre = nullptr,
+              double *sim = nullptr, uint64_t scap = 0)
+{
+    for (int i = 0; i < npairs && counts; ++i) counts[i] = 0;
+    if (!counts) return MSPLIT_E_ARG;
+    if (starts_only && (!sre || !sim || npairs != 1)) return MSPLIT_E_ARG;
+    if (stats && npairs > 0) memset(stats, 0, sizeof(msplit_stats) * npairs);
+    batch_call c;
+    int r = prepare(c, ln, npairs, opts, workspace, ws_bytes, out, out_offs, caps, starts_only);
+    if (r) return r;
+    if (starts_only && scap < (uint64_t)c.bp.td[0].p.NS) return MSPLIT_E_CAPACITY;
+    hipStream_t stream = (hipStream_t)stream_v;
+    call_ctx ctx{stats, npairs};
+    CHK(upload_tables(c, stream));
+    events ev;
+    for (int i = 0; i < 7; ++i) {
+        CHK(hipEventCreate(&ev.e[i]));
+        ev.made = i + 1;
+    }
+    enqueue_level_line(c, stream, ev.e);
+    CHK(hipGetLastError());
+    if (starts_only) {
+        const plan_t &p = c.bp.td[0].p;
+        k_unzip<<<blocks_for(p.NS, 256), 256, 0, stream>>>(ws_at<cd>(c, c.L.starts), sre, sim, p.NS);
+        k_fold_counters<<<fold_blocks(c.bp.T), 256, 0, stream>>>(c.ba.ctr, c.ba.spread, c.bp.T);
+        CHK(hipGetLastError());
+        CHK(hipMemcpyAsync(c.h.data(), c.ba.ctr, sizeof(unsigned long long) * c.h.size(), hipMemcpyDeviceToHost,
+                           stream));
+        CHK(hipStreamSynchronize(stream));
+        counts[0] = (uint64_t)p.NS;
+        float a = 0.f, b = 0.f;
+        (void)hipEventElapsedTime(&a, ev.e[0], ev.e[1]);
+        (void)hipEventElapsedTime(&b, ev.e[1], ev.e[2]);
+        const uint64_t phase_fail = c.h[C_PHASE_FAIL] + c.h[C_SEED_FAIL];
+        if (stats) {
+            stats->starts = (uint64_t)p.NS;
+            stats->phase_fail = phase_fail;
+            stats->steps_lift = c.h[C_STEPS_LIFT];
+            stats->steps_walk = c.h[C_STEPS_WALK];
+            stats->ms_stage[0] = a;
+            stats->ms_stage[1] = b;
+            stats->ms_device = a + b;
+        }
+        return phase_fail ? MSPLIT_E_INCOMPLETE : MSPLIT_OK;
+    }
+    enqueue_roots(c, stream, ev.e);
+    CHK(hipGetLastError());
+    CHK(hipEventSynchronize(ev.e[6]));
+    float ms = 0.f, mss[6] = {0, 0, 0, 0, 0, 0};
+    (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[6]);
+    for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&mss[i], ev.e[i], ev.e[i + 1]);
+    return finish(c, stream, counts, stats, ctx, ms, mss);
+}
+
+// A batch captured as one hipGraph: every kernel of a call from the counter
+// initialisation to the certificate (the sizes they need are on the
+// device, so the capture holds no host round trip).  The type tables are
+// uploaded before each launch, outside the graph.
+struct graph_state {
+    batch_call c;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~graph_state()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+// Capture the call on the stream (kernels only: the runtime does not time
+// events recorded inside a graph, so a launch reports its total time).
+hipError_t capture(graph_state &g, hipStream_t stream)
+{
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    enqueue_level_line(g.c, stream, nullptr);
+    enqueue_roots(g.c, stream, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t e_launch = hipGetLastError();
+    e = hipStreamEndCapture(stream, &graph);
+    if (e == hipSuccess && e_launch != hipSuccess) e = e_launch;
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return e;
+    }
+    g.graph = graph;
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        g.graph = nullptr;
+        g.exec = nullptr;
+    }
+    return e;
 }
 
 } // namespace
@@ -715,9 +796,7 @@ int msplit_batch_workspace_size(const int32_t *ln_pairs, int npairs, const mspli
     batch_plan bp;
     int r = make_batch(ln_pairs, npairs, opts, nullptr, nullptr, bp);
     if (r) return r;
-    size_t tb = 0;
-    if (rocprim_temp(bp.n_starts, bp.T, tb) != hipSuccess) return MSPLIT_E_DEVICE;
-    *bytes = make_layout(bp, tb).total;
+    *bytes = make_layout(bp).total;
     return MSPLIT_OK;
 }
 
@@ -810,16 +889,16 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
     ba.ctr = ctr;
     ba.spread = spread;
     k_init_counters<<<blocks_for((int64_t)C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
-        gctr, ctr, spread, 1);
+        gctr, ctr, spread, 1, nullptr, 0);
     if (count) {
         k_certify<false><<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(
             ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->period, roots->flags, roots->radius,
-            (int64_t)count, nullptr);
-        k_fold_counters<<<1, 64, 0, stream>>>(ctr, spread, 1);
+            nullptr);
+        k_fold_counters<<<fold_blocks(1), 256, 0, stream>>>(ctr, spread, 1);
         k_separation<<<persistent_blocks((int64_t)count, 256), 256, 0, stream>>>(
-            ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->radius, (int64_t)count);
+            ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->radius);
     }
-    k_fold_counters<<<1, 64, 0, stream>>>(ctr, spread, 1);
+    k_fold_counters<<<fold_blocks(1), 256, 0, stream>>>(ctr, spread, 1);
     CHK(hipGetLastError());
     unsigned long long h[C_NCOUNTERS];
     CHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, stream));
@@ -833,5 +912,58 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
     }
     return MSPLIT_OK;
 }
+
+struct msplit_graph {
+    graph_state g;
+};
+
+int msplit_batch_graph(const int32_t *ln_pairs, int npairs, const msplit_options *opts, void *workspace,
+                       uint64_t workspace_bytes, msplit_roots *out, const uint64_t *caps, void *stream_v,
+                       msplit_graph **graph)
+{
+    if (graph) *graph = nullptr;
+    if (!ln_pairs || npairs <= 0 || !out || !caps || !graph || !stream_v) return MSPLIT_E_ARG;
+    std::vector<uint64_t> offs(npairs, 0);
+    for (int i = 1; i < npairs; ++i) offs[i] = offs[i - 1] + caps[i - 1];
+    msplit_graph *G = new (std::nothrow) msplit_graph;
+    if (!G) return MSPLIT_E_ARG;
+    graph_state &g = G->g;
+    int r = prepare(g.c, ln_pairs, npairs, opts, workspace, workspace_bytes, out, offs.data(), caps, false);
+    if (r) {
+        delete G;
+        return r;
+    }
+    hipStream_t stream = (hipStream_t)stream_v;
+    hipError_t e = hipEventCreate(&g.e0);
+    if (e == hipSuccess) e = hipEventCreate(&g.e1);
+    if (e == hipSuccess) e = capture(g, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete G;
+        return MSPLIT_E_DEVICE;
+    }
+    *graph = G;
+    return MSPLIT_OK;
+}
+
+int msplit_graph_launch(msplit_graph *G, uint64_t *counts, msplit_stats *stats, void *stream_v)
+{
+    if (!G || !counts || !stream_v) return MSPLIT_E_ARG;
+    graph_state &g = G->g;
+    const int T = g.c.bp.T;
+    for (int i = 0; i < T; ++i) counts[i] = 0;
+    hipStream_t stream = (hipStream_t)stream_v;
+    call_ctx ctx{stats, T};
+    CHK(upload_tables(g.c, stream));
+    CHK(hipEventRecord(g.e0, stream));
+    CHK(hipGraphLaunch(g.exec, stream));
+    CHK(hipEventRecord(g.e1, stream));
+    CHK(hipEventSynchronize(g.e1));
+    float ms = 0.f;
+    CHK(hipEventElapsedTime(&ms, g.e0, g.e1));
+    return finish(g.c, stream, counts, stats, ctx, ms, nullptr);
+}
+
+void msplit_graph_destroy(msplit_graph *G) { delete G; }
 
 } // extern "C"

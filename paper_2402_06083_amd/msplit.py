@@ -100,13 +100,20 @@ def lib():
     L.msplit_starts.restype = i32
     L.msplit_batch_workspace_size.argtypes = [ctypes.POINTER(ctypes.c_int32), i32, pOpt, pu64]
     L.msplit_batch_workspace_size.restype = i32
+    L.msplit_batch_graph.argtypes = [ctypes.POINTER(ctypes.c_int32), i32, pOpt, vp, u64, pRoots, pu64, vp,
+                                     ctypes.POINTER(vp)]
+    L.msplit_batch_graph.restype = i32
+    L.msplit_graph_launch.argtypes = [vp, pu64, pStats, vp]
+    L.msplit_graph_launch.restype = i32
+    L.msplit_graph_destroy.argtypes = [vp]
+    L.msplit_graph_destroy.restype = None
     _lib = L
     return L
 
 
 EXPORTED = ["msplit_strerror", "msplit_expected_count", "msplit_workspace_size", "msplit_hyperbolic",
             "msplit_misiurewicz", "msplit_certify", "msplit_batch", "msplit_batch_workspace_size",
-            "msplit_starts"]
+            "msplit_starts", "msplit_batch_graph", "msplit_graph_launch", "msplit_graph_destroy"]
 
 
 def strerror(status: int) -> str:
