@@ -73,13 +73,14 @@ def kernel_flops(pairs, stats_list):
     return desc, t_desc, walk, t_walk
 
 
-def run_gpu(pairs, precision, steps, warmup, launch="eager"):
+def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None):
     """eager: every call enqueued by msplit_batch (stage times from HIP
     events on the call's stream); graph: the call captured once as a
-    hipGraph and replayed (msplit_graph_launch: total device time only)."""
+    hipGraph and replayed (msplit_graph_launch: total device time only).
+    tuned: launch parameters from the autotuner (dict of option fields)."""
     import torch
     from paper_2402_06083_amd import batch, msplit
-    opts = msplit.make_options(precision=precision, certify=True)
+    opts = msplit.make_options(precision=precision, certify=True, **(tuned or {}))
     runner = batch.BatchRunner(pairs, opts)
     mode = launch
     if mode == "graph":
@@ -129,6 +130,30 @@ def _time_runner(runner, pairs, steps, warmup, mode):
     return agg
 
 
+def autotune(pairs, prec, other, retune=False):
+    """Launch parameters per precision: the cached tuning (the user's cache,
+    else the one shipped for this GPU) or, when none is cached or retune is
+    set, a tuning run now (before the timed steps)."""
+    from paper_2402_06083_amd import tune
+    tuned, info = {prec: None}, {}
+    for p in [prec] + ([other] if other else []):
+        hit = None if retune else tune.lookup(pairs, p)
+        if hit is None:
+            space = None
+            if p != prec and tuned[prec] is not None:
+                # the second precision keeps the tuned layout; MIXED sweeps its switch
+                space = {k: [v] for k, v in tuned[prec].items()}
+                if p == "mixed":
+                    space["fp32_switch"] = tune.MIXED_SWITCHES
+            t = tune.tune(pairs, p, space=space or None)
+            hit = {"options": t["best"], "ms": t["ms"], "default_ms": t["default_ms"], "source": "tuned now"}
+        else:
+            hit = dict(hit, source="cache")
+        tuned[p] = hit["options"]
+        info[p] = hit
+    return tuned, info
+
+
 def cpu_baseline():
     """The oracle as it stands on this host's cores, on a bounded sample of
     the same workload: p_1..p_20 split and every root certified."""
@@ -157,6 +182,9 @@ def main():
     ap.add_argument("--no-p30", action="store_true", help="skip the period-30 measurement")
     ap.add_argument("--p30-steps", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay measurement")
+    ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the tuned ones")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner before the timed steps even when a tuning is cached")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (scale of the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -172,7 +200,11 @@ def main():
     desc, pairs = WORKLOADS[args.workload]
     main_prec = args.precision
     other = "mixed" if main_prec == "fp64" else "fp64"
-    res = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager")
+    tuned = {main_prec: None, other: None}
+    tune_info = {}
+    if not args.no_tune:
+        tuned, tune_info = autotune(pairs, main_prec, None if args.no_compare else other, args.retune)
+    res = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager", tuned[main_prec])
     value = res["roots"] / res["wall"]
     ms_per_step = 1e3 * res["wall"] / args.steps
     # dominant kernel: the stage with the larger device time
@@ -196,25 +228,31 @@ def main():
         "data": "synthetic: the integers n themselves (no dataset exists for this problem)",
         "config": {"workload": desc, "pairs": len(pairs), "roots_per_step": res["roots"] // args.steps,
                    "precision": main_prec, "certified": True, "parallelism": "single GPU",
-                   "launch": "eager: msplit_batch per step, one host synchronisation per call"},
+                   "launch": "eager: msplit_batch per step, one host synchronisation per call",
+                   "tuning": tune_info},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "kernel_ms_per_step": tms / args.steps},
         "stage_ms_per_step": {k: v / args.steps for k, v in res["stages"].items()},
     }
     if not args.no_graph:
-        rg = run_gpu(pairs, main_prec, args.steps, args.warmup, "graph")
+        rg = run_gpu(pairs, main_prec, args.steps, args.warmup, "graph", tuned[main_prec])
         out["graph"] = {"value": rg["roots"] / rg["wall"], "ms_per_step": 1e3 * rg["wall"] / args.steps,
                         "device_ms_per_step": rg["ms_device"] / args.steps,
                         "launch": "whole call captured once as a hipGraph, replayed each step"}
     if not args.no_compare:
-        r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager")
+        r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager", tuned[other])
         out[other] = {"value": r2["roots"] / r2["wall"], "ms_per_step": 1e3 * r2["wall"] / args.steps,
                       "stage_ms_per_step": {k: v / args.steps for k, v in r2["stages"].items()}}
     if not args.no_p30 and args.workload != "p30":
         p30 = {}
+        p30_pairs = WORKLOADS["p30"][1]
+        t30 = {main_prec: None, other: None}
+        if not args.no_tune:
+            t30, i30 = autotune(p30_pairs, main_prec, None if args.no_compare else other, args.retune)
+            tune_info["p30"] = i30
         for prec in ([main_prec] if args.no_compare else [main_prec, other]):
-            r3 = run_gpu(WORKLOADS["p30"][1], prec, args.p30_steps, 1, "eager")
+            r3 = run_gpu(p30_pairs, prec, args.p30_steps, 1, "eager", t30[prec])
             p30[prec] = {"value": r3["roots"] / r3["wall"], "ms_per_step": 1e3 * r3["wall"] / args.p30_steps,
                          "roots_per_step": r3["roots"] // args.p30_steps,
                          "stage_ms_per_step": {k: v / args.p30_steps for k, v in r3["stages"].items()}}

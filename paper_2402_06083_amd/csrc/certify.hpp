@@ -425,7 +425,9 @@ __global__ void k_separation(batch_args b, const double *re, const double *im, c
         bool pair_bad = false;
         for (int64_t j = i + 1, c = 0; j < end; ++j, ++c) {
             const double dx = (re[j] - xi) + (lo ? re_lo[j] - xl : 0.0);
-            const bool need_pair = radius && dx <= 4.0 * (Ri + rmax);
+            // the list is ordered by real part only to the key resolution
+            // 2^-KEY_RES: a closer root may follow a farther one by that much
+            const bool need_pair = radius && dx <= 4.0 * (Ri + rmax) + 0x1p-45;
             if (!need_pair && (dx > best || c >= 8)) break;
             const double dy = (im[j] - yi) + (lo ? im_lo[j] - yl : 0.0);
             const double d = sqrt(dx * dx + dy * dy);

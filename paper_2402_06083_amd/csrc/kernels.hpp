@@ -378,7 +378,10 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
 // is precision-uniform, so no wave runs both code paths.
 // Rounding in the orbit is amplified by up to about 2^N, so an FP32
 // evaluation of an order-N polynomial has a relative error near 2^(N-24):
-// FP32 steps are taken only up to order FP32_MAX_ORDER (error below 2^-4).
+// FP32 steps are taken only up to order FP32_MAX_ORDER (error below 2^-4),
+// and only for p_n: the roots of q_{l,n} next to -2 are about 8^-N apart
+// (against 4^-N for p_n), closer than steps with that error can aim, so an
+// FP32 step there can carry a start into the basin of a neighbouring root.
 constexpr int FP32_MAX_ORDER = 20;
 
 __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *status, uint8_t *iters)
@@ -429,7 +432,7 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
         if (__ballot(!done) == 0) break;
         if (done) continue;
         cf P, dP;
-        if (pl_N > FP32_MAX_ORDER) { // FP32 carries no information: FP64 from the start
+        if (pl_N > FP32_MAX_ORDER || pl_l != 0) { // FP64 from the start
             roots[g] = starts[g];
             status[g] = ST_NONE;
             iters[g] = 0;

@@ -391,6 +391,42 @@ def test_batch_graph_replays_match_eager():
     runner.close()
 
 
+def test_misiurewicz_batch_mixed_precision():
+    """MIXED precision on Misiurewicz types (their descents run in FP64 from
+    the start) and p_n types in one batch: complete and certified."""
+    from paper_2402_06083_amd import batch
+    pairs = [(0, 16), (2, 8), (3, 11), (6, 6), (5, 12)]
+    say("[gpu] mixed batch with Misiurewicz types")
+    res = batch.run_batch(pairs, certify=True, precision="mixed")
+    for (l, n), (count, st, status) in zip(res.pairs, res.per_pair):
+        assert status == 0 and st["missing"] == 0 and st["certified"] == count, (l, n, st)
+        assert st["total"] == counts.mis_count(l, n) if l else st["total"] == 2 ** (n - 1)
+
+
+def test_autotuner_picks_a_complete_configuration(tmp_path):
+    """The autotuner times candidate launch parameters on a batch, rejects
+    incomplete splits and caches the fastest; the cached options split the
+    batch completely (every root certified)."""
+    from paper_2402_06083_amd import batch, msplit, tune
+    pairs = [(0, n) for n in range(1, 15)] + [(3, 9)]
+    path = str(tmp_path / "tune.json")
+    say("[gpu] autotune")
+    res = tune.tune(pairs, "fp64", space={"block_size": [128, 256], "seg_points": [0, 64],
+                                           "points_per_turn": [8, 16]}, path=path)
+    assert len(res["trials"]) == 9 and all("ms" in t for t in res["trials"]), res["trials"]
+    hit = tune.lookup(pairs, "fp64", path=path)
+    assert hit is not None and hit["options"] == res["best"]
+    opts, cand = tune.tuned_options(pairs, "fp64", path=path)
+    assert cand == res["best"]
+    runner = batch.BatchRunner(pairs, opts)
+    r = runner.run()
+    torch.cuda.synchronize()
+    assert r == 0, msplit.strerror(r)
+    for (l, n), s in zip(pairs, runner.stats):
+        d = s.as_dict()
+        assert d["missing"] == 0 and d["certified"] == d["unique"], (l, n, d)
+
+
 def test_deterministic_output():
     r1, g1 = gpu_split(0, 17)
     r2, g2 = gpu_split(0, 17)
