@@ -27,13 +27,31 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 FLOP/clk)
 
-# algorithmic flops of one evaluation + update of order N:
-# the orbit step (dz <- 2 z dz + 1, z <- z^2 + c) is 16 real flops;
-# the Newton update z -= P/P' is 14; the log-Newton level-line update
-# (T/P, log1p series, scaling by P/P') is 62.
+# algorithmic flops of one evaluation + update of order N: the orbit from
+# its first iterate (p_1 = c, p_1' = 1 need no arithmetic) is N - 1 steps of
+# 16 real flops (dz <- 2 z dz + 1, z <- z^2 + c); the Newton update
+# z -= P/P' is 14; the log-Newton level-line update (T/P, log1p series,
+# scaling by P/P') is 62.
 FLOPS_ORBIT_STEP = 16
 FLOPS_NEWTON_UPDATE = 14
 FLOPS_WALK_UPDATE = 62
+
+# HBM traffic of k_descend<false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
+# per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
+# kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
+DESCEND_TRAFFIC_BYTES = 1226334995.7
+DESCEND_TRAFFIC_SHA256 = "d80164503b9450a1faad93332b745ecc84474a4dfb602d98acf08fbb0f21e168"
+
+
+def descend_traffic():
+    """The measured bytes per launch when the kernel is the one measured, else None."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2402_06083_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return DESCEND_TRAFFIC_BYTES if h.hexdigest() == DESCEND_TRAFFIC_SHA256 else None
+
 
 WORKLOADS = {
     "batch24": ("p_1..p_24 batched, all roots certified", [(0, n) for n in range(1, 25)]),
@@ -65,9 +83,9 @@ def kernel_flops(pairs, stats_list):
     desc = walk = 0.0
     for (l, n), st in zip(pairs, stats_list):
         N = l + n
-        desc += st["steps_desc"] * (FLOPS_ORBIT_STEP * N + FLOPS_NEWTON_UPDATE)
-        desc += st["steps_fp32"] * (FLOPS_ORBIT_STEP * N + FLOPS_NEWTON_UPDATE)
-        walk += st["steps_walk"] * (FLOPS_ORBIT_STEP * N + FLOPS_WALK_UPDATE)
+        desc += st["steps_desc"] * (FLOPS_ORBIT_STEP * (N - 1) + FLOPS_NEWTON_UPDATE)
+        desc += st["steps_fp32"] * (FLOPS_ORBIT_STEP * (N - 1) + FLOPS_NEWTON_UPDATE)
+        walk += st["steps_walk"] * (FLOPS_ORBIT_STEP * (N - 1) + FLOPS_WALK_UPDATE)
     t_desc = stats_list[0]["ms_stage"]["descend"]
     t_walk = stats_list[0]["ms_stage"]["walk"]
     return desc, t_desc, walk, t_walk
@@ -231,7 +249,10 @@ def main():
                    "launch": "eager: msplit_batch per step, one host synchronisation per call",
                    "tuning": tune_info},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": descend_traffic() if (kname == "k_descend" and args.workload == "batch24"
+                                                      and main_prec == "fp64") else None,
+                     "traffic_unit": "bytes per launch",
                      "kernel_ms_per_step": tms / args.steps},
         "stage_ms_per_step": {k: v / args.steps for k, v in res["stages"].items()},
     }

@@ -125,13 +125,22 @@ __device__ __forceinline__ void orbit2_step(orbit2_state<T> &s, T c4r, T c2i)
     s.di = di;
 }
 
-// P = q_{l,n}(c), dP = q_{l,n}'(c), N = l + n (l = 0: p_N)
+// P = q_{l,n}(c), dP = q_{l,n}'(c), N = l + n >= 1 (l = 0: p_N).  The orbit
+// starts from its first iterate, p_1 = c and p_1' = 1 (exact), so an
+// evaluation of order N takes N - 1 steps; p_N needs no subtraction.
 template <typename T, typename C>
 __device__ __forceinline__ void eval_q_t(int l, int N, C c, C &P, C &dP)
 {
-    orbit2_state<T> s = {T(0), T(0), T(0), T(0)};
     const T c4r = T(4) * c.re, c2i = T(2) * c.im;
-    int k = 0;
+    orbit2_state<T> s = {T(2) * c.re, c2i, T(1), T(0)};
+    if (l == 0) {
+#pragma unroll 2
+        for (int k = 1; k < N; ++k) orbit2_step(s, c4r, c2i);
+        P = {T(0.5) * s.ur, T(0.5) * s.ui};
+        dP = {s.dr, s.di};
+        return;
+    }
+    int k = 1;
     for (; k < l; ++k) orbit2_step(s, c4r, c2i);
     const orbit2_state<T> sl = s;
 #pragma unroll 2

@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
     unsigned long long *counter = &b.gctr[iters ? G_START_NEXT2 : G_START_NEXT];
     while (true) {
         const bool need = !exhausted && g == NONE;
-        const uint64_t got = wave_take(wq, counter, b.chunk_start, need);
+        const uint64_t got = __ballot(need) ? wave_take(wq, counter, b.chunk_start, need) : ~0ull;
         if (need) {
             if (got >= n_starts) {
                 exhausted = true;

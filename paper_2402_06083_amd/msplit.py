@@ -11,7 +11,7 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmsplit.so")
+LIB_PATH = os.environ.get("MSPLIT_LIB") or os.path.join(_HERE, "libmsplit.so")
 
 # status codes
 OK, E_ARG, E_CAPACITY, E_WORKSPACE, E_DEVICE, E_INCOMPLETE, E_PRECISION, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
