@@ -28,8 +28,12 @@
 
 namespace msplit {
 
-// Contraction is switched off in every routine below (DD_EXACT): the
-// rounding bounds count one rounding per written operation.
+// Contraction is switched off (DD_EXACT) wherever a rounding bound counts
+// one rounding per written operation: the centres of the disks (explicit
+// round-to-nearest operations) and the bounds below.  The radius recurrences
+// of disk_orbit_step may fuse: they are sums of non-negative products, each
+// inflated by up(), and a fused multiply-add rounds once where the separate
+// operations round twice, so the inflation still covers the rounding.
 //
 // Rounding bound used below: a double r^ = fl(r) rounded to nearest obeys
 // |r^ - r| <= ulp(r^)/2 <= u |r^| + eta with u = 2^-53 (normal results) and
@@ -43,10 +47,12 @@ constexpr double ETA = 0x1p-1074;
 // few dozen non-negative round-to-nearest operations
 __device__ __forceinline__ double up(double x) { DD_EXACT return __dadd_rn(__dmul_rn(x, 1.0 + 0x1p-47), 0x1p-1000); }
 __device__ __forceinline__ double dn(double x) { DD_EXACT return __dsub_rn(__dmul_rn(x, 1.0 - 0x1p-47), 0x1p-1000); }
-// upper bound of |a|
+// upper bound of |a|: sqrt(M^2 + m^2) <= M + m^2 / (2M) <= M + m / 2 for
+// M = max(|re|, |im|) >= m = min(|re|, |im|) (at most 6% above |a|)
 __device__ __forceinline__ double abs_up(cd a)
 { DD_EXACT
-    return up(sqrt(up(__dadd_rn(__dmul_rn(a.re, a.re), __dmul_rn(a.im, a.im)))));
+    const double x = fabs(a.re), y = fabs(a.im);
+    return up(__dadd_rn(fmax(x, y), __dmul_rn(0.5, fmin(x, y))));
 }
 // lower bound of |a|^2
 __device__ __forceinline__ double abs2_dn(cd a)
@@ -63,9 +69,10 @@ struct disk_step {
 };
 
 // One step of the orbit over disks: z <- z^2 + c, dz <- 2 z dz + 1, the centres
-// computed with separate IEEE products and sums (no fused multiply-add).
+// computed with separate IEEE products and sums (no fused multiply-add); the
+// radii (non-negative, inflated by up()) may use fused operations.
 __device__ __forceinline__ void disk_orbit_step(disk_step &s, cd c, double R)
-{ DD_EXACT
+{
     const double x = s.Z.re, y = s.Z.im, u = s.DZ.re, v = s.DZ.im;
     const double xx = __dmul_rn(x, x), yy = __dmul_rn(y, y), xy = __dmul_rn(x, y);
     const cd sq = {__dsub_rn(xx, yy), __dadd_rn(xy, xy)}; // doubling is exact
