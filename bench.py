@@ -91,14 +91,14 @@ def kernel_flops(pairs, stats_list):
     return desc, t_desc, walk, t_walk
 
 
-def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None):
+def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=False):
     """eager: every call enqueued by msplit_batch (stage times from HIP
     events on the call's stream); graph: the call captured once as a
     hipGraph and replayed (msplit_graph_launch: total device time only).
     tuned: launch parameters from the autotuner (dict of option fields)."""
     import torch
     from paper_2402_06083_amd import batch, msplit
-    opts = msplit.make_options(precision=precision, certify=True, **(tuned or {}))
+    opts = msplit.make_options(precision=precision, certify=True, basin=basin, **(tuned or {}))
     runner = batch.BatchRunner(pairs, opts)
     mode = launch
     if mode == "graph":
@@ -136,6 +136,7 @@ def _time_runner(runner, pairs, steps, warmup, mode):
         agg["walk"] += w
         agg["t_walk"] += tw
         agg["roots"] += cr
+        agg["basin"] = agg.get("basin", 0) + sum(st.get("basin", 0) for st in sts)
         # stage times cover the whole call (every type in one launch per stage)
         agg["ms_device"] += sts[0]["ms_device"]
         for k, v in sts[0]["ms_stage"].items():
@@ -200,6 +201,8 @@ def main():
     ap.add_argument("--no-p30", action="store_true", help="skip the period-30 measurement")
     ap.add_argument("--p30-steps", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay measurement")
+    ap.add_argument("--no-basin", action="store_true",
+                    help="skip the measurement with the Newton-basin proof (MSPLIT_F_BASIN)")
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the tuned ones")
     ap.add_argument("--retune", action="store_true",
                     help="run the autotuner before the timed steps even when a tuning is cached")
@@ -261,6 +264,12 @@ def main():
         out["graph"] = {"value": rg["roots"] / rg["wall"], "ms_per_step": 1e3 * rg["wall"] / args.steps,
                         "device_ms_per_step": rg["ms_device"] / args.steps,
                         "launch": "whole call captured once as a hipGraph, replayed each step"}
+    if not args.no_basin:
+        rb = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager", tuned[main_prec], basin=True)
+        out["basin"] = {"value": rb["roots"] / rb["wall"], "ms_per_step": 1e3 * rb["wall"] / args.steps,
+                        "roots_with_basin_per_step": rb["basin"] // args.steps,
+                        "what": "the same workload with a proven disk of Newton convergence around every "
+                                "certified root (Thm proofContract, MSPLIT_F_BASIN)"}
     if not args.no_compare:
         r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager", tuned[other])
         out[other] = {"value": r2["roots"] / r2["wall"], "ms_per_step": 1e3 * r2["wall"] / args.steps,

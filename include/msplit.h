@@ -69,7 +69,9 @@ enum msplit_precision {
 /* ------------------------------------------------------------------- flags */
 enum msplit_flags {
     MSPLIT_F_CERTIFY = 1u, /* run the disk-arithmetic certificate (Thm proofRoots) */
-    MSPLIT_F_NO_LABEL = 2u /* skip period / type classification */
+    MSPLIT_F_NO_LABEL = 2u, /* skip period / type classification */
+    MSPLIT_F_BASIN = 4u     /* with MSPLIT_F_CERTIFY and msplit_roots.basin: prove a disk of
+                               Newton convergence around every certified root (Thm proofContract) */
 };
 
 /* per-root flag bits written to msplit_roots.flags */
@@ -77,8 +79,10 @@ enum msplit_root_flags {
     MSPLIT_R_REAL = 1u,      /* im == 0: the root is real (proven when certified) */
     MSPLIT_R_CERTIFIED = 2u, /* D(root, radius) holds exactly one root of P */
     MSPLIT_R_LABEL = 4u,     /* the period / type label is proven on that disk */
-    MSPLIT_R_DD = 8u         /* double-double root: the value is re + re_lo, im + im_lo (roots
+    MSPLIT_R_DD = 8u,        /* double-double root: the value is re + re_lo, im + im_lo (roots
                                 next to -2 that FP64 cannot separate); certified in double-double */
+    MSPLIT_R_BASIN = 16u     /* D(root, basin) lies in the Newton basin of the root (Thm
+                                proofContract; root = re + re_lo, im + im_lo for a DD root) */
 };
 
 /* Device workspace, in bytes, that msplit_certify needs (counters and one
@@ -108,6 +112,8 @@ typedef struct msplit_roots {
     uint8_t *flags;        /* nullable: msplit_root_flags */
     double *radius;        /* nullable: certificate radius (0 if not certified) */
     uint64_t capacity;
+    double *basin;         /* nullable: Newton-basin radius eps_N (0 if not proven); written
+                              with MSPLIT_F_BASIN (msplit_certify: whenever non-null) */
 } msplit_roots;
 
 /* Statistics (host). */
@@ -148,6 +154,8 @@ typedef struct msplit_stats {
     double ms_stage[6];
     int32_t hip_error;      /* last hipError_t on MSPLIT_E_DEVICE */
     int32_t reserved;
+    uint64_t basin;         /* roots with MSPLIT_R_BASIN */
+    double min_basin;       /* least Newton-basin radius among them */
 } msplit_stats;
 
 /* Human-readable text of a status code (static storage). */
@@ -188,7 +196,9 @@ int msplit_misiurewicz(int l, int n, const msplit_options *opts, void *workspace
  * list must be sorted by increasing real part for the separation check.
  * workspace: device memory of at least MSPLIT_CERTIFY_WORKSPACE bytes, else
  * MSPLIT_E_WORKSPACE.  stats (nullable) receives certified, label_proven,
- * overlaps, min_sep and max_radius. */
+ * overlaps, min_sep and max_radius.  With roots->basin non-null, every
+ * certified root also gets a disk of Newton convergence (Thm proofContract:
+ * basin, MSPLIT_R_BASIN; stats basin and min_basin). */
 int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *workspace,
                    uint64_t workspace_bytes, msplit_stats *stats, void *stream);
 

@@ -57,6 +57,8 @@ def lib():
     L.oracle_split.restype = i64
     L.oracle_certify.argtypes = [ctypes.c_int, ctypes.c_int, i64, d_p, d_p, d_p, d_p, i32_p, u8_p, d_p]
     L.oracle_certify.restype = None
+    L.oracle_basin_check.argtypes = [ctypes.c_int, ctypes.c_int, i64, d_p, d_p, d_p, d_p, u8_p]
+    L.oracle_basin_check.restype = None
     L.oracle_check_set.argtypes = [i64, d_p, d_p, d_p, i64_p, d_p]
     L.oracle_check_set.restype = None
     L.oracle_disk_enclosure.argtypes = [ctypes.c_int, ctypes.c_int, ld_p, ld_p]
@@ -169,6 +171,21 @@ def certify(l: int, n: int, re_hi, im_hi, re_lo=None, im_lo=None, label=None):
                          _ptr(im_hi, ctypes.c_double), _ptr(im_lo, ctypes.c_double),
                          _ptr(label, ctypes.c_int32), _ptr(ok, ctypes.c_uint8), _ptr(rad, ctypes.c_double))
     return ok, rad
+
+
+def basin_check(l: int, n: int, re, im, eta, eps):
+    """Thm proofContract for each claim: a root lies in D(c, eta), and
+    D(c, eps) lies in its Newton basin (c = re + i im as doubles).  Returns a
+    bool array: True when the long-double disk-arithmetic check passes."""
+    re = np.ascontiguousarray(re, dtype=np.float64)
+    im = np.ascontiguousarray(im, dtype=np.float64)
+    m = len(re)
+    eta = np.ascontiguousarray(np.broadcast_to(eta, (m,)), dtype=np.float64)
+    eps = np.ascontiguousarray(np.broadcast_to(eps, (m,)), dtype=np.float64)
+    ok = np.zeros(m, dtype=np.uint8)
+    lib().oracle_basin_check(l, n, m, _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
+                             _ptr(eta, ctypes.c_double), _ptr(eps, ctypes.c_double), _ptr(ok, ctypes.c_uint8))
+    return ok.astype(bool)
 
 
 def disk_enclosure(l: int, n: int, c, R):

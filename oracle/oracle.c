@@ -947,6 +947,40 @@ void oracle_certify(int l, int n, int64_t count, const double *re_hi, const doub
     }
 }
 
+/* Thm proofContract: a root of P lies in D(c, eta); for eps > 3 eta, if
+ * P'(D(c, eps)) lies in a disk whose distance to 0 exceeds twice its diameter
+ * (|centre| > 5 radius), the Newton map sends D(c, eps) strictly into itself,
+ * so D(c, eps) lies in the Newton basin of that root.  Checked with the disk
+ * arithmetic of the certificate, radii rounded upward.  c is the double
+ * centre (re[i], im[i]), exact in long double.  ok[i] = 1 when the check of
+ * the claim (c, eta[i], eps[i]) passes. */
+static int basin_check_one(int l, int n, cld c, ld eta, ld eps)
+{
+    if (!(eps > 3 * eta)) return 0;
+    centre_orbit o;
+    radii_t rr;
+    int N = l + n;
+    centre_pass(&o, c, N);
+    cld dPc = o.DZ[N] - o.DZ[l];
+    int old = fegetround();
+    fesetround(FE_UPWARD);
+    ld abZ[MAXN + 1], abDZ[MAXN + 1];
+    radius_pass(&o, eps, &rr, abZ, abDZ);
+    ld sP = diff_radius(rr.sig[N], rr.sig[l], dPc);
+    ld t = 5 * sP;
+    int ok = abs2_down(dPc) > t * t;
+    fesetround(old);
+    return ok;
+}
+
+void oracle_basin_check(int l, int n, int64_t count, const double *re, const double *im, const double *eta,
+                        const double *eps, uint8_t *ok)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < count; i++)
+        ok[i] = (uint8_t)basin_check_one(l, n, (ld)re[i] + I * (ld)im[i], (ld)eta[i], (ld)eps[i]);
+}
+
 /* Global checks of Thm certif on a certified list (closed upper half plane,
  * sorted lexicographically by the caller): disks pairwise disjoint, disjoint
  * from their conjugates unless centred on the real axis, and, with the

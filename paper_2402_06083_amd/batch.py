@@ -43,12 +43,14 @@ class BatchRunner:
         self.preperiod = torch.empty(tot, dtype=torch.int32, device=device)
         self.flags = torch.empty(tot, dtype=torch.uint8, device=device)
         self.radius = torch.empty(tot, dtype=torch.float64, device=device)
+        self.basin = torch.empty(tot, dtype=torch.float64, device=device) if opts.flags & msplit.F_BASIN else None
         self.caps_arr = (ctypes.c_uint64 * len(self.pairs))(*self.caps)
         self.counts = (ctypes.c_uint64 * len(self.pairs))()
         self.stats = (msplit.Stats * len(self.pairs))()
         self.roots = msplit.RootsC(self.re.data_ptr(), self.im.data_ptr(), self.re_lo.data_ptr(),
                                    self.im_lo.data_ptr(), self.period.data_ptr(),
-                                   self.preperiod.data_ptr(), self.flags.data_ptr(), self.radius.data_ptr(), tot)
+                                   self.preperiod.data_ptr(), self.flags.data_ptr(), self.radius.data_ptr(), tot,
+                                   self.basin.data_ptr() if self.basin is not None else None)
 
         self._graph = None
         self._gstream = None

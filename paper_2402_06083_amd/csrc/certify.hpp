@@ -173,6 +173,102 @@ __device__ cert_result certify_root(int l, int n, int lab, uint32_t divmask_n, c
     return res;
 }
 
+// ------------------------------------------------------- Newton basin
+// Thm proofContract: the certified root z* lies in D(c, eta).  For
+// eps > 3 eta, if P'(D(c, eps)) lies in a disk D(d, e') whose distance to 0
+// exceeds twice its diameter (|d| > 5 e'), the Newton map sends D(c, eps)
+// strictly into itself and D(c, eps) lies in the basin of z*.  eps is guessed
+// from a plain orbit with the second derivative as the power of two below
+// |P'| / (8 |P''|) (P' varies by about |P''| eps over the disk), capped at
+// 1/4, and proven by the disk orbit of disk_orbit_step over D(c, eps);
+// divided by 4 on failure, eight attempts (next to -2 the higher derivatives
+// dominate and the guess can be 2^14 too large).  Returns eps, or 0.
+__device__ __noinline__ double basin_radius(int l, int n, cd c, double eta)
+{
+    const int N = l + n;
+    // z, z', z'' (z'' <- 2 (z'^2 + z z''), z' <- 2 z z' + 1, z <- z^2 + c)
+    double zr = 0.0, zi = 0.0, dr = 0.0, di = 0.0, er = 0.0, ei = 0.0;
+    double dlr = 0.0, dli = 0.0, elr = 0.0, eli = 0.0;
+    for (int k = 1; k <= N; ++k) {
+        const double ner = 2.0 * (dr * dr - di * di + zr * er - zi * ei);
+        const double nei = 2.0 * (2.0 * dr * di + zr * ei + zi * er);
+        const double ndr = 2.0 * (zr * dr - zi * di) + 1.0;
+        const double ndi = 2.0 * (zr * di + zi * dr);
+        const double nzr = zr * zr - zi * zi + c.re;
+        const double nzi = 2.0 * zr * zi + c.im;
+        zr = nzr; zi = nzi; dr = ndr; di = ndi; er = ner; ei = nei;
+        if (k == l) { dlr = dr; dli = di; elr = er; eli = ei; }
+    }
+    const cd d1 = {dr - dlr, di - dli}, d2 = {er - elr, ei - eli};
+    double eps = 0.125 * sqrt(cabs2(d1) / cabs2(d2));
+    if (!(eps < 0.25)) eps = 0.25; // also for P'' = 0 and NaN
+    eps = ldexp(1.0, ilogb(eps));  // power of two at most eps
+    for (int attempt = 0; attempt < 8; ++attempt, eps *= 0.25) {
+        if (!(eps > 3.0 * eta * (1.0 + 0x1p-40))) return 0.0;
+        disk_step t = {{0.0, 0.0}, {0.0, 0.0}, 0.0, 0.0, 0.0};
+        cd DZl = {0.0, 0.0};
+        double sl = 0.0;
+        for (int k = 0; k < N; ++k) {
+            disk_orbit_step(t, c, eps);
+            if (k + 1 == l) { DZl = t.DZ; sl = t.sig; }
+        }
+        cd d;
+        double e1;
+        {
+            DD_EXACT
+            d = {__dsub_rn(t.DZ.re, DZl.re), __dsub_rn(t.DZ.im, DZl.im)};
+            e1 = up(t.sig + sl + rnd(d));
+        }
+        if (abs2_dn(d) > up(25.0 * up(e1 * e1))) return eps;
+    }
+    return 0.0;
+}
+
+// The basin radius of every certified output root (grid-stride over the
+// output index space); a double-double root is taken at its FP64 part c with
+// eta = R + |lo| (z* lies in D(c + lo, R)).
+__global__ void k_basin(batch_args b, const double *re, const double *im, const double *re_lo,
+                        const double *im_lo, uint8_t *flags, const double *radius, double *basin)
+{
+    unsigned long long *const wc = wave_ctr(b);
+    const int64_t n_uniq = b.uniq_offs[b.T];
+    type_count nb;
+    type_cache tc;
+    unsigned long long mbits = ~0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u0 = (int64_t)blockIdx.x * blockDim.x; u0 < n_uniq; u0 += stride) {
+        const int64_t u = u0 + threadIdx.x;
+        const int t = u < n_uniq ? cached_type(tc, b.uniq_offs, b.T, u) : nb.t;
+        if (__ballot(u < n_uniq && t != nb.t)) {
+            flush_count(wc, C_BASIN, nb);
+            wave_reduce_by_key<RED_MIN>(wc, C_NCOUNTERS, C_MIN_BASIN_BITS, mbits != ~0ull ? nb.t : -1, mbits);
+            mbits = ~0ull;
+        }
+        nb.t = t;
+        if (u >= n_uniq) continue;
+        const type_desc &td = b.types[t];
+        const int64_t i = td.out_off + (u - b.uniq_offs[t]);
+        double eps = 0.0;
+        if (flags[i] & 2) {
+            double eta = radius[i];
+            if (re_lo && im_lo) {
+                DD_EXACT
+                eta = up(eta + up(fabs(re_lo[i]) + fabs(im_lo[i])));
+            }
+            eps = basin_radius(td.p.l, td.p.n, {re[i], im[i]}, eta);
+        }
+        basin[i] = eps;
+        if (eps > 0.0) {
+            flags[i] |= 16; // MSPLIT_R_BASIN
+            nb.v += 1;
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(eps);
+            mbits = bits < mbits ? bits : mbits;
+        }
+    }
+    flush_count(wc, C_BASIN, nb);
+    wave_reduce_by_key<RED_MIN>(wc, C_NCOUNTERS, C_MIN_BASIN_BITS, mbits != ~0ull ? nb.t : -1, mbits);
+}
+
 // ------------------------------------------------- double-double centres
 // The same certificate for a double-double candidate c = hi + lo: the centres
 // z_k run in double-double, the derivative centres and every radius in FP64.

@@ -44,7 +44,7 @@ enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_DD_COUNT, G_HAR
 enum {
     C_CONVERGED = 0, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL, C_SEED_FAIL, C_STEPS_LIFT, C_STEPS_WALK,
     C_STEPS_DESC, C_STEPS_FP32, C_UNIQUE, C_REAL, C_CERTIFIED, C_LABEL, C_OVERLAP, C_MIN_SEP_BITS,
-    C_MAX_RAD_BITS, C_SURVIVORS, C_KEPT, C_DD_ROUTED, C_STEPS_DD, C_NCOUNTERS = 20
+    C_MAX_RAD_BITS, C_SURVIVORS, C_KEPT, C_DD_ROUTED, C_STEPS_DD, C_BASIN, C_MIN_BASIN_BITS, C_NCOUNTERS = 22
 };
 
 struct plan_t {

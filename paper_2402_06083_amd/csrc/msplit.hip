@@ -253,7 +253,7 @@ layout make_layout(const batch_plan &bp)
 // the device sizes that are known before the call
 __device__ __forceinline__ unsigned long long ctr_identity(int slot)
 {
-    return slot == C_MIN_SEP_BITS ? 0x7ff0000000000000ull : 0ull;
+    return slot == C_MIN_SEP_BITS || slot == C_MIN_BASIN_BITS ? 0x7ff0000000000000ull : 0ull;
 }
 __global__ void k_init_counters(unsigned long long *gctr, unsigned long long *ctr, unsigned long long *spread, int T,
                                 int64_t *isz, int64_t n_starts)
@@ -265,7 +265,7 @@ __global__ void k_init_counters(unsigned long long *gctr, unsigned long long *ct
     if (isz && i < SZ_N) isz[i] = i == SZ_STARTS ? n_starts : 0;
 }
 // ctr = the copies combined: sums, except the largest radius (max) and the
-// least separation (min); non-negative doubles order like their bit
+// least separation and least basin radius (min); non-negative doubles order like their bit
 // patterns.  One wave per counter, lane k reading copy k.
 static_assert(CTR_SPREAD == 64, "one lane per counter copy");
 __global__ void k_fold_counters(unsigned long long *ctr, const unsigned long long *spread, int T)
@@ -279,7 +279,7 @@ __global__ void k_fold_counters(unsigned long long *ctr, const unsigned long lon
     for (int d = 32; d >= 1; d >>= 1) {
         const unsigned long long o = __shfl_xor(a, d, 64);
         if (slot == C_MAX_RAD_BITS) a = o > a ? o : a;
-        else if (slot == C_MIN_SEP_BITS) a = o < a ? o : a;
+        else if (slot == C_MIN_SEP_BITS || slot == C_MIN_BASIN_BITS) a = o < a ? o : a;
         else a += o;
     }
     if (lane == 0) ctr[i] = a;
@@ -380,7 +380,7 @@ struct batch_call {
     msplit_options o;
     msplit_roots out;
     int bs = 256;
-    bool cert = false, labels = true, any_tip = false;
+    bool cert = false, labels = true, any_tip = false, basin = false;
     batch_args ba;
     char *ws = nullptr;
     int64_t out_max = 0;
@@ -422,6 +422,7 @@ int prepare(batch_call &c, const int32_t *ln, int npairs, const msplit_options *
     c.cert = !starts_only && (opts->flags & MSPLIT_F_CERTIFY) != 0;
     if (c.cert && (!out->radius || !out->flags)) return MSPLIT_E_ARG;
     c.labels = !(opts->flags & MSPLIT_F_NO_LABEL);
+    c.basin = c.cert && (opts->flags & MSPLIT_F_BASIN) && out->basin;
     c.L = make_layout(bp);
     if (ws_bytes < c.L.total) return MSPLIT_E_WORKSPACE;
     c.ws = (char *)workspace;
@@ -592,6 +593,10 @@ void enqueue_roots(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
             k_fold_counters<<<fold_blocks(T), 256, 0, stream>>>(ba.ctr, ba.spread, T);
             k_separation<<<persistent_blocks(c.out_max, 256), 256, 0, stream>>>(ba, out.re, out.im, out.re_lo,
                                                                                 out.im_lo, out.radius);
+            // Newton basins of the certified roots (Thm proofContract)
+            if (c.basin)
+                k_basin<<<persistent_blocks(c.out_max, 128), 128, 0, stream>>>(
+                    ba, out.re, out.im, out.re_lo, out.im_lo, out.flags, out.radius, out.basin);
         } else {
             k_separation<<<persistent_blocks(c.out_max, 256), 256, 0, stream>>>(ba, out.re, out.im, out.re_lo,
                                                                                 out.im_lo, nullptr);
@@ -650,8 +655,12 @@ int finish(batch_call &c, hipStream_t stream, uint64_t *counts, msplit_stats *st
         s.dd_routed = H(t, C_DD_ROUTED);
         s.steps_dd = H(t, C_STEPS_DD);
         unsigned long long ms_bits = H(t, C_MIN_SEP_BITS), mr_bits = H(t, C_MAX_RAD_BITS);
+        unsigned long long mb_bits = H(t, C_MIN_BASIN_BITS);
         memcpy(&s.min_sep, &ms_bits, 8);
         memcpy(&s.max_radius, &mr_bits, 8);
+        s.basin = H(t, C_BASIN);
+        memcpy(&s.min_basin, &mb_bits, 8);
+        if (!s.basin) s.min_basin = 0.0;
         s.ms_device = ms;
         for (int i = 0; i < 6; ++i) s.ms_stage[i] = mss ? mss[i] : 0.f;
     }
@@ -897,6 +906,9 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
         k_fold_counters<<<fold_blocks(1), 256, 0, stream>>>(ctr, spread, 1);
         k_separation<<<persistent_blocks((int64_t)count, 256), 256, 0, stream>>>(
             ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->radius);
+        if (roots->basin)
+            k_basin<<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(
+                ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->flags, roots->radius, roots->basin);
     }
     k_fold_counters<<<fold_blocks(1), 256, 0, stream>>>(ctr, spread, 1);
     CHK(hipGetLastError());
@@ -909,6 +921,9 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
         stats->overlaps = h[C_OVERLAP];
         memcpy(&stats->min_sep, &h[C_MIN_SEP_BITS], 8);
         memcpy(&stats->max_radius, &h[C_MAX_RAD_BITS], 8);
+        stats->basin = h[C_BASIN];
+        memcpy(&stats->min_basin, &h[C_MIN_BASIN_BITS], 8);
+        if (!stats->basin) stats->min_basin = 0.0;
     }
     return MSPLIT_OK;
 }

@@ -16,8 +16,8 @@ LIB_PATH = os.environ.get("MSPLIT_LIB") or os.path.join(_HERE, "libmsplit.so")
 # status codes
 OK, E_ARG, E_CAPACITY, E_WORKSPACE, E_DEVICE, E_INCOMPLETE, E_PRECISION, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED, DD = 0, 1, 2
-F_CERTIFY, F_NO_LABEL = 1, 2
-R_REAL, R_CERTIFIED, R_LABEL, R_DD = 1, 2, 4, 8
+F_CERTIFY, F_NO_LABEL, F_BASIN = 1, 2, 4
+R_REAL, R_CERTIFIED, R_LABEL, R_DD, R_BASIN = 1, 2, 4, 8, 16
 CERTIFY_WORKSPACE = 16384  # MSPLIT_CERTIFY_WORKSPACE
 
 
@@ -42,7 +42,7 @@ class RootsC(ctypes.Structure):
         ("re_lo", ctypes.c_void_p), ("im_lo", ctypes.c_void_p),
         ("period", ctypes.c_void_p), ("preperiod", ctypes.c_void_p),
         ("flags", ctypes.c_void_p), ("radius", ctypes.c_void_p),
-        ("capacity", ctypes.c_uint64),
+        ("capacity", ctypes.c_uint64), ("basin", ctypes.c_void_p),
     ]
 
 
@@ -57,6 +57,7 @@ class Stats(ctypes.Structure):
         ("min_sep", ctypes.c_double), ("max_radius", ctypes.c_double), ("ms_device", ctypes.c_double),
         ("ms_stage", ctypes.c_double * 6),
         ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("basin", ctypes.c_uint64), ("min_basin", ctypes.c_double),
     ]
 
     STAGES = ("seeds", "walk", "descend", "collect", "classify", "certify")
@@ -127,8 +128,8 @@ class MsplitError(RuntimeError):
 
 
 def make_options(precision=FP64, level=0.0, points_per_turn=0, seg_points=0, min_cap=0, cap_factor=0.0,
-                 block_size=0, certify=False, label=True, fp32_switch=0.0):
-    flags = (F_CERTIFY if certify else 0) | (0 if label else F_NO_LABEL)
+                 block_size=0, certify=False, label=True, fp32_switch=0.0, basin=False):
+    flags = (F_CERTIFY if certify else 0) | (0 if label else F_NO_LABEL) | (F_BASIN if basin else 0)
     prec = {"fp64": FP64, "mixed": MIXED, "dd": DD}.get(precision, precision)
     return Options(ctypes.sizeof(Options), prec, level, points_per_turn, seg_points, min_cap, cap_factor,
                    block_size, flags, fp32_switch)
@@ -155,10 +156,11 @@ class Result:
     """Roots of one split (device tensors trimmed to the count)."""
 
     def __init__(self, l, n, re, im, period, flags, radius, count, stats, status, preperiod=None, re_lo=None,
-                 im_lo=None):
+                 im_lo=None, basin=None):
         self.l, self.n = l, n
         self.re, self.im, self.period, self.flags, self.radius = re, im, period, flags, radius
         self.preperiod = preperiod
+        self.basin = basin
         self.re_lo, self.im_lo = re_lo, im_lo
         self.count = count
         self.stats = stats
@@ -170,7 +172,7 @@ class Result:
     def cpu(self):
         import numpy as np
         d = {"re": self.re.cpu().numpy(), "im": self.im.cpu().numpy()}
-        for k in ("period", "preperiod", "flags", "radius", "re_lo", "im_lo"):
+        for k in ("period", "preperiod", "flags", "radius", "re_lo", "im_lo", "basin"):
             t = getattr(self, k)
             d[k] = t.cpu().numpy() if t is not None else None
         d["stats"] = self.stats
@@ -203,11 +205,13 @@ class Buffers:
         self.preperiod = torch.empty(cap, dtype=torch.int32, device=device)
         self.flags = torch.empty(cap, dtype=torch.uint8, device=device)
         self.radius = torch.empty(cap, dtype=torch.float64, device=device)
+        self.basin = torch.empty(cap, dtype=torch.float64, device=device) if opts.flags & F_BASIN else None
 
     def roots_struct(self):
         return RootsC(self.re.data_ptr(), self.im.data_ptr(), self.re_lo.data_ptr(), self.im_lo.data_ptr(),
                       self.period.data_ptr(), self.preperiod.data_ptr(), self.flags.data_ptr(),
-                      self.radius.data_ptr(), self.cap)
+                      self.radius.data_ptr(), self.cap,
+                      self.basin.data_ptr() if self.basin is not None else None)
 
 
 def split(l: int, n: int, opts: Options = None, buffers: Buffers = None, stream=None, check=True) -> Result:
@@ -229,7 +233,8 @@ def split(l: int, n: int, opts: Options = None, buffers: Buffers = None, stream=
         raise MsplitError(r, f"split({l},{n})")
     certified = bool(opts.flags & F_CERTIFY)
     return Result(l, n, b.re[:c], b.im[:c], b.period[:c], b.flags[:c], b.radius[:c] if certified else None, c,
-                  st.as_dict(), r, preperiod=b.preperiod[:c], re_lo=b.re_lo[:c], im_lo=b.im_lo[:c])
+                  st.as_dict(), r, preperiod=b.preperiod[:c], re_lo=b.re_lo[:c], im_lo=b.im_lo[:c],
+                  basin=b.basin[:c] if b.basin is not None else None)
 
 
 def hyperbolic(n: int, **kw) -> Result:
@@ -243,10 +248,11 @@ def misiurewicz(l: int, n: int, **kw) -> Result:
 
 
 def certify(l: int, n: int, re: torch.Tensor, im: torch.Tensor, period: torch.Tensor = None, stream=None,
-            re_lo: torch.Tensor = None, im_lo: torch.Tensor = None):
+            re_lo: torch.Tensor = None, im_lo: torch.Tensor = None, basin: bool = False):
     """Certify candidates (device tensors, sorted by real part; optional
     double-double low parts).  Returns (flags uint8 tensor, radius float64
-    tensor, stats dict)."""
+    tensor, stats dict), and the Newton-basin radii as a fourth element when
+    basin is set."""
     m = re.numel()
     dev = re.device
     re = re.contiguous().to(torch.float64)
@@ -258,13 +264,17 @@ def certify(l: int, n: int, re: torch.Tensor, im: torch.Tensor, period: torch.Te
     if re_lo is not None and im_lo is not None:
         lo = (re_lo.contiguous().to(torch.float64), im_lo.contiguous().to(torch.float64))
     ws = torch.empty(CERTIFY_WORKSPACE, dtype=torch.uint8, device=dev)
+    bas = torch.zeros(m, dtype=torch.float64, device=dev) if basin else None
     rs = RootsC(re.data_ptr(), im.data_ptr(), lo[0].data_ptr() if lo else None, lo[1].data_ptr() if lo else None,
-                per.data_ptr() if per is not None else None, None, flags.data_ptr(), radius.data_ptr(), m)
+                per.data_ptr() if per is not None else None, None, flags.data_ptr(), radius.data_ptr(), m,
+                bas.data_ptr() if bas is not None else None)
     st = Stats()
     r = lib().msplit_certify(l, n, ctypes.byref(rs), m, ctypes.c_void_p(ws.data_ptr()), CERTIFY_WORKSPACE, ctypes.byref(st),
                              _stream_handle(stream))
     if r:
         raise MsplitError(r, "msplit_certify")
+    if basin:
+        return flags, radius, st.as_dict(), bas
     return flags, radius, st.as_dict()
 
 

@@ -3,6 +3,7 @@ include/msplit.h; host-side logic that needs no GPU (counts, status text)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -36,12 +37,27 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(msplit.EXPORTED) == names
 
 
-def test_struct_sizes_match_binding(lib):
+def test_struct_sizes_match_binding(lib, tmp_path):
+    """Every field offset and struct size of the ctypes binding equals the C
+    layout of include/msplit.h (compiled here with gcc)."""
     from paper_2402_06083_amd import msplit
-    # msplit_options: 4+4+8+4+4+4(pad)+8+4+4+8 = 56 bytes on x86-64 SysV
-    assert ctypes.sizeof(msplit.Options) == 56
-    assert ctypes.sizeof(msplit.RootsC) == 8 * 8 + 8
-    assert ctypes.sizeof(msplit.Stats) == 21 * 8 + 3 * 8 + 6 * 8 + 8
+    structs = {"msplit_options": msplit.Options, "msplit_roots": msplit.RootsC, "msplit_stats": msplit.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "msplit.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                              check=True).stdout.split("\n") if line)
+    for cname, py in structs.items():
+        assert int(out[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(out[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
 
 
 def test_header_constants_match_binding():

@@ -427,6 +427,41 @@ def test_autotuner_picks_a_complete_configuration(tmp_path):
         assert d["missing"] == 0 and d["certified"] == d["unique"], (l, n, d)
 
 
+@pytest.mark.parametrize("ln", [(0, 14), (3, 9), (2, 16)])
+def test_basin_radii_verified_by_oracle(ln):
+    """MSPLIT_F_BASIN (Thm proofContract): every certified root gets a disk of
+    Newton convergence; the oracle re-proves each claim (root within
+    radius + |lo| of the FP64 centre, basin disk) in long-double disk
+    arithmetic, and no basin disk reaches another root.  (2,16) includes
+    double-double roots next to -2."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    r, g = gpu_split(l, n, certify=True, basin=True)
+    st = r.stats
+    assert st["certified"] == len(g) and st["basin"] == len(g), st
+    assert np.all(g.flags & msplit.R_BASIN)
+    assert np.all(g.basin > 0) and st["min_basin"] == g.basin.min()
+    eta = g.radius + np.abs(g.re_lo) + np.abs(g.im_lo)
+    assert np.all(oracle.basin_check(l, n, g.re, g.im, eta, g.basin))
+    z = (g.re + g.re_lo) + 1j * (g.im + g.im_lo)
+    allz = np.concatenate([z, np.conj(z[g.im > 0])])
+    from scipy.spatial import cKDTree
+    tree = cKDTree(np.stack([allz.real, allz.imag], axis=1))
+    d, _ = tree.query(np.stack([z.real, z.imag], axis=1), k=2)
+    assert np.all(g.basin < d[:, 1])
+
+
+def test_certify_api_basin():
+    """msplit_certify with a basin array: the same radii as the split."""
+    from paper_2402_06083_amd import msplit
+    r, g = gpu_split(0, 10, certify=True, basin=True)
+    flags, radius, st, bas = msplit.certify(0, 10, r.re, r.im, period=r.period, basin=True)
+    torch.cuda.synchronize()
+    assert st["basin"] == len(g)
+    assert np.array_equal(bas.cpu().numpy(), g.basin)
+    assert np.array_equal(flags.cpu().numpy() & msplit.R_BASIN, g.flags & msplit.R_BASIN)
+
+
 def test_deterministic_output():
     r1, g1 = gpu_split(0, 17)
     r2, g2 = gpu_split(0, 17)

@@ -436,3 +436,68 @@ def test_degree_identity_and_q24_factorization():
             prod = exact.pmul(prod, list(poly))
     assert prod == list(exact.q(2, 4))
     assert counts.eta(2, 1) == 3 and counts.eta(2, 2) == 2 and counts.eta(2, 4) == 2
+
+
+# --------------------------------------------------------------- Newton basin
+# Thm proofContract, checked by the oracle in long-double disk arithmetic.
+
+def test_basin_check_closed_form_p2():
+    """p_2 = c^2 + c, roots 0 and -1, P' = 2c + 1: P'(D(r, eps)) = D(P'(r), 2 eps)
+    with |P'(r)| = 1, so the condition |centre| > 5 radius holds exactly for
+    eps < 1/10; eps must also exceed 3 eta."""
+    ok = oracle.basin_check(0, 2, [0.0, 0.0, -1.0, -1.0], [0.0] * 4, 1e-20, [0.0999, 0.1001, 0.0999, 0.1001])
+    assert list(ok) == [True, False, True, False]
+    assert not oracle.basin_check(0, 2, [0.0], [0.0], 0.04, [0.0999])[0]  # eps <= 3 eta
+    # p_1 = c: P' = 1 everywhere, any eps above 3 eta
+    assert oracle.basin_check(0, 1, [0.0], [0.0], 1e-20, [0.25])[0]
+
+
+def _largest_basin(l, n, z, eta):
+    eps = np.zeros(len(z))
+    for k in range(2, 60):
+        ok = oracle.basin_check(l, n, z.real, z.imag, eta, 2.0 ** -k)
+        eps = np.where((eps == 0) & ok, 2.0 ** -k, eps)
+    return eps
+
+
+def _newton_pn(n, c, iters=80):
+    for _ in range(iters):
+        z = np.zeros_like(c)
+        dz = np.zeros_like(c)
+        for _k in range(n):
+            dz = 2 * z * dz + 1
+            z = z * z + c
+        c = c - z / dz
+    return c
+
+
+@pytest.mark.parametrize("n", [5, 7])
+def test_basin_disks_converge_under_newton(n):
+    """Newton's method started anywhere in a disk the check accepts converges
+    to that disk's root (sampled points, double precision): the consequence
+    Thm proofContract asserts, tested by running the method."""
+    r = oracle.split(0, n)
+    z = r.re_hi + 1j * r.im_hi
+    eps = _largest_basin(0, n, z, 1e-18)
+    assert np.all(eps > 0)
+    rng = np.random.default_rng(11)
+    for zi, ei in zip(z, eps):
+        rad = ei * np.sqrt(rng.random(64))
+        ang = 2 * np.pi * rng.random(64)
+        pts = zi + rad * np.exp(1j * ang)
+        end = _newton_pn(n, pts)
+        assert np.max(np.abs(end - zi)) < 1e-10, (zi, ei)
+
+
+@pytest.mark.parametrize("n", [6, 8])
+def test_basin_check_rejects_disks_holding_two_roots(n):
+    """A disk that reaches another root (or the conjugate) cannot lie in one
+    basin: the check must refuse eps = the distance to the nearest other root
+    (a check that accepted everything would fail here)."""
+    r = oracle.split(0, n)
+    z = r.re_hi + 1j * r.im_hi
+    allz = np.concatenate([z, np.conj(z[r.im_hi > 0])])
+    d = np.abs(z[:, None] - allz[None, :])
+    d[d == 0] = np.inf
+    near = d.min(axis=1)
+    assert not np.any(oracle.basin_check(0, n, z.real, z.imag, 1e-18, near * 1.01))
