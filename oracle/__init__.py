@@ -55,6 +55,8 @@ def lib():
     L.oracle_starts.restype = i64
     L.oracle_split.argtypes = [ctypes.c_int, ctypes.c_int, i64, d_p, d_p, d_p, d_p, i32_p, i64_p]
     L.oracle_split.restype = i64
+    L.oracle_split_simple.argtypes = [ctypes.c_int, ctypes.c_int, i64, d_p, d_p, d_p, d_p, i32_p, i64_p]
+    L.oracle_split_simple.restype = i64
     L.oracle_certify.argtypes = [ctypes.c_int, ctypes.c_int, i64, d_p, d_p, d_p, d_p, i32_p, u8_p, d_p]
     L.oracle_certify.restype = None
     L.oracle_basin_check.argtypes = [ctypes.c_int, ctypes.c_int, i64, d_p, d_p, d_p, d_p, u8_p]
@@ -77,8 +79,9 @@ def max_threads() -> int:
     return int(lib().oracle_max_threads())
 
 
-def evaluate(l: int, n: int, c: complex):
-    """(P(c), P'(c)) for P = q_{l,n} (l = 0: p_n) in long double."""
+def evaluate(l: int, n: int, c: complex, simple: bool = False):
+    """(P(c), P'(c)) for P = q_{l,n} (l = 0: p_n) in long double; with simple,
+    P = s_{l,n} = p_{l+n-1} + p_{l-1} (l >= 2)."""
     out = np.zeros(4, dtype=np.longdouble)
     # long doubles travel by pointer: a by-value ctypes c_longdouble goes
     # through a Python float and would lose the extra bits
@@ -86,7 +89,7 @@ def evaluate(l: int, n: int, c: complex):
         arg = np.array([c[0], c[1]], dtype=np.longdouble)
     else:
         arg = np.array([c.real, c.imag], dtype=np.longdouble)
-    lib().oracle_eval(l, n, _ptr(arg, ctypes.c_longdouble), _ptr(out, ctypes.c_longdouble))
+    lib().oracle_eval(-(l - 1) if simple else l, n, _ptr(arg, ctypes.c_longdouble), _ptr(out, ctypes.c_longdouble))
     return out
 
 
@@ -134,20 +137,23 @@ class Roots:
         return re, im
 
 
-def split(l: int, n: int) -> Roots:
+def split(l: int, n: int, simple: bool = False) -> Roots:
     """Split q_{l,n} (l = 0: p_n) with the oracle.  For p_n all 2^(n-1) roots
-    are returned with their exact period; for q_{l,n} only Mis(l,n)."""
+    are returned with their exact period; for q_{l,n} only Mis(l,n).  With
+    simple (l >= 2), Mis(l,n) is found from the roots of the simplified
+    polynomial s_{l,n} = p_{l+n-1} + p_{l-1} (eq. polySimple) instead."""
     D = 1 << (l + n - 1)
     cap = D + 1
     a = np.zeros((4, cap), dtype=np.float64)
     per = np.zeros(cap, dtype=np.int32)
     st = np.zeros(16, dtype=np.int64)
-    r = lib().oracle_split(l, n, cap, _ptr(a[0], ctypes.c_double), _ptr(a[1], ctypes.c_double),
-                           _ptr(a[2], ctypes.c_double), _ptr(a[3], ctypes.c_double),
-                           _ptr(per, ctypes.c_int32), _ptr(st, ctypes.c_int64))
+    fn = lib().oracle_split_simple if simple else lib().oracle_split
+    r = fn(l, n, cap, _ptr(a[0], ctypes.c_double), _ptr(a[1], ctypes.c_double),
+           _ptr(a[2], ctypes.c_double), _ptr(a[3], ctypes.c_double),
+           _ptr(per, ctypes.c_int32), _ptr(st, ctypes.c_int64))
     stats = dict(zip(STAT_NAMES, st.tolist()))
     if r < 0:
-        raise RuntimeError(f"oracle_split({l},{n}) failed with status {r}: {stats}")
+        raise RuntimeError(f"oracle_split({l},{n}, simple={simple}) failed with status {r}: {stats}")
     return Roots(a[0, :r].copy(), a[1, :r].copy(), a[2, :r].copy(), a[3, :r].copy(), per[:r].copy(), stats)
 
 

@@ -66,16 +66,20 @@ typedef long double complex cld;
 /* same derivative in closed form, eq. DerParamDyna).  q_{0,n} = p_n since    */
 /* p_0 = 0 (eq. hypCase).                                                     */
 /* ------------------------------------------------------------------------- */
+/* A negative l selects the simplified polynomial of eq. polySimple,       */
+/* s_{a+1,n} = p_{a+n} + p_a with a = -l: P = z_{a+n} + z_a (Appendix A,      */
+/* eq. polyMisSimple).                                                        */
 static void eval_q(int l, int n, cld c, cld *P, cld *dP)
 {
+    const int a = l < 0 ? -l : l;
     cld z = 0, dz = 0, zl = 0, dzl = 0;
-    for (int k = 1; k <= l + n; k++) {
+    for (int k = 1; k <= a + n; k++) {
         dz = 2 * z * dz + 1; /* uses p_{k-1} */
         z = z * z + c;
-        if (k == l) { zl = z; dzl = dz; }
+        if (k == a) { zl = z; dzl = dz; }
     }
-    *P = z - zl;
-    *dP = dz - dzl;
+    *P = l < 0 ? z + zl : z - zl;
+    *dP = l < 0 ? dz + dzl : dz - dzl;
 }
 
 /* p_k and p_k' for k = 0..N in one pass */
@@ -170,17 +174,20 @@ static inline dd dd_from_ld(ld x)
 }
 static inline ld ld_from_dd(dd a) { return (ld)a.hi + (ld)a.lo; }
 
-/* Newton step of q_{l,n} evaluated in double-double: returns P/P' */
+/* Newton step of q_{l,n} (negative l: s_{-l+1,n}, as eval_q) evaluated in
+ * double-double: returns P/P' */
 static cdd dd_newton_step(int l, int n, cdd c)
 {
+    const int a = l < 0 ? -l : l;
     cdd z = { { 0, 0 }, { 0, 0 } }, dz = z, zl = z, dzl = z;
     const cdd one = { { 1, 0 }, { 0, 0 } };
-    for (int k = 1; k <= l + n; k++) {
+    for (int k = 1; k <= a + n; k++) {
         cdd t = cdd_mul(z, dz);
         dz = cdd_add(cdd_add(t, t), one);
         z = cdd_add(cdd_mul(z, z), c);
-        if (k == l) { zl = z; dzl = dz; }
+        if (k == a) { zl = z; dzl = dz; }
     }
+    if (l < 0) return cdd_div(cdd_add(z, zl), cdd_add(dz, dzl));
     return cdd_div(cdd_sub(z, zl), cdd_sub(dz, dzl));
 }
 
@@ -188,17 +195,22 @@ static cdd dd_newton_step(int l, int n, cdd c)
 /* Parameters of the method (Section 4.2 and Section 6.3.1).                   */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-    int l, n;          /* type; l = 0 is p_n */
-    int order;         /* l + n; deg P = 2^(order-1) */
+    int l, n;          /* polynomial of eval_q: l = 0 is p_n; l < 0 is s_{-l+1,n} */
+    int tl;            /* preperiod of the type (l, or -l + 1 for s) */
+    int order;         /* order of the leading p_k of P; deg P = 2^(order-1) */
     int64_t D;         /* degree */
     ld level;          /* lambda_0: 5 for p_n, 100 for q_{l,n} */
     int M;             /* points per turn */
     int cap;           /* Newton cap max{20, I_N log d} */
 } method_t;
 
-static void method_init(method_t *m, int l, int n)
+/* simple: P = s_{l,n} = p_{l+n-1} + p_{l-1} (eq. polySimple), l >= 2 */
+static void method_init_p(method_t *m, int l, int n, int simple)
 {
-    m->l = l; m->n = n; m->order = l + n;
+    m->tl = l;
+    m->l = simple ? -(l - 1) : l;
+    m->n = n;
+    m->order = simple ? l + n - 1 : l + n;
     m->D = (int64_t)1 << (m->order - 1);
     m->level = (l == 0) ? 5.0L : 100.0L;
     m->M = (l == 0 && m->order >= 30) ? 16 : 8;
@@ -206,6 +218,8 @@ static void method_init(method_t *m, int l, int n)
     ld capf = ceill(IN * logl((ld)m->D));
     m->cap = capf > 20 ? (int)capf : 20;
 }
+
+static void method_init(method_t *m, int l, int n) { method_init_p(m, l, n, 0); }
 
 /* Thresholds of the oracle's own stopping rules (long double). */
 #define TOL_SOLVE 0x1p-58L   /* Newton-with-target: relative step */
@@ -398,8 +412,8 @@ static int make_starts(const method_t *m, cld *starts, start_stats *st)
         cld z = seed[j];
         for (int k1 = COARSE_ORDER + 1; k1 <= m->order; k1++)
             if (lift_point(k1, m->level, &z, &lift_steps)) { fail = 1; break; }
-        if (m->l > 0 && !fail) {
-            /* onto q_{l,n} = level, same phase index */
+        if (m->l != 0 && !fail) {
+            /* onto q_{l,n} (or s_{l,n}) = level, same phase index */
             if (solve_target(m->l, m->n, &z, m->level, &lift_steps) <= 0) fail = 1;
         }
         seed[j] = z;
@@ -605,13 +619,20 @@ static int at_multiple_root(const method_t *m, cdd c)
 
 /* Membership in Mis(l,n) from eq. def:mis: not a centre of Hyp(k) for k | n
  * (preperiod 0), not a root of q_{l-1,n}, and not a root of q_{l,k} for a
- * strict divisor k of n. */
+ * strict divisor k of n.  On q_{l,n} the centres are multiple roots
+ * (at_multiple_root); on s_{l,n} they are simple roots, found by p_k. */
 static int is_mis_type(const method_t *m, cdd c)
 {
-    if (at_multiple_root(m, c)) return 0;
-    if (newton_zero(m->l - 1, m->n, c)) return 0;
+    const int l = m->tl;
+    if (m->l < 0) {
+        for (int k = 1; k <= m->n; k++)
+            if (m->n % k == 0 && newton_zero(0, k, c)) return 0;
+    } else if (at_multiple_root(m, c)) {
+        return 0;
+    }
+    if (newton_zero(l - 1, m->n, c)) return 0;
     for (int k = 1; k < m->n; k++)
-        if (m->n % k == 0 && newton_zero(m->l, k, c)) return 0;
+        if (m->n % k == 0 && newton_zero(l, k, c)) return 0;
     return 1;
 }
 
@@ -629,8 +650,8 @@ static cdd polish(const method_t *m, cld z)
 
 #define EPS_COLLECT 0x1p-70 /* identification radius on polished points */
 
-static int64_t split_impl(int l, int n, int64_t cap, double *re_hi, double *re_lo, double *im_hi,
-                          double *im_lo, int32_t *period, int64_t *stats);
+static int64_t split_impl(int l, int n, int simple, int64_t cap, double *re_hi, double *re_lo,
+                          double *im_hi, double *im_lo, int32_t *period, int64_t *stats);
 
 /* Split P = q_{l,n} (l = 0: p_n).  Outputs the closed-upper-half-plane roots,
  * lexicographically ordered, as double-double (hi + lo), with
@@ -640,18 +661,28 @@ static int64_t split_impl(int l, int n, int64_t cap, double *re_hi, double *re_l
 int64_t oracle_split(int l, int n, int64_t cap, double *re_hi, double *re_lo, double *im_hi,
                      double *im_lo, int32_t *period, int64_t *stats)
 {
-    return split_impl(l, n, cap, re_hi, re_lo, im_hi, im_lo, period, stats);
+    return split_impl(l, n, 0, cap, re_hi, re_lo, im_hi, im_lo, period, stats);
 }
 
-static int64_t split_impl(int l, int n, int64_t cap, double *re_hi, double *re_lo, double *im_hi,
-                          double *im_lo, int32_t *period, int64_t *stats)
+/* Mis(l,n), l >= 2, from the roots of the simplified polynomial
+ * s_{l,n} = p_{l+n-1} + p_{l-1} (eq. polySimple: simple roots, half the
+ * degree of q_{l,n}); same outputs and status as oracle_split. */
+int64_t oracle_split_simple(int l, int n, int64_t cap, double *re_hi, double *re_lo, double *im_hi,
+                            double *im_lo, int32_t *period, int64_t *stats)
+{
+    if (l < 2) return -101;
+    return split_impl(l, n, 1, cap, re_hi, re_lo, im_hi, im_lo, period, stats);
+}
+
+static int64_t split_impl(int l, int n, int simple, int64_t cap, double *re_hi, double *re_lo,
+                          double *im_hi, double *im_lo, int32_t *period, int64_t *stats)
 {
     int64_t st_local[S_NSTATS];
     if (!stats) stats = st_local;
     memset(stats, 0, sizeof(int64_t) * S_NSTATS);
     if (n < 1 || l < 0 || l == 1 || l + n > 40) return -101;
     method_t m;
-    method_init(&m, l, n);
+    method_init_p(&m, l, n, simple);
     const int64_t ns = 2 * m.D + 1;
     cld *pts = malloc(sizeof(cld) * ns);
     start_stats ss;
@@ -679,7 +710,7 @@ static int64_t split_impl(int l, int n, int64_t cap, double *re_hi, double *re_l
 
     /* q_{l,n}: drop descents stalled next to a multiple (hyperbolic) root */
     unsigned char *drop = calloc(cnt ? cnt : 1, 1);
-    if (l > 0) {
+    if (l > 0 && !simple) {
         int64_t nh = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : nh)
         for (int64_t i = 0; i < cnt; i++)
@@ -710,7 +741,7 @@ static int64_t split_impl(int l, int n, int64_t cap, double *re_hi, double *re_l
             int64_t dk = ((int64_t)1 << (k - 1)) + 1;
             double *a = malloc(sizeof(double) * 4 * dk);
             int32_t *pk = malloc(sizeof(int32_t) * dk);
-            int64_t ck = split_impl(0, k, dk, a, a + dk, a + 2 * dk, a + 3 * dk, pk, NULL);
+            int64_t ck = split_impl(0, k, 0, dk, a, a + dk, a + 2 * dk, a + 3 * dk, pk, NULL);
             if (ck < 0) { free(a); free(pk); free(lab); free(pol); stats[S_STATUS] = -6; return -6; }
             cdd *rk = malloc(sizeof(cdd) * (ck ? ck : 1));
             for (int64_t i = 0; i < ck; i++) {

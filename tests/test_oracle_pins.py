@@ -501,3 +501,62 @@ def test_basin_check_rejects_disks_holding_two_roots(n):
     d[d == 0] = np.inf
     near = d.min(axis=1)
     assert not np.any(oracle.basin_check(0, n, z.real, z.imag, 1e-18, near * 1.01))
+
+
+# ------------------------------------------- simplified polynomials s_{l,n}
+# eq. polySimple / eq. polyMisSimple: s_{l,n} = q_{l,n} / q_{l-1,n}
+# = p_{l+n-1} + p_{l-1}, with simple roots Hyp(k), k | gcd(n, l-1), and
+# Mis(l,k), k | n.
+
+@pytest.mark.parametrize("l,n", [(2, 1), (2, 4), (3, 3), (4, 2), (5, 4), (3, 6)])
+def test_simple_polynomial_is_the_exact_quotient(l, n):
+    """q_{l,n} = s_{l,n} q_{l-1,n} as integer polynomials, s_{l,n} =
+    p_{l+n-1} + p_{l-1}, and s_{l,n} = prod h_k (k | gcd(n, l-1)) prod m_{l,k}
+    (k | n), so its degree 2^(l+n-2) splits into those counts."""
+    from oracle import exact
+    assert exact.pmul(list(exact.s(l, n)), list(exact.q(l - 1, n))) == list(exact.q(l, n))
+    deg = len(exact.s(l, n)) - 1
+    assert deg == 2 ** (l + n - 2)
+    g = math.gcd(n, l - 1)
+    total = sum(counts.hyp_count(k) for k in counts.divisors(g)) + sum(
+        counts.mis_count(l, k) for k in counts.divisors(n))
+    assert total == deg
+
+
+@pytest.mark.parametrize("l,n", [(2, 3), (3, 2), (4, 4), (3, 6)])
+def test_simple_evaluation_matches_exact_polynomial(l, n):
+    """The oracle's orbit evaluation of s_{l,n} and its derivative against the
+    exact integer coefficients (60 digits) at seeded points."""
+    import mpmath
+    from oracle import exact
+    co = list(exact.s(l, n))
+    dco = [k * co[k] for k in range(1, len(co))]
+    rng = np.random.default_rng(5)
+    for _ in range(12):
+        c = complex(rng.uniform(-2, 0.5), rng.uniform(-1.2, 1.2))
+        P = oracle.evaluate(l, n, c, simple=True)
+        Pe = complex(exact.polyval_mp(co, mpmath.mpc(c)))
+        dPe = complex(exact.polyval_mp(dco, mpmath.mpc(c)))
+        assert abs(complex(float(P[0]), float(P[1])) - Pe) <= 1e-15 * (1 + abs(Pe))
+        assert abs(complex(float(P[2]), float(P[3])) - dPe) <= 1e-15 * (1 + abs(dPe))
+
+
+@pytest.mark.parametrize("l,n", [(2, 1), (2, 2), (3, 1), (2, 4), (3, 4), (4, 3), (5, 4), (3, 8), (6, 6), (2, 10)])
+def test_simple_split_equals_q_split(l, n):
+    """Mis(l,n) found from the roots of s_{l,n} (half the degree, simple
+    roots, its own level line and starts) equals Mis(l,n) found from
+    q_{l,n}: two independent routes to the same set."""
+    a = oracle.split(l, n)
+    b = oracle.split(l, n, simple=True)
+    za = np.sort_complex((a.re_hi + a.re_lo) + 1j * (a.im_hi + a.im_lo))
+    zb = np.sort_complex((b.re_hi + b.re_lo) + 1j * (b.im_hi + b.im_lo))
+    assert len(za) == len(zb)
+    assert np.max(np.abs(za - zb)) < 1e-20
+
+
+@pytest.mark.parametrize("l,n", [(2, 12), (4, 10), (7, 7), (12, 2), (3, 13)])
+def test_simple_split_counts(l, n):
+    """|Mis(l,n)| (eq. MisCount) from s_{l,n} at orders 14 to 16."""
+    b = oracle.split(l, n, simple=True)
+    total = int(np.sum(b.im_hi == 0)) + 2 * int(np.sum(b.im_hi != 0))
+    assert total == counts.mis_count(l, n)
