@@ -10,8 +10,10 @@ Each runs in FP64 and in mixed FP32 -> FP64 precision.  A step is one pass
 of the whole hot path over the workload: seeds, level-line walk, descents
 (with the double-double route), collection, classification, certificate.
 The inputs are the integers n themselves (no dataset exists for this
-problem); nothing is cached between steps.  ``mis22`` (every q_{l,n},
-l + n <= 22) is available with --workload.
+problem); nothing is cached between steps.  ``mis22`` (every Mis(l,n),
+l + n <= 22, all 210 types in one batch) is measured next to them through
+q_{l,n} and through the simplified s_{l,n} = p_{l+n-1} + p_{l-1}, and is
+available as the headline with --workload.
 
 Prints one JSON line (metric, value, roofline of the dominant kernel, CPU
 oracle baseline).
@@ -76,13 +78,15 @@ def certified_roots(stats_list):
     return tot
 
 
-def kernel_flops(pairs, stats_list):
+def kernel_flops(pairs, stats_list, simple=False):
     """Algorithmic flops of the walk and descent kernels over the whole call
     (per-type step counts times the per-evaluation cost of that type) and
-    the kernels' device times (one launch each for the whole call)."""
+    the kernels' device times (one launch each for the whole call).  The
+    evaluated polynomial has order N = l + n (p_n, q_{l,n}) or l + n - 1
+    (s_{l,n})."""
     desc = walk = 0.0
     for (l, n), st in zip(pairs, stats_list):
-        N = l + n
+        N = l + n - (1 if simple and l >= 2 else 0)
         desc += st["steps_desc"] * (FLOPS_ORBIT_STEP * (N - 1) + FLOPS_NEWTON_UPDATE)
         desc += st["steps_fp32"] * (FLOPS_ORBIT_STEP * (N - 1) + FLOPS_NEWTON_UPDATE)
         walk += st["steps_walk"] * (FLOPS_ORBIT_STEP * (N - 1) + FLOPS_WALK_UPDATE)
@@ -91,19 +95,19 @@ def kernel_flops(pairs, stats_list):
     return desc, t_desc, walk, t_walk
 
 
-def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=False):
+def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=False, simple=False):
     """eager: every call enqueued by msplit_batch (stage times from HIP
     events on the call's stream); graph: the call captured once as a
     hipGraph and replayed (msplit_graph_launch: total device time only).
     tuned: launch parameters from the autotuner (dict of option fields)."""
     import torch
     from paper_2402_06083_amd import batch, msplit
-    opts = msplit.make_options(precision=precision, certify=True, basin=basin, **(tuned or {}))
+    opts = msplit.make_options(precision=precision, certify=True, basin=basin, simple=simple, **(tuned or {}))
     runner = batch.BatchRunner(pairs, opts)
     mode = launch
     if mode == "graph":
         runner.capture()
-    agg = _time_runner(runner, pairs, steps, warmup, mode)
+    agg = _time_runner(runner, pairs, steps, warmup, mode, simple)
     agg["launch"] = mode
     runner.close()
     del runner
@@ -111,7 +115,7 @@ def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=F
     return agg
 
 
-def _time_runner(runner, pairs, steps, warmup, mode):
+def _time_runner(runner, pairs, steps, warmup, mode, simple=False):
     import torch
     from paper_2402_06083_amd import msplit
     call = runner.launch if mode == "graph" else runner.run
@@ -126,7 +130,7 @@ def _time_runner(runner, pairs, steps, warmup, mode):
             raise RuntimeError(f"msplit_batch failed: {msplit.strerror(r)}")
         res = runner.result(r)
         sts = [st for (_, st, _) in res.per_pair]
-        d, td, w, tw = kernel_flops(pairs, sts)
+        d, td, w, tw = kernel_flops(pairs, sts, simple)
         cr = certified_roots(sts)
         if agg is None:
             agg = dict(desc=0.0, t_desc=0.0, walk=0.0, t_walk=0.0, roots=0, ms_device=0.0,
@@ -149,14 +153,14 @@ def _time_runner(runner, pairs, steps, warmup, mode):
     return agg
 
 
-def autotune(pairs, prec, other, retune=False):
+def autotune(pairs, prec, other, retune=False, simple=False):
     """Launch parameters per precision: the cached tuning (the user's cache,
     else the one shipped for this GPU) or, when none is cached or retune is
     set, a tuning run now (before the timed steps)."""
     from paper_2402_06083_amd import tune
     tuned, info = {prec: None}, {}
     for p in [prec] + ([other] if other else []):
-        hit = None if retune else tune.lookup(pairs, p)
+        hit = None if retune else tune.lookup(pairs, p, simple=simple)
         if hit is None:
             space = None
             if p != prec and tuned[prec] is not None:
@@ -164,7 +168,7 @@ def autotune(pairs, prec, other, retune=False):
                 space = {k: [v] for k, v in tuned[prec].items()}
                 if p == "mixed":
                     space["fp32_switch"] = tune.MIXED_SWITCHES
-            t = tune.tune(pairs, p, space=space or None)
+            t = tune.tune(pairs, p, space=space or None, simple=simple)
             hit = {"options": t["best"], "ms": t["ms"], "default_ms": t["default_ms"], "source": "tuned now"}
         else:
             hit = dict(hit, source="cache")
@@ -200,6 +204,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-p30", action="store_true", help="skip the period-30 measurement")
     ap.add_argument("--p30-steps", type=int, default=2)
+    ap.add_argument("--no-mis22", action="store_true",
+                    help="skip the Misiurewicz batch (q_{l,n} and s_{l,n} routes)")
+    ap.add_argument("--simple", action="store_true",
+                    help="Misiurewicz headline workloads through the simplified s_{l,n}")
     ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay measurement")
     ap.add_argument("--no-basin", action="store_true",
                     help="skip the measurement with the Newton-basin proof (MSPLIT_F_BASIN)")
@@ -224,8 +232,9 @@ def main():
     tuned = {main_prec: None, other: None}
     tune_info = {}
     if not args.no_tune:
-        tuned, tune_info = autotune(pairs, main_prec, None if args.no_compare else other, args.retune)
-    res = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager", tuned[main_prec])
+        tuned, tune_info = autotune(pairs, main_prec, None if args.no_compare else other, args.retune,
+                                    args.simple)
+    res = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager", tuned[main_prec], simple=args.simple)
     value = res["roots"] / res["wall"]
     ms_per_step = 1e3 * res["wall"] / args.steps
     # dominant kernel: the stage with the larger device time
@@ -249,6 +258,7 @@ def main():
         "data": "synthetic: the integers n themselves (no dataset exists for this problem)",
         "config": {"workload": desc, "pairs": len(pairs), "roots_per_step": res["roots"] // args.steps,
                    "precision": main_prec, "certified": True, "parallelism": "single GPU",
+                   "polynomial": "s_{l,n}" if args.simple else "p_n / q_{l,n}",
                    "launch": "eager: msplit_batch per step, one host synchronisation per call",
                    "tuning": tune_info},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
@@ -260,18 +270,19 @@ def main():
         "stage_ms_per_step": {k: v / args.steps for k, v in res["stages"].items()},
     }
     if not args.no_graph:
-        rg = run_gpu(pairs, main_prec, args.steps, args.warmup, "graph", tuned[main_prec])
+        rg = run_gpu(pairs, main_prec, args.steps, args.warmup, "graph", tuned[main_prec], simple=args.simple)
         out["graph"] = {"value": rg["roots"] / rg["wall"], "ms_per_step": 1e3 * rg["wall"] / args.steps,
                         "device_ms_per_step": rg["ms_device"] / args.steps,
                         "launch": "whole call captured once as a hipGraph, replayed each step"}
     if not args.no_basin:
-        rb = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager", tuned[main_prec], basin=True)
+        rb = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager", tuned[main_prec], basin=True,
+                     simple=args.simple)
         out["basin"] = {"value": rb["roots"] / rb["wall"], "ms_per_step": 1e3 * rb["wall"] / args.steps,
                         "roots_with_basin_per_step": rb["basin"] // args.steps,
                         "what": "the same workload with a proven disk of Newton convergence around every "
                                 "certified root (Thm proofContract, MSPLIT_F_BASIN)"}
     if not args.no_compare:
-        r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager", tuned[other])
+        r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager", tuned[other], simple=args.simple)
         out[other] = {"value": r2["roots"] / r2["wall"], "ms_per_step": 1e3 * r2["wall"] / args.steps,
                       "stage_ms_per_step": {k: v / args.steps for k, v in r2["stages"].items()}}
     if not args.no_p30 and args.workload != "p30":
@@ -287,6 +298,22 @@ def main():
                          "roots_per_step": r3["roots"] // args.p30_steps,
                          "stage_ms_per_step": {k: v / args.p30_steps for k, v in r3["stages"].items()}}
         out["p30"] = {"workload": WORKLOADS["p30"][0], "unit": "certified roots/s", **p30}
+    if not args.no_mis22 and args.workload != "mis22":
+        m22 = {}
+        m_pairs = WORKLOADS["mis22"][1]
+        for route, simple in (("q", False), ("s", True)):
+            tm = {main_prec: None}
+            if not args.no_tune:
+                tm, im = autotune(m_pairs, main_prec, None, args.retune, simple)
+                tune_info["mis22_" + route] = im
+            rm = run_gpu(m_pairs, main_prec, args.steps, args.warmup, "eager", tm[main_prec], simple=simple)
+            m22[route] = {"value": rm["roots"] / rm["wall"], "ms_per_step": 1e3 * rm["wall"] / args.steps,
+                          "roots_per_step": rm["roots"] // args.steps,
+                          "stage_ms_per_step": {k: v / args.steps for k, v in rm["stages"].items()}}
+        m22["s"]["speedup_vs_q"] = m22["q"]["ms_per_step"] / m22["s"]["ms_per_step"]
+        out["mis22"] = {"workload": WORKLOADS["mis22"][0], "unit": "certified roots/s",
+                        "q": dict(m22["q"], polynomial="q_{l,n} = p_{l+n} - p_l"),
+                        "s": dict(m22["s"], polynomial="s_{l,n} = p_{l+n-1} + p_{l-1} (eq. polySimple)")}
     if args.copy_probe:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)

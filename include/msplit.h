@@ -70,8 +70,12 @@ enum msplit_precision {
 enum msplit_flags {
     MSPLIT_F_CERTIFY = 1u, /* run the disk-arithmetic certificate (Thm proofRoots) */
     MSPLIT_F_NO_LABEL = 2u, /* skip period / type classification */
-    MSPLIT_F_BASIN = 4u     /* with MSPLIT_F_CERTIFY and msplit_roots.basin: prove a disk of
+    MSPLIT_F_BASIN = 4u,    /* with MSPLIT_F_CERTIFY and msplit_roots.basin: prove a disk of
                                Newton convergence around every certified root (Thm proofContract) */
+    MSPLIT_F_SIMPLE = 8u    /* Misiurewicz types: find Mis(l,n) among the roots of the simplified
+                               polynomial s_{l,n} = p_{l+n-1} + p_{l-1} = q_{l,n} / q_{l-1,n}
+                               (eq. polySimple: simple roots, half the degree of q_{l,n}); the
+                               certificate still applies Thm proofRoots to q_{l,n} */
 };
 
 /* per-root flag bits written to msplit_roots.flags */

@@ -109,8 +109,8 @@ class BatchRunner:
         return slice(off, off + c)
 
 
-def run_batch(pairs, certify=True, precision="fp64"):
-    opts = msplit.make_options(precision=precision, certify=certify)
+def run_batch(pairs, certify=True, precision="fp64", simple=False):
+    opts = msplit.make_options(precision=precision, certify=certify, simple=simple)
     runner = BatchRunner(pairs, opts)
     r = runner.run()
     torch.cuda.synchronize()

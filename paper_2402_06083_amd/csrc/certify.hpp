@@ -608,8 +608,9 @@ __global__ void __launch_bounds__(256) k_classify(batch_args b, const cd *uz, co
             double hmin2 = INFINITY;
             int kmin = pl.n;
             const bool kq = classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c, hmin2, kmin);
+            // s_{l,n} (el < 0) has simple roots only: no stall next to a centre
             const double w = near_centre_radius(pl.l, kmin);
-            hard = kq && hmin2 < w * w;
+            hard = kq && pl.el > 0 && hmin2 < w * w;
             k = kq ? 1u : 0u;
         }
         if (!hard) {
@@ -643,9 +644,10 @@ __global__ void k_classify_hard(batch_args b, const cd *uz, const cd *uz_lo, con
             bool kq = dd ? classify_q_dd(pl.l, pl.n, pl.divmask_lo, pl.tau_dd, cc, hmin2, kmin)
                          : classify_q(pl.l, pl.n, pl.divmask_lo, pl.tau, c, hmin2, kmin);
             // cheap first: the step ratio of Thm fact_mis in double-double
-            if (kq && !dd && hmin2 < 1e-12 && stalled_at_multiple_root(pl.l, pl.n, kmin, c)) kq = false;
+            const bool multiple = pl.el > 0; // q_{l,n}; s_{l,n} has simple roots only
+            if (multiple && kq && !dd && hmin2 < 1e-12 && stalled_at_multiple_root(pl.l, pl.n, kmin, c)) kq = false;
             const double w = near_centre_radius(pl.l, kmin);
-            if (kq && hmin2 < w * w) {
+            if (multiple && kq && hmin2 < w * w) {
                 cert_result r = {0, 0.0};
                 if (!dd) r = certify_root(pl.l, pl.n, pl.n, pl.divmask_lo, c);
                 if (!(r.flags & 2)) r = certify_root_dd(pl.l, pl.n, pl.n, pl.divmask_lo, cc);

@@ -127,7 +127,9 @@ __device__ __forceinline__ void orbit2_step(orbit2_state<T> &s, T c4r, T c2i)
 
 // P = q_{l,n}(c), dP = q_{l,n}'(c), N = l + n >= 1 (l = 0: p_N).  The orbit
 // starts from its first iterate, p_1 = c and p_1' = 1 (exact), so an
-// evaluation of order N takes N - 1 steps; p_N needs no subtraction.
+// evaluation of order N takes N - 1 steps; p_N needs no subtraction.  A
+// negative l selects a sum: P = z_N + z_{-l}, the simplified polynomial
+// s_{a+1,n} = p_{a+n} + p_a (eq. polySimple) for l = -a, N = a + n.
 template <typename T, typename C>
 __device__ __forceinline__ void eval_q_t(int l, int N, C c, C &P, C &dP)
 {
@@ -140,13 +142,15 @@ __device__ __forceinline__ void eval_q_t(int l, int N, C c, C &P, C &dP)
         dP = {s.dr, s.di};
         return;
     }
+    const int la = l < 0 ? -l : l;
+    const T sg = l < 0 ? T(-1) : T(1);
     int k = 1;
-    for (; k < l; ++k) orbit2_step(s, c4r, c2i);
+    for (; k < la; ++k) orbit2_step(s, c4r, c2i);
     const orbit2_state<T> sl = s;
 #pragma unroll 2
     for (; k < N; ++k) orbit2_step(s, c4r, c2i);
-    P = {T(0.5) * (s.ur - sl.ur), T(0.5) * (s.ui - sl.ui)};
-    dP = {s.dr - sl.dr, s.di - sl.di};
+    P = {T(0.5) * fmat(-sg, sl.ur, s.ur), T(0.5) * fmat(-sg, sl.ui, s.ui)};
+    dP = {fmat(-sg, sl.dr, s.dr), fmat(-sg, sl.di, s.di)};
 }
 
 __device__ __forceinline__ void eval_q(int l, int N, cd c, cd &P, cd &dP) { eval_q_t<double>(l, N, c, P, dP); }

@@ -87,6 +87,7 @@ __device__ __forceinline__ cdd cdd_sqr_add(cdd z, cdd c)
     return {re, im};
 }
 __device__ __forceinline__ cdd cdd_sub(cdd a, cdd b) { DD_EXACT return {dd_sub(a.re, b.re), dd_sub(a.im, b.im)}; }
+__device__ __forceinline__ cdd cdd_neg(cdd a) { return {dd_neg(a.re), dd_neg(a.im)}; }
 __device__ __forceinline__ double cdd_abs2_hi(cdd a) { DD_EXACT return a.re.hi * a.re.hi + a.im.hi * a.im.hi; }
 
 } // namespace msplit

@@ -49,6 +49,8 @@ enum {
 
 struct plan_t {
     int l, n, N;          // type and order N = l + n
+    int el, eN;           // the polynomial P evaluated (eval_q_t): q_{l,n} and p_n are (l, N); the
+                          // simplified s_{l,n} = p_{N-1} + p_{l-1} is (-(l-1), N-1)
     int M;                // fine points per turn
     int q;                // M / 4: fine points between starts
     int cap;              // Newton cap
@@ -194,7 +196,8 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
         steps.t = fail.t = t;
         if (g >= b.n_seeds) continue;
         const plan_t &plr = b.types[t].p;
-        const struct { int l, N; int64_t S, F, q; double level; } pl = {plr.l, plr.N, plr.S, plr.F, plr.q, plr.level};
+        // (l, N) of the evaluated polynomial: its leading term p_N is the last lift
+        const struct { int l, N; int64_t S, F, q; double level; } pl = {plr.el, plr.eN, plr.S, plr.F, plr.q, plr.level};
         bool failed = false;
         const int64_t j = g - b.seed_offs[t];
         const int64_t twoS = 2 * pl.S;
@@ -287,8 +290,8 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
                     t_lo = (uint32_t)b.seg_offs[t];
                     t_hi = (uint32_t)b.seg_offs[t + 1];
                     const plan_t &pl = b.types[t].p;
-                    pl_l = pl.l;
-                    pl_N = pl.N;
+                    pl_l = pl.el;
+                    pl_N = pl.eN;
                     pl_M = pl.M;
                     pl_q = pl.q;
                     pl_F = (int)pl.F;
@@ -411,8 +414,8 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
                 if (t1 != t) {
                     t = t1;
                     const plan_t &pl = b.types[t].p;
-                    pl_l = pl.l;
-                    pl_N = pl.N;
+                    pl_l = pl.el;
+                    pl_N = pl.eN;
                     pl_cap = pl.cap;
                     pl_sw = pl.fp32_switch;
                 }
@@ -527,8 +530,8 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
                     t_lo = (uint32_t)b.start_offs[t];
                     t_hi = (uint32_t)b.start_offs[t + 1];
                     const plan_t &pl = b.types[t].p;
-                    pl_l = pl.l;
-                    pl_N = pl.N;
+                    pl_l = pl.el;
+                    pl_N = pl.eN;
                     pl_cap = pl.cap;
                     pl_tol2 = pl.tol_desc * pl.tol_desc;
                     if (ROUTE) pl_route = pl.x_tip > 0.0;

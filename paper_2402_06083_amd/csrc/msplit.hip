@@ -77,7 +77,12 @@ plan_t make_plan(int l, int n, const msplit_options *o)
     p.l = l;
     p.n = n;
     p.N = l + n;
-    p.D = (int64_t)1 << (p.N - 1);
+    // MSPLIT_F_SIMPLE: Mis(l,n) from the simple roots of s_{l,n} = p_{N-1} +
+    // p_{l-1} = q_{l,n} / q_{l-1,n} (eq. polySimple), half the degree of q_{l,n}
+    const bool simple = l >= 2 && (o->flags & MSPLIT_F_SIMPLE);
+    p.el = simple ? -(l - 1) : l;
+    p.eN = simple ? p.N - 1 : p.N;
+    p.D = (int64_t)1 << (p.eN - 1);
     p.level = o->level > 0 ? o->level : (l == 0 ? 5.0 : 100.0);
     p.M = o->points_per_turn ? (int)o->points_per_turn : 8;
     p.q = p.M / 4;

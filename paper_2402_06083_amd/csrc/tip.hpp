@@ -32,6 +32,8 @@ __device__ __forceinline__ dd dd_div_by(dd a, double b)
 
 __device__ dd_step dd_newton_step(int l, int N, cdd c)
 {
+    // l < 0: P = z_N + z_{-l} (the simplified polynomial, as eval_q_t)
+    const int la = l < 0 ? -l : l;
     cdd z = {{0.0, 0.0}, {0.0, 0.0}}, zl = z;
     double dr = 0.0, di = 0.0, dlr = 0.0, dli = 0.0;
     for (int i = 1; i <= N; ++i) {
@@ -39,7 +41,12 @@ __device__ dd_step dd_newton_step(int l, int N, cdd c)
         dr = 2.0 * tr + 1.0;
         di = 2.0 * ti;
         z = cdd_sqr_add(z, c);
-        if (i == l) { zl = z; dlr = dr; dli = di; }
+        if (i == la) { zl = z; dlr = dr; dli = di; }
+    }
+    if (l < 0) {
+        zl = cdd_neg(zl);
+        dlr = -dlr;
+        dli = -dli;
     }
     const cdd P = cdd_sub(z, zl);
     const double pr = dr - dlr, pi = di - dli;
@@ -177,7 +184,7 @@ __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t
         bool fin = false;
         uint8_t st = ST_TIMEOUT;
         for (int it = 1; it <= cap + 1; ++it) {
-            const dd_step r = dd_newton_step(pl.l, pl.N, z);
+            const dd_step r = dd_newton_step(pl.el, pl.eN, z);
             ++steps.v;
             z = cdd_sub(z, r.s);
             const double a2 = cdd_abs2_hi(r.s), az2 = cdd_abs2_hi(z);

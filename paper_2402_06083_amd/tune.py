@@ -13,7 +13,8 @@ the work distribution, never the set of starting points, Section 4.1):
 Each candidate runs the whole batch through ``msplit_batch`` (device time
 from the call's own events); a candidate whose split is not complete and
 certified is rejected.  The best options are cached per
-(GPU architecture, list of types, precision) in a JSON file:
+(GPU architecture, list of types, precision, polynomial: q_{l,n} or the
+simplified s_{l,n}) in a JSON file:
 ``$MSPLIT_TUNE_CACHE``, else ``~/.cache/msplit/tune.json``.  Lookups also
 read the tunings shipped with the package (``tuned_<arch>.json``, written by
 this module on that GPU); the user's cache takes precedence.
@@ -42,9 +43,9 @@ def cache_path():
     return os.path.join(base, "msplit", "tune.json")
 
 
-def cache_key(arch, pairs, precision):
+def cache_key(arch, pairs, precision, simple=False):
     types = ",".join(f"{l}:{n}" for (l, n) in pairs)
-    return f"{arch}|{precision}|{types}"
+    return f"{arch}|{precision}{'+simple' if simple else ''}|{types}"
 
 
 def load_cache(path=None):
@@ -81,27 +82,27 @@ def candidates(precision, space=None):
         yield dict(zip(keys, vals))
 
 
-def _options(precision, certify, cand):
+def _options(precision, certify, cand, simple=False):
     kw = {k: cand[k] for k in TUNED_FIELDS if k in cand}
-    return msplit.make_options(precision=precision, certify=certify, **kw)
+    return msplit.make_options(precision=precision, certify=certify, simple=simple, **kw)
 
 
 def shipped_path(arch):
     return os.path.join(os.path.dirname(os.path.abspath(__file__)), f"tuned_{arch}.json")
 
 
-def lookup(pairs, precision="fp64", path=None, arch=None):
+def lookup(pairs, precision="fp64", path=None, arch=None, simple=False):
     """Cached options (a dict: options, ms, default_ms) or None: the given
     cache file, else the user's cache, else the tunings shipped for arch."""
     arch = arch or device_arch()
-    key = cache_key(arch, pairs, precision)
+    key = cache_key(arch, pairs, precision, simple)
     if path is not None:
         return load_cache(path).get(key)
     hit = load_cache(cache_path()).get(key)
     return hit if hit is not None else load_cache(shipped_path(arch)).get(key)
 
 
-def tune(pairs, precision="fp64", space=None, repeats=2, path=None, certify=True, verbose=False):
+def tune(pairs, precision="fp64", space=None, repeats=2, path=None, certify=True, verbose=False, simple=False):
     """Time every candidate on the batch and cache the fastest complete one.
     Returns {"best": {...}, "ms": best device ms, "default_ms": ..., "trials": [...]}."""
     import torch
@@ -110,7 +111,7 @@ def tune(pairs, precision="fp64", space=None, repeats=2, path=None, certify=True
     trials = []
     best = None
     for cand in [{}] + list(candidates(precision, space)):
-        opts = _options(precision, certify, cand)
+        opts = _options(precision, certify, cand, simple)
         try:
             runner = batch.BatchRunner(pairs, opts)
         except msplit.MsplitError as e:
@@ -145,21 +146,21 @@ def tune(pairs, precision="fp64", space=None, repeats=2, path=None, certify=True
     if default_ms is not None and default_ms <= t:
         chosen, t = {}, default_ms
     cache = load_cache(path)
-    cache[cache_key(arch, pairs, precision)] = {"options": chosen, "ms": t, "default_ms": default_ms}
+    cache[cache_key(arch, pairs, precision, simple)] = {"options": chosen, "ms": t, "default_ms": default_ms}
     save_cache(cache, path)
     return {"best": chosen, "ms": t, "default_ms": default_ms, "trials": trials}
 
 
-def tuned_options(pairs, precision="fp64", certify=True, path=None):
+def tuned_options(pairs, precision="fp64", certify=True, path=None, simple=False):
     """msplit options for the batch: the cached tuning if present, else the
     defaults."""
     hit = None
     try:
-        hit = lookup(pairs, precision, path)
+        hit = lookup(pairs, precision, path, simple=simple)
     except Exception:
         hit = None
     cand = hit["options"] if hit else {}
-    return _options(precision, certify, cand), cand
+    return _options(precision, certify, cand, simple), cand
 
 
 # named batches for the command line
@@ -176,6 +177,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="tune launch parameters of named batches on this GPU")
     ap.add_argument("--out", default=None, help="cache file to update (default: the user cache)")
     ap.add_argument("--precision", nargs="+", default=["fp64", "mixed"], choices=["fp64", "mixed"])
+    ap.add_argument("--simple", action="store_true",
+                    help="Misiurewicz types through the simplified polynomials s_{l,n}")
     ap.add_argument("batches", nargs="+", choices=sorted(BATCHES))
     a = ap.parse_args(argv)
     for name in a.batches:
@@ -188,13 +191,14 @@ def main(argv=None):
                 if prec == "mixed":
                     space["fp32_switch"] = MIXED_SWITCHES
             try:
-                t = tune(pairs, prec, space=space or None, path=a.out)
+                t = tune(pairs, prec, space=space or None, path=a.out, simple=a.simple)
             except RuntimeError as e:
                 print(f"[tune] {name} {prec}: {e}", flush=True)
                 continue
             if best is None:
                 best = t["best"]
-            print(f"[tune] {name} {prec}: {t['best']} {t['ms']:.3f} ms (defaults {t['default_ms']:.3f} ms)",
+            print(f"[tune] {name} {prec}{' simple' if a.simple else ''}: {t['best']} {t['ms']:.3f} ms "
+                  f"(defaults {t['default_ms']:.3f} ms)",
                   flush=True)
 
 

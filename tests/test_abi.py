@@ -67,7 +67,9 @@ def test_header_constants_match_binding():
     assert m and int(m.group(1)) == msplit.CERTIFY_WORKSPACE
     for name, val in [("MSPLIT_R_REAL", msplit.R_REAL), ("MSPLIT_R_CERTIFIED", msplit.R_CERTIFIED),
                       ("MSPLIT_R_LABEL", msplit.R_LABEL), ("MSPLIT_R_DD", msplit.R_DD), ("MSPLIT_F_CERTIFY", msplit.F_CERTIFY),
-                      ("MSPLIT_F_NO_LABEL", msplit.F_NO_LABEL), ("MSPLIT_E_WORKSPACE", msplit.E_WORKSPACE)]:
+                      ("MSPLIT_F_NO_LABEL", msplit.F_NO_LABEL), ("MSPLIT_F_BASIN", msplit.F_BASIN),
+                      ("MSPLIT_F_SIMPLE", msplit.F_SIMPLE), ("MSPLIT_R_BASIN", msplit.R_BASIN),
+                      ("MSPLIT_E_WORKSPACE", msplit.E_WORKSPACE)]:
         m = re.search(name + r"\s*=\s*(-?\d+)u?", text)
         assert m and int(m.group(1)) == val, name
 

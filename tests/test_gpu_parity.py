@@ -462,6 +462,93 @@ def test_certify_api_basin():
     assert np.array_equal(flags.cpu().numpy() & msplit.R_BASIN, g.flags & msplit.R_BASIN)
 
 
+# ---------------------------------------------------------------------------
+# Mis(l,n) from the simplified polynomial s_{l,n} = p_{l+n-1} + p_{l-1}
+# (eq. polySimple, MSPLIT_F_SIMPLE): the same set as the q_{l,n} route and as
+# the oracle's s route, from half as many starts.
+
+@functools.lru_cache(maxsize=None)
+def oracle_split_simple(l, n):
+    return oracle.split(l, n, simple=True)
+
+
+SIMPLE_SMALL = [(2, 1), (3, 1), (2, 2), (4, 2), (3, 4), (5, 3), (2, 8), (7, 2), (4, 6), (9, 3), (12, 2), (6, 8),
+                (3, 12), (13, 2), (5, 10)]
+
+
+@pytest.mark.parametrize("ln", SIMPLE_SMALL)
+def test_simple_parity_small(ln):
+    """s_{l,n} route: exact count |Mis(l,n)|, start count 2^(l+n-1) + 1 (half
+    the q route's), the oracle's s-route set, and the oracle's q-route set."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    r, g = gpu_split(l, n, simple=True)
+    assert r.status == msplit.OK, (r.status, r.stats)
+    st = r.stats
+    assert st["phase_fail"] == 0 and st["missing"] == 0 and st["total"] == counts.mis_count(l, n), st
+    assert st["starts"] == 2 ** (l + n - 1) + 1, st
+    compare_sets(g, oracle_split_simple(l, n))
+    compare_sets(g, oracle_split(l, n))
+    assert np.all(g.period == n) and np.all(g.preperiod == l)
+
+
+@pytest.mark.parametrize("ln", [(2, 10), (5, 7), (3, 15), (2, 16)])
+def test_simple_certified(ln):
+    """s_{l,n} route with the certificate (Thm proofRoots on q_{l,n}): every
+    root certified with its type proven; at orders 18 and 19 (the tip next to
+    -2 in double-double) the set equals the oracle's q-route set."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    r, g = gpu_split(l, n, certify=True, simple=True)
+    st = r.stats
+    assert r.status == msplit.OK, (r.status, st)
+    assert st["total"] == counts.mis_count(l, n), st
+    assert st["certified"] == len(g) and st["label_proven"] == len(g) and st["overlaps"] == 0, st
+    o = oracle_split(l, n)
+    compare_sets(g, o)
+    rng = np.random.default_rng(l * 100 + n)
+    idx = np.sort(rng.choice(len(g), size=min(2000, len(g)), replace=False))
+    ok, rad = oracle.certify(l, n, g.re[idx], g.im[idx], g.re_lo[idx], g.im_lo[idx])
+    assert np.all(ok == 3) and rad.max() <= 1e-10
+
+
+@pytest.mark.parametrize("ln", [(2, 6), (5, 4), (3, 11)])
+def test_simple_starts_on_level_line(ln):
+    """Start k of the s route has s_{l,n} = lambda_0 i^k (level 100), checked by
+    the oracle's long-double evaluation of s_{l,n}."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    say(f"[gpu] starts s l={l} n={n}")
+    re, im, st, status = msplit.starts(l, n, msplit.make_options(simple=True), check=False)
+    assert status == msplit.OK and st["phase_fail"] == 0, st
+    g = re.cpu().numpy() + 1j * im.cpu().numpy()
+    assert len(g) == 2 ** (l + n - 1) + 1
+    for k in range(0, len(g), max(1, len(g) // 64)):
+        P = oracle.evaluate(l, n, complex(g[k]), simple=True)
+        val = complex(float(P[0]), float(P[1]))
+        assert abs(val / (100 * [1, 1j, -1, -1j][k % 4]) - 1) < 2 ** -5 + 1e-9, k
+
+
+def test_simple_batch_all_pairs():
+    """All 210 types with l + n <= 22 through the s route in one certified
+    batch: exact counts per pair, every root certified, and per pair the same
+    roots as the q-route batch (sorted real parts agree to 1e-12)."""
+    from paper_2402_06083_amd import batch
+    pairs = mis_pairs(22)
+    say("[gpu] batch of all s_{l,n}, l + n <= 22")
+    rs = batch.run_batch(pairs, certify=True, simple=True)
+    rq = batch.run_batch(pairs, certify=True)
+    for i, ((l, n), (count, st, status)) in enumerate(zip(rs.pairs, rs.per_pair)):
+        assert status == 0, ((l, n), status, st)
+        assert st["total"] == counts.mis_count(l, n), ((l, n), st)
+        assert st["certified"] == count and st["label_proven"] == count and st["overlaps"] == 0, ((l, n), st)
+        assert count == rq.per_pair[i][0], (l, n)
+        zs = rs.bufs.re[rs.bufs.slices(i)].cpu().numpy() + 1j * rs.bufs.im[rs.bufs.slices(i)].cpu().numpy()
+        zq = rq.bufs.re[rq.bufs.slices(i)].cpu().numpy() + 1j * rq.bufs.im[rq.bufs.slices(i)].cpu().numpy()
+        zs, zq = np.sort_complex(zs), np.sort_complex(zq)
+        assert np.max(np.abs(zs - zq)) <= 1e-12, (l, n)
+
+
 def test_deterministic_output():
     r1, g1 = gpu_split(0, 17)
     r2, g2 = gpu_split(0, 17)

@@ -20,10 +20,12 @@ def test_cache_key_and_round_trip(tmp_path):
     k1 = tune.cache_key("gfx950", [(0, 1), (0, 2)], "fp64")
     k2 = tune.cache_key("gfx950", [(0, 1), (0, 2)], "mixed")
     k3 = tune.cache_key("gfx950", [(0, 2), (0, 1)], "fp64")
-    assert len({k1, k2, k3}) == 3
+    k4 = tune.cache_key("gfx950", [(0, 1), (0, 2)], "fp64", simple=True)
+    assert len({k1, k2, k3, k4}) == 4
     tune.save_cache({k1: {"options": {"block_size": 128}, "ms": 1.0, "default_ms": 2.0}}, path)
     assert tune.lookup([(0, 1), (0, 2)], "fp64", path=path, arch="gfx950")["options"] == {"block_size": 128}
     assert tune.lookup([(0, 1), (0, 2)], "mixed", path=path, arch="gfx950") is None
+    assert tune.lookup([(0, 1), (0, 2)], "fp64", path=path, arch="gfx950", simple=True) is None
 
 
 def test_corrupt_cache_is_ignored(tmp_path):
@@ -37,3 +39,10 @@ def test_options_from_candidate():
                                       "fp32_switch": 2.0 ** -10})
     assert (o.block_size, o.seg_points, o.points_per_turn, o.fp32_switch) == (128, 64, 16, 2.0 ** -10)
     assert o.flags & 1 and o.precision == 1
+
+
+def test_simple_flag_reaches_options():
+    from paper_2402_06083_amd import msplit
+    o = tune._options("fp64", True, {}, simple=True)
+    assert o.flags & msplit.F_SIMPLE and o.flags & msplit.F_CERTIFY
+    assert not tune._options("fp64", True, {}).flags & msplit.F_SIMPLE
