@@ -41,8 +41,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1226334995.7
-DESCEND_TRAFFIC_SHA256 = "d80164503b9450a1faad93332b745ecc84474a4dfb602d98acf08fbb0f21e168"
+DESCEND_TRAFFIC_BYTES = 1230058788.3
+DESCEND_TRAFFIC_SHA256 = "f4ecc7b1f0cf3f88905dd633ec99b7f7519ec8c7ac9f92baf2c0e7de055e805f"
 
 
 def descend_traffic():
