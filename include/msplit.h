@@ -157,7 +157,8 @@ typedef struct msplit_stats {
      * [4] classification, [5] certificate and separation */
     double ms_stage[6];
     int32_t hip_error;      /* last hipError_t on MSPLIT_E_DEVICE */
-    int32_t reserved;
+    int32_t mark_capped;    /* identification scans that ended on their length bound, not on
+                               the key window (a duplicate may survive; 0 in every tested run) */
     uint64_t basin;         /* roots with MSPLIT_R_BASIN */
     double min_basin;       /* least Newton-basin radius among them */
 } msplit_stats;
@@ -230,6 +231,32 @@ int msplit_batch(const int32_t *ln_pairs, int npairs, const msplit_options *opts
 /* Workspace bytes for msplit_batch over these pairs. */
 int msplit_batch_workspace_size(const int32_t *ln_pairs, int npairs, const msplit_options *opts,
                                 uint64_t *bytes);
+
+/* Split one type whose level line does not fit the device in one pass, p_n
+ * up to n = 33 (the paper's FP80 frontier, Section 6.3.2), streamed: the
+ * upper half of the level line is cut into chunks of about chunk_starts
+ * consecutive starts (0: 2^28), the paper's independent jobs over seed
+ * ranges of one level line (Section 6.4.1).  Each chunk is walked, descended
+ * (FP64, double-double next to -2) and identified on its own; its roots are
+ * accumulated; the roots found from two chunks (the paper's overlap between
+ * jobs) are identified by real-part partitions of the accumulation; the
+ * output is the same sorted, classified and certified set as one pass of
+ * msplit_hyperbolic / msplit_misiurewicz (q_{l,n} stays limited by
+ * MSPLIT_E_PRECISION to order 25).  Valid for n >= 1, l = 0 or l >= 2,
+ * l + n <= 33.  Arguments and errors as msplit_hyperbolic; workspace of
+ * msplit_stream_workspace_size bytes (p_33: about 117 GB with the default
+ * chunks, besides the output, whose capacity must hold the upper-half roots:
+ * 2^31 plus half the real ones).  The host synchronises
+ * once per chunk and per partition.  stats: the sums over the chunks;
+ * sorted = the entries of the chunks' sorts, discarded = roots found from
+ * more than one chunk plus those dropped by the classification. */
+int msplit_split_streamed(int l, int n, const msplit_options *opts, uint64_t chunk_starts, void *workspace,
+                          uint64_t workspace_bytes, msplit_roots *out, uint64_t *count, msplit_stats *stats,
+                          void *stream);
+
+/* Workspace bytes for msplit_split_streamed. */
+int msplit_stream_workspace_size(int l, int n, const msplit_options *opts, uint64_t chunk_starts,
+                                 uint64_t *bytes);
 
 /* A batch captured once as a hipGraph and replayed (the batch scheduling of
  * the paper's job runs, Section 6.4.1, as one device graph): every kernel of

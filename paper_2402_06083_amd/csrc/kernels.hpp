@@ -44,7 +44,8 @@ enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_DD_COUNT, G_HAR
 enum {
     C_CONVERGED = 0, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL, C_SEED_FAIL, C_STEPS_LIFT, C_STEPS_WALK,
     C_STEPS_DESC, C_STEPS_FP32, C_UNIQUE, C_REAL, C_CERTIFIED, C_LABEL, C_OVERLAP, C_MIN_SEP_BITS,
-    C_MAX_RAD_BITS, C_SURVIVORS, C_KEPT, C_DD_ROUTED, C_STEPS_DD, C_BASIN, C_MIN_BASIN_BITS, C_NCOUNTERS = 22
+    C_MAX_RAD_BITS, C_SURVIVORS, C_KEPT, C_DD_ROUTED, C_STEPS_DD, C_BASIN, C_MIN_BASIN_BITS, C_MARK_CAPPED,
+    C_NCOUNTERS = 23
 };
 
 struct plan_t {
@@ -56,8 +57,10 @@ struct plan_t {
     int cap;              // Newton cap
     int64_t D;            // degree 2^(N-1)
     int64_t F;            // fine points per segment
-    int64_t S;            // segments in the upper half plane
-    int64_t NS;           // starts: 2 D + 1
+    int64_t S;            // segments in the upper half plane (the seed angle is pi j / S)
+    int64_t seg0, nseg;   // the segments [seg0, seg0 + nseg) of this item: the whole upper half
+                          // (0, S), or one chunk of it when the level line is streamed
+    int64_t NS;           // starts of this item: nseg F / q, + 1 with the left end (2 D + 1 in all)
     double level;         // lambda_0
     double tau;           // nset identification radius
     double tol_desc;      // relative step of a converged descent
@@ -199,7 +202,8 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
         // (l, N) of the evaluated polynomial: its leading term p_N is the last lift
         const struct { int l, N; int64_t S, F, q; double level; } pl = {plr.el, plr.eN, plr.S, plr.F, plr.q, plr.level};
         bool failed = false;
-        const int64_t j = g - b.seed_offs[t];
+        const int64_t jl = g - b.seed_offs[t]; // seed within the item
+        const int64_t j = jl + plr.seg0;       // seed on the whole line
         const int64_t twoS = 2 * pl.S;
         double sn, cs;
         sincospi((double)j / (double)pl.S, &sn, &cs);
@@ -236,7 +240,8 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
         }
         fail.v += failed;
         seeds[g] = z;
-        starts[b.types[t].start_off + j * (pl.F / pl.q)] = z;
+        // the last seed of a chunk is the next chunk's first start
+        if (jl * (pl.F / pl.q) < plr.NS) starts[b.types[t].start_off + jl * (pl.F / pl.q)] = z;
     }
     flush_count(wc, C_STEPS_LIFT, steps);
     flush_count(wc, C_SEED_FAIL, fail);
@@ -300,7 +305,7 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
                 const uint32_t j = g - t_lo;
                 seed_j = (uint32_t)b.types[t].seed_off + j;
                 start0 = (uint32_t)b.types[t].start_off + j * (uint32_t)(pl_F / pl_q);
-                r0 = (int)(((uint64_t)j * (uint64_t)pl_F) % (uint64_t)pl_M);
+                r0 = (int)(((uint64_t)(j + b.types[t].p.seg0) * (uint64_t)pl_F) % (uint64_t)pl_M);
                 z = seeds[seed_j];
                 s = 1;
                 it = 0;
@@ -690,8 +695,10 @@ __device__ __forceinline__ void load_tables_lds(collect_tables &c, const batch_a
 constexpr int PREKEY_WINDOW = 8;
 constexpr int COLLECT_BLOCK = 256;
 
+// window = 0 keeps every converged start (candidates that are already
+// identified, where only the sort's identification may decide).
 __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const cd *roots, const cd *roots_lo,
-                                                           const uint8_t *status, uint32_t *flag)
+                                                           const uint8_t *status, uint32_t *flag, int window)
 {
     __shared__ collect_tables tabs;
     __shared__ cd zs[COLLECT_BLOCK + PREKEY_WINDOW], zl[COLLECT_BLOCK + PREKEY_WINDOW];
@@ -734,7 +741,7 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
         const cd z = zs[i], lo = zl[i];
         const bool dd = dds[i];
         f = 1;
-        for (int d = 1; d <= PREKEY_WINDOW; ++d) {
+        for (int d = 1; d <= window; ++d) {
             if (ts[i - d] != t) continue;
             if (same_root(z, lo, dd, zs[i - d], zl[i - d], dds[i - d], tau, tdd)) { f = 0; break; }
         }
@@ -802,31 +809,50 @@ __global__ void k_gather(batch_args b, const cd *roots, const cd *roots_lo, cons
 // A sorted point is a duplicate when an earlier point of the same type is the
 // same root (same_root: the nset identification, the first point of a
 // cluster kept).  The backward scan stops at the key window (real parts tau
-// apart) or after 256 points.
+// apart) or after MARK_LOOKBACK points.  The window is crowded only where
+// FP64 keys collapse: next to -2, where the roots of p_n lie about 4^-n apart
+// and each is reached from several starts, some hundred candidates of order
+// 31 share a window.  A scan ended by the bound, not by the window, is
+// counted (C_MARK_CAPPED): a duplicate may survive it.
+constexpr int MARK_LOOKBACK = 4096;
+
 __global__ void k_mark(batch_args b, const uint64_t *keys, const cd *zs, const cd *zs_lo, const uint8_t *zs_dd,
                        uint32_t *flag)
 {
+    unsigned long long *const wc = wave_ctr(b);
     const int64_t m = b.surv_offs[b.T];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
-        const uint64_t ki = keys[i];
-        const int t = key_type(ki);
-        if (t >= b.T) {
-            flag[i] = 1;
-            continue;
+    type_count capped;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        bool cap_hit = false;
+        int t = -1;
+        if (i < m) {
+            const uint64_t ki = keys[i];
+            t = key_type(ki);
+            uint32_t f = 1;
+            if (t < b.T) {
+                const double tau = b.types[t].p.tau, tdd = b.types[t].p.tau_dd;
+                const uint64_t win = key_window(tau);
+                const cd zi = zs[i], li = zs_lo[i];
+                const bool di = zs_dd[i];
+                int c = 0;
+                for (int64_t j = i - 1; j >= 0 && c < MARK_LOOKBACK; --j, ++c) {
+                    const uint64_t kj = keys[j];
+                    if (key_type(kj) != t || ki - kj >= win) break;
+                    if (same_root(zi, li, di, zs[j], zs_lo[j], zs_dd[j], tau, tdd)) { f = 0; break; }
+                }
+                cap_hit = f && c == MARK_LOOKBACK;
+            }
+            flag[i] = f;
         }
-        const double tau = b.types[t].p.tau, tdd = b.types[t].p.tau_dd;
-        const uint64_t win = key_window(tau);
-        const cd zi = zs[i], li = zs_lo[i];
-        const bool di = zs_dd[i];
-        uint32_t f = 1;
-        for (int64_t j = i - 1, c = 0; j >= 0 && c < 256; --j, ++c) {
-            const uint64_t kj = keys[j];
-            if (key_type(kj) != t || ki - kj >= win) break;
-            if (same_root(zi, li, di, zs[j], zs_lo[j], zs_dd[j], tau, tdd)) { f = 0; break; }
+        if (__ballot(cap_hit && t != capped.t)) flush_count(wc, C_MARK_CAPPED, capped);
+        if (cap_hit) {
+            capped.t = t;
+            capped.v += 1;
         }
-        flag[i] = f;
     }
+    flush_count(wc, C_MARK_CAPPED, capped);
 }
 
 // Per type: first index in the collected index space (coll_offs, from the

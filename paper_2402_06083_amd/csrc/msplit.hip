@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 #include "certify.hpp"
 #include "sort.hpp"
+#include "stream.hpp"
 
 using namespace msplit;
 
@@ -100,6 +101,8 @@ plan_t make_plan(int l, int n, const msplit_options *o)
     F = std::max<int64_t>(f2, p.q);
     p.F = F;
     p.S = half / F;
+    p.seg0 = 0;
+    p.nseg = p.S;
     p.NS = 2 * p.D + 1;
     double IN = o->cap_factor > 0 ? o->cap_factor : (l == 0 ? 1.0 : 2.6);
     double capf = ceil(IN * log((double)p.D));
@@ -128,7 +131,9 @@ plan_t make_plan(int l, int n, const msplit_options *o)
         p.tau = 0x1p-44;
         // from order 28 the left end of the level line (about -2 - 14.7 / 4^n)
         // is closer to -2 than the FP64 spacing: re-solve the starts there
-        if (p.N >= 28) p.tip_starts = (int)std::min<int64_t>(p.NS, 4096);
+        // (the FP64 walk failed over the last 320 starts at order 30 and the
+        // last 1088 at order 31: a tip four times larger per order beyond 30)
+        if (p.N >= 28) p.tip_starts = (int)std::min<int64_t>(p.NS, (int64_t)4096 << (2 * std::max(0, p.N - 30)));
         const double a = 128.0 * p.tau * ldexp(1.0, p.N) / (4.0 * M_PI);
         const double x_sat = 128.0 * p.tau / (6e-8 * ldexp(1.0, 26 - p.N));
         p.x_tip = std::max(2.0 * a * a, x_sat);
@@ -188,8 +193,8 @@ int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uin
         d.tip_lo_off = bp.n_tip;
         bp.n_tip += d.p.tip_starts;
         d.cap = caps ? caps[c] : 0;
-        bp.seed_offs[t + 1] = bp.seed_offs[t] + d.p.S + 1;
-        bp.seg_offs[t + 1] = bp.seg_offs[t] + d.p.S;
+        bp.seed_offs[t + 1] = bp.seed_offs[t] + d.p.nseg + 1;
+        bp.seg_offs[t + 1] = bp.seg_offs[t] + d.p.nseg;
         bp.start_offs[t + 1] = bp.start_offs[t] + d.p.NS;
     }
     bp.n_seeds = bp.seed_offs[npairs];
@@ -396,14 +401,10 @@ struct batch_call {
 template <typename P>
 P *ws_at(const batch_call &c, size_t off) { return (P *)(c.ws + off); }
 
-// Validation, plan and layout; no device work.
-int prepare(batch_call &c, const int32_t *ln, int npairs, const msplit_options *opts, void *workspace,
-            uint64_t ws_bytes, const msplit_roots *out, const uint64_t *out_offs, const uint64_t *caps,
-            bool starts_only)
+// Options of a call (no device work).
+int check_options(batch_call &c, const msplit_options *opts, const msplit_roots *out, bool starts_only)
 {
-    if (!workspace || !ln) return MSPLIT_E_ARG;
     if (!starts_only && (!out || !out->re || !out->im)) return MSPLIT_E_ARG;
-    if (!opts) opts = defaults();
     if (opts->struct_size && opts->struct_size != sizeof(msplit_options)) return MSPLIT_E_ARG;
     if (opts->precision < 0 || opts->precision > 2) return MSPLIT_E_ARG;
     if (opts->precision == MSPLIT_DD) return MSPLIT_E_UNSUPPORTED;
@@ -412,9 +413,17 @@ int prepare(batch_call &c, const int32_t *ln, int npairs, const msplit_options *
     if (c.bs % 64 || c.bs > 256) return MSPLIT_E_ARG;
     c.o = *opts;
     if (out) c.out = *out; else memset(&c.out, 0, sizeof(c.out));
-    int r = make_batch(ln, npairs, opts, out_offs, caps, c.bp);
-    if (r) return r;
-    const batch_plan &bp = c.bp;
+    c.cert = !starts_only && (opts->flags & MSPLIT_F_CERTIFY) != 0;
+    if (c.cert && (!out->radius || !out->flags)) return MSPLIT_E_ARG;
+    c.labels = !(opts->flags & MSPLIT_F_NO_LABEL);
+    c.basin = c.cert && (opts->flags & MSPLIT_F_BASIN) && out->basin;
+    return MSPLIT_OK;
+}
+
+// Limits of the plan: the identification radius against FP64 keys, 32-bit
+// item indices, one M per call.
+int check_plan(const batch_plan &bp)
+{
     for (int t = 0; t < bp.T; ++t) {
         // FP64 keys separate the roots only while the identification radius
         // stays well above the FP64 rounding of a root
@@ -424,13 +433,14 @@ int prepare(batch_call &c, const int32_t *ln, int npairs, const msplit_options *
     // every type of one call shares M (the cis table)
     for (int t = 1; t < bp.T; ++t)
         if (bp.td[t].p.M != bp.td[0].p.M) return MSPLIT_E_ARG;
-    c.cert = !starts_only && (opts->flags & MSPLIT_F_CERTIFY) != 0;
-    if (c.cert && (!out->radius || !out->flags)) return MSPLIT_E_ARG;
-    c.labels = !(opts->flags & MSPLIT_F_NO_LABEL);
-    c.basin = c.cert && (opts->flags & MSPLIT_F_BASIN) && out->basin;
-    c.L = make_layout(bp);
-    if (ws_bytes < c.L.total) return MSPLIT_E_WORKSPACE;
-    c.ws = (char *)workspace;
+    return MSPLIT_OK;
+}
+
+// Kernel arguments over the workspace carved by c.L (no device work).
+void setup_args(batch_call &c, char *ws)
+{
+    const batch_plan &bp = c.bp;
+    c.ws = ws;
     const int T = bp.T;
     c.offs.assign(7 * (T + 1), 0);
     std::copy(bp.seed_offs.begin(), bp.seed_offs.end(), c.offs.begin());
@@ -461,7 +471,48 @@ int prepare(batch_call &c, const int32_t *ln, int npairs, const msplit_options *
     c.out_max = 0;
     for (int t = 0; t < T; ++t) c.out_max += (int64_t)std::min<uint64_t>(bp.td[t].cap, (uint64_t)bp.td[t].p.D);
     c.h.assign((size_t)T * C_NCOUNTERS, 0ull);
+}
+
+// Validation, plan and layout; no device work.
+int prepare(batch_call &c, const int32_t *ln, int npairs, const msplit_options *opts, void *workspace,
+            uint64_t ws_bytes, const msplit_roots *out, const uint64_t *out_offs, const uint64_t *caps,
+            bool starts_only)
+{
+    if (!workspace || !ln) return MSPLIT_E_ARG;
+    if (!opts) opts = defaults();
+    int r = check_options(c, opts, out, starts_only);
+    if (r) return r;
+    r = make_batch(ln, npairs, opts, out_offs, caps, c.bp);
+    if (r) return r;
+    r = check_plan(c.bp);
+    if (r) return r;
+    c.L = make_layout(c.bp);
+    if (ws_bytes < c.L.total) return MSPLIT_E_WORKSPACE;
+    setup_args(c, (char *)workspace);
     return MSPLIT_OK;
+}
+
+// One item of a streamed split (a chunk of the level line, or a partition of
+// the candidates: collect_only, no seeds and no segments) on a given layout.
+void plan_item(batch_plan &bp, const plan_t &p, int64_t out_off, uint64_t cap, bool collect_only)
+{
+    bp.T = 1;
+    bp.slot.assign(1, 0);
+    bp.td.resize(1);
+    type_desc &d = bp.td[0];
+    memset(&d, 0, sizeof(d));
+    d.p = p;
+    if (collect_only) d.p.tip_starts = 0;
+    d.out_off = out_off;
+    d.cap = cap;
+    const int64_t nseed = collect_only ? 0 : p.nseg + 1, nseg = collect_only ? 0 : p.nseg;
+    bp.seed_offs = {0, nseed};
+    bp.seg_offs = {0, nseg};
+    bp.start_offs = {0, p.NS};
+    bp.n_seeds = nseed;
+    bp.n_segs = nseg;
+    bp.n_starts = p.NS;
+    bp.n_tip = d.p.tip_starts;
 }
 
 // Type descriptors and item offsets to the workspace (the other offset
@@ -493,121 +544,187 @@ void enqueue_level_line(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
     if (ev) (void)hipEventRecord(ev[1], stream);
     // level-line walk
     k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, ws_at<uint8_t>(c, c.L.segf));
-    if (bp.n_tip > 0) k_refine_tip_starts<<<blocks_for(bp.n_tip, 256), 256, 0, stream>>>(ba, starts, tip_lo, bp.n_tip);
+    if (bp.n_tip > 0) k_lift_tip_starts<<<blocks_for(bp.n_tip, 64), 64, 0, stream>>>(ba, starts, tip_lo, bp.n_tip);
     if (ev) (void)hipEventRecord(ev[2], stream);
+}
+
+// The workspace arrays of the root stages, from the layout.
+struct pipe_bufs {
+    int64_t *isz, *rtile;
+    cd *starts, *zs, *zs_lo, *roots, *roots_lo, *tip_lo;
+    uint8_t *status, *iters;
+    uint32_t *flag0, *pos0, *vals, *vals2, *flag, *pos, *rcounts, *part;
+    uint64_t *keys, *keys2;
+};
+
+pipe_bufs bufs_of(const batch_call &c)
+{
+    pipe_bufs B;
+    B.isz = ws_at<int64_t>(c, c.L.isz);
+    B.rtile = ws_at<int64_t>(c, c.L.rtile);
+    B.starts = ws_at<cd>(c, c.L.starts);
+    B.status = ws_at<uint8_t>(c, c.L.status);
+    B.iters = ws_at<uint8_t>(c, c.L.iters);
+    B.flag0 = ws_at<uint32_t>(c, c.L.flag0);
+    B.pos0 = ws_at<uint32_t>(c, c.L.pos0);
+    B.keys = ws_at<uint64_t>(c, c.L.keys);
+    B.keys2 = ws_at<uint64_t>(c, c.L.keys2);
+    B.zs = ws_at<cd>(c, c.L.zs);
+    B.zs_lo = ws_at<cd>(c, c.L.zs_lo);
+    B.roots = ws_at<cd>(c, c.L.roots);
+    B.roots_lo = ws_at<cd>(c, c.L.roots_lo);
+    B.tip_lo = ws_at<cd>(c, c.L.tip_lo);
+    B.vals = ws_at<uint32_t>(c, c.L.vals);
+    B.vals2 = ws_at<uint32_t>(c, c.L.vals2);
+    B.flag = ws_at<uint32_t>(c, c.L.flag);
+    B.pos = ws_at<uint32_t>(c, c.L.pos);
+    B.rcounts = ws_at<uint32_t>(c, c.L.counts);
+    B.part = ws_at<uint32_t>(c, c.L.part);
+    return B;
+}
+
+// Where the collection leaves the identified roots, and the buffers it frees.
+struct collected {
+    cd *uz, *uz_lo;
+    uint8_t *uz_dd;
+    uint64_t *fkeys;         // the sort's spare key buffer
+    uint32_t *svals, *fvals; // its value buffers (free once gathered)
+};
+
+// Descents from the starts (MIXED: an FP32 pass first), then the
+// double-double route: the routed starts (next to -2, or stalled at the
+// FP64 precision floor) descend again from their starting points (the list
+// lives in flag0 until the collection).
+void enqueue_descents(const batch_call &c, const pipe_bufs &B, hipStream_t stream)
+{
+    const batch_plan &bp = c.bp;
+    const batch_args &ba = c.ba;
+    const int bs = c.bs;
+    auto descend64 = [&](const cd *src, const uint8_t *it) {
+        if (c.any_tip)
+            k_descend<true><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, B.roots, B.status, it);
+        else
+            k_descend<false><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, B.roots, B.status, it);
+    };
+    if (c.o.precision == MSPLIT_MIXED) {
+        k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, B.starts, B.roots, B.status, B.iters);
+        descend64(B.roots, B.iters);
+    } else {
+        descend64(B.starts, nullptr);
+    }
+    if (c.any_tip) {
+        k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, B.roots, B.status, B.flag0);
+        k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, B.flag0, B.starts, B.tip_lo, B.roots, B.roots_lo,
+                                                           B.status);
+    }
+}
+
+// nset collection of the descents' results (roots, roots_lo, status):
+// local identification (window: PREKEY_WINDOW, or 0 for candidates that are
+// already identified), compaction, sort, global identification, and the
+// identified roots in the collected index space (type-major, by real part).
+collected enqueue_collect(const batch_call &c, const pipe_bufs &B, hipStream_t stream, int window)
+{
+    const batch_plan &bp = c.bp;
+    const batch_args &ba = c.ba;
+    const int T = bp.T;
+    const unsigned gs = persistent_blocks(bp.n_starts, 256);
+    k_prekeys<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.roots_lo,
+                                                                                    B.status, B.flag0, window);
+    scan_u32(B.flag0, B.pos0, B.isz + SZ_STARTS, bp.n_starts, B.part, stream);
+    k_compact<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.flag0, B.pos0,
+                                                                                    B.keys, B.vals);
+    uint64_t *skeys = B.keys;
+    uint32_t *svals = B.vals;
+    sort_pairs(&skeys, &svals, B.keys2, B.vals2, ba.surv_offs, B.rtile, T, KEY_BITS, bp.n_starts, B.rcounts,
+               B.isz + SZ_COUNTS, B.part, stream);
+    collected C;
+    C.fkeys = skeys == B.keys ? B.keys2 : B.keys;
+    C.fvals = svals == B.vals ? B.vals2 : B.vals;
+    C.svals = svals;
+    k_gather<<<gs, 256, 0, stream>>>(ba, B.roots, B.roots_lo, B.status, skeys, svals, B.zs, B.zs_lo, B.iters);
+    k_mark<<<gs, 256, 0, stream>>>(ba, skeys, B.zs, B.zs_lo, B.iters, B.flag);
+    scan_u32(B.flag, B.pos, ba.surv_offs + T, bp.n_starts, B.part, stream);
+    k_type_bounds<<<1, 256, 0, stream>>>(ba, B.flag, B.pos);
+    // the starts, the descent results and their status are no longer needed
+    // once gathered
+    C.uz = B.starts;
+    C.uz_lo = B.roots_lo;
+    C.uz_dd = B.status;
+    k_scatter<<<gs, 256, 0, stream>>>(ba, B.flag, B.pos, B.zs, B.zs_lo, B.iters, C.uz, C.uz_lo, C.uz_dd);
+    return C;
+}
+
+// Classification: period labels (p_n), type Mis(l,n) (q_{l,n}); the kept
+// roots go to the caller's slices.  flag0/pos0 and the sort's spare buffers
+// are free here.  key_lo > 0: collected roots with a key below key_lo are
+// not emitted (the look-back margin of a partition of streamed candidates).
+void enqueue_classify(const batch_call &c, const pipe_bufs &B, const collected &C, hipStream_t stream,
+                      uint64_t key_lo = 0)
+{
+    const batch_plan &bp = c.bp;
+    const batch_args &ba = c.ba;
+    const msplit_roots &out = c.out;
+    const int T = bp.T;
+    const unsigned gs = persistent_blocks(bp.n_starts, 256);
+    uint32_t *keep = B.flag0, *kpos = B.pos0;
+    int32_t *cls = (int32_t *)C.fvals;
+    uint32_t *hard = C.svals;
+    k_classify<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, C.uz, C.uz_dd, keep, cls, c.labels ? 1 : 0,
+                                                                 hard);
+    k_classify_hard<<<device_cus() * 4, 256, 0, stream>>>(ba, C.uz, C.uz_lo, C.uz_dd, keep, cls, hard);
+    if (key_lo) k_drop_below<<<gs, 256, 0, stream>>>(ba, C.uz, keep, key_lo);
+    scan_u32(keep, kpos, ba.coll_offs + T, bp.n_starts, B.part, stream);
+    k_kept_bounds<<<1, 256, 0, stream>>>(ba, keep, kpos);
+    k_emit<<<gs, 256, 0, stream>>>(ba, C.uz, C.uz_lo, C.uz_dd, keep, kpos, cls, out.re, out.im, out.re_lo, out.im_lo,
+                                   c.labels ? out.period : nullptr, out.preperiod, out.flags);
+}
+
+// Certificate, separation and Newton basins over the output index space
+// (uniq_offs: min(kept, capacity) roots per type, on the device); n_max
+// bounds the number of roots (grid sizes), hard_c is a list of n_max slots.
+void enqueue_certify(const batch_args &ba, const msplit_roots &out, bool cert, bool labels, bool basin, int T,
+                     int64_t n_max, uint32_t *hard_c, hipStream_t stream)
+{
+    if (n_max <= 0) return;
+    if (cert) {
+        const int32_t *lab = labels ? out.period : nullptr;
+        if (out.re_lo && out.im_lo) {
+            k_certify<true><<<persistent_blocks(n_max, 128), 128, 0, stream>>>(
+                ba, out.re, out.im, out.re_lo, out.im_lo, lab, out.flags, out.radius, hard_c);
+            k_certify_dd<<<device_cus() * 2, 128, 0, stream>>>(ba, out.re, out.im, out.re_lo, out.im_lo, lab,
+                                                               out.flags, out.radius, hard_c);
+        } else {
+            k_certify<false><<<persistent_blocks(n_max, 128), 128, 0, stream>>>(
+                ba, out.re, out.im, nullptr, nullptr, lab, out.flags, out.radius, nullptr);
+        }
+        // k_separation reads the largest radius of each type
+        k_fold_counters<<<fold_blocks(T), 256, 0, stream>>>(ba.ctr, ba.spread, T);
+        k_separation<<<persistent_blocks(n_max, 256), 256, 0, stream>>>(ba, out.re, out.im, out.re_lo, out.im_lo,
+                                                                        out.radius);
+        // Newton basins of the certified roots (Thm proofContract)
+        if (basin)
+            k_basin<<<persistent_blocks(n_max, 128), 128, 0, stream>>>(ba, out.re, out.im, out.re_lo, out.im_lo,
+                                                                       out.flags, out.radius, out.basin);
+    } else {
+        k_separation<<<persistent_blocks(n_max, 256), 256, 0, stream>>>(ba, out.re, out.im, out.re_lo, out.im_lo,
+                                                                        nullptr);
+    }
 }
 
 // Descents, collection, classification, certificate (events ev[3..6]).
 // Every size after the level line is computed and read on the device.
 void enqueue_roots(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
 {
-    const batch_plan &bp = c.bp;
-    const batch_args &ba = c.ba;
-    const msplit_roots &out = c.out;
-    const int T = bp.T, bs = c.bs;
-    int64_t *isz = ws_at<int64_t>(c, c.L.isz);
-    int64_t *rtile = ws_at<int64_t>(c, c.L.rtile);
-    cd *starts = ws_at<cd>(c, c.L.starts);
-    uint8_t *status = ws_at<uint8_t>(c, c.L.status);
-    uint8_t *iters = ws_at<uint8_t>(c, c.L.iters);
-    uint32_t *flag0 = ws_at<uint32_t>(c, c.L.flag0), *pos0 = ws_at<uint32_t>(c, c.L.pos0);
-    uint64_t *keys = ws_at<uint64_t>(c, c.L.keys), *keys2 = ws_at<uint64_t>(c, c.L.keys2);
-    cd *zs = ws_at<cd>(c, c.L.zs), *zs_lo = ws_at<cd>(c, c.L.zs_lo);
-    cd *roots = ws_at<cd>(c, c.L.roots), *roots_lo = ws_at<cd>(c, c.L.roots_lo);
-    cd *tip_lo = ws_at<cd>(c, c.L.tip_lo);
-    uint32_t *vals = ws_at<uint32_t>(c, c.L.vals), *vals2 = ws_at<uint32_t>(c, c.L.vals2);
-    uint32_t *flag = ws_at<uint32_t>(c, c.L.flag), *pos = ws_at<uint32_t>(c, c.L.pos);
-    uint32_t *rcounts = ws_at<uint32_t>(c, c.L.counts), *part = ws_at<uint32_t>(c, c.L.part);
-
-    // descents (MIXED: an FP32 pass first)
-    auto descend64 = [&](const cd *src, const uint8_t *it) {
-        if (c.any_tip)
-            k_descend<true><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, roots, status, it);
-        else
-            k_descend<false><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, roots, status, it);
-    };
-    if (c.o.precision == MSPLIT_MIXED) {
-        k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, starts, roots, status, iters);
-        descend64(roots, iters);
-    } else {
-        descend64(starts, nullptr);
-    }
-    // double-double route: the routed starts (next to -2, or stalled at the
-    // FP64 precision floor) descend again from their starting points (the
-    // list lives in flag0 until the collection)
-    if (c.any_tip) {
-        k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, roots, status, flag0);
-        k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, flag0, starts, tip_lo, roots, roots_lo, status);
-    }
+    const pipe_bufs B = bufs_of(c);
+    enqueue_descents(c, B, stream);
     if (ev) (void)hipEventRecord(ev[3], stream);
-    // nset collection: local identification, compaction, sort, global
-    // identification, per-type output slices
-    const unsigned gs = persistent_blocks(bp.n_starts, 256);
-    k_prekeys<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, roots, roots_lo, status,
-                                                                                    flag0);
-    scan_u32(flag0, pos0, isz + SZ_STARTS, bp.n_starts, part, stream);
-    k_compact<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, roots, flag0, pos0, keys,
-                                                                                    vals);
-    uint64_t *skeys = keys;
-    uint32_t *svals = vals;
-    sort_pairs(&skeys, &svals, keys2, vals2, ba.surv_offs, rtile, T, KEY_BITS, bp.n_starts, rcounts,
-               isz + SZ_COUNTS, part, stream);
-    uint64_t *fkeys = skeys == keys ? keys2 : keys; // the sort's other buffers, free now
-    uint32_t *fvals = svals == vals ? vals2 : vals;
-    k_gather<<<gs, 256, 0, stream>>>(ba, roots, roots_lo, status, skeys, svals, zs, zs_lo, iters);
-    k_mark<<<gs, 256, 0, stream>>>(ba, skeys, zs, zs_lo, iters, flag);
-    scan_u32(flag, pos, ba.surv_offs + T, bp.n_starts, part, stream);
-    k_type_bounds<<<1, 256, 0, stream>>>(ba, flag, pos);
-    // the identified roots into the collected index space; the starts, the
-    // descent results and their status are no longer needed once gathered
-    cd *uz = starts, *uz_lo = roots_lo;
-    uint8_t *uz_dd = status;
-    k_scatter<<<gs, 256, 0, stream>>>(ba, flag, pos, zs, zs_lo, iters, uz, uz_lo, uz_dd);
+    const collected C = enqueue_collect(c, B, stream, PREKEY_WINDOW);
     if (ev) (void)hipEventRecord(ev[4], stream);
-
-    // classification: period labels (p_n), type Mis(l,n) (q_{l,n}); the kept
-    // roots go to the caller's slices.  flag0/pos0 and the sort's spare
-    // buffers are free here.
-    uint32_t *keep = flag0, *kpos = pos0;
-    int32_t *cls = (int32_t *)fvals;
-    uint32_t *hard = svals; // free once gathered
-    k_classify<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, uz, uz_dd, keep, cls, c.labels ? 1 : 0, hard);
-    k_classify_hard<<<device_cus() * 4, 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, cls, hard);
-    scan_u32(keep, kpos, ba.coll_offs + T, bp.n_starts, part, stream);
-    k_kept_bounds<<<1, 256, 0, stream>>>(ba, keep, kpos);
-    k_emit<<<gs, 256, 0, stream>>>(ba, uz, uz_lo, uz_dd, keep, kpos, cls, out.re, out.im, out.re_lo, out.im_lo,
-                                   c.labels ? out.period : nullptr, out.preperiod, out.flags);
+    enqueue_classify(c, B, C, stream);
     if (ev) (void)hipEventRecord(ev[5], stream);
-
-    // certificate and separation over the output index space (uniq_offs,
-    // min(kept, capacity) roots per type, on the device)
-    if (c.out_max > 0) {
-        if (c.cert) {
-            const int32_t *lab = c.labels ? out.period : nullptr;
-            uint32_t *hard_c = (uint32_t *)fkeys;
-            if (out.re_lo && out.im_lo) {
-                k_certify<true><<<persistent_blocks(c.out_max, 128), 128, 0, stream>>>(
-                    ba, out.re, out.im, out.re_lo, out.im_lo, lab, out.flags, out.radius, hard_c);
-                k_certify_dd<<<device_cus() * 2, 128, 0, stream>>>(ba, out.re, out.im, out.re_lo, out.im_lo, lab,
-                                                                   out.flags, out.radius, hard_c);
-            } else {
-                k_certify<false><<<persistent_blocks(c.out_max, 128), 128, 0, stream>>>(
-                    ba, out.re, out.im, nullptr, nullptr, lab, out.flags, out.radius, nullptr);
-            }
-            // k_separation reads the largest radius of each type
-            k_fold_counters<<<fold_blocks(T), 256, 0, stream>>>(ba.ctr, ba.spread, T);
-            k_separation<<<persistent_blocks(c.out_max, 256), 256, 0, stream>>>(ba, out.re, out.im, out.re_lo,
-                                                                                out.im_lo, out.radius);
-            // Newton basins of the certified roots (Thm proofContract)
-            if (c.basin)
-                k_basin<<<persistent_blocks(c.out_max, 128), 128, 0, stream>>>(
-                    ba, out.re, out.im, out.re_lo, out.im_lo, out.flags, out.radius, out.basin);
-        } else {
-            k_separation<<<persistent_blocks(c.out_max, 256), 256, 0, stream>>>(ba, out.re, out.im, out.re_lo,
-                                                                                out.im_lo, nullptr);
-        }
-    }
-    k_fold_counters<<<fold_blocks(T), 256, 0, stream>>>(ba.ctr, ba.spread, T);
+    enqueue_certify(c.ba, c.out, c.cert, c.labels, c.basin, c.bp.T, c.out_max, (uint32_t *)C.fkeys, stream);
+    k_fold_counters<<<fold_blocks(c.bp.T), 256, 0, stream>>>(c.ba.ctr, c.ba.spread, c.bp.T);
     if (ev) (void)hipEventRecord(ev[6], stream);
 }
 
@@ -659,6 +776,7 @@ int finish(batch_call &c, hipStream_t stream, uint64_t *counts, msplit_stats *st
         s.discarded = H(t, C_UNIQUE) - uniq;
         s.dd_routed = H(t, C_DD_ROUTED);
         s.steps_dd = H(t, C_STEPS_DD);
+        s.mark_capped = (int32_t)std::min<uint64_t>(H(t, C_MARK_CAPPED), 0x7fffffff);
         unsigned long long ms_bits = H(t, C_MIN_SEP_BITS), mr_bits = H(t, C_MAX_RAD_BITS);
         unsigned long long mb_bits = H(t, C_MIN_BASIN_BITS);
         memcpy(&s.min_sep, &ms_bits, 8);
@@ -730,6 +848,323 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[6]);
     for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&mss[i], ev.e[i], ev.e[i + 1]);
     return finish(c, stream, counts, stats, ctx, ms, mss);
+}
+
+// --------------------------------------------------------------- streaming
+// One type too large for a single pass (stream.hpp): chunks of the level line
+// (seeds, walk, descents, identification within the chunk) append their
+// roots to an accumulation; partitions of the accumulation by real part are
+// identified, classified and emitted in key order; the certificate runs over
+// the whole output.  Workspace: the accumulation and its tables, then one
+// region shared by the chunk calls, the partition calls and the certificate.
+struct stream_plan {
+    plan_t p;               // the whole type
+    int64_t segs_per_chunk = 0, nchunks = 0, chunk_starts_max = 0;
+    int64_t acc_cap = 0;    // accumulated roots
+    int64_t part_cap = 0;   // candidates of one partition
+    layout LA, LB;          // a chunk call, a partition call
+    size_t acc_off = 0, acc_lo_off = 0, acc_dd_off = 0, tab_off = 0, work_off = 0, hard_off = 0, total = 0;
+};
+
+constexpr int64_t STREAM_DEFAULT_CHUNK = (int64_t)1 << 28;
+
+bool valid_stream_type(int l, int n) { return n >= 1 && l >= 0 && l != 1 && l + n <= 33; }
+
+// The chunk item c of the level line (segments [c s, c s + s), the last
+// chunk up to S with the left end and the tip starts).
+plan_t chunk_item(const stream_plan &z, int64_t c)
+{
+    plan_t q = z.p;
+    q.seg0 = c * z.segs_per_chunk;
+    const bool last = c == z.nchunks - 1;
+    q.nseg = last ? z.p.S - q.seg0 : z.segs_per_chunk;
+    q.NS = q.nseg * (z.p.F / z.p.q) + (last ? 1 : 0);
+    if (!last) q.tip_starts = 0;
+    return q;
+}
+
+int make_stream_plan(int l, int n, const msplit_options *o, uint64_t chunk_starts, stream_plan &z)
+{
+    if (!valid_stream_type(l, n)) return MSPLIT_E_ARG;
+    z.p = make_plan(l, n, o);
+    const plan_t &p = z.p;
+    if (p.tau < 0x1p-50) return MSPLIT_E_PRECISION;
+    const int64_t per_seg = p.F / p.q; // starts per segment
+    int64_t C = chunk_starts ? (int64_t)chunk_starts : STREAM_DEFAULT_CHUNK;
+    if (C < 4 * per_seg || C >= ((int64_t)1 << 31)) return MSPLIT_E_ARG;
+    z.segs_per_chunk = std::max<int64_t>(1, C / per_seg);
+    z.nchunks = (p.S + z.segs_per_chunk - 1) / z.segs_per_chunk;
+    // the last chunk carries the tip starts: fold a short remainder into the
+    // chunk before it
+    if (z.nchunks > 1 && (p.S - (z.nchunks - 1) * z.segs_per_chunk) * per_seg < 2 * (int64_t)p.tip_starts + 2)
+        z.nchunks -= 1;
+    if (z.nchunks > STREAM_MAX_CHUNKS) return MSPLIT_E_ARG;
+    int64_t longest = 0, longest_seg = 0;
+    for (int64_t c = std::max<int64_t>(0, z.nchunks - 2); c < z.nchunks; ++c) {
+        longest = std::max(longest, chunk_item(z, c).NS);
+        longest_seg = std::max(longest_seg, chunk_item(z, c).nseg);
+    }
+    z.chunk_starts_max = longest;
+    if (longest >= ((int64_t)1 << 32)) return MSPLIT_E_UNSUPPORTED;
+    // upper-half roots: D / 2 plus half the real ones (6.3% of the roots of
+    // p_16, fewer from there on), and the repeats between chunks (the roots
+    // reached from both sides of a chunk boundary)
+    z.acc_cap = p.D / 2 + p.D / 16 + 65536;
+    z.part_cap = std::max<int64_t>(1 << 16, longest / 2);
+    batch_plan ba_, bb_;
+    plan_item(ba_, chunk_item(z, z.nchunks - 1), 0, 0, false);
+    ba_.n_starts = longest;
+    ba_.n_seeds = longest_seg + 1;
+    ba_.n_segs = longest_seg;
+    z.LA = make_layout(ba_);
+    plan_t pb = p;
+    pb.NS = z.part_cap;
+    plan_item(bb_, pb, 0, 0, true);
+    z.LB = make_layout(bb_);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o2 = off; off += align256(bytes); return o2; };
+    z.acc_off = take(sizeof(cd) * (size_t)z.acc_cap);
+    z.acc_lo_off = take(sizeof(cd) * (size_t)z.acc_cap);
+    z.acc_dd_off = take((size_t)z.acc_cap);
+    z.tab_off = take(sizeof(int64_t) * (4 * (STREAM_MAX_CHUNKS + 1)) + sizeof(unsigned long long) * STREAM_HIST_BINS);
+    z.work_off = off;
+    // the certificate's hard list after the partition layout's tables
+    z.hard_off = z.LB.seeds;
+    const size_t work = std::max({z.LA.total, z.LB.total, z.hard_off + align256(4 * (size_t)z.acc_cap)});
+    z.total = z.work_off + work;
+    return MSPLIT_OK;
+}
+
+struct stream_events {
+    hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    ~stream_events()
+    {
+        for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    float ms(int i, int j) const
+    {
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e[i], e[j]);
+        return t;
+    }
+};
+
+int run_stream(int l, int n, const msplit_options *opts, uint64_t chunk_starts, void *workspace, uint64_t ws_bytes,
+               msplit_roots *out, uint64_t *count, msplit_stats *stats, void *stream_v)
+{
+    if (count) *count = 0;
+    if (!count || !out || !workspace) return MSPLIT_E_ARG;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (!opts) opts = defaults();
+    stream_plan z;
+    int r = make_stream_plan(l, n, opts, chunk_starts, z);
+    if (r) return r;
+    if (ws_bytes < z.total) return MSPLIT_E_WORKSPACE;
+    {
+        batch_call probe;
+        r = check_options(probe, opts, out, false);
+        if (r) return r;
+    }
+    hipStream_t stream = (hipStream_t)stream_v;
+    call_ctx ctx{stats, 1};
+    char *ws = (char *)workspace;
+    cd *acc = (cd *)(ws + z.acc_off), *acc_lo = (cd *)(ws + z.acc_lo_off);
+    uint8_t *acc_dd = (uint8_t *)(ws + z.acc_dd_off);
+    int64_t *chunk_offs = (int64_t *)(ws + z.tab_off);
+    int64_t *sl = chunk_offs + (STREAM_MAX_CHUNKS + 1);
+    int64_t *pre = sl + 2 * (STREAM_MAX_CHUNKS + 1);
+    unsigned long long *hist = (unsigned long long *)(pre + (STREAM_MAX_CHUNKS + 1));
+    char *work = ws + z.work_off;
+    const plan_t &p = z.p;
+    // stage times from events on the stream, read after each synchronisation
+    stream_events ev;
+    for (hipEvent_t &x : ev.e) CHK(hipEventCreate(&x));
+    float ms_stage[6] = {0, 0, 0, 0, 0, 0};
+    auto H = [](const batch_call &c, int slot) { return c.h[slot]; };
+    uint64_t sum[C_NCOUNTERS] = {0};
+    auto add = [&](const batch_call &c, std::initializer_list<int> slots) {
+        for (int s2 : slots) sum[s2] += H(c, s2);
+    };
+    auto counters_to_host = [&](batch_call &c) -> bool {
+        k_fold_counters<<<fold_blocks(1), 256, 0, stream>>>(c.ba.ctr, c.ba.spread, 1);
+        return ctx.check(hipGetLastError()) &&
+               ctx.check(hipMemcpyAsync(c.h.data(), c.ba.ctr, sizeof(unsigned long long) * c.h.size(),
+                                        hipMemcpyDeviceToHost, stream)) &&
+               ctx.check(hipStreamSynchronize(stream));
+    };
+
+    // chunks of the level line
+    std::vector<int64_t> h_chunk_offs(z.nchunks + 1, 0);
+    int64_t acc_n = 0;
+    for (int64_t ci = 0; ci < z.nchunks; ++ci) {
+        batch_call c;
+        r = check_options(c, opts, out, false);
+        if (r) return r;
+        c.cert = c.basin = false;
+        plan_item(c.bp, chunk_item(z, ci), 0, 0, false);
+        r = check_plan(c.bp);
+        if (r) return r;
+        c.L = z.LA;
+        setup_args(c, work);
+        CHK(upload_tables(c, stream));
+        enqueue_level_line(c, stream, ev.e); // records e[0], e[1], e[2]
+        const pipe_bufs B = bufs_of(c);
+        enqueue_descents(c, B, stream);
+        CHK(hipEventRecord(ev.e[3], stream));
+        const collected C = enqueue_collect(c, B, stream, PREKEY_WINDOW);
+        k_append<<<persistent_blocks(c.bp.n_starts, 256), 256, 0, stream>>>(c.ba, C.uz, C.uz_lo, C.uz_dd, acc, acc_lo,
+                                                                            acc_dd, acc_n, z.acc_cap);
+        CHK(hipEventRecord(ev.e[4], stream));
+        if (!counters_to_host(c)) return ctx.err;
+        for (int i = 0; i < 4; ++i) ms_stage[i] += ev.ms(i, i + 1);
+        const int64_t u = (int64_t)H(c, C_UNIQUE);
+        add(c, {C_CONVERGED, C_DIVERGED, C_TIMEOUT, C_PHASE_FAIL, C_SEED_FAIL, C_STEPS_LIFT, C_STEPS_WALK,
+                C_STEPS_DESC, C_STEPS_FP32, C_DD_ROUTED, C_STEPS_DD, C_SURVIVORS, C_UNIQUE, C_MARK_CAPPED});
+        if (acc_n + u > z.acc_cap) return MSPLIT_E_WORKSPACE;
+        acc_n += u;
+        h_chunk_offs[ci + 1] = acc_n;
+    }
+
+    // partitions of the accumulation by real part: bins of the key histogram,
+    // greedily, each with the bin below it (the look-back margin) within the
+    // partition capacity
+    CHK(hipMemcpyAsync(chunk_offs, h_chunk_offs.data(), sizeof(int64_t) * h_chunk_offs.size(),
+                       hipMemcpyHostToDevice, stream));
+    k_fill_u64<<<blocks_for(STREAM_HIST_BINS, 256), 256, 0, stream>>>(hist, STREAM_HIST_BINS, 0ull);
+    k_key_hist<<<device_cus(), 256, 0, stream>>>(acc, acc_n, hist);
+    std::vector<unsigned long long> hh(STREAM_HIST_BINS);
+    CHK(hipGetLastError());
+    CHK(hipMemcpyAsync(hh.data(), hist, sizeof(unsigned long long) * STREAM_HIST_BINS, hipMemcpyDeviceToHost,
+                       stream));
+    CHK(hipStreamSynchronize(stream));
+    // bounds[k]: first bin of partition k; a partition holds its bins and,
+    // as its look-back margin, at most the bin before its first
+    std::vector<int> bounds = {0};
+    {
+        uint64_t cur = 0;
+        for (int bin = 0; bin < STREAM_HIST_BINS; ++bin) {
+            if (bin > bounds.back() && cur + hh[bin] > (uint64_t)z.part_cap) {
+                bounds.push_back(bin);
+                cur = hh[bin - 1];
+            }
+            cur += hh[bin];
+            if (cur > (uint64_t)z.part_cap) return MSPLIT_E_WORKSPACE; // one bin beyond a partition
+        }
+        bounds.push_back(STREAM_HIST_BINS);
+    }
+    const uint64_t win = 1ull + (uint64_t)ceil(p.tau * 0x1p46); // key_window of the identification radius
+    int64_t out_n = 0;
+    for (size_t k = 0; k + 1 < bounds.size(); ++k) {
+        const uint64_t lo = (uint64_t)bounds[k] << STREAM_HIST_SHIFT;
+        const uint64_t hi = bounds[k + 1] == STREAM_HIST_BINS ? ~0ull : (uint64_t)bounds[k + 1] << STREAM_HIST_SHIFT;
+        const uint64_t lo_w = lo > win ? lo - win : 0;
+        CHK(hipEventRecord(ev.e[0], stream));
+        k_slices<<<blocks_for(2 * z.nchunks, 256), 256, 0, stream>>>(acc, chunk_offs, (int)z.nchunks, lo_w, hi, sl);
+        k_slice_prefix<<<1, 64, 0, stream>>>(sl, (int)z.nchunks, pre);
+        int64_t m = 0;
+        CHK(hipGetLastError());
+        CHK(hipMemcpyAsync(&m, pre + z.nchunks, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        CHK(hipStreamSynchronize(stream));
+        if (m > z.part_cap) return MSPLIT_E_WORKSPACE;
+        if (m == 0) continue;
+        batch_call c;
+        r = check_options(c, opts, out, false);
+        if (r) return r;
+        c.cert = c.basin = false;
+        plan_t pk = p;
+        pk.NS = m;
+        const uint64_t cap = out->capacity > (uint64_t)out_n ? out->capacity - (uint64_t)out_n : 0;
+        plan_item(c.bp, pk, out_n, cap, true);
+        c.L = z.LB;
+        setup_args(c, work);
+        CHK(upload_tables(c, stream));
+        const pipe_bufs B = bufs_of(c);
+        k_init_counters<<<blocks_for((int64_t)C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
+            c.ba.gctr, c.ba.ctr, c.ba.spread, 1, B.isz, m);
+        k_select<<<persistent_blocks(m, 256), 256, 0, stream>>>(acc, acc_lo, acc_dd, sl, pre, (int)z.nchunks, m,
+                                                                B.roots, B.roots_lo, B.status);
+        const collected C = enqueue_collect(c, B, stream, 0);
+        CHK(hipEventRecord(ev.e[1], stream));
+        enqueue_classify(c, B, C, stream, lo);
+        CHK(hipEventRecord(ev.e[2], stream));
+        if (!counters_to_host(c)) return ctx.err;
+        ms_stage[3] += ev.ms(0, 1);
+        ms_stage[4] += ev.ms(1, 2);
+        const int64_t kept = (int64_t)H(c, C_KEPT);
+        add(c, {C_KEPT, C_REAL, C_MARK_CAPPED});
+        if ((uint64_t)(out_n + kept) > out->capacity) {
+            out_n += kept;
+            *count = (uint64_t)out_n;
+            return MSPLIT_E_CAPACITY;
+        }
+        out_n += kept;
+    }
+
+    // certificate and separation over the whole output
+    batch_call c;
+    r = check_options(c, opts, out, false);
+    if (r) return r;
+    {
+        plan_t pc = p;
+        pc.NS = 0;
+        plan_item(c.bp, pc, 0, (uint64_t)out_n, true);
+        c.L = z.LB;
+        setup_args(c, work);
+        CHK(hipEventRecord(ev.e[0], stream));
+        CHK(upload_tables(c, stream));
+        const int64_t uo[2] = {0, out_n};
+        CHK(hipMemcpyAsync(c.ba.uniq_offs, uo, sizeof(uo), hipMemcpyHostToDevice, stream));
+        k_init_counters<<<blocks_for((int64_t)C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
+            c.ba.gctr, c.ba.ctr, c.ba.spread, 1, nullptr, 0);
+        enqueue_certify(c.ba, c.out, c.cert, c.labels, c.basin, 1, out_n, (uint32_t *)(work + z.hard_off), stream);
+        CHK(hipEventRecord(ev.e[1], stream));
+        if (!counters_to_host(c)) return ctx.err;
+        ms_stage[5] += ev.ms(0, 1);
+    }
+    *count = (uint64_t)out_n;
+    const uint64_t uniq = (uint64_t)out_n, nreal = sum[C_REAL];
+    const uint64_t total = nreal + 2 * (uniq - nreal);
+    const uint64_t expected = p.l == 0 ? (uint64_t)p.D : (uint64_t)mis_count(p.l, p.n);
+    if (stats) {
+        msplit_stats &s = *stats;
+        s.starts = (uint64_t)(2 * p.D + 1);
+        s.converged = sum[C_CONVERGED];
+        s.diverged = sum[C_DIVERGED];
+        s.timeouts = sum[C_TIMEOUT];
+        s.unique = uniq;
+        s.n_real = nreal;
+        s.total = total;
+        s.expected = expected;
+        s.missing = expected > total ? expected - total : 0;
+        s.phase_fail = sum[C_PHASE_FAIL] + sum[C_SEED_FAIL];
+        s.certified = H(c, C_CERTIFIED);
+        s.label_proven = H(c, C_LABEL);
+        s.overlaps = H(c, C_OVERLAP);
+        s.steps_lift = sum[C_STEPS_LIFT];
+        s.steps_walk = sum[C_STEPS_WALK];
+        s.steps_desc = sum[C_STEPS_DESC];
+        s.steps_fp32 = sum[C_STEPS_FP32];
+        s.sorted = sum[C_SURVIVORS];
+        s.discarded = sum[C_UNIQUE] - uniq;
+        s.dd_routed = sum[C_DD_ROUTED];
+        s.steps_dd = sum[C_STEPS_DD];
+        s.mark_capped = (int32_t)std::min<uint64_t>(sum[C_MARK_CAPPED], 0x7fffffff);
+        unsigned long long ms_bits = H(c, C_MIN_SEP_BITS), mr_bits = H(c, C_MAX_RAD_BITS),
+                           mb_bits = H(c, C_MIN_BASIN_BITS);
+        memcpy(&s.min_sep, &ms_bits, 8);
+        memcpy(&s.max_radius, &mr_bits, 8);
+        s.basin = H(c, C_BASIN);
+        memcpy(&s.min_basin, &mb_bits, 8);
+        if (!s.basin) s.min_basin = 0.0;
+        float all = 0.f;
+        for (int i = 0; i < 6; ++i) {
+            s.ms_stage[i] = ms_stage[i];
+            all += ms_stage[i];
+        }
+        s.ms_device = all;
+    }
+    return total == expected ? MSPLIT_OK : MSPLIT_E_INCOMPLETE;
 }
 
 // A batch captured as one hipGraph: every kernel of a call from the counter
@@ -860,6 +1295,23 @@ int msplit_batch(const int32_t *ln_pairs, int npairs, const msplit_options *opts
     for (int i = 1; i < npairs; ++i) offs[i] = offs[i - 1] + caps[i - 1];
     return run_batch(ln_pairs, npairs, opts, workspace, workspace_bytes, out, offs.data(), caps, counts, stats,
                      stream);
+}
+
+int msplit_stream_workspace_size(int l, int n, const msplit_options *opts, uint64_t chunk_starts, uint64_t *bytes)
+{
+    if (!bytes) return MSPLIT_E_ARG;
+    stream_plan z;
+    int r = make_stream_plan(l, n, opts ? opts : defaults(), chunk_starts, z);
+    if (r) return r;
+    *bytes = z.total;
+    return MSPLIT_OK;
+}
+
+int msplit_split_streamed(int l, int n, const msplit_options *opts, uint64_t chunk_starts, void *workspace,
+                          uint64_t workspace_bytes, msplit_roots *out, uint64_t *count, msplit_stats *stats,
+                          void *stream)
+{
+    return run_stream(l, n, opts, chunk_starts, workspace, workspace_bytes, out, count, stats, stream);
 }
 
 int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *workspace, uint64_t workspace_bytes,

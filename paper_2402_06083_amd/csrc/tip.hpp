@@ -57,15 +57,45 @@ __device__ dd_step dd_newton_step(int l, int N, cdd c)
     return {{dd_div_by(nr, d2), dd_div_by(ni, d2)}, d2};
 }
 
-// Starts at the left tip.  From order about 28 on the level line passes
-// -2 closer than the FP64 spacing there (its left end lies near
-// -2 - 14.7 / 4^n): the last starts of the upper half plane, start k with
-// P = lambda_0 i^k, collapse onto the same FP64 values.  Each of the last
-// tip_starts starts is re-solved in double-double, Newton on P(z) = T_k with
-// the exact target T_k = lambda_0 i^k from its FP64 value: the high part
-// replaces the start, the low part goes to tip_lo (read by the
-// double-double descent).
-__global__ void k_refine_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t n_tip)
+// P(z) and P'(z) of the polynomial (l, N) of eval_q_t: P in double-double,
+// P' in FP64.
+__device__ void dd_eval(int l, int N, cdd c, cdd &P, cd &dP)
+{
+    const int la = l < 0 ? -l : l;
+    cdd z = {{0.0, 0.0}, {0.0, 0.0}}, zl = z;
+    double dr = 0.0, di = 0.0, dlr = 0.0, dli = 0.0;
+    for (int i = 1; i <= N; ++i) {
+        const double tr = z.re.hi * dr - z.im.hi * di, ti = z.re.hi * di + z.im.hi * dr;
+        dr = 2.0 * tr + 1.0;
+        di = 2.0 * ti;
+        z = cdd_sqr_add(z, c);
+        if (i == la) { zl = z; dlr = dr; dli = di; }
+    }
+    if (l < 0) {
+        zl = cdd_neg(zl);
+        dlr = -dlr;
+        dli = -dli;
+    }
+    P = l ? cdd_sub(z, zl) : z;
+    dP = {dr - dlr, di - dli};
+}
+
+// Starts at the left tip.  From order about 28 on the level line passes -2
+// closer than the FP64 spacing there (its left end lies near
+// -2 - 14.7 / 4^n): the fine points of the FP64 walk collapse onto the same
+// values, the walk loses its way over the last segments (5 of them at order
+// 30, 17 at order 31) and the starts it leaves there are not on the right
+// branch of the level line.  Each of the last tip_starts starts is instead
+// lifted on its own in double-double, like a seed (Section 4.2): from the
+// circle |p_1| = lambda_0 at the start's own angle pi a / (S F) (a = its
+// fine-point index) through every level p_2 .. p_N, the angle doubling at
+// each level, Newton with target in log form; at the last level the target
+// is the start's exact value lambda_0 i^k and the point is polished to
+// double-double accuracy by Newton on P - T.  The high part replaces the
+// start, the low part goes to tip_lo (read by the double-double descent).
+// A start whose lift fails becomes NaN (its descent then ends as divergent)
+// and is counted in C_SEED_FAIL.
+__global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t n_tip)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_tip) return;
@@ -75,34 +105,63 @@ __global__ void k_refine_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_
     const plan_t &pl = td.p;
     const int64_t j = i - td.tip_lo_off;
     if (j >= pl.tip_starts) return;
-    const int64_t k = pl.NS - pl.tip_starts + j; // start index within the type
+    const int64_t k = pl.NS - pl.tip_starts + j;    // start index within the item
+    const int64_t kg = k + pl.seg0 * (pl.F / pl.q); // on the whole line: P = lambda_0 i^kg
     const int64_t g = td.start_off + k;
-    const double tr[4] = {pl.level, 0.0, -pl.level, 0.0}, ti[4] = {0.0, pl.level, 0.0, -pl.level};
-    const double Tr = tr[k & 3], Ti = ti[k & 3];
-    const cd s0 = starts[g];
-    cdd z = {{s0.re, 0.0}, {s0.im, 0.0}};
-    for (int it = 0; it < 16; ++it) {
-        // P - T in double-double, P' in FP64 (dd_newton_step of P - T)
-        cdd w = {{0.0, 0.0}, {0.0, 0.0}}, wl = w;
-        double dr = 0.0, di = 0.0, dlr = 0.0, dli = 0.0;
-        for (int m = 1; m <= pl.N; ++m) {
-            const double a = w.re.hi * dr - w.im.hi * di, c = w.re.hi * di + w.im.hi * dr;
-            dr = 2.0 * a + 1.0;
-            di = 2.0 * c;
-            w = cdd_sqr_add(w, z);
-            if (m == pl.l) { wl = w; dlr = dr; dli = di; }
+    const bool real_end = kg == 0 || kg == 2 * pl.D;
+    const int64_t Sp = pl.S * pl.F, twoSp = 2 * Sp; // fine points of the upper half
+    const double lam = pl.level;
+    int64_t a = (kg * pl.q) % twoSp;
+    auto circle = [&](int64_t x) -> cd {
+        double sn, cs;
+        sincospi((double)x / (double)Sp, &sn, &cs);
+        if (x == 0) return {lam, 0.0};
+        if (x == Sp) return {-lam, 0.0};
+        return {lam * cs, lam * sn};
+    };
+    const cd z0 = circle(a);
+    cdd z = {{z0.re, 0.0}, {z0.im, 0.0}};
+    const int top = pl.el ? pl.eN + 1 : pl.eN;
+    bool ok = true;
+    for (int lev = 2; lev <= top && ok; ++lev) {
+        int ll = 0, NN = lev;
+        if (lev <= pl.eN) a = (2 * a) % twoSp;
+        else { ll = pl.el; NN = pl.eN; }
+        const cd T = circle(a);
+        const bool last = lev == top;
+        ok = false;
+        for (int it = 0; it < 48; ++it) {
+            cdd P;
+            cd dP;
+            dd_eval(ll, NN, z, P, dP);
+            const cd Ph = {P.re.hi, P.im.hi};
+            if (!cfinite(Ph) || !cfinite(dP)) break;
+            const cd w = cdiv(T, Ph);
+            const cd v = {w.re - 1.0, w.im};
+            if (!last && cabs2(v) < 0x1p-10) { ok = true; break; }
+            if (last && cabs2(v) < 0x1p-40) {
+                // polish: Newton on P - T, the residual in double-double
+                const cdd r = {dd_add_d(P.re, -T.re), dd_add_d(P.im, -T.im)};
+                const double d2 = dP.re * dP.re + dP.im * dP.im;
+                if (!(d2 > 0.0)) break;
+                const dd nr = dd_add(dd_mul_d(r.re, dP.re), dd_mul_d(r.im, dP.im));
+                const dd ni = dd_sub(dd_mul_d(r.im, dP.re), dd_mul_d(r.re, dP.im));
+                const cdd st = {dd_div_by(nr, d2), dd_div_by(ni, d2)};
+                z = cdd_sub(z, st);
+                if (real_end) z.im = {0.0, 0.0};
+                if (cdd_abs2_hi(st) <= 0x1p-200 * fmax(cdd_abs2_hi(z), 0x1p-16)) { ok = true; break; }
+                continue;
+            }
+            const cd h = cmul(clog_near1(w), cdiv(Ph, dP));
+            z.re = dd_add_d(z.re, h.re);
+            z.im = dd_add_d(z.im, h.im);
+            if (real_end) z.im = {0.0, 0.0};
         }
-        cdd P = cdd_sub(w, wl);
-        P.re = dd_add_d(P.re, -Tr);
-        P.im = dd_add_d(P.im, -Ti);
-        const double pr = dr - dlr, pi = di - dli, d2 = pr * pr + pi * pi;
-        if (!(d2 > 0.0) || !isfinite(d2)) break;
-        const dd nr = dd_add(dd_mul_d(P.re, pr), dd_mul_d(P.im, pi));
-        const dd ni = dd_sub(dd_mul_d(P.im, pr), dd_mul_d(P.re, pi));
-        const cdd st = {dd_div_by(nr, d2), dd_div_by(ni, d2)};
-        z = cdd_sub(z, st);
-        if (k == 0 || k == pl.NS - 1) z.im = {0.0, 0.0}; // the real end points
-        if (cdd_abs2_hi(st) <= 0x1p-200 * fmax(cdd_abs2_hi(z), 0x1p-16)) break;
+    }
+    if (!ok) {
+        const double nan = __longlong_as_double(0x7ff8000000000000ll);
+        z = {{nan, 0.0}, {nan, 0.0}};
+        atomicAdd(&wave_ctr(b)[(int64_t)t * C_NCOUNTERS + C_SEED_FAIL], 1ull);
     }
     starts[g] = {z.re.hi, z.im.hi};
     tip_lo[i] = {z.re.lo, z.im.lo};

@@ -56,14 +56,14 @@ class Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in _STAT_U64] + [
         ("min_sep", ctypes.c_double), ("max_radius", ctypes.c_double), ("ms_device", ctypes.c_double),
         ("ms_stage", ctypes.c_double * 6),
-        ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("hip_error", ctypes.c_int32), ("mark_capped", ctypes.c_int32),
         ("basin", ctypes.c_uint64), ("min_basin", ctypes.c_double),
     ]
 
     STAGES = ("seeds", "walk", "descend", "collect", "classify", "certify")
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "ms_stage")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("ms_stage",)}
         d["ms_stage"] = dict(zip(self.STAGES, list(self.ms_stage)))
         return d
 
@@ -108,13 +108,18 @@ def lib():
     L.msplit_graph_launch.restype = i32
     L.msplit_graph_destroy.argtypes = [vp]
     L.msplit_graph_destroy.restype = None
+    L.msplit_split_streamed.argtypes = [i32, i32, pOpt, u64, vp, u64, pRoots, pu64, pStats, vp]
+    L.msplit_split_streamed.restype = i32
+    L.msplit_stream_workspace_size.argtypes = [i32, i32, pOpt, u64, pu64]
+    L.msplit_stream_workspace_size.restype = i32
     _lib = L
     return L
 
 
 EXPORTED = ["msplit_strerror", "msplit_expected_count", "msplit_workspace_size", "msplit_hyperbolic",
             "msplit_misiurewicz", "msplit_certify", "msplit_batch", "msplit_batch_workspace_size",
-            "msplit_starts", "msplit_batch_graph", "msplit_graph_launch", "msplit_graph_destroy"]
+            "msplit_starts", "msplit_batch_graph", "msplit_graph_launch", "msplit_graph_destroy",
+            "msplit_split_streamed", "msplit_stream_workspace_size"]
 
 
 def strerror(status: int) -> str:
@@ -192,25 +197,26 @@ class _Host:
 class Buffers:
     """Reusable device buffers for repeated splits of one type (benchmarks)."""
 
-    def __init__(self, l, n, opts, device="cuda"):
+    def __init__(self, l, n, opts, device="cuda", ws_bytes=None, cap=None, preperiod=True):
         self.l, self.n, self.opts = l, n, opts
-        self.ws_bytes = workspace_size(l, n, opts)
+        self.ws_bytes = workspace_size(l, n, opts) if ws_bytes is None else ws_bytes
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
-        cap = 1 << (l + n - 1)
+        cap = cap or 1 << (l + n - 1)
         self.cap = cap
         self.re = torch.empty(cap, dtype=torch.float64, device=device)
         self.im = torch.empty(cap, dtype=torch.float64, device=device)
         self.re_lo = torch.empty(cap, dtype=torch.float64, device=device)
         self.im_lo = torch.empty(cap, dtype=torch.float64, device=device)
         self.period = torch.empty(cap, dtype=torch.int32, device=device)
-        self.preperiod = torch.empty(cap, dtype=torch.int32, device=device)
+        self.preperiod = torch.empty(cap, dtype=torch.int32, device=device) if preperiod else None
         self.flags = torch.empty(cap, dtype=torch.uint8, device=device)
         self.radius = torch.empty(cap, dtype=torch.float64, device=device)
         self.basin = torch.empty(cap, dtype=torch.float64, device=device) if opts.flags & F_BASIN else None
 
     def roots_struct(self):
         return RootsC(self.re.data_ptr(), self.im.data_ptr(), self.re_lo.data_ptr(), self.im_lo.data_ptr(),
-                      self.period.data_ptr(), self.preperiod.data_ptr(), self.flags.data_ptr(),
+                      self.period.data_ptr(), self.preperiod.data_ptr() if self.preperiod is not None else None,
+                      self.flags.data_ptr(),
                       self.radius.data_ptr(), self.cap,
                       self.basin.data_ptr() if self.basin is not None else None)
 
@@ -232,10 +238,52 @@ def split(l: int, n: int, opts: Options = None, buffers: Buffers = None, stream=
     c = int(cnt.value)
     if check and r not in (OK,):
         raise MsplitError(r, f"split({l},{n})")
+    return _result(l, n, opts, b, c, st, r)
+
+
+def _result(l, n, opts, b, c, st, r):
+    c = min(c, b.cap)
     certified = bool(opts.flags & F_CERTIFY)
     return Result(l, n, b.re[:c], b.im[:c], b.period[:c], b.flags[:c], b.radius[:c] if certified else None, c,
-                  st.as_dict(), r, preperiod=b.preperiod[:c], re_lo=b.re_lo[:c], im_lo=b.im_lo[:c],
-                  basin=b.basin[:c] if b.basin is not None else None)
+                  st.as_dict(), r, preperiod=b.preperiod[:c] if b.preperiod is not None else None,
+                  re_lo=b.re_lo[:c], im_lo=b.im_lo[:c], basin=b.basin[:c] if b.basin is not None else None)
+
+
+def stream_workspace_size(l: int, n: int, opts: Options = None, chunk_starts: int = 0) -> int:
+    b = ctypes.c_uint64()
+    r = lib().msplit_stream_workspace_size(l, n, ctypes.byref(opts or make_options()), chunk_starts, ctypes.byref(b))
+    if r:
+        raise MsplitError(r, f"msplit_stream_workspace_size({l},{n})")
+    return int(b.value)
+
+
+def stream_capacity(l: int, n: int) -> int:
+    """Output slots a streamed split needs: the upper-half roots (half the
+    degree plus half the real roots) with a margin."""
+    d = 1 << (l + n - 1)
+    return d // 2 + d // 16 + 65536
+
+
+def stream_buffers(l: int, n: int, opts: Options = None, chunk_starts: int = 0, device="cuda"):
+    opts = opts or make_options()
+    return Buffers(l, n, opts, device, ws_bytes=stream_workspace_size(l, n, opts, chunk_starts),
+                   cap=stream_capacity(l, n), preperiod=False)
+
+
+def split_streamed(l: int, n: int, opts: Options = None, chunk_starts: int = 0, buffers: Buffers = None,
+                   stream=None, check=True) -> Result:
+    """Split one type chunk by chunk (msplit_split_streamed): p_n up to n = 33."""
+    opts = opts or make_options()
+    b = buffers or stream_buffers(l, n, opts, chunk_starts)
+    rs = b.roots_struct()
+    cnt = ctypes.c_uint64()
+    st = Stats()
+    r = lib().msplit_split_streamed(l, n, ctypes.byref(opts), chunk_starts, ctypes.c_void_p(b.ws.data_ptr()),
+                                    b.ws_bytes, ctypes.byref(rs), ctypes.byref(cnt), ctypes.byref(st),
+                                    _stream_handle(stream))
+    if check and r not in (OK,):
+        raise MsplitError(r, f"split_streamed({l},{n})")
+    return _result(l, n, opts, b, int(cnt.value), st, r)
 
 
 def hyperbolic(n: int, **kw) -> Result:
