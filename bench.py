@@ -41,8 +41,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1230058788.3
-DESCEND_TRAFFIC_SHA256 = "f4ecc7b1f0cf3f88905dd633ec99b7f7519ec8c7ac9f92baf2c0e7de055e805f"
+DESCEND_TRAFFIC_BYTES = 1231183586.8
+DESCEND_TRAFFIC_SHA256 = "c55474754b55775a4c14a780cf3da1659a0914f97f4b639921e92c07d7b58803"
 
 
 def descend_traffic():
@@ -177,6 +177,32 @@ def autotune(pairs, prec, other, retune=False, simple=False):
     return tuned, info
 
 
+def run_streamed(n, steps=1, warmup=1):
+    """p_n streamed (msplit_split_streamed) with buffers allocated once; wall
+    time of the steps (one host synchronisation per chunk and partition)."""
+    import torch
+    from paper_2402_06083_amd import msplit
+    opts = msplit.make_options(certify=True)
+    b = msplit.stream_buffers(0, n, opts)
+    for _ in range(warmup):
+        msplit.split_streamed(0, n, opts, buffers=b, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = msplit.split_streamed(0, n, opts, buffers=b, check=False)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    st = r.stats
+    ok = r.status == 0 and st["certified"] == st["unique"]
+    res = {"value": (st["total"] if ok else 0) / wall, "ms_per_step": 1e3 * wall, "status": r.status,
+           "roots": st["total"], "certified_upper_half": st["certified"], "dd_routed": st["dd_routed"],
+           "stage_ms": {k: round(v, 1) for k, v in st["ms_stage"].items()},
+           "workspace_bytes": b.ws_bytes}
+    del r, b
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline():
     """The oracle as it stands on this host's cores, on a bounded sample of
     the same workload: p_1..p_20 split and every root certified."""
@@ -204,6 +230,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-p30", action="store_true", help="skip the period-30 measurement")
     ap.add_argument("--p30-steps", type=int, default=2)
+    ap.add_argument("--no-frontier", action="store_true",
+                    help="skip the streamed splits of p_31, p_32 and p_33")
+    ap.add_argument("--frontier", type=int, nargs="+", default=[31, 32, 33],
+                    help="orders of the streamed splits")
     ap.add_argument("--no-mis22", action="store_true",
                     help="skip the Misiurewicz batch (q_{l,n} and s_{l,n} routes)")
     ap.add_argument("--simple", action="store_true",
@@ -314,6 +344,10 @@ def main():
         out["mis22"] = {"workload": WORKLOADS["mis22"][0], "unit": "certified roots/s",
                         "q": dict(m22["q"], polynomial="q_{l,n} = p_{l+n} - p_l"),
                         "s": dict(m22["s"], polynomial="s_{l,n} = p_{l+n-1} + p_{l-1} (eq. polySimple)")}
+    if not args.no_frontier:
+        out["frontier"] = {"unit": "certified roots/s", "workload": "p_n split chunk by chunk "
+                           "(msplit_split_streamed, chunks of 2^28 starts), every root certified",
+                           **{f"p{n}": run_streamed(n) for n in args.frontier}}
     if args.copy_probe:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
