@@ -298,6 +298,10 @@ def main():
                      "traffic_unit": "bytes per launch",
                      "kernel_ms_per_step": tms / args.steps},
         "stage_ms_per_step": {k: v / args.steps for k, v in res["stages"].items()},
+        # the other evaluation-bound kernel, same accounting
+        "walk": {"kernel": "k_walk", "tflops": res["walk"] / (res["t_walk"] * 1e-3) / 1e12 if res["t_walk"] else 0.0,
+                 "frac": res["walk"] / (res["t_walk"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS if res["t_walk"] else 0.0,
+                 "evaluations_per_step": sum(st["steps_walk"] for st in res["last_stats"])},
     }
     if not args.no_graph:
         rg = run_gpu(pairs, main_prec, args.steps, args.warmup, "graph", tuned[main_prec], simple=args.simple)

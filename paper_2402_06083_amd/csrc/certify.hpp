@@ -106,8 +106,12 @@ struct cert_result { uint8_t flags; double R; };
 // rounding noise of a root, rounded up to a power of two; then one fused pass
 // carries the centres, the point radii e and the disk radii rho, sigma.
 // If the test fails, R grows by 16 (two more attempts).
-__device__ cert_result certify_root(int l, int n, int lab, uint32_t divmask_n, cd c)
+// P_ONLY: a p_n-only instance (l = 0), without the registers of the q_{l,n}
+// label tests.
+template <bool P_ONLY = false>
+__device__ cert_result certify_root(int l_arg, int n, int lab, uint32_t divmask_n, cd c)
 { DD_EXACT
+    const int l = P_ONLY ? 0 : l_arg;
     const int N = l + n;
     cd P0, dP0;
     eval_q(l, N, c, P0, dP0);
@@ -390,7 +394,7 @@ __device__ __noinline__ cert_result certify_root_dd(int l, int n, int lab, uint3
 // certificate; MSPLIT_R_DD marks it.  With a hard list (list non-null)
 // those candidates are appended to it for k_certify_dd instead, so that
 // this kernel keeps the registers of the FP64 certificate alone.
-template <bool HARD_LIST>
+template <bool HARD_LIST, bool P_ONLY = false>
 __global__ void k_certify(batch_args b, const double *re, const double *im, const double *re_lo,
                           const double *im_lo, const int32_t *period, uint8_t *flags, double *radius, uint32_t *list)
 {
@@ -420,7 +424,7 @@ __global__ void k_certify(batch_args b, const double *re, const double *im, cons
             const cd lo = re_lo && im_lo ? cd{re_lo[i], im_lo[i]} : cd{0.0, 0.0};
             const bool has_lo = lo.re != 0.0 || lo.im != 0.0;
             cert_result r = {0, 0.0};
-            if (!has_lo) r = certify_root(td.p.l, td.p.n, lab, td.p.divmask_lo, c);
+            if (!has_lo) r = certify_root<P_ONLY>(td.p.l, td.p.n, lab, td.p.divmask_lo, c);
             const bool use_dd = re_lo && im_lo && (has_lo || !(r.flags & 2));
             hard = HARD_LIST && use_dd;
             if (!hard) {

@@ -143,14 +143,15 @@ __device__ __forceinline__ void eval_q_t(int l, int N, C c, C &P, C &dP)
         return;
     }
     const int la = l < 0 ? -l : l;
-    const T sg = l < 0 ? T(-1) : T(1);
     int k = 1;
     for (; k < la; ++k) orbit2_step(s, c4r, c2i);
-    const orbit2_state<T> sl = s;
+    // the subtracted term, negated for the sum (no sign kept live in the loop)
+    orbit2_state<T> sl = s;
+    if (l < 0) sl = {-s.ur, -s.ui, -s.dr, -s.di};
 #pragma unroll 2
     for (; k < N; ++k) orbit2_step(s, c4r, c2i);
-    P = {T(0.5) * fmat(-sg, sl.ur, s.ur), T(0.5) * fmat(-sg, sl.ui, s.ui)};
-    dP = {fmat(-sg, sl.dr, s.dr), fmat(-sg, sl.di, s.di)};
+    P = {T(0.5) * (s.ur - sl.ur), T(0.5) * (s.ui - sl.ui)};
+    dP = {s.dr - sl.dr, s.di - sl.di};
 }
 
 __device__ __forceinline__ void eval_q(int l, int N, cd c, cd &P, cd &dP) { eval_q_t<double>(l, N, c, P, dP); }

@@ -273,8 +273,10 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
     bool exhausted = false;
     int t = -1;
     uint32_t t_lo = 0, t_hi = 0;
+    // M and q are the same for every type of a call (wave-uniform)
+    const int pl_M = b.types[0].p.M, pl_q = b.types[0].p.q;
     // the fields of the current type's plan that the walk uses
-    int pl_l = 0, pl_N = 1, pl_M = 8, pl_q = 2, pl_F = 1;
+    int pl_l = 0, pl_N = 1, pl_F = 1;
     double pl_level = 5.0;
     uint32_t seed_j = 0;  // global index of the segment's first seed
     uint32_t start0 = 0;  // global start index of fine point j F of the segment
@@ -297,8 +299,6 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
                     const plan_t &pl = b.types[t].p;
                     pl_l = pl.el;
                     pl_N = pl.eN;
-                    pl_M = pl.M;
-                    pl_q = pl.q;
                     pl_F = (int)pl.F;
                     pl_level = pl.level;
                 }
@@ -566,9 +566,13 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
         const double a2 = cabs2(d);
         const double az2 = cabs2(z);
         const bool bad = !(a2 <= 0x1p1000) || !(az2 <= 64.0) || (it > it0 + 3 && a2 > 64.0 * prev);
+        // converged once a step is small.  At a simple root the next step
+        // would be about K |d|^2 with K = |d| / |d_prev|^2 (quadratic
+        // convergence): when that is below the FP64 rounding of z the point
+        // is final, else one more step is taken (the certificate settles the
+        // accuracy a posteriori, Section 4.2)
         const bool small = a2 <= pl_tol2 * fmax(az2, 0x1p-16);
-        const uint8_t st = fin ? (stall ? ST_STALL : ST_CONVERGED)
-                               : bad ? ST_DIVERGED : (!small && it >= pl_cap) ? ST_TIMEOUT : ST_NONE;
+        const bool done = small && a2 * a2 * a2 <= 0x1p-106 * fmax(az2, 0x1p-16) * prev * prev;
         // a simple root is met by a step far below the one before (quadratic
         // convergence); a descent that creeps onto close roots or meets the
         // test on rounding noise does not, and is redone in double-double
@@ -578,6 +582,8 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
             const bool ill = cabs2(dP) * fmax(az2, 0x1p-16) > 0x1p84;
             stall = pl_route && (slow || ill);
         }
+        const uint8_t st = fin || done ? (stall ? ST_STALL : ST_CONVERGED)
+                                       : bad ? ST_DIVERGED : (!small && it >= pl_cap) ? ST_TIMEOUT : ST_NONE;
         fin = small;
         prev = a2;
         cnt[0] += 1u;

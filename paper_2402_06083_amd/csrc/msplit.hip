@@ -683,15 +683,20 @@ void enqueue_classify(const batch_call &c, const pipe_bufs &B, const collected &
 // Certificate, separation and Newton basins over the output index space
 // (uniq_offs: min(kept, capacity) roots per type, on the device); n_max
 // bounds the number of roots (grid sizes), hard_c is a list of n_max slots.
+// p_only: every type is some p_n (the certificate's p_n-only instance).
 void enqueue_certify(const batch_args &ba, const msplit_roots &out, bool cert, bool labels, bool basin, int T,
-                     int64_t n_max, uint32_t *hard_c, hipStream_t stream)
+                     int64_t n_max, uint32_t *hard_c, hipStream_t stream, bool p_only = false)
 {
     if (n_max <= 0) return;
     if (cert) {
         const int32_t *lab = labels ? out.period : nullptr;
         if (out.re_lo && out.im_lo) {
-            k_certify<true><<<persistent_blocks(n_max, 128), 128, 0, stream>>>(
-                ba, out.re, out.im, out.re_lo, out.im_lo, lab, out.flags, out.radius, hard_c);
+            if (p_only)
+                k_certify<true, true><<<persistent_blocks(n_max, 128), 128, 0, stream>>>(
+                    ba, out.re, out.im, out.re_lo, out.im_lo, lab, out.flags, out.radius, hard_c);
+            else
+                k_certify<true><<<persistent_blocks(n_max, 128), 128, 0, stream>>>(
+                    ba, out.re, out.im, out.re_lo, out.im_lo, lab, out.flags, out.radius, hard_c);
             k_certify_dd<<<device_cus() * 2, 128, 0, stream>>>(ba, out.re, out.im, out.re_lo, out.im_lo, lab,
                                                                out.flags, out.radius, hard_c);
         } else {
@@ -723,7 +728,9 @@ void enqueue_roots(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
     if (ev) (void)hipEventRecord(ev[4], stream);
     enqueue_classify(c, B, C, stream);
     if (ev) (void)hipEventRecord(ev[5], stream);
-    enqueue_certify(c.ba, c.out, c.cert, c.labels, c.basin, c.bp.T, c.out_max, (uint32_t *)C.fkeys, stream);
+    bool p_only = true;
+    for (const type_desc &d : c.bp.td) p_only = p_only && d.p.l == 0;
+    enqueue_certify(c.ba, c.out, c.cert, c.labels, c.basin, c.bp.T, c.out_max, (uint32_t *)C.fkeys, stream, p_only);
     k_fold_counters<<<fold_blocks(c.bp.T), 256, 0, stream>>>(c.ba.ctr, c.ba.spread, c.bp.T);
     if (ev) (void)hipEventRecord(ev[6], stream);
 }
@@ -1117,7 +1124,8 @@ int run_stream(int l, int n, const msplit_options *opts, uint64_t chunk_starts, 
         CHK(hipMemcpyAsync(c.ba.uniq_offs, uo, sizeof(uo), hipMemcpyHostToDevice, stream));
         k_init_counters<<<blocks_for((int64_t)C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
             c.ba.gctr, c.ba.ctr, c.ba.spread, 1, nullptr, 0);
-        enqueue_certify(c.ba, c.out, c.cert, c.labels, c.basin, 1, out_n, (uint32_t *)(work + z.hard_off), stream);
+        enqueue_certify(c.ba, c.out, c.cert, c.labels, c.basin, 1, out_n, (uint32_t *)(work + z.hard_off), stream,
+                        p.l == 0);
         CHK(hipEventRecord(ev.e[1], stream));
         if (!counters_to_host(c)) return ctx.err;
         ms_stage[5] += ev.ms(0, 1);

@@ -252,8 +252,15 @@ __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t
                 st = ST_DIVERGED;
                 break;
             }
-            if (a2 <= 0x1p-196 * fmax(az2, 0x1p-16)) fin = true;
-            else if (it >= cap) break;
+            // converged once a step is below 2^-98 |z|; final at once when the
+            // next step predicted by quadratic convergence, |d|^3 / |d_prev|^2,
+            // is below the double-double rounding, else after one more step
+            if (a2 <= 0x1p-196 * fmax(az2, 0x1p-16)) {
+                if (a2 * a2 * a2 <= 0x1p-212 * fmax(az2, 0x1p-16) * prev * prev) { st = ST_DD; break; }
+                fin = true;
+            } else if (it >= cap) {
+                break;
+            }
             prev = a2;
         }
         roots[g] = {z.re.hi, z.im.hi};
