@@ -195,49 +195,49 @@ __global__ void __launch_bounds__(SC_BLOCK) k_rs_upsweep(const uint64_t *keys, r
     }
 }
 
-// Stable scatter of every tile: ranks within the tile by rows (a row is
-// SC_BLOCK consecutive items, ranked by wave with 8 ballots and by LDS
-// counts across the waves and the rows before), then the tile is reordered
-// by digit in LDS so that consecutive threads write consecutive addresses.
+// Stable scatter of every tile.  Wave w ranks its own RS_WAVE_ITEMS
+// consecutive items of the tile (rows of 64, 8 ballots per row) against
+// wave-private digit counts in LDS -- the lanes of one wave need no barrier
+// between rows, LDS operations of a wave complete in order -- then the waves'
+// counts are combined (exclusive over the waves per digit, exclusive over
+// the digits for the tile), and the tile is reordered by digit in LDS so that
+// consecutive threads write consecutive addresses.  Six barriers per tile.
+constexpr int RS_WAVE_ITEMS = RS_TILE / (SC_BLOCK / 64);
+constexpr int RS_WAVE_ROWS = RS_WAVE_ITEMS / 64;
+static_assert(RS_WAVE_ROWS * 64 * (SC_BLOCK / 64) == RS_TILE, "whole rows per wave");
+
 __global__ void __launch_bounds__(SC_BLOCK) k_rs_downsweep(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                            uint32_t *vout, rs_segs s, int shift,
                                                            const uint32_t *offs)
 {
     __shared__ int64_t sseg[MAX_SEGS + 1], stile[MAX_SEGS + 1];
-    __shared__ uint32_t run[RS_BINS], loc[RS_BINS];
-    __shared__ uint32_t gbase[RS_BINS];
-    __shared__ uint32_t wcnt[2][SC_BLOCK / 64][RS_BINS];
+    __shared__ uint32_t loc[RS_BINS], gbase[RS_BINS];
+    __shared__ uint32_t wh[SC_BLOCK / 64][RS_BINS]; // per-wave digit counts, then the bases of each wave
     __shared__ uint32_t wsum[4];
     __shared__ uint64_t sk[RS_TILE];
     __shared__ uint32_t sv[RS_TILE];
     rs_load_tables(sseg, stile, s);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int u = 0; u < SC_BLOCK / 64; ++u) wh[u][threadIdx.x] = 0u;
     __syncthreads();
-    const int w = threadIdx.x >> 6;
     const int64_t total = stile[s.T], m = sseg[s.T];
     for (int64_t i = blockIdx.x; i < total; i += gridDim.x) {
         const int t = rs_find(stile, s.T, i);
         const int64_t j = i - stile[t], nt = stile[t + 1] - stile[t];
         const int64_t lo = sseg[t] + j * RS_TILE, hi = min(lo + RS_TILE, sseg[t + 1]);
         const int n_tile = (int)(hi - lo);
-        uint64_t kk[RS_ROWS];
-        uint32_t vv[RS_ROWS], rk[RS_ROWS];
+        uint64_t kk[RS_WAVE_ROWS];
+        uint32_t vv[RS_WAVE_ROWS], rk[RS_WAVE_ROWS];
 #pragma unroll
-        for (int k = 0; k < RS_ROWS; ++k) {
-            const int64_t g = lo + (int64_t)k * SC_BLOCK + threadIdx.x;
-            kk[k] = g < hi ? kin[g] : 0ull;
-            vv[k] = g < hi ? vin[g] : 0u;
+        for (int r = 0; r < RS_WAVE_ROWS; ++r) {
+            const int idx = w * RS_WAVE_ITEMS + r * 64 + lane;
+            kk[r] = idx < n_tile ? kin[lo + idx] : 0ull;
+            vv[r] = idx < n_tile ? vin[lo + idx] : 0u;
         }
-        run[threadIdx.x] = 0u;
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int u = 0; u < SC_BLOCK / 64; ++u) wcnt[b][u][threadIdx.x] = 0u;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < RS_ROWS; ++k) {
-            const int buf = k & 1;
-            const bool valid = k * SC_BLOCK + (int)threadIdx.x < n_tile;
-            const uint32_t d = (uint32_t)(kk[k] >> shift) & 255u;
+        for (int r = 0; r < RS_WAVE_ROWS; ++r) {
+            const bool valid = w * RS_WAVE_ITEMS + r * 64 + lane < n_tile;
+            const uint32_t d = (uint32_t)(kk[r] >> shift) & 255u;
             uint64_t peers = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
@@ -246,40 +246,41 @@ __global__ void __launch_bounds__(SC_BLOCK) k_rs_downsweep(const uint64_t *kin, 
                 peers &= bit ? bb : ~bb;
             }
             const uint32_t below = lanes_below(peers);
-            if (valid && below == 0u) wcnt[buf][w][d] = (uint32_t)__popcll(peers);
-            __syncthreads();
-            uint32_t r = run[d] + below;
-#pragma unroll
-            for (int u = 0; u < SC_BLOCK / 64; ++u) r += u < w ? wcnt[buf][u][d] : 0u;
-            rk[k] = (d << 16) | r;
-            __syncthreads();
-            // fold the row into the running counts; clear its buffer (the
-            // next row writes the other one, the row after waits for the
-            // next row's first barrier)
-            uint32_t add = 0u;
-#pragma unroll
-            for (int u = 0; u < SC_BLOCK / 64; ++u) {
-                add += wcnt[buf][u][threadIdx.x];
-                wcnt[buf][u][threadIdx.x] = 0u;
-            }
-            run[threadIdx.x] += add;
+            // every lane reads its digit's count before the digit's first
+            // lane writes the count after this row
+            const uint32_t base = wh[w][d];
+            rk[r] = (d << 16) | (base + below);
+            if (valid && below == 0u) wh[w][d] = base + (uint32_t)__popcll(peers);
         }
         __syncthreads();
+        // thread = digit: bases of the waves, the tile's count
+        uint32_t acc = 0u;
+#pragma unroll
+        for (int u = 0; u < SC_BLOCK / 64; ++u) {
+            const uint32_t c = wh[u][threadIdx.x];
+            wh[u][threadIdx.x] = acc;
+            acc += c;
+        }
         uint32_t tot;
-        loc[threadIdx.x] = block_excl_sum(run[threadIdx.x], wsum, tot);
+        loc[threadIdx.x] = block_excl_sum(acc, wsum, tot);
         gbase[threadIdx.x] = offs[RS_BINS * stile[t] + (int64_t)threadIdx.x * nt + j];
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < RS_ROWS; ++k) {
-            if (k * SC_BLOCK + (int)threadIdx.x < n_tile) {
-                const uint32_t p = loc[rk[k] >> 16] + (rk[k] & 0xffffu);
+        for (int r = 0; r < RS_WAVE_ROWS; ++r) {
+            if (w * RS_WAVE_ITEMS + r * 64 + lane < n_tile) {
+                const uint32_t d = rk[r] >> 16;
+                const uint32_t p = loc[d] + wh[w][d] + (rk[r] & 0xffffu);
                 if (p < (uint32_t)RS_TILE) {
-                    sk[p] = kk[k];
-                    sv[p] = vv[k];
+                    sk[p] = kk[r];
+                    sv[p] = vv[r];
                 }
             }
         }
         __syncthreads();
+        // the counts start from zero for the next tile (read above, before
+        // the barrier)
+#pragma unroll
+        for (int u = 0; u < SC_BLOCK / 64; ++u) wh[u][threadIdx.x] = 0u;
 #pragma unroll
         for (int k = 0; k < RS_ROWS; ++k) {
             const int p = k * SC_BLOCK + (int)threadIdx.x;
