@@ -41,8 +41,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1231183586.8
-DESCEND_TRAFFIC_SHA256 = "c55474754b55775a4c14a780cf3da1659a0914f97f4b639921e92c07d7b58803"
+DESCEND_TRAFFIC_BYTES = 1247570122.0
+DESCEND_TRAFFIC_SHA256 = "a38b83c1fb10f80c5e68186e85ee0bcb9aeb7e6c5bd440135fd1edc7832ea02c"
 
 
 def descend_traffic():
