@@ -202,73 +202,96 @@ __global__ void k_route_tip(batch_args b, const cd *roots, const uint8_t *status
 }
 
 // Double-double Newton descent of the routed starts, from their starting
-// points: same outcome rules as the FP64 descent (Algorithm S_par), converged
-// when the step falls below 2^-98 max(|z|, 2^-8), then one more step.  Next
-// to two roots at distance s, Newton from distance d >> s contracts only by
-// one half per step (the pair acts like a double root), so reaching a pair
-// 1e-20 apart from 1e-2 takes about 60 steps: the cap is DD_CAP, which the
-// few routed starts make cheap.  Work list length read on the device.
+// points: same outcome rules as the FP64 descent (Algorithm S_par),
+// converged when a step falls below 2^-98 max(|z|, 2^-8).  Next to two
+// roots at distance s, Newton from distance d >> s contracts only by one half
+// per step (the pair acts like a double root), so reaching a pair 1e-20
+// apart from 1e-2 takes about 60 steps, against about 12 on average: the cap
+// is DD_CAP, and the lanes take the routed starts from a per-wave work queue
+// (as the FP64 descent), so that a lane whose descent ends takes the next
+// start instead of idling until the slowest lane of its wave finishes.
+// Work list length read on the device.
 constexpr int DD_CAP = 256;
 
 __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t *list, const cd *starts,
                                                     const cd *tip_lo, cd *roots, cd *roots_lo, uint8_t *status)
 {
+    constexpr int64_t NONE = -1;
     unsigned long long *const wc = wave_ctr(b);
     const uint64_t n = b.gctr[G_DD_COUNT];
-    type_count steps, routed;
-    type_cache tc;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < (int64_t)n; i0 += stride) {
-        const int64_t i = i0 + threadIdx.x;
-        const int64_t g = i < (int64_t)n ? (int64_t)list[i] : -1;
-        const int t = g >= 0 ? cached_type(tc, b.start_offs, b.T, g) : steps.t;
-        if (__ballot(g >= 0 && t != steps.t)) {
-            flush_count(wc, C_STEPS_DD, steps);
-            flush_count(wc, C_DD_ROUTED, routed);
-        }
-        steps.t = routed.t = t;
-        if (g < 0) continue;
-        routed.v += 1;
-        const plan_t &pl = b.types[t].p;
-        const cd s0 = starts[g];
-        cdd z = {{s0.re, 0.0}, {s0.im, 0.0}};
-        const int64_t k = g - b.types[t].start_off;
-        if (k >= pl.NS - pl.tip_starts) { // a start re-solved in double-double
-            const cd lo = tip_lo[b.types[t].tip_lo_off + (k - (pl.NS - pl.tip_starts))];
-            z.re.lo = lo.re;
-            z.im.lo = lo.im;
-        }
-        const int cap = DD_CAP;
-        double prev = 0.0;
-        bool fin = false;
-        uint8_t st = ST_TIMEOUT;
-        for (int it = 1; it <= cap + 1; ++it) {
-            const dd_step r = dd_newton_step(pl.el, pl.eN, z);
-            ++steps.v;
-            z = cdd_sub(z, r.s);
-            const double a2 = cdd_abs2_hi(r.s), az2 = cdd_abs2_hi(z);
-            if (fin) { st = ST_DD; break; }
-            if (!(a2 <= 0x1p1000) || !(az2 <= 64.0) || !(r.d2 > 0.0) || (it > 3 && a2 > 64.0 * prev)) {
-                st = ST_DIVERGED;
-                break;
+    // per-lane counts of type ct: double-double steps, routed starts
+    int ct = -1;
+    uint32_t cnt[4] = {0u, 0u, 0u, 0u};
+    const int slots[4] = {C_STEPS_DD, C_DD_ROUTED, C_STEPS_DD, C_STEPS_DD};
+    int64_t g = NONE;
+    bool exhausted = false;
+    int t = -1, el = 0, eN = 1, it = 0;
+    bool fin = false;
+    double prev = 0.0;
+    cdd z = {{0.0, 0.0}, {0.0, 0.0}};
+    wave_queue wq = {0, 0};
+    while (true) {
+        const bool need = !exhausted && g == NONE;
+        const uint64_t got = __ballot(need) ? wave_take(wq, &b.gctr[G_DD_NEXT], 64, need) : ~0ull;
+        if (need) {
+            if (got >= n) {
+                exhausted = true;
+            } else {
+                g = (int64_t)list[got];
+                t = find_type(b.start_offs, b.T, g);
+                const type_desc &td = b.types[t];
+                el = td.p.el;
+                eN = td.p.eN;
+                const cd s0 = starts[g];
+                z = {{s0.re, 0.0}, {s0.im, 0.0}};
+                const int64_t k = g - td.start_off;
+                if (k >= td.p.NS - td.p.tip_starts) { // a start lifted in double-double
+                    const cd lo = tip_lo[td.tip_lo_off + (k - (td.p.NS - td.p.tip_starts))];
+                    z.re.lo = lo.re;
+                    z.im.lo = lo.im;
+                }
+                it = 0;
+                fin = false;
+                prev = 0.0;
             }
-            // converged once a step is below 2^-98 |z|; final at once when the
-            // next step predicted by quadratic convergence, |d|^3 / |d_prev|^2,
-            // is below the double-double rounding, else after one more step
-            if (a2 <= 0x1p-196 * fmax(az2, 0x1p-16)) {
-                if (a2 * a2 * a2 <= 0x1p-212 * fmax(az2, 0x1p-16) * prev * prev) { st = ST_DD; break; }
-                fin = true;
-            } else if (it >= cap) {
-                break;
-            }
-            prev = a2;
         }
-        roots[g] = {z.re.hi, z.im.hi};
-        roots_lo[g] = {z.re.lo, z.im.lo};
-        status[g] = st;
+        const bool change = g != NONE && t != ct;
+        if (__ballot(change)) {
+            wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
+            cnt[0] = cnt[1] = 0u;
+            if (change) ct = t;
+        }
+        if (__ballot(g != NONE || !exhausted) == 0) break;
+        if (g == NONE) continue;
+        cnt[1] += it == 0;
+        const dd_step r = dd_newton_step(el, eN, z);
+        ++it;
+        cnt[0] += 1u;
+        z = cdd_sub(z, r.s);
+        const double a2 = cdd_abs2_hi(r.s), az2 = cdd_abs2_hi(z);
+        uint8_t st = ST_NONE;
+        if (fin) {
+            st = ST_DD;
+        } else if (!(a2 <= 0x1p1000) || !(az2 <= 64.0) || !(r.d2 > 0.0) || (it > 3 && a2 > 64.0 * prev)) {
+            st = ST_DIVERGED;
+        } else if (a2 <= 0x1p-196 * fmax(az2, 0x1p-16)) {
+            // final at once when the next step predicted by quadratic
+            // convergence, |d|^3 / |d_prev|^2, is below the double-double
+            // rounding, else after one more step
+            if (a2 * a2 * a2 <= 0x1p-212 * fmax(az2, 0x1p-16) * prev * prev) st = ST_DD;
+            else fin = true;
+        } else if (it >= DD_CAP) {
+            st = ST_TIMEOUT;
+        }
+        prev = a2;
+        if (st != ST_NONE) {
+            roots[g] = {z.re.hi, z.im.hi};
+            roots_lo[g] = {z.re.lo, z.im.lo};
+            status[g] = st;
+            g = NONE;
+        }
     }
-    flush_count(wc, C_STEPS_DD, steps);
-    flush_count(wc, C_DD_ROUTED, routed);
+    wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
 }
 
 } // namespace msplit
