@@ -560,6 +560,7 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
         if (g == NONE) continue;
         cd P, dP;
         eval_q_wave(pl_l, pl_N, z, P, dP);
+        const double dp2 = ROUTE ? cabs2(dP) : 0.0; // |P'|^2 for the routing test (P' dies here)
         const cd d = cdiv_fast(P, dP);
         z = csub(z, d);
         ++it;
@@ -581,7 +582,7 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
         // (precision routing: progress stalled at the precision floor)
         if (ROUTE && small && !fin) {
             const bool slow = it > it0 + 1 && 64.0 * a2 > prev;
-            const bool ill = cabs2(dP) * fmax(az2, 0x1p-16) > 0x1p84;
+            const bool ill = dp2 * fmax(az2, 0x1p-16) > 0x1p84;
             stall = pl_route && (slow || ill);
         }
         const uint8_t st = fin || done ? (stall ? ST_STALL : ST_CONVERGED)
