@@ -447,9 +447,13 @@ __global__ void k_certify(batch_args b, const double *re, const double *im, cons
 }
 
 // The double-double certificates of the hard list of k_certify<true>.
-__global__ void k_certify_dd(batch_args b, const double *re, const double *im, const double *re_lo,
-                             const double *im_lo, const int32_t *period, uint8_t *flags, double *radius,
-                             const uint32_t *list)
+// An FP64 root whose certificate fails (no low part) is first polished by
+// double-double Newton steps on the certified polynomial (its rounding error,
+// not its position, may be what the disk test cannot absorb next to a close
+// root); when the polished point is certified it replaces the root in the
+// output (high and low parts, MSPLIT_R_DD).
+__global__ void k_certify_dd(batch_args b, double *re, double *im, double *re_lo, double *im_lo,
+                             const int32_t *period, uint8_t *flags, double *radius, const uint32_t *list)
 {
     unsigned long long *const wc = wave_ctr(b);
     const int64_t n = (int64_t)b.gctr[G_HARD_CERT];
@@ -471,9 +475,27 @@ __global__ void k_certify_dd(batch_args b, const double *re, const double *im, c
         if (u < 0) continue;
         const type_desc &td = b.types[t];
         const int64_t i = td.out_off + (u - b.uniq_offs[t]);
-        const cd c = {re[i], im[i]}, lo = {re_lo[i], im_lo[i]};
+        cd c = {re[i], im[i]}, lo = {re_lo[i], im_lo[i]};
         const int lab = period ? period[i] : td.p.n;
-        const cert_result r = certify_root_dd(td.p.l, td.p.n, lab, td.p.divmask_lo, {{c.re, lo.re}, {c.im, lo.im}});
+        cert_result r = certify_root_dd(td.p.l, td.p.n, lab, td.p.divmask_lo, {{c.re, lo.re}, {c.im, lo.im}});
+        if (!(r.flags & 2) && lo.re == 0.0 && lo.im == 0.0) {
+            cdd z = {{c.re, 0.0}, {c.im, 0.0}};
+            for (int s = 0; s < 4; ++s) {
+                const dd_step st = dd_newton_step(td.p.l, td.p.N, z);
+                if (!isfinite(st.s.re.hi) || !isfinite(st.s.im.hi)) break;
+                z = cdd_sub(z, st.s);
+            }
+            const cert_result r2 = certify_root_dd(td.p.l, td.p.n, lab, td.p.divmask_lo, z);
+            if (r2.flags & 2) {
+                r = r2;
+                c = {z.re.hi, z.im.hi};
+                lo = {z.re.lo, z.im.lo};
+                re[i] = c.re;
+                im[i] = c.im;
+                re_lo[i] = lo.re;
+                im_lo[i] = lo.im;
+            }
+        }
         flags[i] = (c.im == 0.0 && lo.im == 0.0 ? 1 : 0) | r.flags | 8;
         radius[i] = r.R;
         nc.v += (r.flags & 2) != 0;

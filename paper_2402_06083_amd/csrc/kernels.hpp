@@ -285,6 +285,7 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
     int s = 0, r0 = 0;    // fine point within the segment (1..F); (j F) mod M
     int it = 0;
     cd z = {0.0, 0.0};
+    cd gprev = {0.0, 0.0}; // P/P' at the last accepted fine point (the seed first)
     wave_queue wq = {0, 0};
     while (true) {
         const bool need = !exhausted && g == NONE;
@@ -341,6 +342,7 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
             g = NONE;
             continue;
         }
+        if (s == 1 && it == 0) gprev = step; // at the seed
         cd u0 = clog_near1(w);
         const cd h = cmul(u0, step);
         const bool is_start = (s % pl_q) == 0;
@@ -361,7 +363,11 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
             ++s;
             it = 0;
             u0.im += 2.0 * M_PI / pl_M;
-            z = cadd(z, cmul(u0, step));
+            // second order along the level-line flow (uniform phase steps):
+            // the change of P/P' since the last accepted point
+            const cd dg = csub(step, gprev);
+            z = cadd(z, cmul(u0, cadd(step, {0.5 * dg.re, 0.5 * dg.im})));
+            gprev = step;
         } else {
             ++it;
             z = cadd(z, h);
