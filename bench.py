@@ -41,8 +41,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1247570122.0
-DESCEND_TRAFFIC_SHA256 = "a38b83c1fb10f80c5e68186e85ee0bcb9aeb7e6c5bd440135fd1edc7832ea02c"
+DESCEND_TRAFFIC_BYTES = 1250763872.1
+DESCEND_TRAFFIC_SHA256 = "bf84849bd09dfcd4515d0a232b87502595ddc526959eaafe320536b9daa10546"
 
 
 def descend_traffic():
