@@ -131,7 +131,9 @@ typedef struct msplit_stats {
     uint64_t total;         /* n_real + 2 (unique - n_real): roots counted in C */
     uint64_t expected;      /* exact count: 2^(n-1) for p_n, |Mis(l,n)| for q */
     uint64_t missing;       /* expected - total when positive */
-    uint64_t phase_fail;    /* level-line segments whose end missed the next seed */
+    uint64_t phase_fail;    /* level-line segments whose FP64 walk missed the next seed (their
+                               starts are then lifted again in double-double, one by one),
+                               plus seed and double-double lifts that did not converge */
     uint64_t certified;     /* roots with MSPLIT_R_CERTIFIED */
     uint64_t label_proven;  /* roots with MSPLIT_R_LABEL */
     uint64_t overlaps;      /* certified disks that are not quarter-separated */

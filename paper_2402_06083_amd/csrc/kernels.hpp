@@ -40,7 +40,8 @@ __device__ __forceinline__ bool st_converged(uint8_t s) { return s == ST_CONVERG
 // G_HARD_CLS / G_HARD_CERT: lengths of the lists of hard cases of the
 // classification and of the certificate (handled by kernels of their own)
 // G_DD_NEXT: work queue of the double-double descents
-enum { G_SEG_NEXT = 0, G_START_NEXT, G_COMPACT, G_START_NEXT2, G_DD_COUNT, G_HARD_CLS, G_HARD_CERT, G_DD_NEXT,
+// G_FAILED_SEGS: length of the list of walk segments that failed their phase check
+enum { G_SEG_NEXT = 0, G_START_NEXT, G_FAILED_SEGS, G_START_NEXT2, G_DD_COUNT, G_HARD_CLS, G_HARD_CERT, G_DD_NEXT,
        G_NCOUNTERS = 8 };
 // per-type counters (uint64 slots, C_NCOUNTERS per type)
 enum {

@@ -544,6 +544,12 @@ void enqueue_level_line(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
     if (ev) (void)hipEventRecord(ev[1], stream);
     // level-line walk
     k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, ws_at<uint8_t>(c, c.L.segf));
+    // segments whose walk failed its phase check: starts lifted again in
+    // double-double (the list lives in flag0, free until the descents)
+    uint32_t *failed = ws_at<uint32_t>(c, c.L.flag0);
+    k_failed_list<<<blocks_for(std::max<int64_t>(bp.n_segs, 1), 256), 256, 0, stream>>>(ba, ws_at<uint8_t>(c, c.L.segf),
+                                                                                     failed);
+    k_relift_failed<<<device_cus() * 4, 64, 0, stream>>>(ba, failed, starts);
     if (bp.n_tip > 0) k_lift_tip_starts<<<blocks_for(bp.n_tip, 64), 64, 0, stream>>>(ba, starts, tip_lo, bp.n_tip);
     if (ev) (void)hipEventRecord(ev[2], stream);
 }
@@ -846,7 +852,9 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
             stats->ms_stage[1] = b;
             stats->ms_device = a + b;
         }
-        return phase_fail ? MSPLIT_E_INCOMPLETE : MSPLIT_OK;
+        // a failed walk is repaired by the double-double lift of its starts;
+        // a lift that did not converge is not
+        return c.h[C_SEED_FAIL] ? MSPLIT_E_INCOMPLETE : MSPLIT_OK;
     }
     enqueue_roots(c, stream, ev.e);
     CHK(hipGetLastError());

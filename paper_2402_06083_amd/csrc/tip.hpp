@@ -80,34 +80,16 @@ __device__ void dd_eval(int l, int N, cdd c, cdd &P, cd &dP)
     dP = {dr - dlr, di - dli};
 }
 
-// Starts at the left tip.  From order about 28 on the level line passes -2
-// closer than the FP64 spacing there (its left end lies near
-// -2 - 14.7 / 4^n): the fine points of the FP64 walk collapse onto the same
-// values, the walk loses its way over the last segments (5 of them at order
-// 30, 17 at order 31) and the starts it leaves there are not on the right
-// branch of the level line.  Each of the last tip_starts starts is instead
-// lifted on its own in double-double, like a seed (Section 4.2): from the
+// Start kg of the whole upper half of the level line (P = lambda_0 i^kg),
+// lifted on its own in double-double like a seed (Section 4.2): from the
 // circle |p_1| = lambda_0 at the start's own angle pi a / (S F) (a = its
 // fine-point index) through every level p_2 .. p_N, the angle doubling at
 // each level, Newton with target in log form; at the last level the target
-// is the start's exact value lambda_0 i^k and the point is polished to
-// double-double accuracy by Newton on P - T.  The high part replaces the
-// start, the low part goes to tip_lo (read by the double-double descent).
-// A start whose lift fails becomes NaN (its descent then ends as divergent)
-// and is counted in C_SEED_FAIL.
-__global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t n_tip)
+// is the start's exact value lambda_0 i^kg and the point is polished to
+// double-double accuracy by Newton on P - T.  Returns false when a level
+// does not converge.
+__device__ bool dd_lift_start(const plan_t &pl, int64_t kg, cdd &z)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_tip) return;
-    int t = 0; // type owning slot i (few types carry tip starts)
-    while (t + 1 < b.T && b.types[t + 1].tip_lo_off <= i) ++t;
-    const type_desc &td = b.types[t];
-    const plan_t &pl = td.p;
-    const int64_t j = i - td.tip_lo_off;
-    if (j >= pl.tip_starts) return;
-    const int64_t k = pl.NS - pl.tip_starts + j;    // start index within the item
-    const int64_t kg = k + pl.seg0 * (pl.F / pl.q); // on the whole line: P = lambda_0 i^kg
-    const int64_t g = td.start_off + k;
     const bool real_end = kg == 0 || kg == 2 * pl.D;
     const int64_t Sp = pl.S * pl.F, twoSp = 2 * Sp; // fine points of the upper half
     const double lam = pl.level;
@@ -120,7 +102,7 @@ __global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t 
         return {lam * cs, lam * sn};
     };
     const cd z0 = circle(a);
-    cdd z = {{z0.re, 0.0}, {z0.im, 0.0}};
+    z = {{z0.re, 0.0}, {z0.im, 0.0}};
     const int top = pl.el ? pl.eN + 1 : pl.eN;
     bool ok = true;
     for (int lev = 2; lev <= top && ok; ++lev) {
@@ -158,13 +140,78 @@ __global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t 
             if (real_end) z.im = {0.0, 0.0};
         }
     }
-    if (!ok) {
+    return ok;
+}
+
+// Starts at the left tip.  From order about 28 on the level line passes -2
+// closer than the FP64 spacing there (its left end lies near
+// -2 - 14.7 / 4^n): the fine points of the FP64 walk collapse onto the same
+// values, the walk loses its way over the last segments (5 of them at order
+// 30, 17 at order 31) and the starts it leaves there are not on the right
+// branch of the level line.  Each of the last tip_starts starts is instead
+// lifted on its own in double-double (dd_lift_start): the high part replaces
+// the start, the low part goes to tip_lo (read by the double-double
+// descent).  A start whose lift fails becomes NaN (its descent then ends as
+// divergent) and is counted in C_SEED_FAIL.
+__global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t n_tip)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tip) return;
+    int t = 0; // type owning slot i (few types carry tip starts)
+    while (t + 1 < b.T && b.types[t + 1].tip_lo_off <= i) ++t;
+    const type_desc &td = b.types[t];
+    const plan_t &pl = td.p;
+    const int64_t j = i - td.tip_lo_off;
+    if (j >= pl.tip_starts) return;
+    const int64_t k = pl.NS - pl.tip_starts + j;    // start index within the item
+    const int64_t kg = k + pl.seg0 * (pl.F / pl.q); // on the whole line: P = lambda_0 i^kg
+    const int64_t g = td.start_off + k;
+    cdd z;
+    if (!dd_lift_start(pl, kg, z)) {
         const double nan = __longlong_as_double(0x7ff8000000000000ll);
         z = {{nan, 0.0}, {nan, 0.0}};
         atomicAdd(&wave_ctr(b)[(int64_t)t * C_NCOUNTERS + C_SEED_FAIL], 1ull);
     }
     starts[g] = {z.re.hi, z.im.hi};
     tip_lo[i] = {z.re.lo, z.im.lo};
+}
+
+// Segments whose FP64 walk failed its phase check (seg_flag != 0) to a list
+// (global segment indices, count in G_FAILED_SEGS; one atomic per wave).
+__global__ void k_failed_list(batch_args b, const uint8_t *seg_flag, uint32_t *list)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = g < b.n_segs && seg_flag[g] != 0;
+    wave_append(list, &b.gctr[G_FAILED_SEGS], bad, (uint32_t)g);
+}
+
+// The starts of a failed segment, lifted again one by one in double-double.
+// A walk fails where consecutive fine points come closer than FP64 resolves
+// -- next to -2 and next to the tips of M where the rays of dyadic angles
+// land (angles k / 2^m: the failures of p_28 and p_29 cluster at 7/16,
+// 15/32, 29/64, ...) -- or where a seed sits on another branch; the lift by
+// angle does not depend on either.  Segment j's starts j F/q + 1 .. (j + 1)
+// F/q (its walk's starts and the next seed) are replaced by the high parts
+// of their lifts (the starts of the left tip have their own lift); a start
+// whose lift fails keeps the walk's value.  One wave per failed segment.
+__global__ void __launch_bounds__(64) k_relift_failed(batch_args b, const uint32_t *list, cd *starts)
+{
+    const uint64_t n = b.gctr[G_FAILED_SEGS];
+    for (uint64_t e = blockIdx.x; e < n; e += gridDim.x) {
+        const uint32_t g = list[e];
+        const int t = find_type(b.seg_offs, b.T, g);
+        const type_desc &td = b.types[t];
+        const plan_t &pl = td.p;
+        const int64_t j = (int64_t)g - b.seg_offs[t];
+        const int64_t per = pl.F / pl.q;
+        for (int64_t u = threadIdx.x; u < per; u += blockDim.x) {
+            const int64_t k = j * per + 1 + u;
+            if (k >= pl.NS - pl.tip_starts) continue; // past the item, or a tip start
+            cdd z;
+            if (dd_lift_start(pl, k + pl.seg0 * per, z)) starts[td.start_off + k] = {z.re.hi, z.im.hi};
+            else atomicAdd(&wave_ctr(b)[(int64_t)t * C_NCOUNTERS + C_SEED_FAIL], 1ull);
+        }
+    }
 }
 
 // Routing: starts whose FP64 descent ended within x_tip of -2 (any status:
