@@ -223,8 +223,11 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
             cd T = {pl.level * cs, pl.level * sn};
             if (a == 0) T = {pl.level, 0.0};
             // intermediate levels only have to land in the basin of the
-            // next one; the last level is solved to rounding level
-            const double tolv2 = (k < top) ? 0x1p-10 : 1e-26;
+            // next one (accepted like the walk's intermediate fine points: a
+            // seed that lands on another branch fails the phase checks of its
+            // segments, whose starts are then lifted again one by one); the
+            // last level is solved to rounding level
+            const double tolv2 = (k < top) ? 0x1p-4 : 1e-26;
             for (int it = 0;; ++it) {
                 cd P, dP;
                 eval_q(ll, NN, z, P, dP);
