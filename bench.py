@@ -41,8 +41,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1250763872.1
-DESCEND_TRAFFIC_SHA256 = "bf84849bd09dfcd4515d0a232b87502595ddc526959eaafe320536b9daa10546"
+DESCEND_TRAFFIC_BYTES = 1253208383.1
+DESCEND_TRAFFIC_SHA256 = "4befc35a21dd4faf609099fd7521b87f1d4eeecaa94ff124820b75b168cc2119"
 
 
 def descend_traffic():
