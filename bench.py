@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 FLOP/clk)
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FP32; this build's unpacked FP32 issues at the FP64 rate)
 
 # algorithmic flops of one evaluation + update of order N: the orbit from
 # its first iterate (p_1 = c, p_1' = 1 need no arithmetic) is N - 1 steps of
@@ -95,6 +96,35 @@ def kernel_flops(pairs, stats_list, simple=False):
     return desc, t_desc, walk, t_walk
 
 
+def descent_flops_by_precision(pairs, stats_list, simple=False):
+    """Algorithmic flops of the FP64 and of the FP32 descent steps."""
+    f64 = f32 = 0.0
+    for (l, n), st in zip(pairs, stats_list):
+        N = l + n - (1 if simple and l >= 2 else 0)
+        per = FLOPS_ORBIT_STEP * (N - 1) + FLOPS_NEWTON_UPDATE
+        f64 += st["steps_desc"] * per
+        f32 += st["steps_fp32"] * per
+    return f64, f32
+
+
+def distinct_parameters(runner):
+    """Roots of the batch counted once per parameter c: a root of p_n whose
+    exact period is n (a root of p_k, k | n, k < n, is already counted with
+    p_k), conjugates included; for q_{l,n} every root (Mis(l,n))."""
+    tot = 0
+    for i, (l, n) in enumerate(runner.pairs):
+        sl = runner.slices(i)
+        real = runner.im[sl] == 0
+        sel = runner.period[sl] == n if l == 0 else torch_ones_like(real)
+        tot += int((sel & real).sum().item()) + 2 * int((sel & ~real).sum().item())
+    return tot
+
+
+def torch_ones_like(t):
+    import torch
+    return torch.ones_like(t, dtype=torch.bool)
+
+
 def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=False, simple=False):
     """eager: every call enqueued by msplit_batch (stage times from HIP
     events on the call's stream); graph: the call captured once as a
@@ -109,6 +139,8 @@ def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=F
         runner.capture()
     agg = _time_runner(runner, pairs, steps, warmup, mode, simple)
     agg["launch"] = mode
+    if mode == "eager":
+        agg["distinct"] = distinct_parameters(runner)
     runner.close()
     del runner
     torch.cuda.empty_cache()
@@ -131,11 +163,14 @@ def _time_runner(runner, pairs, steps, warmup, mode, simple=False):
         res = runner.result(r)
         sts = [st for (_, st, _) in res.per_pair]
         d, td, w, tw = kernel_flops(pairs, sts, simple)
+        d64, d32 = descent_flops_by_precision(pairs, sts, simple)
         cr = certified_roots(sts)
         if agg is None:
             agg = dict(desc=0.0, t_desc=0.0, walk=0.0, t_walk=0.0, roots=0, ms_device=0.0,
                        stages={k: 0.0 for k in msplit.Stats.STAGES})
         agg["desc"] += d
+        agg["desc64"] = agg.get("desc64", 0.0) + d64
+        agg["desc32"] = agg.get("desc32", 0.0) + d32
         agg["t_desc"] += td
         agg["walk"] += w
         agg["t_walk"] += tw
@@ -201,6 +236,29 @@ def run_streamed(n, steps=1, warmup=1):
     del r, b
     torch.cuda.empty_cache()
     return res
+
+
+def work_per_root(stats_list):
+    roots = sum(st["total"] for st in stats_list)
+    if not roots:
+        return None
+    s = lambda k: sum(st[k] for st in stats_list)
+    return {"lift_evaluations": s("steps_lift") / roots, "walk_evaluations": s("steps_walk") / roots,
+            "descent_steps": (s("steps_desc") + s("steps_fp32")) / roots,
+            "descent_steps_fp32": s("steps_fp32") / roots, "double_double_steps": s("steps_dd") / roots}
+
+
+def blended_roofline(agg):
+    """Descent kernels of a MIXED run: FP64 and FP32 steps each against their
+    own vector peak, time-weighted (sum of flops_p / peak_p over the time),
+    beside the FP64-only fraction."""
+    t = agg["t_desc"] * 1e-3
+    if t <= 0:
+        return None
+    f64, f32 = agg.get("desc64", 0.0), agg.get("desc32", 0.0)
+    return {"blended_frac": (f64 / (FP64_PEAK_TFLOPS * 1e12) + f32 / (FP32_PEAK_TFLOPS * 1e12)) / t,
+            "fp64_frac": f64 / (FP64_PEAK_TFLOPS * 1e12) / t,
+            "fp32_share_of_flops": f32 / (f32 + f64) if f32 + f64 else 0.0}
 
 
 def cpu_baseline():
@@ -302,6 +360,10 @@ def main():
         "walk": {"kernel": "k_walk", "tflops": res["walk"] / (res["t_walk"] * 1e-3) / 1e12 if res["t_walk"] else 0.0,
                  "frac": res["walk"] / (res["t_walk"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS if res["t_walk"] else 0.0,
                  "evaluations_per_step": sum(st["steps_walk"] for st in res["last_stats"])},
+        # the work per root that replaces the paper's W_N (level-line points
+        # and descent steps per root): the instrumented counts of the last step
+        "work_per_root": work_per_root(res["last_stats"]),
+        "distinct_parameters": res.get("distinct"),
     }
     if not args.no_graph:
         rg = run_gpu(pairs, main_prec, args.steps, args.warmup, "graph", tuned[main_prec], simple=args.simple)
@@ -318,7 +380,8 @@ def main():
     if not args.no_compare:
         r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager", tuned[other], simple=args.simple)
         out[other] = {"value": r2["roots"] / r2["wall"], "ms_per_step": 1e3 * r2["wall"] / args.steps,
-                      "stage_ms_per_step": {k: v / args.steps for k, v in r2["stages"].items()}}
+                      "stage_ms_per_step": {k: v / args.steps for k, v in r2["stages"].items()},
+                      "descent_roofline": blended_roofline(r2)}
     if not args.no_p30 and args.workload != "p30":
         p30 = {}
         p30_pairs = WORKLOADS["p30"][1]
