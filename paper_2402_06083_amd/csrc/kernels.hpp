@@ -186,7 +186,12 @@ __device__ __forceinline__ int cached_type(type_cache &c, const int64_t *offs, i
 // q_{l,n} = lambda_0 e^{i pi a_N / S} (same phase: |p_l| << lambda_0 there).
 // Grid-stride loop: per-type counts stay in registers and are flushed when a
 // lane's type changes and at the end (a few atomics per wave in all).
-__global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
+// Every writer of a start also writes the descent's first Newton iterate
+// from it, first[k] = z - P(z)/P'(z): the seeds and the walk have just
+// evaluated P and P' there (the lifts evaluate once more), and the value is
+// bitwise the descent's own first step (same evaluation, same division), so
+// the descent starts one step in.
+__global__ void k_seeds(batch_args b, cd *seeds, cd *starts, cd *first)
 {
     unsigned long long *const wc = wave_ctr(b);
     type_count steps, fail;
@@ -215,6 +220,7 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
         if (j == 0) z = {pl.level, 0.0};
         int64_t a = j % twoS;
         const int top = pl.l ? pl.N + 1 : pl.N;
+        cd P = {0.0, 0.0}, dP = {1.0, 0.0}; // at z, of the last level (the type's polynomial)
         for (int k = 2; k <= top && !failed; ++k) {
             int ll = 0, NN = k;
             if (k <= pl.N) a = (2 * a) % twoS;
@@ -229,7 +235,6 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
             // last level is solved to rounding level
             const double tolv2 = (k < top) ? 0x1p-4 : 1e-26;
             for (int it = 0;; ++it) {
-                cd P, dP;
                 eval_q(ll, NN, z, P, dP);
                 ++steps.v;
                 cd w = cdiv(T, P);
@@ -247,7 +252,11 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
         fail.v += failed;
         seeds[g] = z;
         // the last seed of a chunk is the next chunk's first start
-        if (jl * (pl.F / pl.q) < plr.NS) starts[b.types[t].start_off + jl * (pl.F / pl.q)] = z;
+        if (jl * (pl.F / pl.q) < plr.NS) {
+            const int64_t k = b.types[t].start_off + jl * (pl.F / pl.q);
+            starts[k] = z;
+            first[k] = failed ? z : csub(z, cdiv_fast(P, dP));
+        }
     }
     flush_count(wc, C_STEPS_LIFT, steps);
     flush_count(wc, C_SEED_FAIL, fail);
@@ -265,7 +274,7 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts)
 // target, and the next target is aimed from the actual value, so no error
 // accumulates.  Lane state is 32-bit (segment index, fine point within the
 // segment) to keep the kernel within 64 VGPRs.
-__global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag)
+__global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag, cd *first)
 {
     constexpr uint32_t NONE = 0xffffffffu;
     // |T/P - 1| < 2^-5 sqrt(0.9) keeps |P/T - 1| = |v| / |1 + v| below 2^-5
@@ -339,8 +348,11 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
             // the starts of the segment not reached yet get no value (NaN:
             // their descents end as divergent)
             const double nan = __longlong_as_double(0x7ff8000000000000ll);
-            for (int s2 = (s + pl_q - 1) / pl_q * pl_q; s2 < pl_F; s2 += pl_q)
-                starts[start0 + (uint32_t)(s2 / pl_q)] = {nan, nan};
+            for (int s2 = (s + pl_q - 1) / pl_q * pl_q; s2 < pl_F; s2 += pl_q) {
+                const uint32_t k = start0 + (uint32_t)(s2 / pl_q);
+                starts[k] = {nan, nan};
+                first[k] = {nan, nan};
+            }
             seg_flag[g] = 2;
             cnt[1] += 1u;
             g = NONE;
@@ -362,7 +374,11 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
                 g = NONE;
                 continue;
             }
-            if (is_start) starts[start0 + (uint32_t)(s / pl_q)] = z;
+            if (is_start) {
+                const uint32_t k = start0 + (uint32_t)(s / pl_q);
+                starts[k] = z;
+                first[k] = csub(z, step);
+            }
             // aim at the next fine point: log(T_{s+1}/P) = i dphi + log(T_s/P)
             ++s;
             it = 0;
@@ -512,7 +528,7 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
 // double-double centre.
 template <bool ROUTE>
 __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd *roots, uint8_t *status,
-                                                 const uint8_t *iters)
+                                                 const uint8_t *iters, bool after_fp32)
 {
     constexpr uint32_t NONE = 0xffffffffu;
     unsigned long long *const wc = wave_ctr(b);
@@ -533,14 +549,14 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
     int it = 0, it0 = 0;
     bool fin = false, stall = false;
     wave_queue wq = {0, 0};
-    unsigned long long *counter = &b.gctr[iters ? G_START_NEXT2 : G_START_NEXT];
+    unsigned long long *counter = &b.gctr[after_fp32 ? G_START_NEXT2 : G_START_NEXT];
     while (true) {
         const bool need = !exhausted && g == NONE;
         const uint64_t got = __ballot(need) ? wave_take(wq, counter, b.chunk_start, need) : ~0ull;
         if (need) {
             if (got >= n_starts) {
                 exhausted = true;
-            } else if (!(iters && status[got] != ST_NONE)) { // else: discarded by the FP32 pass
+            } else if (!(after_fp32 && status[got] != ST_NONE)) { // else: discarded by the FP32 pass
                 g = (uint32_t)got;
                 if (g < t_lo || g >= t_hi) {
                     t = find_type(b.start_offs, b.T, g);
@@ -554,7 +570,9 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
                     if (ROUTE) pl_route = pl.x_tip > 0.0;
                 }
                 z = src[g];
-                it0 = it = iters ? iters[g] : 0;
+                // the first step from a start was taken where the start was
+                // written; after the FP32 pass, its count of steps
+                it0 = it = after_fp32 ? iters[g] : 1;
                 prev = 0.0;
                 fin = stall = false;
             }
@@ -578,7 +596,9 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
         // a NaN or infinite value fails the <= tests
         const double a2 = cabs2(d);
         const double az2 = cabs2(z);
-        const bool bad = !(a2 <= 0x1p1000) || !(az2 <= 64.0) || (it > it0 + 3 && a2 > 64.0 * prev);
+        // (the jump test counts the steps from the start, the first one or
+        // the FP32 pass included, and needs a previous step of this descent)
+        const bool bad = !(a2 <= 0x1p1000) || !(az2 <= 64.0) || (it > 3 && it > it0 + 1 && a2 > 64.0 * prev);
         // converged once a step is small.  At a simple root the next step
         // would be about K |d|^2 with K = |d| / |d_prev|^2 (quadratic
         // convergence): when that is below the FP64 rounding of z the point

@@ -540,17 +540,20 @@ void enqueue_level_line(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
         ba.gctr, ba.ctr, ba.spread, T, ws_at<int64_t>(c, c.L.isz), bp.n_starts);
     k_cis<<<1, 64, 0, stream>>>(bp.td[0].p.M, (double *)ba.cis);
     // seeds: lift from the circle |p_1| = lambda_0
-    k_seeds<<<persistent_blocks(bp.n_seeds, bs), bs, 0, stream>>>(ba, seeds, starts);
+    // (and the descent's first iterates, in roots)
+    cd *first = ws_at<cd>(c, c.L.roots);
+    k_seeds<<<persistent_blocks(bp.n_seeds, bs), bs, 0, stream>>>(ba, seeds, starts, first);
     if (ev) (void)hipEventRecord(ev[1], stream);
     // level-line walk
-    k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, ws_at<uint8_t>(c, c.L.segf));
+    k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, ws_at<uint8_t>(c, c.L.segf), first);
     // segments whose walk failed its phase check: starts lifted again in
     // double-double (the list lives in flag0, free until the descents)
     uint32_t *failed = ws_at<uint32_t>(c, c.L.flag0);
     k_failed_list<<<blocks_for(std::max<int64_t>(bp.n_segs, 1), 256), 256, 0, stream>>>(ba, ws_at<uint8_t>(c, c.L.segf),
                                                                                      failed);
-    k_relift_failed<<<device_cus() * 4, 64, 0, stream>>>(ba, failed, starts);
-    if (bp.n_tip > 0) k_lift_tip_starts<<<blocks_for(bp.n_tip, 64), 64, 0, stream>>>(ba, starts, tip_lo, bp.n_tip);
+    k_relift_failed<<<device_cus() * 4, 64, 0, stream>>>(ba, failed, starts, first);
+    if (bp.n_tip > 0)
+        k_lift_tip_starts<<<blocks_for(bp.n_tip, 64), 64, 0, stream>>>(ba, starts, tip_lo, bp.n_tip, first);
     if (ev) (void)hipEventRecord(ev[2], stream);
 }
 
@@ -606,17 +609,21 @@ void enqueue_descents(const batch_call &c, const pipe_bufs &B, hipStream_t strea
     const batch_plan &bp = c.bp;
     const batch_args &ba = c.ba;
     const int bs = c.bs;
-    auto descend64 = [&](const cd *src, const uint8_t *it) {
+    // the FP64 descent continues from roots: the first iterates written with
+    // the starts, or the FP32 pass's results after the steps in iters
+    auto descend64 = [&](bool after_fp32) {
         if (c.any_tip)
-            k_descend<true><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, B.roots, B.status, it);
+            k_descend<true><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, B.roots, B.roots, B.status,
+                                                                                   B.iters, after_fp32);
         else
-            k_descend<false><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, src, B.roots, B.status, it);
+            k_descend<false><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, B.roots, B.roots, B.status,
+                                                                                    B.iters, after_fp32);
     };
     if (c.o.precision == MSPLIT_MIXED) {
         k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, B.starts, B.roots, B.status, B.iters);
-        descend64(B.roots, B.iters);
+        descend64(true);
     } else {
-        descend64(B.starts, nullptr);
+        descend64(false);
     }
     if (c.any_tip) {
         k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, B.roots, B.status, B.flag0);

@@ -143,6 +143,15 @@ __device__ bool dd_lift_start(const plan_t &pl, int64_t kg, cdd &z)
     return ok;
 }
 
+// The descent's first Newton iterate from a lifted start (the same
+// evaluation and division as the descent's own step).
+__device__ __forceinline__ cd first_iterate(int l, int N, cd z)
+{
+    cd P, dP;
+    eval_q(l, N, z, P, dP);
+    return csub(z, cdiv_fast(P, dP));
+}
+
 // Starts at the left tip.  From order about 28 on the level line passes -2
 // closer than the FP64 spacing there (its left end lies near
 // -2 - 14.7 / 4^n): the fine points of the FP64 walk collapse onto the same
@@ -153,7 +162,7 @@ __device__ bool dd_lift_start(const plan_t &pl, int64_t kg, cdd &z)
 // the start, the low part goes to tip_lo (read by the double-double
 // descent).  A start whose lift fails becomes NaN (its descent then ends as
 // divergent) and is counted in C_SEED_FAIL.
-__global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t n_tip)
+__global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t n_tip, cd *first)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_tip) return;
@@ -173,6 +182,7 @@ __global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t 
         atomicAdd(&wave_ctr(b)[(int64_t)t * C_NCOUNTERS + C_SEED_FAIL], 1ull);
     }
     starts[g] = {z.re.hi, z.im.hi};
+    first[g] = first_iterate(pl.el, pl.eN, starts[g]);
     tip_lo[i] = {z.re.lo, z.im.lo};
 }
 
@@ -194,7 +204,7 @@ __global__ void k_failed_list(batch_args b, const uint8_t *seg_flag, uint32_t *l
 // F/q (its walk's starts and the next seed) are replaced by the high parts
 // of their lifts (the starts of the left tip have their own lift); a start
 // whose lift fails keeps the walk's value.  One wave per failed segment.
-__global__ void __launch_bounds__(64) k_relift_failed(batch_args b, const uint32_t *list, cd *starts)
+__global__ void __launch_bounds__(64) k_relift_failed(batch_args b, const uint32_t *list, cd *starts, cd *first)
 {
     const uint64_t n = b.gctr[G_FAILED_SEGS];
     for (uint64_t e = blockIdx.x; e < n; e += gridDim.x) {
@@ -208,8 +218,13 @@ __global__ void __launch_bounds__(64) k_relift_failed(batch_args b, const uint32
             const int64_t k = j * per + 1 + u;
             if (k >= pl.NS - pl.tip_starts) continue; // past the item, or a tip start
             cdd z;
-            if (dd_lift_start(pl, k + pl.seg0 * per, z)) starts[td.start_off + k] = {z.re.hi, z.im.hi};
-            else atomicAdd(&wave_ctr(b)[(int64_t)t * C_NCOUNTERS + C_SEED_FAIL], 1ull);
+            if (dd_lift_start(pl, k + pl.seg0 * per, z)) {
+                const cd s = {z.re.hi, z.im.hi};
+                starts[td.start_off + k] = s;
+                first[td.start_off + k] = first_iterate(pl.el, pl.eN, s);
+            } else {
+                atomicAdd(&wave_ctr(b)[(int64_t)t * C_NCOUNTERS + C_SEED_FAIL], 1ull);
+            }
         }
     }
 }
