@@ -42,8 +42,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1253208383.1
-DESCEND_TRAFFIC_SHA256 = "4befc35a21dd4faf609099fd7521b87f1d4eeecaa94ff124820b75b168cc2119"
+DESCEND_TRAFFIC_BYTES = 1266265954.1
+DESCEND_TRAFFIC_SHA256 = "1442726a1b2c4a58174a643fc2bf9df4815fe9c97acbf13e6cc8b5926fa7d23c"
 
 
 def descend_traffic():

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(SC_BLOCK) k_scan_down(const uint32_t *in, uint
 // first output position.  Segment order is kept, so bits above the sorted
 // range need no pass when the input is ordered by segment.
 constexpr int RS_BINS = 256;
-constexpr int RS_ROWS = 8;
+constexpr int RS_ROWS = 16;
 constexpr int RS_TILE = SC_BLOCK * RS_ROWS;
 static_assert(SC_BLOCK == RS_BINS, "one thread per digit");
 static_assert(RS_TILE < 65536, "ranks packed in 16 bits");
