@@ -43,7 +43,7 @@ FLOPS_WALK_UPDATE = 62
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
 DESCEND_TRAFFIC_BYTES = 1266265954.1
-DESCEND_TRAFFIC_SHA256 = "1442726a1b2c4a58174a643fc2bf9df4815fe9c97acbf13e6cc8b5926fa7d23c"
+DESCEND_TRAFFIC_SHA256 = "1664a303682b013b415b1d4a4546e4e95a974797a9ed7a1a5039df185d415801"
 
 
 def descend_traffic():

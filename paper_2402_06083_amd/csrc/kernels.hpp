@@ -401,7 +401,11 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
 // (Algorithm S_par).  Discarded as divergent: non-finite, |z| > 8 (far from
 // M, which lies in D(0,2) u {-2}), or a long-distance jump (step more than 8
 // times the previous one after the third step, Section 6.4.3).  Converged
-// when the step falls below tol * max(|z|, 2^-8); one more step is taken.
+// when the step falls below tol * max(|z|, 2^-8); one more step is taken
+// unless quadratic convergence predicts the next step below the rounding.
+// In FP64 the first step from every start was taken where the start was
+// written (its P and P' were evaluated there), so the descent begins at the
+// first iterate with one step counted.
 //
 // MIXED precision runs k_descend32 first over all starts: FP32 Newton steps
 // while the step exceeds fp32_switch * max(|z|, 2^-8).  The rounding noise of
@@ -512,8 +516,9 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
     flush_count(wc, C_TIMEOUT, ntime);
 }
 
-// iters == nullptr: FP64 from the start.  Otherwise the FP32 pass ran: starts
-// it discarded keep their status, the others resume with their step count.
+// src holds the first iterates (after_fp32 false: one step counted) or the
+// FP32 pass's results (after_fp32 true: starts it discarded keep their
+// status, the others resume with the step count in iters).
 // The lane state is kept small (32-bit start indices and type bounds, one
 // type tag for the four 32-bit counts, branch-free status selection) so that
 // the kernel fits 64 VGPRs: 8 waves per SIMD hide the load of a new start
