@@ -39,7 +39,7 @@ FLOPS_ORBIT_STEP = 16
 FLOPS_NEWTON_UPDATE = 14
 FLOPS_WALK_UPDATE = 62
 
-# HBM traffic of k_descend<false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
+# HBM traffic of k_descend<false, false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
 DESCEND_TRAFFIC_BYTES = 1266265954.1

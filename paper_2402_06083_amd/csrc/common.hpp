@@ -170,13 +170,28 @@ __device__ __forceinline__ void eval_q_f32(int l, int N, cf c, cf &P, cf &dP) { 
 // ---------------------------------------------------------- wave helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-// Per-wave work queue: the wave owns the index range [next, end) taken from
-// the global counter `chunk` items at a time (one atomic per chunk instead
-// of one per item: a single counter hit by every wave at every Newton step
-// serialises in the L2 atomic unit).  The two fields are wave-uniform: every
-// lane holds the same copy and applies the same updates.  Lanes with need get
-// distinct indices (possibly >= the item count: no work left).  chunk >= 64.
+// Per-wave work queue over the items [0, n): the wave owns the index range
+// [next, end), taken `chunk` items at a time (one atomic per chunk instead
+// of one per item).  Requests to one address serialise -- about 16 ns each
+// across the XCDs of the chip, so the 8192 waves of a persistent grid asking
+// at once would wait up to 130 us -- hence wave w of the grid (W waves)
+// starts with the chunk [w chunk, (w + 1) chunk) without an atomic, and the
+// counter hands out the chunks from W chunk on.  A plain read of the counter
+// first spares the atomic once the items are exhausted (the counter only
+// grows, so a stale value never ends a queue early).  The two fields are
+// wave-uniform: every lane holds the same copy and applies the same updates.
+// Lanes with need get distinct indices (>= n: no work left).  chunk >= 64.
 struct wave_queue { uint64_t next, end; };
+
+__device__ __forceinline__ uint64_t grid_waves() { return ((uint64_t)gridDim.x * blockDim.x) >> 6; }
+
+__device__ __forceinline__ wave_queue wave_queue_start(uint64_t chunk)
+{
+    // wave-uniform (scalar registers)
+    const uint32_t wb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wb;
+    return {w * chunk, (w + 1) * chunk};
+}
 
 // value of `x` in lane `lane` as a wave-uniform (scalar) value
 __device__ __forceinline__ uint64_t read_lane_u64(uint64_t x, int lane)
@@ -186,7 +201,11 @@ __device__ __forceinline__ uint64_t read_lane_u64(uint64_t x, int lane)
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t wave_take(wave_queue &q, unsigned long long *counter, uint64_t chunk, bool need)
+// The plain form: every chunk from the counter, which counts from 0 (the
+// queue starts empty, {0, 0}).  The FP64 descent uses it: the static first
+// chunk costs it two VGPRs, past its 64 (one wave per SIMD less).
+__device__ __forceinline__ uint64_t wave_take_plain(wave_queue &q, unsigned long long *counter, uint64_t chunk,
+                                                    bool need)
 {
     const unsigned long long mask = __ballot(need);
     uint64_t idx = ~0ull;
@@ -203,6 +222,40 @@ __device__ __forceinline__ uint64_t wave_take(wave_queue &q, unsigned long long 
         if (need) idx = rank < avail ? q.next + rank : base + (rank - avail);
         q.next = base + (cnt - avail);
         q.end = base + chunk;
+    } else {
+        if (need) idx = q.next + rank;
+        q.next += cnt;
+    }
+    return idx;
+}
+
+__device__ __forceinline__ uint64_t wave_take(wave_queue &q, unsigned long long *counter, uint64_t chunk, uint64_t n,
+                                              bool need)
+{
+    const unsigned long long mask = __ballot(need);
+    uint64_t idx = ~0ull;
+    if (!mask) return idx;
+    const uint32_t cnt = (uint32_t)__popcll(mask);
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    const uint64_t avail = q.end - q.next;
+    if (avail < cnt) {
+        const uint64_t first = grid_waves() * chunk; // counter value 0
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        unsigned long long b = 0;
+        if (lane_id() == leader) {
+            const unsigned long long seen = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            b = first + seen >= n ? ~0ull : first + atomicAdd(counter, (unsigned long long)chunk);
+        }
+        const uint64_t base = read_lane_u64(b, leader);
+        if (base == ~0ull) { // no chunk left: the lanes past this range get n
+            if (need) idx = rank < avail ? q.next + rank : n;
+            q.next = q.end;
+        } else {
+            if (need) idx = rank < avail ? q.next + rank : base + (rank - avail);
+            q.next = base + (cnt - avail);
+            q.end = base + chunk;
+        }
     } else {
         if (need) idx = q.next + rank;
         q.next += cnt;

@@ -95,6 +95,12 @@ struct batch_args {
     int T;
     int64_t n_seeds, n_segs, n_starts;
     uint32_t chunk_seg, chunk_start;
+    // the starts of the types an FP32 pass runs on (MIXED), as one index
+    // space: type t holds [fp32_offs[t], fp32_offs[t + 1]), empty for the
+    // others; n_fp32 = fp32_offs[T]
+    const int64_t *fp32_offs;
+    int64_t n_fp32;
+    uint32_t chunk_fp32;
     unsigned long long *gctr;   // global counters
     unsigned long long *ctr;    // T x C_NCOUNTERS, folded from spread
     unsigned long long *spread; // CTR_SPREAD copies of T x C_NCOUNTERS
@@ -299,10 +305,10 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
     int it = 0;
     cd z = {0.0, 0.0};
     cd gprev = {0.0, 0.0}; // P/P' at the last accepted fine point (the seed first)
-    wave_queue wq = {0, 0};
+    wave_queue wq = wave_queue_start(b.chunk_seg);
     while (true) {
         const bool need = !exhausted && g == NONE;
-        const uint64_t got = wave_take(wq, &b.gctr[G_SEG_NEXT], b.chunk_seg, need);
+        const uint64_t got = wave_take(wq, &b.gctr[G_SEG_NEXT], b.chunk_seg, n_segs, need);
         if (need) {
             if (got >= n_segs) {
                 exhausted = true;
@@ -423,8 +429,9 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
 // (against 4^-N for p_n), closer than steps with that error can aim, so an
 // FP32 step there can carry a start into the basin of a neighbouring root.
 constexpr int FP32_MAX_ORDER = 20;
+__host__ __device__ __forceinline__ bool fp32_eligible(int l, int N) { return l == 0 && N <= FP32_MAX_ORDER; }
 
-__global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *status, uint8_t *iters)
+__global__ void k_descend32(batch_args b, cd *roots, uint8_t *status, uint8_t *iters)
 {
     unsigned long long *const wc = wave_ctr(b);
     type_count steps32, ndiv, ntime;
@@ -436,18 +443,18 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
     float prev = 0.f; // previous squared step length
     int it = 0;
     bool done = false;
-    wave_queue wq = {0, 0};
+    wave_queue wq = wave_queue_start(b.chunk_fp32);
     type_cache tc;
+    int64_t to_start = 0; // start index minus FP32 index within the current type
     while (true) {
         const bool need = !done && g < 0;
-        const uint64_t got = wave_take(wq, &b.gctr[G_START_NEXT], b.chunk_start, need);
+        const uint64_t got = wave_take(wq, &b.gctr[G_START_NEXT], b.chunk_fp32, (uint64_t)b.n_fp32, need);
         bool change = false;
         if (need) {
-            if (got >= (uint64_t)b.n_starts) {
+            if (got >= (uint64_t)b.n_fp32) {
                 done = true;
             } else {
-                g = (int64_t)got;
-                const int t1 = cached_type(tc, b.start_offs, b.T, g);
+                const int t1 = cached_type(tc, b.fp32_offs, b.T, (int64_t)got);
                 if (t1 != t) {
                     t = t1;
                     const plan_t &pl = b.types[t].p;
@@ -455,11 +462,15 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
                     pl_N = pl.eN;
                     pl_cap = pl.cap;
                     pl_sw = pl.fp32_switch;
+                    to_start = b.types[t].start_off - tc.lo;
                 }
+                g = (int64_t)got + to_start;
                 change = steps32.t != t;
-                const cd zd = starts[g];
+                // from the first iterate (the first step was taken in FP64
+                // where the start was written)
+                const cd zd = roots[g];
                 z = {(float)zd.re, (float)zd.im};
-                it = 0;
+                it = 1;
                 prev = 0.f;
             }
         }
@@ -472,13 +483,6 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
         if (__ballot(!done) == 0) break;
         if (done) continue;
         cf P, dP;
-        if (pl_N > FP32_MAX_ORDER || pl_l != 0) { // FP64 from the start
-            roots[g] = starts[g];
-            status[g] = ST_NONE;
-            iters[g] = 0;
-            g = -1;
-            continue;
-        }
         eval_q_f32_wave(pl_l, pl_N, z, P, dP);
         ++steps32.v;
         const float den = dP.re * dP.re + dP.im * dP.im;
@@ -503,7 +507,8 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
             prev = a2;
         }
         if (handoff || st != ST_NONE) {
-            roots[g] = it > 0 ? cd{(double)z.re, (double)z.im} : starts[g];
+            // without an FP32 step the FP64 first iterate stays
+            if (it > 1) roots[g] = cd{(double)z.re, (double)z.im};
             status[g] = st;
             iters[g] = (uint8_t)it;
             ndiv.v += st == ST_DIVERGED;
@@ -516,9 +521,9 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
     flush_count(wc, C_TIMEOUT, ntime);
 }
 
-// src holds the first iterates (after_fp32 false: one step counted) or the
-// FP32 pass's results (after_fp32 true: starts it discarded keep their
-// status, the others resume with the step count in iters).
+// src holds the first iterates (one step counted) and, after the FP32 pass
+// (AFTER32), its results for the types it ran on: starts it discarded keep
+// their status, the others resume with the step count in iters.
 // The lane state is kept small (32-bit start indices and type bounds, one
 // type tag for the four 32-bit counts, branch-free status selection) so that
 // the kernel fits 64 VGPRs: 8 waves per SIMD hide the load of a new start
@@ -531,9 +536,9 @@ __global__ void k_descend32(batch_args b, const cd *starts, cd *roots, uint8_t *
 // image of D(c, R) under the orbit to stay small, R |P'| << 1, and an FP64
 // centre leaves R ~ 2^-46 |z|, so |P'| 2^-46 |z| > 1/16 asks for a
 // double-double centre.
-template <bool ROUTE>
+template <bool ROUTE, bool AFTER32>
 __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd *roots, uint8_t *status,
-                                                 const uint8_t *iters, bool after_fp32)
+                                                 const uint8_t *iters)
 {
     constexpr uint32_t NONE = 0xffffffffu;
     unsigned long long *const wc = wave_ctr(b);
@@ -554,17 +559,17 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
     int it = 0, it0 = 0;
     bool fin = false, stall = false;
     wave_queue wq = {0, 0};
-    unsigned long long *counter = &b.gctr[after_fp32 ? G_START_NEXT2 : G_START_NEXT];
+    unsigned long long *counter = &b.gctr[AFTER32 ? G_START_NEXT2 : G_START_NEXT];
     while (true) {
         const bool need = !exhausted && g == NONE;
-        const uint64_t got = __ballot(need) ? wave_take(wq, counter, b.chunk_start, need) : ~0ull;
+        const uint64_t got = __ballot(need) ? wave_take_plain(wq, counter, b.chunk_start, need) : ~0ull;
         if (need) {
             if (got >= n_starts) {
                 exhausted = true;
-            } else if (!(after_fp32 && status[got] != ST_NONE)) { // else: discarded by the FP32 pass
-                g = (uint32_t)got;
-                if (g < t_lo || g >= t_hi) {
-                    t = find_type(b.start_offs, b.T, g);
+            } else {
+                const uint32_t gg = (uint32_t)got;
+                if (gg < t_lo || gg >= t_hi) {
+                    t = find_type(b.start_offs, b.T, gg);
                     t_lo = (uint32_t)b.start_offs[t];
                     t_hi = (uint32_t)b.start_offs[t + 1];
                     const plan_t &pl = b.types[t].p;
@@ -574,12 +579,17 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
                     pl_tol2 = pl.tol_desc * pl.tol_desc;
                     if (ROUTE) pl_route = pl.x_tip > 0.0;
                 }
-                z = src[g];
-                // the first step from a start was taken where the start was
-                // written; after the FP32 pass, its count of steps
-                it0 = it = after_fp32 ? iters[g] : 1;
-                prev = 0.0;
-                fin = stall = false;
+                // the FP32 pass ran on the starts of this type
+                const bool ran32 = AFTER32 && fp32_eligible(pl_l, pl_N);
+                if (!(ran32 && status[gg] != ST_NONE)) { // else: discarded by the FP32 pass
+                    g = gg;
+                    z = src[g];
+                    // the first step from a start was taken where the start
+                    // was written; after FP32 steps, their count
+                    it0 = it = ran32 ? iters[g] : 1;
+                    prev = 0.0;
+                    fin = stall = false;
+                }
             }
         }
         const bool change = g != NONE && t != ct;

@@ -232,7 +232,7 @@ layout make_layout(const batch_plan &bp)
     L.isz = take(sizeof(int64_t) * SZ_N);
     L.cis = take(sizeof(double) * 128);
     L.types = take(sizeof(type_desc) * T);
-    L.offs = take(sizeof(int64_t) * 7 * (T + 1));
+    L.offs = take(sizeof(int64_t) * 8 * (T + 1));
     L.rtile = take(sizeof(int64_t) * (T + 1));
     L.seeds = take(sizeof(cd) * bp.n_seeds);
     L.starts = take(sizeof(cd) * NS);
@@ -442,7 +442,7 @@ void setup_args(batch_call &c, char *ws)
     const batch_plan &bp = c.bp;
     c.ws = ws;
     const int T = bp.T;
-    c.offs.assign(7 * (T + 1), 0);
+    c.offs.assign(8 * (T + 1), 0);
     std::copy(bp.seed_offs.begin(), bp.seed_offs.end(), c.offs.begin());
     std::copy(bp.seg_offs.begin(), bp.seg_offs.end(), c.offs.begin() + (T + 1));
     std::copy(bp.start_offs.begin(), bp.start_offs.end(), c.offs.begin() + 2 * (T + 1));
@@ -456,6 +456,15 @@ void setup_args(batch_call &c, char *ws)
     ba.coll_offs = doffs + 4 * (T + 1);
     ba.kept_offs = doffs + 5 * (T + 1);
     ba.surv_offs = doffs + 6 * (T + 1);
+    // the FP32 pass's index space (MIXED): the starts of the types it runs on
+    int64_t *v32 = c.offs.data() + 7 * (T + 1);
+    for (int t = 0; t < T; ++t)
+        v32[t + 1] = v32[t] + (c.o.precision == MSPLIT_MIXED && fp32_eligible(bp.td[t].p.el, bp.td[t].p.eN)
+                                   ? bp.start_offs[t + 1] - bp.start_offs[t] : 0);
+    ba.fp32_offs = doffs + 7 * (T + 1);
+    ba.n_fp32 = v32[T];
+    // about one evaluation per start: one static chunk per wave, no atomics
+    ba.chunk_fp32 = (uint32_t)std::max<int64_t>(64, std::min<int64_t>(4096, (ba.n_fp32 + 8191) / 8192));
     ba.cis = ws_at<double>(c, c.L.cis);
     ba.T = T;
     ba.n_seeds = bp.n_seeds;
@@ -610,20 +619,16 @@ void enqueue_descents(const batch_call &c, const pipe_bufs &B, hipStream_t strea
     const batch_args &ba = c.ba;
     const int bs = c.bs;
     // the FP64 descent continues from roots: the first iterates written with
-    // the starts, or the FP32 pass's results after the steps in iters
-    auto descend64 = [&](bool after_fp32) {
-        if (c.any_tip)
-            k_descend<true><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, B.roots, B.roots, B.status,
-                                                                                   B.iters, after_fp32);
-        else
-            k_descend<false><<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, B.roots, B.roots, B.status,
-                                                                                    B.iters, after_fp32);
-    };
-    if (c.o.precision == MSPLIT_MIXED) {
-        k_descend32<<<persistent_blocks(bp.n_starts, bs), bs, 0, stream>>>(ba, B.starts, B.roots, B.status, B.iters);
-        descend64(true);
+    // the starts, or the FP32 pass's results after the steps in iters (for
+    // the types the FP32 pass runs on; without such a type it is skipped)
+    const int nb = persistent_blocks(bp.n_starts, bs);
+    if (ba.n_fp32 > 0) {
+        k_descend32<<<persistent_blocks(ba.n_fp32, bs), bs, 0, stream>>>(ba, B.roots, B.status, B.iters);
+        if (c.any_tip) k_descend<true, true><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
+        else k_descend<false, true><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
     } else {
-        descend64(false);
+        if (c.any_tip) k_descend<true, false><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
+        else k_descend<false, false><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
     }
     if (c.any_tip) {
         k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, B.roots, B.status, B.flag0);

@@ -291,10 +291,10 @@ __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t
     bool fin = false;
     double prev = 0.0;
     cdd z = {{0.0, 0.0}, {0.0, 0.0}};
-    wave_queue wq = {0, 0};
+    wave_queue wq = wave_queue_start(64);
     while (true) {
         const bool need = !exhausted && g == NONE;
-        const uint64_t got = __ballot(need) ? wave_take(wq, &b.gctr[G_DD_NEXT], 64, need) : ~0ull;
+        const uint64_t got = __ballot(need) ? wave_take(wq, &b.gctr[G_DD_NEXT], 64, n, need) : ~0ull;
         if (need) {
             if (got >= n) {
                 exhausted = true;
