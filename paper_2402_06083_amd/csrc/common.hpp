@@ -183,6 +183,11 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 // Lanes with need get distinct indices (>= n: no work left).  chunk >= 64.
 struct wave_queue { uint64_t next, end; };
 
+__global__ void k_set_counter(unsigned long long *counter, unsigned long long v)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = v;
+}
+
 __device__ __forceinline__ uint64_t grid_waves() { return ((uint64_t)gridDim.x * blockDim.x) >> 6; }
 
 __device__ __forceinline__ wave_queue wave_queue_start(uint64_t chunk)
@@ -201,9 +206,11 @@ __device__ __forceinline__ uint64_t read_lane_u64(uint64_t x, int lane)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// The plain form: every chunk from the counter, which counts from 0 (the
-// queue starts empty, {0, 0}).  The FP64 descent uses it: the static first
-// chunk costs it two VGPRs, past its 64 (one wave per SIMD less).
+// The plain form: every chunk from the counter as it stands.  The FP64
+// descent uses it with the static first chunk (wave_queue_start) and a
+// counter the host sets to W chunk beforehand (k_set_counter): computing
+// that base in the kernel costs it two VGPRs, past its 64 (one wave per SIMD
+// less).
 __device__ __forceinline__ uint64_t wave_take_plain(wave_queue &q, unsigned long long *counter, uint64_t chunk,
                                                     bool need)
 {

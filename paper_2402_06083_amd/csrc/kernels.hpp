@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
     double prev = 0.0; // previous squared step length
     int it = 0, it0 = 0;
     bool fin = false, stall = false;
-    wave_queue wq = {0, 0};
+    wave_queue wq = wave_queue_start(b.chunk_start);
     unsigned long long *counter = &b.gctr[AFTER32 ? G_START_NEXT2 : G_START_NEXT];
     while (true) {
         const bool need = !exhausted && g == NONE;

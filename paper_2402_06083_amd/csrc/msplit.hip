@@ -622,11 +622,16 @@ void enqueue_descents(const batch_call &c, const pipe_bufs &B, hipStream_t strea
     // the starts, or the FP32 pass's results after the steps in iters (for
     // the types the FP32 pass runs on; without such a type it is skipped)
     const int nb = persistent_blocks(bp.n_starts, bs);
+    // the FP64 descent's queue: every wave starts on its static chunk, the
+    // counter hands out the chunks after them
+    const unsigned long long q0 = (unsigned long long)nb * (bs / 64) * ba.chunk_start;
     if (ba.n_fp32 > 0) {
         k_descend32<<<persistent_blocks(ba.n_fp32, bs), bs, 0, stream>>>(ba, B.roots, B.status, B.iters);
+        k_set_counter<<<1, 64, 0, stream>>>(&ba.gctr[G_START_NEXT2], q0);
         if (c.any_tip) k_descend<true, true><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
         else k_descend<false, true><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
     } else {
+        k_set_counter<<<1, 64, 0, stream>>>(&ba.gctr[G_START_NEXT], q0);
         if (c.any_tip) k_descend<true, false><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
         else k_descend<false, false><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
     }
