@@ -42,8 +42,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false, false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1266265954.1
-DESCEND_TRAFFIC_SHA256 = "1664a303682b013b415b1d4a4546e4e95a974797a9ed7a1a5039df185d415801"
+DESCEND_TRAFFIC_BYTES = 1267655817.1
+DESCEND_TRAFFIC_SHA256 = "a74a87bc9bbbbc59a502f433924530840572bf349225ab9915290e897901dd43"
 
 
 def descend_traffic():

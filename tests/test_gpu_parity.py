@@ -403,6 +403,41 @@ def test_misiurewicz_batch_mixed_precision():
         assert st["total"] == counts.mis_count(l, n) if l else st["total"] == 2 ** (n - 1)
 
 
+def test_mixed_batch_equals_fp64_eligible_types_interleaved():
+    """MIXED on a batch whose FP32-eligible types (p_n, n <= 20) lie between
+    types without an FP32 pass (p_21, q_{l,n}): the FP32 pass runs over the
+    eligible starts alone (its own index space), the others descend in FP64
+    from the walk's first iterate; per type the same certified roots as the
+    FP64 run (same count and period labels, roots within 1e-12), FP32 steps
+    on the eligible types only."""
+    from paper_2402_06083_amd import batch, msplit
+    pairs = [(0, 21), (0, 12), (3, 9), (0, 9), (2, 10), (0, 17)]
+    runs = {}
+    for prec in ("fp64", "mixed"):
+        say(f"[gpu] interleaved batch {prec}")
+        opts = msplit.make_options(precision=prec, certify=True, fp32_switch=2.0 ** -4)
+        r = batch.BatchRunner(pairs, opts)
+        assert r.run() == 0
+        torch.cuda.synchronize()
+        runs[prec] = r
+    for i, (l, n) in enumerate(pairs):
+        a, b = runs["fp64"], runs["mixed"]
+        sa, sb = a.stats[i].as_dict(), b.stats[i].as_dict()
+        assert sa["missing"] == sb["missing"] == 0 and sb["certified"] == int(b.counts[i]), (l, n, sb)
+        assert int(a.counts[i]) == int(b.counts[i]), (l, n)
+        eligible = l == 0 and n <= 20
+        assert (sb["steps_fp32"] > 0) == eligible and sa["steps_fp32"] == 0, (l, n, sb["steps_fp32"])
+        za, zb = a.slices(i), b.slices(i)
+        ra, ia = a.re[za].cpu().numpy(), a.im[za].cpu().numpy()
+        rb, ib = b.re[zb].cpu().numpy(), b.im[zb].cpu().numpy()
+        oa, ob = np.lexsort((ia, ra)), np.lexsort((ib, rb))
+        d = np.abs((ra[oa] - rb[ob]) + 1j * (ia[oa] - ib[ob]))
+        assert d.max() <= 1e-12, (l, n, d.max())
+        assert np.array_equal(a.period[za].cpu().numpy()[oa], b.period[zb].cpu().numpy()[ob]), (l, n)
+    for r in runs.values():
+        r.close()
+
+
 def test_autotuner_picks_a_complete_configuration(tmp_path):
     """The autotuner times candidate launch parameters on a batch, rejects
     incomplete splits and caches the fastest; the cached options split the
