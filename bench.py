@@ -148,18 +148,30 @@ def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=F
 
 
 def _time_runner(runner, pairs, steps, warmup, mode, simple=False):
+    """The timed region holds the K calls (each ends with the library's one
+    host synchronisation) and a byte copy of each call's counts and stats;
+    they are checked and summed after it, call by call."""
+    import ctypes
     import torch
     from paper_2402_06083_amd import msplit
     call = runner.launch if mode == "graph" else runner.run
     for _ in range(warmup):
         r = call()
     torch.cuda.synchronize()
+    snap = lambda a: ctypes.string_at(ctypes.addressof(a), ctypes.sizeof(a))
+    shots = []
     t0 = time.perf_counter()
-    agg = None
     for _ in range(steps):
         r = call()
+        shots.append((r, snap(runner.counts), snap(runner.stats)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    agg = None
+    for r, counts, stats in shots:
         if r not in (0,):
             raise RuntimeError(f"msplit_batch failed: {msplit.strerror(r)}")
+        ctypes.memmove(ctypes.addressof(runner.counts), counts, len(counts))
+        ctypes.memmove(ctypes.addressof(runner.stats), stats, len(stats))
         res = runner.result(r)
         sts = [st for (_, st, _) in res.per_pair]
         d, td, w, tw = kernel_flops(pairs, sts, simple)
@@ -180,8 +192,6 @@ def _time_runner(runner, pairs, steps, warmup, mode, simple=False):
         agg["ms_device"] += sts[0]["ms_device"]
         for k, v in sts[0]["ms_stage"].items():
             agg["stages"][k] += v
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
     wall = t1 - t0
     agg["wall"] = wall
     agg["last_stats"] = sts
