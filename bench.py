@@ -43,7 +43,7 @@ FLOPS_WALK_UPDATE = 62
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
 DESCEND_TRAFFIC_BYTES = 1267655817.1
-DESCEND_TRAFFIC_SHA256 = "a74a87bc9bbbbc59a502f433924530840572bf349225ab9915290e897901dd43"
+DESCEND_TRAFFIC_SHA256 = "cc9a86c18e78556b85e6024991adacbc0e3b868ae490af24a40e42e1ac766b6d"
 
 
 def descend_traffic():

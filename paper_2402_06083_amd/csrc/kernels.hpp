@@ -413,8 +413,10 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
 // written (its P and P' were evaluated there), so the descent begins at the
 // first iterate with one step counted.
 //
-// MIXED precision runs k_descend32 first over all starts: FP32 Newton steps
-// while the step exceeds fp32_switch * max(|z|, 2^-8).  The rounding noise of
+// MIXED precision runs k_descend32 first, over the starts of the types with
+// an FP32 pass (fp32_eligible; their own index space, fp32_offs), from the
+// first iterates: FP32 Newton steps while the step exceeds
+// fp32_switch * max(|z|, 2^-8).  The rounding noise of
 // an FP32 Newton step of p_n is about 8 u |z| (the orbit's error grows like
 // its derivative), far below that threshold, so FP32 only takes the steps it
 // resolves.  A start whose first FP32 step is already below the threshold --
