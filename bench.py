@@ -15,6 +15,14 @@ l + n <= 22, all 210 types in one batch) is measured next to them through
 q_{l,n} and through the simplified s_{l,n} = p_{l+n-1} + p_{l-1}, and is
 available as the headline with --workload.
 
+Beside them: p_10, and p_20 in FP64 against FP32 steps then FP64.  After
+the timed runs the CPU oracle splits and certifies the headline workload on
+the host's cores (``cpu_baseline``), and every configuration up to order 24
+is compared with the oracle's roots (``accuracy``: max |gpu - oracle| and
+that distance over the local root separation).  Every timed call must prove
+its root sets (exact counts, every root certified, disks quarter-separated,
+radius <= 1e-10), else the run fails.
+
 Prints one JSON line (metric, value, roofline of the dominant kernel, CPU
 oracle baseline).
 """
@@ -66,16 +74,19 @@ WORKLOADS = {
 }
 
 
-def certified_roots(stats_list):
-    """Roots counted as roots of P (p_n: all 2^(n-1); q_{l,n}: |Mis(l,n)|):
-    a certified non-real root in the upper half plane stands for itself and
-    its conjugate."""
+def certified_roots(pairs, stats_list, what):
+    """Roots counted as roots of P (p_n: all 2^(n-1); q_{l,n}: |Mis(l,n)|),
+    a non-real root in the upper half plane standing for itself and its
+    conjugate -- counted only when the type's root set is proven (Thm
+    certif: exact count, every root certified with its label, disks
+    quarter-separated, radius <= 1e-10); otherwise the run fails."""
+    from paper_2402_06083_amd import batch
     tot = 0
-    for st in stats_list:
-        if st["certified"] == st["unique"]:
-            tot += st["total"]
-        else:
-            tot += st["certified"]  # conservative
+    for (l, n), st in zip(pairs, stats_list):
+        why = batch.unproven(st)
+        if why:
+            raise RuntimeError(f"{what}: the split of ({l},{n}) is not proven: {'; '.join(why)}")
+        tot += st["total"]
     return tot
 
 
@@ -125,11 +136,20 @@ def torch_ones_like(t):
     return torch.ones_like(t, dtype=torch.bool)
 
 
-def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=False, simple=False):
+def host_roots(runner, i):
+    """Host copy of type i's roots from the last call (for the comparison
+    with the oracle after the timed region)."""
+    sl = runner.slices(i)
+    return {k: getattr(runner, k)[sl].cpu().numpy() for k in ("re", "im", "re_lo", "im_lo", "period", "flags",
+                                                               "radius")}
+
+
+def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=False, simple=False, keep=False):
     """eager: every call enqueued by msplit_batch (stage times from HIP
     events on the call's stream); graph: the call captured once as a
     hipGraph and replayed (msplit_graph_launch: total device time only).
-    tuned: launch parameters from the autotuner (dict of option fields)."""
+    tuned: launch parameters from the autotuner (dict of option fields).
+    keep: host copies of the p_n roots of the last call (agg["roots_of"])."""
     import torch
     from paper_2402_06083_amd import batch, msplit
     opts = msplit.make_options(precision=precision, certify=True, basin=basin, simple=simple, **(tuned or {}))
@@ -141,6 +161,8 @@ def run_gpu(pairs, precision, steps, warmup, launch="eager", tuned=None, basin=F
     agg["launch"] = mode
     if mode == "eager":
         agg["distinct"] = distinct_parameters(runner)
+    if keep:
+        agg["roots_of"] = {n: host_roots(runner, i) for i, (l, n) in enumerate(pairs) if l == 0}
     runner.close()
     del runner
     torch.cuda.empty_cache()
@@ -176,7 +198,7 @@ def _time_runner(runner, pairs, steps, warmup, mode, simple=False):
         sts = [st for (_, st, _) in res.per_pair]
         d, td, w, tw = kernel_flops(pairs, sts, simple)
         d64, d32 = descent_flops_by_precision(pairs, sts, simple)
-        cr = certified_roots(sts)
+        cr = certified_roots(pairs, sts, "timed call")
         if agg is None:
             agg = dict(desc=0.0, t_desc=0.0, walk=0.0, t_walk=0.0, roots=0, ms_device=0.0,
                        stages={k: 0.0 for k in msplit.Stats.STAGES})
@@ -238,9 +260,13 @@ def run_streamed(n, steps=1, warmup=1):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     st = r.stats
-    ok = r.status == 0 and st["certified"] == st["unique"]
-    res = {"value": (st["total"] if ok else 0) / wall, "ms_per_step": 1e3 * wall, "status": r.status,
+    from paper_2402_06083_amd import batch
+    why = batch.unproven(st) if r.status == 0 else [f"status {r.status}"]
+    if why:
+        raise RuntimeError(f"streamed p_{n}: the split is not proven: {'; '.join(why)}")
+    res = {"value": st["total"] / wall, "ms_per_step": 1e3 * wall, "status": r.status,
            "roots": st["total"], "certified_upper_half": st["certified"], "dd_routed": st["dd_routed"],
+           "max_certified_radius": st["max_radius"], "min_sep": st["min_sep"],
            "stage_ms": {k: round(v, 1) for k, v in st["ms_stage"].items()},
            "workspace_bytes": b.ws_bytes}
     del r, b
@@ -271,20 +297,87 @@ def blended_roofline(agg):
             "fp32_share_of_flops": f32 / (f32 + f64) if f32 + f64 else 0.0}
 
 
-def cpu_baseline():
-    """The oracle as it stands on this host's cores, on a bounded sample of
-    the same workload: p_1..p_20 split and every root certified."""
+def host_info():
+    """CPU model, hardware threads and RAM of this host (for the record)."""
+    model, ram = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_threads": os.cpu_count(), "ram_gib": ram}
+
+
+def cpu_baseline(max_n=24):
+    """The oracle as it stands on this host's cores, on the headline
+    workload: p_1..p_max_n split and every root certified (long double, its
+    own OpenMP threads).  Returns the record and the oracle's roots, which
+    the accuracy check then compares with the GPU's."""
     import oracle
     t0 = time.perf_counter()
     roots = 0
-    for n in range(1, 21):
+    splits = {}
+    for n in range(1, max_n + 1):
         r = oracle.split(0, n)
         ok, rad = oracle.certify(0, n, r.re_hi, r.im_hi, r.re_lo, r.im_lo, r.period)
         nr = int((r.im_hi[ok & 1 == 1] == 0).sum())
         roots += nr + 2 * (int((ok & 1).sum()) - nr)
+        splits[n] = r
     dt = time.perf_counter() - t0
-    return {"value": roots / dt, "unit": "certified roots/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"p_1..p_20 split and certified by the long-double oracle ({roots} roots, {dt:.1f} s)"}
+    rec = {"value": roots / dt, "unit": "certified roots/s", "cores": oracle.max_threads(), "kind": "oracle",
+           "sample": f"the whole headline workload: p_1..p_{max_n} split and certified by the long-double "
+                     f"oracle ({roots} roots, {dt:.1f} s)", **host_info()}
+    return rec, splits
+
+
+def error_vs_oracle(g, o):
+    """Max |gpu - oracle| over a nearest-neighbour matching of the GPU roots g
+    (dict of host arrays) onto the oracle's o, the max of that distance over
+    the local separation of the oracle root (nearest other root or
+    conjugate), and whether the sets are identical in the tested sense (same
+    count, a bijection, every distance <= 1e-10 and <= a quarter of the
+    separation, equal period labels and real flags)."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    if len(g["re"]) != len(o.re_hi):
+        return {"identical": False, "why": f"count {len(g['re'])} against {len(o.re_hi)}"}
+    tree = cKDTree(np.stack([o.re_hi, o.im_hi], axis=1))
+    d, idx = tree.query(np.stack([g["re"], g["im"]], axis=1), k=1)
+    if len(o.re_hi) > 1:
+        sep = tree.query(np.stack([o.re_hi, o.im_hi], axis=1), k=2)[0][:, 1]
+    else:
+        sep = np.full(1, np.inf)
+    sep = np.minimum(sep, np.where(o.im_hi > 0, 2 * o.im_hi, np.inf))
+    ratio = d / sep[idx]
+    identical = (len(np.unique(idx)) == len(idx) and d.max() <= 1e-10 and ratio.max() <= 0.25
+                 and np.array_equal(g["period"], o.period[idx]) and np.array_equal(g["im"] == 0, o.im_hi[idx] == 0))
+    return {"identical": bool(identical), "max_abs": float(d.max()), "max_over_sep": float(ratio.max())}
+
+
+def accuracy(roots_of, splits):
+    """Per-workload error against the oracle: the worst type."""
+    worst = {"identical": True, "max_abs": 0.0, "max_over_sep": 0.0, "types_compared": 0}
+    for n, g in sorted(roots_of.items()):
+        if n not in splits:
+            continue
+        e = error_vs_oracle(g, splits[n])
+        worst["types_compared"] += 1
+        if not e["identical"]:
+            worst["identical"] = False
+            worst.setdefault("differs", []).append(n)
+        for k in ("max_abs", "max_over_sep"):
+            if k in e:
+                worst[k] = max(worst[k], e[k])
+    worst["max_certified_radius"] = max(float(g["radius"].max()) for g in roots_of.values())
+    return worst
 
 
 def main():
@@ -312,6 +405,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the tuned ones")
     ap.add_argument("--retune", action="store_true",
                     help="run the autotuner before the timed steps even when a tuning is cached")
+    ap.add_argument("--no-small", action="store_true", help="skip the p_10 and p_20 lines")
+    ap.add_argument("--small-steps", type=int, default=20)
+    ap.add_argument("--cpu-max-n", type=int, default=24,
+                    help="the oracle baseline splits and certifies p_1..p_N (default: the headline workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (scale of the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -332,7 +429,8 @@ def main():
     if not args.no_tune:
         tuned, tune_info = autotune(pairs, main_prec, None if args.no_compare else other, args.retune,
                                     args.simple)
-    res = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager", tuned[main_prec], simple=args.simple)
+    res = run_gpu(pairs, main_prec, args.steps, args.warmup, "eager", tuned[main_prec], simple=args.simple,
+                  keep=True)
     value = res["roots"] / res["wall"]
     ms_per_step = 1e3 * res["wall"] / args.steps
     # dominant kernel: the stage with the larger device time
@@ -387,11 +485,34 @@ def main():
                         "roots_with_basin_per_step": rb["basin"] // args.steps,
                         "what": "the same workload with a proven disk of Newton convergence around every "
                                 "certified root (Thm proofContract, MSPLIT_F_BASIN)"}
+    kept = {"main": res.pop("roots_of")}
     if not args.no_compare:
-        r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager", tuned[other], simple=args.simple)
+        r2 = run_gpu(pairs, other, args.steps, args.warmup, "eager", tuned[other], simple=args.simple, keep=True)
+        kept[other] = r2.pop("roots_of")
         out[other] = {"value": r2["roots"] / r2["wall"], "ms_per_step": 1e3 * r2["wall"] / args.steps,
                       "stage_ms_per_step": {k: v / args.steps for k, v in r2["stages"].items()},
                       "descent_roofline": blended_roofline(r2)}
+    # the small configurations: p_10, and p_20 in FP64 against FP32 -> FP64
+    small = {}
+    if not args.no_small:
+        for name, n in (("p10", 10), ("p20", 20)):
+            sp = [(0, n)]
+            ts = {"fp64": None, "mixed": None}
+            if not args.no_tune:
+                ts, info = autotune(sp, "fp64", "mixed", args.retune)
+                tune_info[name] = info
+            small[name] = {}
+            for prec in ("fp64", "mixed"):
+                rs = run_gpu(sp, prec, args.small_steps, args.warmup, "eager", ts[prec], keep=True)
+                small[name][prec] = {"value": rs["roots"] / rs["wall"],
+                                     "ms_per_step": 1e3 * rs["wall"] / args.small_steps,
+                                     "device_ms_per_step": rs["ms_device"] / args.small_steps,
+                                     "steps_fp32_per_root": rs["last_stats"][0]["steps_fp32"] / rs["roots"]
+                                     * args.small_steps}
+                kept[f"{name}_{prec}"] = rs.pop("roots_of")
+        out["p10"] = {"workload": "p_10, all 512 roots certified", "unit": "certified roots/s", **small["p10"]}
+        out["p20"] = {"workload": "p_20, all 524 288 roots certified: plain FP64 against FP32 steps then FP64",
+                      "unit": "certified roots/s", **small["p20"]}
     if not args.no_p30 and args.workload != "p30":
         p30 = {}
         p30_pairs = WORKLOADS["p30"][1]
@@ -401,10 +522,19 @@ def main():
             tune_info["p30"] = i30
         for prec in ([main_prec] if args.no_compare else [main_prec, other]):
             r3 = run_gpu(p30_pairs, prec, args.p30_steps, 1, "eager", t30[prec])
+            st = r3["last_stats"][0]
             p30[prec] = {"value": r3["roots"] / r3["wall"], "ms_per_step": 1e3 * r3["wall"] / args.p30_steps,
                          "roots_per_step": r3["roots"] // args.p30_steps,
-                         "stage_ms_per_step": {k: v / args.p30_steps for k, v in r3["stages"].items()}}
-        out["p30"] = {"workload": WORKLOADS["p30"][0], "unit": "certified roots/s", **p30}
+                         "stage_ms_per_step": {k: v / args.p30_steps for k, v in r3["stages"].items()},
+                         "max_certified_radius": st["max_radius"], "min_sep": st["min_sep"],
+                         "steps_fp32": st["steps_fp32"]}
+            if prec == "mixed":
+                p30[prec]["same_work_as_fp64"] = True
+                p30[prec]["note"] = ("FP32 steps run on p_n of order <= 20 only: at order 30 the mixed "
+                                     "call runs the FP64 kernels, and its rate differs from FP64 by noise")
+        out["p30"] = {"workload": WORKLOADS["p30"][0], "unit": "certified roots/s",
+                      "accuracy": "every root certified in a disk of radius <= max_certified_radius; "
+                                  "parity with the oracle: tests/test_gpu_oracle_exact.py", **p30}
     if not args.no_mis22 and args.workload != "mis22":
         m22 = {}
         m_pairs = WORKLOADS["mis22"][1]
@@ -432,7 +562,22 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"], splits = cpu_baseline(args.cpu_max_n)
+        # error against the oracle, per configuration (the worst type)
+        acc = {}
+        if args.workload == "batch24":
+            acc["batch24_" + main_prec] = accuracy(kept["main"], splits)
+            if other in kept:
+                acc["batch24_" + other] = accuracy(kept[other], splits)
+        for name, n in (("p10", 10), ("p20", 20)):
+            for prec in ("fp64", "mixed"):
+                if f"{name}_{prec}" in kept:
+                    acc[f"{name}_{prec}"] = accuracy(kept[f"{name}_{prec}"], splits)
+        out["accuracy"] = {"what": "max |gpu - oracle| and max |gpu - oracle| / local separation over a "
+                                   "nearest-neighbour matching with the oracle's roots (long double, "
+                                   "double-double polish), per configuration; identical = same count, a "
+                                   "bijection within 1e-10 and a quarter of the separation, equal period "
+                                   "labels and real flags", **acc}
     print(json.dumps(out), flush=True)
 
 

@@ -219,7 +219,11 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
 int msplit_starts(int l, int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes,
                   double *re, double *im, uint64_t capacity, uint64_t *count, msplit_stats *stats, void *stream);
 
-/* Split a list of types in one call: ln_pairs holds npairs (l, n) pairs
+/* Split a list of types in one call (Section 6.4.1: the raw searches of many
+ * polynomials, each a set of independent tasks over pieces of its level line,
+ * then the merge of what they found; here every piece of every type is an
+ * item of one device work queue per stage, and the merge is one sort):
+ * ln_pairs holds npairs (l, n) pairs
  * (l = 0 for p_n), 1 <= npairs <= 256; all types share one launch per
  * stage and the host synchronises once, at the end.  Roots of pair i are
  * written at out[offsets[i] .. offsets[i] + counts[i]) where offsets[i] is

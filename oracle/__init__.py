@@ -63,6 +63,8 @@ def lib():
     L.oracle_basin_check.restype = None
     L.oracle_check_set.argtypes = [i64, d_p, d_p, d_p, i64_p, d_p]
     L.oracle_check_set.restype = None
+    L.oracle_check_set_dd.argtypes = [i64, d_p, d_p, d_p, d_p, d_p, i64_p, d_p]
+    L.oracle_check_set_dd.restype = None
     L.oracle_disk_enclosure.argtypes = [ctypes.c_int, ctypes.c_int, ld_p, ld_p]
     L.oracle_disk_enclosure.restype = None
     L.oracle_max_threads.argtypes = []
@@ -205,17 +207,30 @@ def disk_enclosure(l: int, n: int, c, R):
     return dict(P=(out[0], out[1]), eP=out[2], dP=(out[3], out[4]), sigma=out[5], rho=out[6])
 
 
-def check_set(re, im, radius):
-    """Global part of Thm certif on a lexicographically sorted list:
-    returns dict(disjoint, quarter, n_real, n_complex, min_sep)."""
+def check_set(re, im, radius, re_lo=None, im_lo=None):
+    """Global part of Thm certif on a list of certified roots (closed upper
+    half plane): returns dict(disjoint, quarter, n_real, n_complex, min_sep).
+    With re_lo / im_lo a root is the double-double value re + re_lo,
+    im + im_lo (compared in long double).  The list is sorted here by real
+    part (the scan needs only that order)."""
     re = np.ascontiguousarray(re, dtype=np.float64)
     im = np.ascontiguousarray(im, dtype=np.float64)
     radius = np.ascontiguousarray(radius, dtype=np.float64)
-    order = np.lexsort((im, re))
-    re, im, radius = re[order], im[order], radius[order]
     out = np.zeros(4, dtype=np.int64)
     ms = ctypes.c_double()
-    lib().oracle_check_set(len(re), _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
-                           _ptr(radius, ctypes.c_double), _ptr(out, ctypes.c_int64), ctypes.byref(ms))
+    if re_lo is None and im_lo is None:
+        order = np.lexsort((im, re))
+        re, im, radius = re[order], im[order], radius[order]
+        lib().oracle_check_set(len(re), _ptr(re, ctypes.c_double), _ptr(im, ctypes.c_double),
+                               _ptr(radius, ctypes.c_double), _ptr(out, ctypes.c_int64), ctypes.byref(ms))
+    else:
+        rl = np.zeros_like(re) if re_lo is None else np.ascontiguousarray(re_lo, dtype=np.float64)
+        il = np.zeros_like(im) if im_lo is None else np.ascontiguousarray(im_lo, dtype=np.float64)
+        # (hi, lo) order is the order of hi + lo for canonical double-doubles
+        order = np.lexsort((rl, re))
+        re, im, radius, rl, il = re[order], im[order], radius[order], rl[order], il[order]
+        lib().oracle_check_set_dd(len(re), _ptr(re, ctypes.c_double), _ptr(rl, ctypes.c_double),
+                                  _ptr(im, ctypes.c_double), _ptr(il, ctypes.c_double),
+                                  _ptr(radius, ctypes.c_double), _ptr(out, ctypes.c_int64), ctypes.byref(ms))
     return dict(disjoint=bool(out[0]), quarter=bool(out[1]), n_real=int(out[2]),
                 n_complex=int(out[3]), min_sep=ms.value)

@@ -438,7 +438,7 @@ static int make_starts(const method_t *m, cld *starts, start_stats *st)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Newton descent (Section 4.2, Algorithm S_par; discard rules Section 6.4.3) */
+/* Newton descent (Section 4.2, Algorithm S_par; discard rules Section 6.4.2) */
 /* ------------------------------------------------------------------------- */
 enum { D_CONVERGED = 1, D_DIVERGED = 2, D_TIMEOUT = 3 };
 
@@ -1015,18 +1015,23 @@ void oracle_basin_check(int l, int n, int64_t count, const double *re, const dou
 /* Global checks of Thm certif on a certified list (closed upper half plane,
  * sorted lexicographically by the caller): disks pairwise disjoint, disjoint
  * from their conjugates unless centred on the real axis, and, with the
- * quarter-separation reading, |z_i - z_j| >= 4 max(R_i, R_j).
+ * quarter-separation reading, |z_i - z_j| >= 4 max(R_i, R_j).  A root is
+ * re[i] + re_lo[i], im[i] + im_lo[i] (the low parts may be NULL: zero),
+ * summed in long double, so that double-double roots closer than the FP64
+ * spacing (next to -2, Section 6.3.2) stay apart.
  * out[0] = 1 if disjoint, out[1] = 1 if quarter-separated, out[2] = #real,
  * out[3] = #non-real; min_sep = least distance among the roots and their
  * conjugates (double). */
-void oracle_check_set(int64_t count, const double *re, const double *im, const double *radius,
-                      int64_t *out, double *min_sep)
+void oracle_check_set_dd(int64_t count, const double *re, const double *re_lo, const double *im,
+                         const double *im_lo, const double *radius, int64_t *out, double *min_sep)
 {
     int64_t disjoint = 1, quarter = 1, nreal = 0, ncplx = 0;
     ld Rmax = 0, best = INFINITY;
+#define X_(k) ((ld)re[k] + (re_lo ? (ld)re_lo[k] : 0.0L))
+#define Y_(k) ((ld)im[k] + (im_lo ? (ld)im_lo[k] : 0.0L))
     for (int64_t i = 0; i < count; i++) Rmax = fmaxl(Rmax, radius[i]);
     for (int64_t i = 0; i < count; i++) {
-        ld xi = re[i], yi = im[i], Ri = radius[i];
+        ld xi = X_(i), yi = Y_(i), Ri = radius[i];
         if (yi == 0) nreal++;
         else {
             ncplx++;
@@ -1035,8 +1040,8 @@ void oracle_check_set(int64_t count, const double *re, const double *im, const d
             best = fminl(best, 2 * yi);
         }
         ld win = fmaxl(4 * (Ri + Rmax), best) * (1 + 1e-12L);
-        for (int64_t j = i + 1; j < count && (ld)re[j] - xi <= win; j++) {
-            ld dx = (ld)re[j] - xi, dy = (ld)im[j] - yi;
+        for (int64_t j = i + 1; j < count && X_(j) - xi <= win; j++) {
+            ld dx = X_(j) - xi, dy = Y_(j) - yi;
             ld d = sqrtl(dx * dx + dy * dy);
             ld Rj = radius[j];
             if (d < best) best = d;
@@ -1045,8 +1050,16 @@ void oracle_check_set(int64_t count, const double *re, const double *im, const d
             win = fmaxl(4 * (Ri + Rmax), best) * (1 + 1e-12L);
         }
     }
+#undef X_
+#undef Y_
     out[0] = disjoint; out[1] = quarter; out[2] = nreal; out[3] = ncplx;
     *min_sep = (double)best;
+}
+
+void oracle_check_set(int64_t count, const double *re, const double *im, const double *radius,
+                      int64_t *out, double *min_sep)
+{
+    oracle_check_set_dd(count, re, NULL, im, NULL, radius, out, min_sep);
 }
 
 int oracle_max_threads(void)

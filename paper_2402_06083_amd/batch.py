@@ -10,6 +10,31 @@ import torch
 from . import msplit
 
 
+# the stated accuracy of a certified root: the radius of its unique-root disk
+RADIUS_MAX = 1e-10
+
+
+def unproven(st, certify=True, labels=True):
+    """Why a type's split does not prove its root set (empty when it does).
+    By Thm certif (Section 6.2) the list is the root set when every root has
+    a disk holding exactly one root of P, the disks are pairwise disjoint
+    (here quarter-separated) and the count equals the degree (|Mis(l,n)| for
+    q_{l,n}); the stated accuracy is radius <= 1e-10."""
+    why = []
+    if st["missing"] or st["total"] != st["expected"]:
+        why.append(f"count {st['total']} of {st['expected']}")
+    if certify:
+        if st["certified"] != st["unique"]:
+            why.append(f"certified {st['certified']} of {st['unique']}")
+        if labels and st["label_proven"] != st["unique"]:
+            why.append(f"labels proven {st['label_proven']} of {st['unique']}")
+        if st["overlaps"]:
+            why.append(f"{st['overlaps']} disks not quarter-separated")
+        if not st["max_radius"] <= RADIUS_MAX:
+            why.append(f"radius {st['max_radius']:.3g} > {RADIUS_MAX:g}")
+    return why
+
+
 class BatchResult:
     def __init__(self, pairs, caps, counts, stats, statuses, bufs):
         self.pairs = pairs

@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
 // One lane per start, Newton map N_P (eq. Newton), cap max{20, I_N log d}
 // (Algorithm S_par).  Discarded as divergent: non-finite, |z| > 8 (far from
 // M, which lies in D(0,2) u {-2}), or a long-distance jump (step more than 8
-// times the previous one after the third step, Section 6.4.3).  Converged
+// times the previous one after the third step, Section 6.4.2).  Converged
 // when the step falls below tol * max(|z|, 2^-8); one more step is taken
 // unless quadratic convergence predicts the next step below the rounding.
 // In FP64 the first step from every start was taken where the start was
@@ -615,7 +615,10 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
         const double az2 = cabs2(z);
         // (the jump test counts the steps from the start, the first one or
         // the FP32 pass included, and needs a previous step of this descent)
-        const bool bad = !(a2 <= 0x1p1000) || !(az2 <= 64.0) || (it > 3 && it > it0 + 1 && a2 > 64.0 * prev);
+        // wild: non-finite, or far outside M; such an iterate is never kept,
+        // not even as the extra step after a small one (a P' = 0 there)
+        const bool wild = !(a2 <= 0x1p1000) || !(az2 <= 64.0);
+        const bool bad = wild || (it > 3 && it > it0 + 1 && a2 > 64.0 * prev);
         // converged once a step is small.  At a simple root the next step
         // would be about K |d|^2 with K = |d| / |d_prev|^2 (quadratic
         // convergence): when that is below the FP64 rounding of z the point
@@ -632,8 +635,8 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
             const bool ill = dp2 * fmax(az2, 0x1p-16) > 0x1p84;
             stall = pl_route && (slow || ill);
         }
-        const uint8_t st = fin || done ? (stall ? ST_STALL : ST_CONVERGED)
-                                       : bad ? ST_DIVERGED : (!small && it >= pl_cap) ? ST_TIMEOUT : ST_NONE;
+        const uint8_t st = (fin || done) && !wild ? (stall ? ST_STALL : ST_CONVERGED)
+                           : bad ? ST_DIVERGED : (!small && it >= pl_cap) ? ST_TIMEOUT : ST_NONE;
         fin = small;
         prev = a2;
         cnt[0] += 1u;
@@ -745,7 +748,7 @@ __device__ __forceinline__ void load_tables_lds(collect_tables &c, const batch_a
 // (Section 6.1, nset), and drop a start whose root repeats the root of one
 // of the PREKEY_WINDOW previous converged starts of the same type: the starts
 // of one level-line turn mostly reach the same root (73% repeats, Section
-// 6.4.3), so this local identification removes most duplicates before the
+// 6.4.2), so this local identification removes most duplicates before the
 // sort.  A block stages its starts and the window before them in LDS; every
 // global load is issued before the first wait.
 constexpr int PREKEY_WINDOW = 8;

@@ -183,7 +183,7 @@ class Result:
             d[k] = t.cpu().numpy() if t is not None else None
         d["stats"] = self.stats
         d["status"] = self.status
-        return type("HostRoots", (), d)() if False else _Host(**d)
+        return _Host(**d)
 
 
 class _Host:

@@ -11,8 +11,9 @@ the work distribution, never the set of starting points, Section 4.1):
 - ``fp32_switch``     MIXED only: relative step at which a lane leaves FP32.
 
 Each candidate runs the whole batch through ``msplit_batch`` (device time
-from the call's own events); a candidate whose split is not complete and
-certified is rejected.  The best options are cached per
+from the call's own events); a candidate whose split is not proven (exact
+count, every root certified with its label, disks quarter-separated, radius
+<= 1e-10: ``batch.unproven``) is rejected.  The best options are cached per
 (GPU architecture, list of types, precision, polynomial: q_{l,n} or the
 simplified s_{l,n}) in a JSON file:
 ``$MSPLIT_TUNE_CACHE``, else ``~/.cache/msplit/tune.json``.  Lookups also
@@ -123,7 +124,7 @@ def tune(pairs, precision="fp64", space=None, repeats=2, path=None, certify=True
             r = runner.run()
             torch.cuda.synchronize()
             sts = [s.as_dict() for s in runner.stats]
-            if r != 0 or any(s["missing"] or (certify and s["certified"] != s["unique"]) for s in sts):
+            if r != 0 or any(batch.unproven(s, certify) for s in sts):
                 ok = False
                 break
             ms.append(sts[0]["ms_device"])

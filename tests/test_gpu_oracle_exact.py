@@ -1,0 +1,275 @@
+"""The headline workloads against the oracle, through the C ABI.
+
+- p_1..p_24 in one msplit_batch call with the launch options the benchmark
+  uses (the tuned cache entry), FP64 and mixed: every type compared root by
+  root with ``oracle.split`` (same count, nearest-neighbour bijection within
+  1e-10 and a quarter of the local separation, identical period labels and
+  real flags), every root certified with its period proven, quarter-separated,
+  radius <= 1e-10, exact per-period counts (eq. HypCount).
+- p_25, the first order whose tip goes through double-double: compared root by
+  root with the oracle, double-double roots to 1e-25.
+- p_30 (2^29 roots): the GPU certificate on every root, exact per-period
+  counts, the oracle's set check (Thm certif: disjoint, quarter-separated
+  disks, count = degree) over the whole double-double list, and the oracle's
+  own certificate on the double-double roots, on the roots next to -2 and on
+  a uniform sample.  With MSPLIT_FULL_ORACLE=1 the oracle certifies every
+  root and the set check runs on the oracle's radii: by Thm certif that
+  proves the whole set with oracle arithmetic alone (about ten minutes of
+  the host's cores).
+- a batch mixing p_n and Misiurewicz types, through q_{l,n} and through
+  s_{l,n}, and the streamed split, each compared with the oracle type by type.
+- all 210 Misiurewicz types of order <= 22: every root certified again by
+  the oracle and the set check per type.
+- the incomplete-split path: descents capped at one step through the normal
+  options must end in MSPLIT_E_INCOMPLETE with the roots still written.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import counts
+from parity import Host, compare_sets, oracle_split, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+RADIUS_MAX = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_06083_amd import msplit
+    msplit.lib()  # raises if the HIP library is missing
+    return torch.device("cuda:0")
+
+
+def check_type_stats(l, n, st, count):
+    assert st["missing"] == 0, ((l, n), st)
+    exp = 2 ** (n - 1) if l == 0 else counts.mis_count(l, n)
+    assert st["total"] == exp, ((l, n), st)
+    assert st["certified"] == count and st["label_proven"] == count, ((l, n), st)
+    assert st["overlaps"] == 0 and st["max_radius"] <= RADIUS_MAX, ((l, n), st)
+
+
+def check_period_counts(g, n):
+    for k in counts.divisors(n):
+        sel = g.period == k
+        cnt = int((g.im[sel] == 0).sum()) + 2 * int((g.im[sel] > 0).sum())
+        assert cnt == counts.hyp_count(k), (n, k, cnt)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_headline_batch_matches_oracle(precision):
+    """p_1..p_24, one msplit_batch call in the benchmark's launch
+    configuration, root by root against the oracle."""
+    from paper_2402_06083_amd import batch, tune
+    pairs = [(0, n) for n in range(1, 25)]
+    opts, cand = tune.tuned_options(pairs, precision)
+    say(f"[gpu] p_1..p_24 {precision} with the tuned options {cand}")
+    runner = batch.BatchRunner(pairs, opts)
+    r = runner.run()
+    torch.cuda.synchronize()
+    assert r == 0, r
+    worst = dict(max_abs=0.0, max_over_sep=0.0)
+    for i, (l, n) in enumerate(pairs):
+        st = runner.stats[i].as_dict()
+        g = Host(runner, i)
+        check_type_stats(l, n, st, len(g))
+        assert g.radius.max() <= RADIUS_MAX and np.all(g.flags & 2) and np.all(g.flags & 4)
+        check_period_counts(g, n)
+        c = compare_sets(g, oracle_split(0, n))
+        worst = {k: max(worst[k], c[k]) for k in worst}
+    say(f"[gpu] p_1..p_24 {precision}: max |gpu - oracle| = {worst['max_abs']:.3e}, "
+        f"max |gpu - oracle| / separation = {worst['max_over_sep']:.3e}")
+    runner.close()
+
+
+def test_period_25_matches_oracle():
+    """p_25 (16 777 216 roots): the tip next to -2 in double-double; every
+    root matched with the oracle's, double-double roots to 1e-25."""
+    from paper_2402_06083_amd import msplit
+    n = 25
+    say("[gpu] p_25")
+    opts = msplit.make_options(certify=True)
+    r = msplit.split(0, n, opts, check=False)
+    torch.cuda.synchronize()
+    st = r.stats
+    assert r.status == msplit.OK, (r.status, st)
+    g = r.cpu()
+    del r
+    torch.cuda.empty_cache()
+    check_type_stats(0, n, st, len(g))
+    check_period_counts(g, n)
+    assert ((g.flags & msplit.R_DD) != 0).sum() > 0
+    c = compare_sets(g, oracle_split(0, n), dd_flags=g.flags)
+    say(f"[gpu] p_25: max |gpu - oracle| = {c['max_abs']:.3e}, / separation {c['max_over_sep']:.3e}, "
+        f"double-double {c['max_dd']:.3e}")
+
+
+def _flagged(flags, bit, step=1 << 28):
+    out = [np.zeros(0, dtype=np.int64)]
+    for s in range(0, flags.numel(), step):
+        nz = torch.nonzero((flags[s:s + step] & bit) != 0).flatten()
+        out.append(nz.cpu().numpy().astype(np.int64) + s)
+    return np.concatenate(out)
+
+
+def test_period_30_oracle_certificate():
+    """p_30 in the benchmark's launch configuration: the set check of Thm
+    certif by the oracle over all 2^29 roots, and the oracle's certificate on
+    every double-double root, every root within 1e-3 of -2 and a uniform
+    sample of 2M (every root with MSPLIT_FULL_ORACLE=1)."""
+    from paper_2402_06083_amd import msplit, tune
+    n = 30
+    pairs = [(0, n)]
+    opts, cand = tune.tuned_options(pairs, "fp64")
+    say(f"[gpu] p_30 with the tuned options {cand}")
+    b = msplit.Buffers(0, n, opts)
+    r = msplit.split(0, n, opts, buffers=b, check=False)
+    torch.cuda.synchronize()
+    st = r.stats
+    say(f"[gpu] p_30: status {r.status} ms {st['ms_device']:.0f} dd_routed {st['dd_routed']} "
+        f"max_radius {st['max_radius']:.3g} min_sep {st['min_sep']:.3g}")
+    assert r.status == msplit.OK, (r.status, st)
+    m = len(r)
+    check_type_stats(0, n, st, m)
+    # the whole list on the host (hi, lo, period, radius: about 10 GB)
+    say("[gpu] p_30: copy to the host")
+    re, im = r.re.cpu().numpy(), r.im.cpu().numpy()
+    re_lo, im_lo = r.re_lo.cpu().numpy(), r.im_lo.cpu().numpy()
+    per, rad = r.period.cpu().numpy(), r.radius.cpu().numpy()
+    dd = _flagged(r.flags, msplit.R_DD)
+    del r, b
+    torch.cuda.empty_cache()
+    assert rad.max() <= RADIUS_MAX
+    real = im == 0
+    for k in counts.divisors(n):
+        sel = per == k
+        cnt = int((sel & real).sum()) + 2 * int((sel & ~real).sum())
+        assert cnt == counts.hyp_count(k), (k, cnt)
+    full = os.environ.get("MSPLIT_FULL_ORACLE") == "1"
+    if full:
+        idx = np.arange(m)
+    else:
+        rng = np.random.default_rng(30)
+        near = np.nonzero(np.abs(re + 2.0) < 1e-3)[0]
+        idx = np.unique(np.concatenate([rng.choice(m, size=2_000_000, replace=False), dd, near]))
+    say(f"[oracle] p_30: certify {len(idx)} roots ({len(dd)} double-double)")
+    orad = np.empty(len(idx))
+    step = 1 << 24
+    for s in range(0, len(idx), step):
+        j = idx[s:s + step]
+        ok, orad[s:s + step] = oracle.certify(0, n, re[j], im[j], re_lo[j], im_lo[j], per[j])
+        assert np.all(ok == 3), (s, int((ok != 3).sum()))
+        say(f"[oracle] p_30: {min(s + step, len(idx))} of {len(idx)} certified")
+    assert orad.max() <= RADIUS_MAX
+    # Thm certif over the whole list: the oracle's radii where it certified,
+    # the GPU's elsewhere (all of them the oracle's with MSPLIT_FULL_ORACLE=1)
+    rr = rad.copy()
+    rr[idx] = orad
+    say("[oracle] p_30: set check")
+    cs = oracle.check_set(re, im, rr, re_lo, im_lo)
+    say(f"[oracle] p_30: {cs}")
+    assert cs["disjoint"] and cs["quarter"], cs
+    assert cs["n_real"] + 2 * cs["n_complex"] == 2 ** (n - 1)
+
+
+def test_mixed_type_batch_matches_oracle():
+    """p_1..p_20 with three Misiurewicz types in one batch, through q_{l,n}
+    and through the simplified s_{l,n}: every type equal to the oracle's
+    split, every root certified with its type proven."""
+    from paper_2402_06083_amd import batch, msplit
+    pairs = [(0, n) for n in range(1, 21)] + [(2, 10), (5, 7), (3, 13)]
+    for simple in (False, True):
+        opts = msplit.make_options(certify=True, simple=simple)
+        say(f"[gpu] mixed-type batch, {'s' if simple else 'q'} route")
+        runner = batch.BatchRunner(pairs, opts)
+        assert runner.run() == 0
+        torch.cuda.synchronize()
+        for i, (l, n) in enumerate(pairs):
+            st = runner.stats[i].as_dict()
+            g = Host(runner, i)
+            check_type_stats(l, n, st, len(g))
+            if l:
+                assert np.all(g.period == n) and np.all(g.preperiod == l)
+            else:
+                check_period_counts(g, n)
+            compare_sets(g, oracle_split(l, n), dd_flags=g.flags)
+        runner.close()
+
+
+@pytest.mark.parametrize("n,chunk", [(20, 1 << 15), (24, 1 << 21)])
+def test_streamed_matches_oracle(n, chunk):
+    """msplit_split_streamed with many chunks and partitions, compared with
+    the oracle's split root by root."""
+    from paper_2402_06083_amd import msplit
+    opts = msplit.make_options(certify=True)
+    say(f"[gpu] streamed p_{n}, chunks of {chunk} starts")
+    r = msplit.split_streamed(0, n, opts, chunk_starts=chunk, check=False)
+    torch.cuda.synchronize()
+    st = r.stats
+    assert r.status == msplit.OK, (r.status, st)
+    g = r.cpu()
+    del r
+    torch.cuda.empty_cache()
+    check_type_stats(0, n, st, len(g))
+    c = compare_sets(g, oracle_split(0, n))
+    say(f"[gpu] streamed p_{n}: max |gpu - oracle| = {c['max_abs']:.3e}")
+
+
+def test_misiurewicz_batch_oracle_certificate():
+    """All 210 types q_{l,n}, l >= 2, l + n <= 22, in one certified batch:
+    every root of every type certified again by the oracle with its type
+    proven (Thm proofRoots on q_{l,n}, double-double values), and per type
+    the oracle's set check: disjoint, quarter-separated disks whose count is
+    |Mis(l,n)| (eq. MisCount)."""
+    from paper_2402_06083_amd import batch, msplit
+    pairs = [(l, s - l) for s in range(3, 23) for l in range(2, s)]
+    assert len(pairs) == 210
+    say("[gpu] batch of all q_{l,n}, l + n <= 22")
+    runner = batch.BatchRunner(pairs, msplit.make_options(certify=True))
+    assert runner.run() == 0
+    torch.cuda.synchronize()
+    tot = 0
+    for i, (l, n) in enumerate(pairs):
+        st = runner.stats[i].as_dict()
+        g = Host(runner, i)
+        check_type_stats(l, n, st, len(g))
+        ok, rad = oracle.certify(l, n, g.re, g.im, g.re_lo, g.im_lo)
+        assert np.all(ok == 3), (l, n, int((ok != 3).sum()))
+        assert rad.max() <= RADIUS_MAX
+        cs = oracle.check_set(g.re, g.im, rad, g.re_lo, g.im_lo)
+        assert cs["disjoint"] and cs["quarter"], ((l, n), cs)
+        assert cs["n_real"] + 2 * cs["n_complex"] == counts.mis_count(l, n)
+        tot += len(g)
+    say(f"[oracle] {tot} Misiurewicz roots (upper half plane) certified")
+    runner.close()
+
+
+def test_incomplete_split_is_reported():
+    """Descents capped at five steps (min_cap = 5 and a cap factor that makes
+    I_N log d round up to 1, against about 8 steps per start): most time out,
+    the split returns MSPLIT_E_INCOMPLETE with stats.missing > 0, and the
+    roots it found are still written (each a root of p_12 to within 1e-10)."""
+    from paper_2402_06083_amd import msplit
+    n = 12
+    opts = msplit.make_options(min_cap=5, cap_factor=1e-9)
+    say("[gpu] p_12 with descents capped at five steps")
+    r = msplit.split(0, n, opts, check=False)
+    torch.cuda.synchronize()
+    st = r.stats
+    assert r.status == msplit.E_INCOMPLETE, (r.status, st)
+    assert st["missing"] > 0 and st["timeouts"] > 0 and st["total"] + st["missing"] == 2 ** (n - 1), st
+    g = r.cpu()
+    say(f"[gpu] capped p_12: {len(g)} roots written, stats {st}")
+    assert 0 < len(g) < 2 ** (n - 1)
+    assert np.all(np.isfinite(g.re)) and np.all(np.isfinite(g.im))
+    o = oracle_split(0, n)
+    from scipy.spatial import cKDTree
+    d, _ = cKDTree(np.stack([o.re_hi, o.im_hi], axis=1)).query(np.stack([g.re, g.im], axis=1), k=1)
+    assert d.max() <= 1e-10

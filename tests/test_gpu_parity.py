@@ -7,24 +7,18 @@ flags.  At the full period-24 size every returned root is checked one by one
 by the oracle's own certificate (Thm proofRoots in long double) on a sample,
 and by the GPU certificate plus exact counts on all of them.
 """
-import functools
 import math
-import sys
 
 import numpy as np
 import pytest
 
 import oracle
 from oracle import counts
+from parity import compare_sets, oracle_split, say
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-
-
-def say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -36,11 +30,6 @@ def device():
     return torch.device("cuda:0")
 
 
-@functools.lru_cache(maxsize=None)
-def oracle_split(l, n):
-    return oracle.split(l, n)
-
-
 def gpu_split(l, n, **kw):
     from paper_2402_06083_amd import msplit
     say(f"[gpu] split l={l} n={n} {kw}")
@@ -48,29 +37,6 @@ def gpu_split(l, n, **kw):
     r = msplit.split(l, n, opts, check=False)
     torch.cuda.synchronize()
     return r, r.cpu()
-
-
-def compare_sets(g, o, tol=1e-10):
-    """Nearest-neighbour bijection GPU -> oracle; returns max distance."""
-    from scipy.spatial import cKDTree
-    oz = np.stack([o.re_hi, o.im_hi], axis=1)
-    gz = np.stack([g.re, g.im], axis=1)
-    assert len(gz) == len(oz), (len(gz), len(oz))
-    tree = cKDTree(oz)
-    d, idx = tree.query(gz, k=1)
-    assert len(np.unique(idx)) == len(oz), "not a bijection"
-    # local separation of the oracle roots (and their conjugates)
-    if len(oz) > 1:
-        dd, _ = tree.query(oz, k=2)
-        sep = dd[:, 1]
-    else:
-        sep = np.full(1, np.inf)
-    sep = np.minimum(sep, np.where(o.im_hi > 0, 2 * o.im_hi, np.inf))
-    assert d.max() <= tol, d.max()
-    assert np.all(d <= sep[idx] / 4), "a root moved by more than a quarter of its separation"
-    assert np.array_equal(g.period, o.period[idx]), "period labels differ"
-    assert np.array_equal(g.im == 0, o.im_hi[idx] == 0), "real flags differ"
-    return float(d.max()), idx
 
 
 @pytest.mark.parametrize("n", list(range(1, 17)))
@@ -92,7 +58,7 @@ def test_hyperbolic_parity_n20(precision):
     r, g = gpu_split(0, 20, precision=precision)
     assert r.status == msplit.OK, (r.status, r.stats)
     o = oracle_split(0, 20)
-    dmax, _ = compare_sets(g, o)
+    dmax = compare_sets(g, o)["max_abs"]
     say(f"[gpu] n=20 {precision}: max |gpu - oracle| = {dmax:.3e}, stats={r.stats}")
     if precision == "mixed":
         assert r.stats["steps_fp32"] > 0
@@ -127,7 +93,7 @@ def check_full_period(n, sample=4000, seed=0):
     say(f"[gpu] p_{n}: status {r.status} stages {st['ms_stage']} dd_routed {st['dd_routed']}")
     assert r.status == msplit.OK, (r.status, st)
     assert st["total"] == 2 ** (n - 1) and st["certified"] == len(r) and st["label_proven"] == len(r), st
-    assert st["overlaps"] == 0
+    assert st["overlaps"] == 0 and st["max_radius"] <= 1e-10, st
     for k in counts.divisors(n):
         sel = r.period == k
         cnt = int((r.im[sel] == 0).sum().item()) + 2 * int((r.im[sel] > 0).sum().item())
@@ -139,7 +105,7 @@ def check_full_period(n, sample=4000, seed=0):
     t = torch.as_tensor(idx, device=r.re.device)
     ok, rad = oracle.certify(0, n, r.re[t].cpu().numpy(), r.im[t].cpu().numpy(), r.re_lo[t].cpu().numpy(),
                              r.im_lo[t].cpu().numpy(), label=r.period[t].cpu().numpy())
-    assert np.all(ok == 3)
+    assert np.all(ok == 3) and rad.max() <= 1e-10
     del b, r
     torch.cuda.empty_cache()
 
@@ -188,15 +154,18 @@ def test_full_size_period_24():
     assert abs(s1 - (-(2 ** (n - 2)))) < 1e-6
 
 
-def test_batch_periods_1_to_24():
-    """All periods 1..24 through msplit_batch, certified, in the benchmark's
-    launch configuration."""
+def test_batch_periods_1_to_24_default_options():
+    """All periods 1..24 through msplit_batch with the default launch options
+    (the tuned options of the benchmark are compared with the oracle in
+    test_gpu_oracle_exact): exact counts, every root certified with its
+    period proven, radius <= 1e-10, quarter-separated."""
     from paper_2402_06083_amd import batch
-    say("[gpu] batch 1..24")
+    say("[gpu] batch 1..24, default options")
     res = batch.run_batch([(0, n) for n in range(1, 25)], certify=True)
     for (l, n), (count, st, status) in zip(res.pairs, res.per_pair):
         assert status == 0, (n, status, st)
         assert st["total"] == 2 ** (n - 1) and st["certified"] == count and st["overlaps"] == 0, (n, st)
+        assert st["label_proven"] == count and st["max_radius"] <= 1e-10, (n, st)
 
 
 # q_{l,n}: preperiods 2..15, periods 1..13, orders 3..16
@@ -254,40 +223,12 @@ def test_misiurewicz_parity_tip(ln):
     assert st["total"] == counts.mis_count(l, n) and st["certified"] == len(g) and st["overlaps"] == 0, st
     assert st["dd_routed"] > 0
     o = oracle_split(l, n)
-    _, idx = compare_sets(g, o)
+    idx = compare_sets(g, o)["idx"]
     dd = (g.flags & msplit.R_DD) != 0
     assert dd.any()
     ere = (g.re[dd] - o.re_hi[idx[dd]]) + (g.re_lo[dd] - o.re_lo[idx[dd]])
     eim = (g.im[dd] - o.im_hi[idx[dd]]) + (g.im_lo[dd] - o.im_lo[idx[dd]])
     assert np.max(np.abs(ere)) < 1e-25 and np.max(np.abs(eim)) < 1e-25
-
-
-def test_batch_misiurewicz_all_pairs():
-    """Every q_{l,n} with l >= 2, n >= 1, l + n <= 22 (210 pairs) in one
-    batch, certified: exact counts |Mis(l,n)| (eq. MisCount) per pair, every
-    root certified with its type proven, quarter-separated; a sample of each of
-    three of the largest pairs certified again by the oracle."""
-    from paper_2402_06083_amd import batch
-    pairs = mis_pairs(22)
-    assert len(pairs) == 210
-    say("[gpu] batch of all q_{l,n}, l + n <= 22")
-    res = batch.run_batch(pairs, certify=True)
-    tot = 0
-    for i, ((l, n), (count, st, status)) in enumerate(zip(res.pairs, res.per_pair)):
-        assert status == 0, ((l, n), status, st)
-        assert st["total"] == counts.mis_count(l, n), ((l, n), st)
-        assert st["certified"] == count and st["label_proven"] == count and st["overlaps"] == 0, ((l, n), st)
-        tot += st["total"]
-    say(f"[gpu] C4: {tot} roots, stage ms {res.per_pair[0][1]['ms_stage']}")
-    b = res.bufs
-    rng = np.random.default_rng(22)
-    for (l, n) in [(2, 20), (11, 11), (20, 2)]:
-        sl = b.slices(res.pairs.index((l, n)))
-        re, im = b.re[sl].cpu().numpy(), b.im[sl].cpu().numpy()
-        rl, il = b.re_lo[sl].cpu().numpy(), b.im_lo[sl].cpu().numpy()
-        idx = np.sort(rng.choice(len(re), size=min(4000, len(re)), replace=False))
-        ok, rad = oracle.certify(l, n, re[idx], im[idx], rl[idx], il[idx])
-        assert np.all(ok == 3) and rad.max() <= 1e-10, (l, n)
 
 
 def test_certify_api_and_rejection():
@@ -502,9 +443,8 @@ def test_certify_api_basin():
 # (eq. polySimple, MSPLIT_F_SIMPLE): the same set as the q_{l,n} route and as
 # the oracle's s route, from half as many starts.
 
-@functools.lru_cache(maxsize=None)
 def oracle_split_simple(l, n):
-    return oracle.split(l, n, simple=True)
+    return oracle_split(l, n, simple=True)
 
 
 SIMPLE_SMALL = [(2, 1), (3, 1), (2, 2), (4, 2), (3, 4), (5, 3), (2, 8), (7, 2), (4, 6), (9, 3), (12, 2), (6, 8),
