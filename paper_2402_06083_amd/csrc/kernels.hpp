@@ -51,6 +51,9 @@ enum {
     C_NCOUNTERS = 23
 };
 
+// types of one call (batch_args.T)
+constexpr int MAX_TYPES = 256;
+
 struct plan_t {
     int l, n, N;          // type and order N = l + n
     int el, eN;           // the polynomial P evaluated (eval_q_t): q_{l,n} and p_n are (l, N); the
@@ -92,6 +95,7 @@ struct batch_args {
     int64_t *kept_offs;       // roots kept by the classification per type, set on the device
     int64_t *surv_offs;       // sorted candidates per type, set on the device
     const double *cis;        // cos, then sin, of 2 pi s / M, s < 64 (k_cis)
+    double dphi;              // 2 pi / M (a kernel argument: wave-uniform, no VGPR)
     int T;
     int64_t n_seeds, n_segs, n_starts;
     uint32_t chunk_seg, chunk_start;
@@ -279,12 +283,42 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts, cd *first)
 // an intermediate point only has to lie in the Newton basin of the next
 // target, and the next target is aimed from the actual value, so no error
 // accumulates.  Lane state is 32-bit (segment index, fine point within the
-// segment) to keep the kernel within 64 VGPRs.
-__global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag, cd *first)
+// segment).  M, q = M / 4 and F are powers of two: the phase index and the
+// start test are masks, and the M values e^{2 i pi r / M} sit in LDS.
+// Per-type fields the walk reads, staged in LDS by every block (the lanes
+// keep only their segment, type, fine point and iterate in registers).
+struct walk_type {
+    uint32_t seg_lo;   // first global segment of the type
+    uint32_t start_lo; // first global start of the type
+    uint32_t seg0;     // first segment of the item on the whole line
+    uint32_t F;        // fine points per segment (a power of two)
+    int l, N;          // the evaluated polynomial (eval_q_t)
+    double level;      // lambda_0
+};
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag, cd *first)
 {
     constexpr uint32_t NONE = 0xffffffffu;
     // |T/P - 1| < 2^-5 sqrt(0.9) keeps |P/T - 1| = |v| / |1 + v| below 2^-5
     const double tol2_start = 0.9 * 0x1p-10, tol2_mid = 0x1p-4;
+    __shared__ double cis_l[128];
+    __shared__ walk_type wt[MAX_TYPES + 1];
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) cis_l[i] = b.cis[i];
+    for (int i = threadIdx.x; i <= b.T; i += blockDim.x) {
+        walk_type w;
+        w.seg_lo = (uint32_t)b.seg_offs[i];
+        if (i < b.T) {
+            const type_desc &td = b.types[i];
+            w.start_lo = (uint32_t)td.start_off;
+            w.seg0 = (uint32_t)td.p.seg0;
+            w.F = (uint32_t)td.p.F;
+            w.l = td.p.el;
+            w.N = td.p.eN;
+            w.level = td.p.level;
+        }
+        wt[i] = w;
+    }
+    __syncthreads();
     unsigned long long *const wc = wave_ctr(b);
     const uint32_t n_segs = (uint32_t)b.n_segs;
     int ct = -1;
@@ -292,19 +326,17 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
     const int slots[4] = {C_STEPS_WALK, C_PHASE_FAIL, C_STEPS_WALK, C_STEPS_WALK};
     uint32_t g = NONE; // current segment (global)
     bool exhausted = false;
-    int t = -1;
-    uint32_t t_lo = 0, t_hi = 0;
-    // M and q are the same for every type of a call (wave-uniform)
+    int t = 0;
+    // M and q are the same for every type of a call (wave-uniform), powers of two
     const int pl_M = b.types[0].p.M, pl_q = b.types[0].p.q;
-    // the fields of the current type's plan that the walk uses
-    int pl_l = 0, pl_N = 1, pl_F = 1;
-    double pl_level = 5.0;
-    uint32_t seed_j = 0;  // global index of the segment's first seed
-    uint32_t start0 = 0;  // global start index of fine point j F of the segment
-    int s = 0, r0 = 0;    // fine point within the segment (1..F); (j F) mod M
+    const uint32_t mmask = (uint32_t)pl_M - 1u, qmask = (uint32_t)pl_q - 1u;
+    const int qshift = __builtin_ctz((uint32_t)pl_q);
+    uint32_t s = 0, r0 = 0; // fine point within the segment (1..F); (j F) mod M
     int it = 0;
     cd z = {0.0, 0.0};
-    cd gprev = {0.0, 0.0}; // P/P' at the last accepted fine point (the seed first)
+    // P/P' at the last accepted fine point (the seed first), for the second-order
+    // prediction only: FP32 is enough there and saves two VGPRs
+    cf gprev = {0.f, 0.f};
     wave_queue wq = wave_queue_start(b.chunk_seg);
     while (true) {
         const bool need = !exhausted && g == NONE;
@@ -314,21 +346,18 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
                 exhausted = true;
             } else {
                 g = (uint32_t)got;
-                if (g < t_lo || g >= t_hi) {
-                    t = find_type(b.seg_offs, b.T, g);
-                    t_lo = (uint32_t)b.seg_offs[t];
-                    t_hi = (uint32_t)b.seg_offs[t + 1];
-                    const plan_t &pl = b.types[t].p;
-                    pl_l = pl.el;
-                    pl_N = pl.eN;
-                    pl_F = (int)pl.F;
-                    pl_level = pl.level;
+                if (g < wt[t].seg_lo || g >= wt[t + 1].seg_lo) {
+                    int lo = 0, hi = b.T; // wt[lo].seg_lo <= g < wt[hi].seg_lo
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (wt[mid].seg_lo <= g) lo = mid; else hi = mid;
+                    }
+                    t = lo;
                 }
-                const uint32_t j = g - t_lo;
-                seed_j = (uint32_t)b.types[t].seed_off + j;
-                start0 = (uint32_t)b.types[t].start_off + j * (uint32_t)(pl_F / pl_q);
-                r0 = (int)(((uint64_t)(j + b.types[t].p.seg0) * (uint64_t)pl_F) % (uint64_t)pl_M);
-                z = seeds[seed_j];
+                r0 = ((g - wt[t].seg_lo + wt[t].seg0) * wt[t].F) & mmask;
+                // seed j of the type sits at seed_offs[t] + j = g + t (a type of
+                // S segments has S + 1 seeds)
+                z = seeds[g + (uint32_t)t];
                 s = 1;
                 it = 0;
             }
@@ -342,20 +371,26 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
         if (__ballot(g != NONE || !exhausted) == 0) break;
         if (g == NONE) continue;
         cd P, dP;
-        eval_q_wave(pl_l, pl_N, z, P, dP);
+        eval_q_wave(wt[t].l, wt[t].N, z, P, dP);
         cnt[0] += 1u;
-        const int r = (r0 + s) % pl_M;
-        const cd T = {pl_level * b.cis[r], pl_level * b.cis[64 + r]};
-        cd w = cdiv_fast(T, P);
-        const cd v = {w.re - 1.0, w.im};
-        const double a2 = cabs2(v);
+        // at the seed (P = T_{s-1} there, to rounding) the first update aims
+        // from T_{s-1}: log(T_s / P) = i dphi + log(T_{s-1} / P), whose log
+        // is near 1 where the series below is accurate
+        const bool at_seed = s == 1 && it == 0;
+        const uint32_t r = (r0 + s - (at_seed ? 1u : 0u)) & mmask;
+        const double lev = wt[t].level;
+        const cd T = {lev * cis_l[r], lev * cis_l[64 + r]};
+        const cd w = cdiv_fast(T, P);
+        const double a2 = cabs2({w.re - 1.0, w.im});
         const cd step = cdiv_fast(P, dP);
         if (!cfinite(w) || !cfinite(step) || it > 24) {
             // the starts of the segment not reached yet get no value (NaN:
             // their descents end as divergent)
             const double nan = __longlong_as_double(0x7ff8000000000000ll);
-            for (int s2 = (s + pl_q - 1) / pl_q * pl_q; s2 < pl_F; s2 += pl_q) {
-                const uint32_t k = start0 + (uint32_t)(s2 / pl_q);
+            const uint32_t F = wt[t].F;
+            const uint32_t start0 = wt[t].start_lo + (g - wt[t].seg_lo) * (F >> qshift);
+            for (uint32_t s2 = (s + qmask) & ~qmask; s2 < F; s2 += (uint32_t)pl_q) {
+                const uint32_t k = start0 + (s2 >> qshift);
                 starts[k] = {nan, nan};
                 first[k] = {nan, nan};
             }
@@ -364,16 +399,20 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
             g = NONE;
             continue;
         }
-        if (s == 1 && it == 0) gprev = step; // at the seed
-        cd u0 = clog_near1(w);
+        cd u0 = clog_series(w);
+        if (at_seed) {
+            gprev = {(float)step.re, (float)step.im};
+            u0.im += b.dphi;
+        }
         const cd h = cmul(u0, step);
-        const bool is_start = (s % pl_q) == 0;
-        if (a2 < (is_start || s == pl_F ? tol2_start : tol2_mid) ||
-            cabs2(h) <= 0x1p-96 * fmax(cabs2(z), 0x1p-16)) {
-            if (s == pl_F) {
+        const bool is_start = (s & qmask) == 0;
+        const bool last = s == wt[t].F;
+        if (!at_seed && (a2 < (is_start || last ? tol2_start : tol2_mid) ||
+                         cabs2(h) <= 0x1p-96 * fmax(cabs2(z), 0x1p-16))) {
+            if (last) {
                 // the walk must end on the next seed (phase check): a skipped
                 // turn would land about 2 pi |P/P'| away
-                const cd e = csub(z, seeds[seed_j + 1]);
+                const cd e = csub(z, seeds[g + (uint32_t)t + 1u]);
                 const bool ok = cabs2(e) < 1e-2 * cabs2(step);
                 seg_flag[g] = ok ? 0 : 1;
                 cnt[1] += !ok;
@@ -381,19 +420,19 @@ __global__ void __launch_bounds__(256) k_walk(batch_args b, const cd *seeds, cd 
                 continue;
             }
             if (is_start) {
-                const uint32_t k = start0 + (uint32_t)(s / pl_q);
+                const uint32_t k = wt[t].start_lo + (g - wt[t].seg_lo) * (wt[t].F >> qshift) + (s >> qshift);
                 starts[k] = z;
                 first[k] = csub(z, step);
             }
             // aim at the next fine point: log(T_{s+1}/P) = i dphi + log(T_s/P)
             ++s;
             it = 0;
-            u0.im += 2.0 * M_PI / pl_M;
+            u0.im += b.dphi;
             // second order along the level-line flow (uniform phase steps):
             // the change of P/P' since the last accepted point
-            const cd dg = csub(step, gprev);
+            const cd dg = {step.re - (double)gprev.re, step.im - (double)gprev.im};
             z = cadd(z, cmul(u0, cadd(step, {0.5 * dg.re, 0.5 * dg.im})));
-            gprev = step;
+            gprev = {(float)step.re, (float)step.im};
         } else {
             ++it;
             z = cadd(z, h);
@@ -663,7 +702,6 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
 constexpr int KEY_TYPE_SHIFT = 50;
 constexpr int KEY_RES = 46;
 constexpr int KEY_BITS = KEY_RES + 2;
-constexpr int MAX_TYPES = 256;
 
 __device__ __forceinline__ uint64_t root_key(int t, double re)
 {

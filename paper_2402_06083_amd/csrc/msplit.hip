@@ -408,7 +408,10 @@ int check_options(batch_call &c, const msplit_options *opts, const msplit_roots 
     if (opts->struct_size && opts->struct_size != sizeof(msplit_options)) return MSPLIT_E_ARG;
     if (opts->precision < 0 || opts->precision > 2) return MSPLIT_E_ARG;
     if (opts->precision == MSPLIT_DD) return MSPLIT_E_UNSUPPORTED;
-    if (opts->points_per_turn && (opts->points_per_turn % 4 || opts->points_per_turn > 64)) return MSPLIT_E_ARG;
+    // M: a power of two, 4 .. 64 (the walk takes phase indices and starts by masks)
+    if (opts->points_per_turn && (opts->points_per_turn < 4 || opts->points_per_turn > 64 ||
+                                  (opts->points_per_turn & (opts->points_per_turn - 1))))
+        return MSPLIT_E_ARG;
     c.bs = opts->block_size ? (int)opts->block_size : 256;
     if (c.bs % 64 || c.bs > 256) return MSPLIT_E_ARG;
     c.o = *opts;
@@ -466,6 +469,7 @@ void setup_args(batch_call &c, char *ws)
     // about one evaluation per start: one static chunk per wave, no atomics
     ba.chunk_fp32 = (uint32_t)std::max<int64_t>(64, std::min<int64_t>(4096, (ba.n_fp32 + 8191) / 8192));
     ba.cis = ws_at<double>(c, c.L.cis);
+    ba.dphi = 2.0 * M_PI / bp.td[0].p.M;
     ba.T = T;
     ba.n_seeds = bp.n_seeds;
     ba.n_segs = bp.n_segs;
