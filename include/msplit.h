@@ -21,7 +21,9 @@
  * - Array pointers inside msplit_roots and the workspace are HIP DEVICE
  *   pointers owned by the caller.  Scalars (counts, stats) are HOST pointers.
  *   The library never allocates or frees device memory; it uses the
- *   workspace only, whose size msplit_workspace_size() reports.
+ *   workspace only, whose size msplit_workspace_size() reports (except
+ *   msplit_hyperbolic_static, which runs in a static device array of the
+ *   library instead).
  * - stream is a hipStream_t (NULL = the null stream).  Kernels are enqueued
  *   on it; every entry point synchronises that stream before returning
  *   because it reports counts on the host.  Calls on distinct streams with
@@ -188,6 +190,26 @@ int msplit_workspace_size(int l, int n, const msplit_options *opts, uint64_t *by
  * still written), MSPLIT_E_PRECISION (n beyond what FP64 separates). */
 int msplit_hyperbolic(int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes,
                       msplit_roots *out, uint64_t *count, msplit_stats *stats, void *stream);
+
+/* Bytes of the static device scratch array of msplit_hyperbolic_static
+ * (64 MiB: p_n up to n = 19 with the default options). */
+#define MSPLIT_STATIC_SCRATCH_BYTES (64ull << 20)
+
+/* msplit_hyperbolic without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation): the call runs in a static device array
+ * of MSPLIT_STATIC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends, and allocates nothing (no device memory,
+ * no events; stats->ms_device and ms_stage stay 0).  The caller still
+ * passes the output arrays.  Same roots, counts and errors as
+ * msplit_hyperbolic, plus MSPLIT_E_WORKSPACE when msplit_workspace_size for
+ * (0, n, opts) exceeds MSPLIT_STATIC_SCRATCH_BYTES (nothing runs then).
+ * All calls on one device share its array, which keeps the last call's
+ * contents (every call initialises what it reads): calls that overlap on
+ * one device race -- serialise them (one stream, or the caller's lock).
+ * MSPLIT_E_DEVICE when the array's address cannot be taken (hip_error). */
+int msplit_hyperbolic_static(int n, const msplit_options *opts, msplit_roots *out, uint64_t *count,
+                             msplit_stats *stats, void *stream);
 
 /* Split q_{l,n}, l >= 2, n >= 1 (Section 2.2, eq. def:mis; Section 6.3.1,
  * misQuick) and keep Mis(l,n): roots of q_{l,n} that are neither roots of

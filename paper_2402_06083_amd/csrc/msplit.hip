@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -20,6 +21,13 @@
 #include "stream.hpp"
 
 using namespace msplit;
+
+// The workspace of msplit_hyperbolic_static: a device array of fixed size in
+// the library, so that the call allocates nothing.  Each device holds its
+// own copy until the process ends.  In host code the name is a stand-in, not
+// a device address: the address comes from hipGetSymbolAddress, taken once
+// per device (scratch_of_device).
+static __device__ __align__(256) unsigned char scratch[MSPLIT_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -828,10 +836,12 @@ int finish(batch_call &c, hipStream_t stream, uint64_t *counts, msplit_stats *st
 // type i go to out at out_offs[i] with capacity caps[i].  counts[i] and
 // stats[i] are written for every type.  starts_only: stop after the level
 // line and copy the starts of the single type to sre / sim.
+// timed = false: no events (stage and device times stay 0), for the entry
+// point that creates nothing.
 int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *workspace, uint64_t ws_bytes,
               msplit_roots *out, const uint64_t *out_offs, const uint64_t *caps, uint64_t *counts,
               msplit_stats *stats, void *stream_v, bool starts_only = false, double *sre = nullptr,
-              double *sim = nullptr, uint64_t scap = 0)
+              double *sim = nullptr, uint64_t scap = 0, bool timed = true)
 {
     for (int i = 0; i < npairs && counts; ++i) counts[i] = 0;
     if (!counts) return MSPLIT_E_ARG;
@@ -845,11 +855,11 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
     call_ctx ctx{stats, npairs};
     CHK(upload_tables(c, stream));
     events ev;
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < 7 && timed; ++i) {
         CHK(hipEventCreate(&ev.e[i]));
         ev.made = i + 1;
     }
-    enqueue_level_line(c, stream, ev.e);
+    enqueue_level_line(c, stream, timed ? ev.e : nullptr);
     CHK(hipGetLastError());
     if (starts_only) {
         const plan_t &p = c.bp.td[0].p;
@@ -877,12 +887,14 @@ int run_batch(const int32_t *ln, int npairs, const msplit_options *opts, void *w
         // a lift that did not converge is not
         return c.h[C_SEED_FAIL] ? MSPLIT_E_INCOMPLETE : MSPLIT_OK;
     }
-    enqueue_roots(c, stream, ev.e);
+    enqueue_roots(c, stream, timed ? ev.e : nullptr);
     CHK(hipGetLastError());
-    CHK(hipEventSynchronize(ev.e[6]));
     float ms = 0.f, mss[6] = {0, 0, 0, 0, 0, 0};
-    (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[6]);
-    for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&mss[i], ev.e[i], ev.e[i + 1]);
+    if (timed) {
+        CHK(hipEventSynchronize(ev.e[6]));
+        (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[6]);
+        for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&mss[i], ev.e[i], ev.e[i + 1]);
+    }
     return finish(c, stream, counts, stats, ctx, ms, mss);
 }
 
@@ -1251,6 +1263,34 @@ hipError_t capture(graph_state &g, hipStream_t stream)
 } // namespace
 
 // ===================================================================== C ABI
+namespace {
+
+// Address of this device's copy of the static scratch array: looked up once
+// per device, with that device current, and kept.
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_at[SCRATCH_DEVICES];
+
+hipError_t scratch_of_device(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_at[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_at[dev] = p;
+    }
+    *ptr = scratch_at[dev];
+    return hipSuccess;
+}
+
+} // namespace
+
 extern "C" {
 
 const char *msplit_strerror(int status)
@@ -1301,6 +1341,28 @@ int msplit_hyperbolic(int n, const msplit_options *opts, void *workspace, uint64
     const int32_t ln[2] = {0, n};
     const uint64_t off = 0, cap = out->capacity;
     return run_batch(ln, 1, opts, workspace, workspace_bytes, out, &off, &cap, count, stats, stream);
+}
+
+int msplit_hyperbolic_static(int n, const msplit_options *opts, msplit_roots *out, uint64_t *count,
+                             msplit_stats *stats, void *stream)
+{
+    if (count) *count = 0;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (!count || !out) return MSPLIT_E_ARG;
+    uint64_t need = 0;
+    int r = msplit_workspace_size(0, n, opts, &need);
+    if (r) return r;
+    if (need > MSPLIT_STATIC_SCRATCH_BYTES) return MSPLIT_E_WORKSPACE;
+    void *ws = nullptr;
+    const hipError_t e = scratch_of_device(&ws);
+    if (e != hipSuccess) {
+        if (stats) stats->hip_error = (int32_t)e;
+        return MSPLIT_E_DEVICE;
+    }
+    const int32_t ln[2] = {0, n};
+    const uint64_t off = 0, cap = out->capacity;
+    return run_batch(ln, 1, opts, ws, MSPLIT_STATIC_SCRATCH_BYTES, out, &off, &cap, count, stats, stream, false,
+                     nullptr, nullptr, 0, false);
 }
 
 int msplit_misiurewicz(int l, int n, const msplit_options *opts, void *workspace, uint64_t workspace_bytes,

@@ -91,6 +91,8 @@ def lib():
     L.msplit_workspace_size.restype = i32
     L.msplit_hyperbolic.argtypes = [i32, pOpt, vp, u64, pRoots, pu64, pStats, vp]
     L.msplit_hyperbolic.restype = i32
+    L.msplit_hyperbolic_static.argtypes = [i32, pOpt, pRoots, pu64, pStats, vp]
+    L.msplit_hyperbolic_static.restype = i32
     L.msplit_misiurewicz.argtypes = [i32, i32, pOpt, vp, u64, pRoots, pu64, pStats, vp]
     L.msplit_misiurewicz.restype = i32
     L.msplit_certify.argtypes = [i32, i32, pRoots, u64, vp, u64, pStats, vp]
@@ -116,7 +118,10 @@ def lib():
     return L
 
 
+STATIC_SCRATCH_BYTES = 64 << 20  # MSPLIT_STATIC_SCRATCH_BYTES
+
 EXPORTED = ["msplit_strerror", "msplit_expected_count", "msplit_workspace_size", "msplit_hyperbolic",
+            "msplit_hyperbolic_static",
             "msplit_misiurewicz", "msplit_certify", "msplit_batch", "msplit_batch_workspace_size",
             "msplit_starts", "msplit_batch_graph", "msplit_graph_launch", "msplit_graph_destroy",
             "msplit_split_streamed", "msplit_stream_workspace_size"]
@@ -239,6 +244,22 @@ def split(l: int, n: int, opts: Options = None, buffers: Buffers = None, stream=
     if check and r not in (OK,):
         raise MsplitError(r, f"split({l},{n})")
     return _result(l, n, opts, b, c, st, r)
+
+
+def hyperbolic_static(n: int, opts: Options = None, buffers: Buffers = None, stream=None, check=True) -> Result:
+    """Split p_n with msplit_hyperbolic_static: no workspace argument (the
+    library's static device array; p_n up to n = 19 with the default
+    options).  buffers supplies the output arrays (its workspace is unused)."""
+    opts = opts or make_options()
+    b = buffers or Buffers(0, n, opts, ws_bytes=0)
+    rs = b.roots_struct()
+    cnt = ctypes.c_uint64()
+    st = Stats()
+    r = lib().msplit_hyperbolic_static(n, ctypes.byref(opts), ctypes.byref(rs), ctypes.byref(cnt), ctypes.byref(st),
+                                       _stream_handle(stream))
+    if check and r not in (OK,):
+        raise MsplitError(r, f"hyperbolic_static({n})")
+    return _result(0, n, opts, b, int(cnt.value), st, r)
 
 
 def _result(l, n, opts, b, c, st, r):

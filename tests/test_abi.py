@@ -105,3 +105,19 @@ def test_invalid_arguments_without_device(lib):
     assert L.msplit_hyperbolic(0, None, None, 0, None, ctypes.byref(cnt), None, None) == msplit.E_ARG
     assert cnt.value == 0
     assert L.msplit_misiurewicz(1, 3, None, None, 0, None, ctypes.byref(cnt), None, None) == msplit.E_ARG
+
+
+def test_static_entry_point_limits_without_device(lib):
+    """msplit_hyperbolic_static refuses, before any device work, a split
+    whose workspace exceeds its static array (p_20 with the defaults), and
+    null arguments; p_19 fits the array."""
+    from paper_2402_06083_amd import msplit
+    L = msplit.lib()
+    assert msplit.workspace_size(0, 19, msplit.make_options(certify=True)) <= msplit.STATIC_SCRATCH_BYTES
+    assert msplit.workspace_size(0, 20, msplit.make_options(certify=True)) > msplit.STATIC_SCRATCH_BYTES
+    rs = msplit.RootsC(1, 1, None, None, None, None, None, None, 1, None)
+    cnt = ctypes.c_uint64(7)
+    assert L.msplit_hyperbolic_static(20, None, ctypes.byref(rs), ctypes.byref(cnt), None, None) == msplit.E_WORKSPACE
+    assert cnt.value == 0
+    assert L.msplit_hyperbolic_static(0, None, ctypes.byref(rs), ctypes.byref(cnt), None, None) == msplit.E_ARG
+    assert L.msplit_hyperbolic_static(12, None, None, ctypes.byref(cnt), None, None) == msplit.E_ARG
