@@ -359,7 +359,14 @@ def error_vs_oracle(g, o):
     ratio = d / sep[idx]
     identical = (len(np.unique(idx)) == len(idx) and d.max() <= 1e-10 and ratio.max() <= 0.25
                  and np.array_equal(g["period"], o.period[idx]) and np.array_equal(g["im"] == 0, o.im_hi[idx] == 0))
-    return {"identical": bool(identical), "max_abs": float(d.max()), "max_over_sep": float(ratio.max())}
+    out = {"identical": bool(identical), "max_abs": float(d.max()), "max_over_sep": float(ratio.max())}
+    dd = (g["flags"] & 8) != 0  # MSPLIT_R_DD: compare the double-double values
+    if dd.any():
+        j = idx[dd]
+        ere = (g["re"][dd] - o.re_hi[j]) + (g["re_lo"][dd] - o.re_lo[j])
+        eim = (g["im"][dd] - o.im_hi[j]) + (g["im_lo"][dd] - o.im_lo[j])
+        out["max_abs_double_double"] = float(max(np.abs(ere).max(), np.abs(eim).max()))
+    return out
 
 
 def accuracy(roots_of, splits):
@@ -373,9 +380,9 @@ def accuracy(roots_of, splits):
         if not e["identical"]:
             worst["identical"] = False
             worst.setdefault("differs", []).append(n)
-        for k in ("max_abs", "max_over_sep"):
+        for k in ("max_abs", "max_over_sep", "max_abs_double_double"):
             if k in e:
-                worst[k] = max(worst[k], e[k])
+                worst[k] = max(worst.get(k, 0.0), e[k])
     worst["max_certified_radius"] = max(float(g["radius"].max()) for g in roots_of.values())
     return worst
 
@@ -472,6 +479,12 @@ def main():
         # and descent steps per root): the instrumented counts of the last step
         "work_per_root": work_per_root(res["last_stats"]),
         "distinct_parameters": res.get("distinct"),
+        # the sizes the collection kernels work on, per step: starts, the
+        # candidates left by the local identification (the sort's entries),
+        # the identified roots, the roots kept by the classification
+        "collection_sizes": {k: sum(st[f] for st in res["last_stats"]) for k, f in
+                             (("starts", "starts"), ("candidates", "sorted"), ("kept", "unique"),
+                              ("discarded", "discarded"))},
     }
     if not args.no_graph:
         rg = run_gpu(pairs, main_prec, args.steps, args.warmup, "graph", tuned[main_prec], simple=args.simple)
@@ -502,8 +515,11 @@ def main():
                 ts, info = autotune(sp, "fp64", "mixed", args.retune)
                 tune_info[name] = info
             small[name] = {}
-            for prec in ("fp64", "mixed"):
-                rs = run_gpu(sp, prec, args.small_steps, args.warmup, "eager", ts[prec], keep=True)
+            precs = ("fp64", "mixed", "dd") if n == 20 else ("fp64", "mixed")
+            for prec in precs:
+                # MSPLIT_DD: every descent in double-double, with the FP64 launch options
+                rs = run_gpu(sp, prec, args.small_steps, args.warmup, "eager", ts["fp64" if prec == "dd" else prec],
+                             keep=True)
                 small[name][prec] = {"value": rs["roots"] / rs["wall"],
                                      "ms_per_step": 1e3 * rs["wall"] / args.small_steps,
                                      "device_ms_per_step": rs["ms_device"] / args.small_steps,
@@ -511,7 +527,8 @@ def main():
                                      * args.small_steps}
                 kept[f"{name}_{prec}"] = rs.pop("roots_of")
         out["p10"] = {"workload": "p_10, all 512 roots certified", "unit": "certified roots/s", **small["p10"]}
-        out["p20"] = {"workload": "p_20, all 524 288 roots certified: plain FP64 against FP32 steps then FP64",
+        out["p20"] = {"workload": "p_20, all 524 288 roots certified: plain FP64 against FP32 steps then FP64 "
+                                  "(and every descent in double-double, the DD precision)",
                       "unit": "certified roots/s", **small["p20"]}
     if not args.no_p30 and args.workload != "p30":
         p30 = {}
@@ -570,7 +587,7 @@ def main():
             if other in kept:
                 acc["batch24_" + other] = accuracy(kept[other], splits)
         for name, n in (("p10", 10), ("p20", 20)):
-            for prec in ("fp64", "mixed"):
+            for prec in ("fp64", "mixed", "dd"):
                 if f"{name}_{prec}" in kept:
                     acc[f"{name}_{prec}"] = accuracy(kept[f"{name}_{prec}"], splits)
         out["accuracy"] = {"what": "max |gpu - oracle| and max |gpu - oracle| / local separation over a "

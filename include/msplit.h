@@ -32,7 +32,7 @@
  * - Roots are returned in the closed upper half plane (Section 6.1: only
  *   Im >= 0 is stored; p_n and q_{l,n} have integer coefficients): a real
  *   root appears once with im == 0 exactly, a non-real root stands for
- *   itself and its conjugate.  Order: increasing real part, to 2^-46 (roots
+ *   itself and its conjugate (MSPLIT_F_CONJUGATES writes both).  Order: increasing real part, to 2^-46 (roots
  *   whose real parts are closer than that come in start order).  Where FP64 cannot separate the roots (next to c = -2) a root is
  *   a double-double value re + re_lo, im + im_lo (flag MSPLIT_R_DD); give
  *   re_lo and im_lo to receive the low parts (otherwise such roots are
@@ -65,7 +65,10 @@ enum msplit_status {
 enum msplit_precision {
     MSPLIT_FP64 = 0,  /* walk and descent in FP64 */
     MSPLIT_MIXED = 1, /* descent starts in FP32, FP64 refinement */
-    MSPLIT_DD = 2     /* double-double refinement (reserved) */
+    MSPLIT_DD = 2     /* every descent in double-double from its starting point (Section 6.4.3:
+                         the high-precision tier for a whole job); every root is a double-double
+                         value (MSPLIT_R_DD: msplit_roots.re_lo and im_lo are required, else
+                         MSPLIT_E_ARG), identified, classified and certified in double-double */
 };
 
 /* ------------------------------------------------------------------- flags */
@@ -74,10 +77,16 @@ enum msplit_flags {
     MSPLIT_F_NO_LABEL = 2u, /* skip period / type classification */
     MSPLIT_F_BASIN = 4u,    /* with MSPLIT_F_CERTIFY and msplit_roots.basin: prove a disk of
                                Newton convergence around every certified root (Thm proofContract) */
-    MSPLIT_F_SIMPLE = 8u    /* Misiurewicz types: find Mis(l,n) among the roots of the simplified
+    MSPLIT_F_SIMPLE = 8u,   /* Misiurewicz types: find Mis(l,n) among the roots of the simplified
                                polynomial s_{l,n} = p_{l+n-1} + p_{l-1} = q_{l,n} / q_{l-1,n}
                                (eq. polySimple: simple roots, half the degree of q_{l,n}); the
                                certificate still applies Thm proofRoots to q_{l,n} */
+    MSPLIT_F_CONJUGATES = 16u /* write all the roots of P, not the upper half plane only: each
+                                 non-real root preceded by its conjugate (order: real part, then
+                                 imaginary part); the conjugate carries the same label, radius and
+                                 basin (P has real coefficients).  The capacity must hold every root
+                                 (2^(n-1) for p_n), else MSPLIT_E_CAPACITY.  Not with
+                                 msplit_split_streamed (MSPLIT_E_UNSUPPORTED) */
 };
 
 /* per-root flag bits written to msplit_roots.flags */

@@ -521,56 +521,92 @@ __global__ void k_certify_dd(batch_args b, double *re, double *im, double *re_lo
 // roots, are adjacent in that order).  radius == nullptr: only the statistic.
 // With low parts the distances are taken on hi + lo (the list is ordered by
 // the real part to 2^-46, so closer roots may come in either order).
-__global__ void k_separation(batch_args b, const double *re, const double *im, const double *re_lo,
-                             const double *im_lo, const double *radius)
+__global__ void __launch_bounds__(256) k_separation(batch_args b, const double *re, const double *im,
+                                                    const double *re_lo, const double *im_lo, const double *radius)
 {
+    // blocks loop over tiles of 256 roots of the output index space; a tile
+    // and the SEP_HALO roots after it are staged in LDS (the scan of a root
+    // reads up to 8 successors, more only where disks are large), the rest
+    // of a long scan reads global memory
+    constexpr int SEP_HALO = 8, NT = 256 + SEP_HALO;
+    __shared__ double sx[NT], sy[NT], sxl[NT], syl[NT], sR[NT];
+    __shared__ int stp[NT];
     const int64_t n_uniq = b.uniq_offs[b.T];
     unsigned long long *const wc = wave_ctr(b);
     type_count bad;
-    type_cache tc;
+    type_cache tc, th;
     unsigned long long sbits = ~0ull;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t u0 = (int64_t)blockIdx.x * blockDim.x; u0 < n_uniq; u0 += stride) {
+    const bool lo = re_lo && im_lo;
+    for (int64_t u0 = (int64_t)blockIdx.x * 256; u0 < n_uniq; u0 += (int64_t)gridDim.x * 256) {
+        for (int k = threadIdx.x; k < NT; k += 256) {
+            const int64_t u = u0 + k;
+            int t = -1;
+            if (u < n_uniq) {
+                type_cache &c = k < 256 ? tc : th;
+                t = cached_type(c, b.uniq_offs, b.T, u);
+                const int64_t i = b.types[t].out_off + (u - c.lo);
+                sx[k] = re[i];
+                sy[k] = im[i];
+                sxl[k] = lo ? re_lo[i] : 0.0;
+                syl[k] = lo ? im_lo[i] : 0.0;
+                sR[k] = radius ? radius[i] : 0.0;
+            }
+            stp[k] = t;
+        }
+        __syncthreads();
         const int64_t u = u0 + threadIdx.x;
-        const int t = u < n_uniq ? cached_type(tc, b.uniq_offs, b.T, u) : bad.t;
+        const int t = u < n_uniq ? stp[threadIdx.x] : bad.t;
         if (__ballot(u < n_uniq && t != bad.t)) {
             flush_count(wc, C_OVERLAP, bad);
             wave_reduce_by_key<RED_MIN>(wc, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);
             sbits = ~0ull;
         }
         bad.t = t;
-        if (u >= n_uniq) continue;
-        const type_desc &td = b.types[t];
-        const int64_t i = td.out_off + (u - b.uniq_offs[t]);
-        const int64_t end = td.out_off + (b.uniq_offs[t + 1] - b.uniq_offs[t]);
-        const double rmax =
-            radius ? __longlong_as_double((long long)b.ctr[(int64_t)t * C_NCOUNTERS + C_MAX_RAD_BITS]) : 0.0;
-        const bool lo = re_lo && im_lo;
-        const double xi = re[i], yi = im[i], Ri = radius ? radius[i] : 0.0;
-        const double xl = lo ? re_lo[i] : 0.0, yl = lo ? im_lo[i] : 0.0;
-        const double yt = yi + yl;
-        double best = yt > 0.0 ? 2.0 * yt : INFINITY;
-        if (radius && (yi != 0.0 || yl != 0.0) && !(yt >= 2.0 * Ri)) bad.v += 1;
-        bool pair_bad = false;
-        for (int64_t j = i + 1, c = 0; j < end; ++j, ++c) {
-            const double dx = (re[j] - xi) + (lo ? re_lo[j] - xl : 0.0);
-            // the list is ordered by real part only to the key resolution
-            // 2^-KEY_RES: a closer root may follow a farther one by that much
-            const bool need_pair = radius && dx <= 4.0 * (Ri + rmax) + 0x1p-45;
-            if (!need_pair && (dx > best || c >= 8)) break;
-            const double dy = (im[j] - yi) + (lo ? im_lo[j] - yl : 0.0);
-            const double d = sqrt(dx * dx + dy * dy);
-            best = fmin(best, d);
-            if (radius) {
-                const double Rj = radius[j];
-                if (!(d >= 4.0 * fmax(Ri, Rj) * (1.0 + 1e-15))) pair_bad = true;
+        if (u < n_uniq) {
+            const type_desc &td = b.types[t];
+            const int64_t u_end = tc.hi; // the type's roots end there (tc holds type t: u < n_uniq)
+            const double rmax =
+                radius ? __longlong_as_double((long long)b.ctr[(int64_t)t * C_NCOUNTERS + C_MAX_RAD_BITS]) : 0.0;
+            const int k0 = threadIdx.x;
+            const double xi = sx[k0], yi = sy[k0], Ri = sR[k0], xl = sxl[k0], yl = syl[k0];
+            const double yt = yi + yl;
+            double best = yt > 0.0 ? 2.0 * yt : INFINITY;
+            if (radius && (yi != 0.0 || yl != 0.0) && !(yt >= 2.0 * Ri)) bad.v += 1;
+            bool pair_bad = false;
+            for (int64_t j = u + 1, c = 0; j < u_end; ++j, ++c) {
+                const int64_t k = j - u0;
+                double xj, yj, xlj, ylj, Rj;
+                if (k < NT) {
+                    xj = sx[k];
+                    yj = sy[k];
+                    xlj = sxl[k];
+                    ylj = syl[k];
+                    Rj = sR[k];
+                } else {
+                    const int64_t ij = td.out_off + (j - tc.lo);
+                    xj = re[ij];
+                    yj = im[ij];
+                    xlj = lo ? re_lo[ij] : 0.0;
+                    ylj = lo ? im_lo[ij] : 0.0;
+                    Rj = radius ? radius[ij] : 0.0;
+                }
+                const double dx = (xj - xi) + (xlj - xl);
+                // the list is ordered by real part only to the key resolution
+                // 2^-KEY_RES: a closer root may follow a farther one by that much
+                const bool need_pair = radius && dx <= 4.0 * (Ri + rmax) + 0x1p-45;
+                if (!need_pair && (dx > best || c >= 8)) break;
+                const double dy = (yj - yi) + (ylj - yl);
+                const double d = sqrt(dx * dx + dy * dy);
+                best = fmin(best, d);
+                if (radius && !(d >= 4.0 * fmax(Ri, Rj) * (1.0 + 1e-15))) pair_bad = true;
+            }
+            bad.v += pair_bad;
+            if (isfinite(best)) {
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(best);
+                sbits = bits < sbits ? bits : sbits;
             }
         }
-        bad.v += pair_bad;
-        if (isfinite(best)) {
-            const unsigned long long bits = (unsigned long long)__double_as_longlong(best);
-            sbits = bits < sbits ? bits : sbits;
-        }
+        __syncthreads();
     }
     flush_count(wc, C_OVERLAP, bad);
     wave_reduce_by_key<RED_MIN>(wc, C_NCOUNTERS, C_MIN_SEP_BITS, sbits != ~0ull ? bad.t : -1, sbits);

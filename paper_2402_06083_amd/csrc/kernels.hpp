@@ -793,81 +793,99 @@ constexpr int PREKEY_WINDOW = 8;
 constexpr int COLLECT_BLOCK = 256;
 
 // window = 0 keeps every converged start (candidates that are already
-// identified, where only the sort's identification may decide).
+// identified, where only the sort's identification may decide).  Blocks
+// loop over tiles of COLLECT_BLOCK starts, so that each loads the type
+// tables into LDS once (a load per block and tile cost a full memory latency
+// for every 256 starts).
 __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const cd *roots, const cd *roots_lo,
                                                            const uint8_t *status, uint32_t *flag, int window)
 {
     __shared__ collect_tables tabs;
-    __shared__ cd zs[COLLECT_BLOCK + PREKEY_WINDOW], zl[COLLECT_BLOCK + PREKEY_WINDOW];
-    __shared__ int ts[COLLECT_BLOCK + PREKEY_WINDOW]; // type, or -1: not converged
-    __shared__ uint8_t dds[COLLECT_BLOCK + PREKEY_WINDOW];
-    const int64_t base = (int64_t)blockIdx.x * COLLECT_BLOCK - PREKEY_WINDOW;
-    const int64_t g0 = base + threadIdx.x, g1 = base + COLLECT_BLOCK + threadIdx.x;
-    const bool has1 = threadIdx.x < PREKEY_WINDOW;
-    const bool v0 = g0 >= 0 && g0 < b.n_starts, v1 = has1 && g1 < b.n_starts;
-    const uint8_t s0 = v0 ? status[g0] : ST_NONE, s1 = v1 ? status[g1] : ST_NONE;
-    const cd z0 = v0 ? roots[g0] : cd{0.0, 0.0}, z1 = v1 ? roots[g1] : cd{0.0, 0.0};
+    __shared__ cd zs[COLLECT_BLOCK + PREKEY_WINDOW];
+    __shared__ int ts[COLLECT_BLOCK + PREKEY_WINDOW]; // type, | 1 << 16 when double-double; -1: not converged
     load_tables_lds(tabs, b);
-    __syncthreads();
+    const int64_t ntiles = (b.n_starts + COLLECT_BLOCK - 1) / COLLECT_BLOCK;
+    const bool has1 = threadIdx.x < PREKEY_WINDOW;
     auto stage = [&](int i, int64_t g, uint8_t st, cd z) {
-        const int t = st_converged(st) ? find_type_lds(tabs.offs, b.T, g) : -1;
-        cd lo = {0.0, 0.0};
-        if (t >= 0) {
+        int t = -1;
+        if (st_converged(st)) {
+            t = find_type_lds(tabs.offs, b.T, g);
             if (st == ST_DD) {
-                lo = roots_lo[g];
+                cd lo = roots_lo[g];
                 fold_snap_dd(z, lo, tabs.tau_dd[t]);
+                t |= 1 << 16;
             } else {
                 z = fold_snap(z, tabs.tau[t]);
             }
         }
         ts[i] = t;
         zs[i] = z;
-        zl[i] = lo;
-        dds[i] = st == ST_DD;
     };
-    stage(threadIdx.x, g0, s0, z0);
-    if (has1) stage(COLLECT_BLOCK + threadIdx.x, g1, s1, z1);
-    __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * COLLECT_BLOCK + threadIdx.x;
-    if (g >= b.n_starts) return;
-    const int i = threadIdx.x + PREKEY_WINDOW;
-    const int t = ts[i];
-    uint32_t f = 0;
-    if (t >= 0) {
-        const double tau = tabs.tau[t], tdd = tabs.tau_dd[t];
-        const cd z = zs[i], lo = zl[i];
-        const bool dd = dds[i];
-        f = 1;
-        for (int d = 1; d <= window; ++d) {
-            if (ts[i - d] != t) continue;
-            if (same_root(z, lo, dd, zs[i - d], zl[i - d], dds[i - d], tau, tdd)) { f = 0; break; }
+    // the low part of a double-double start, folded like its high part
+    auto lo_of = [&](int64_t g, double tdd) {
+        cd z = roots[g], lo = roots_lo[g];
+        fold_snap_dd(z, lo, tdd);
+        return lo;
+    };
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t base = tile * COLLECT_BLOCK - PREKEY_WINDOW;
+        const int64_t g0 = base + threadIdx.x, g1 = base + COLLECT_BLOCK + threadIdx.x;
+        const bool v0 = g0 >= 0 && g0 < b.n_starts, v1 = has1 && g1 < b.n_starts;
+        const uint8_t s0 = v0 ? status[g0] : ST_NONE, s1 = v1 ? status[g1] : ST_NONE;
+        const cd z0 = v0 ? roots[g0] : cd{0.0, 0.0}, z1 = v1 ? roots[g1] : cd{0.0, 0.0};
+        __syncthreads(); // the tables (first tile), or the previous tile's reads
+        stage(threadIdx.x, g0, s0, z0);
+        if (has1) stage(COLLECT_BLOCK + threadIdx.x, g1, s1, z1);
+        __syncthreads();
+        const int64_t g = tile * COLLECT_BLOCK + threadIdx.x;
+        if (g >= b.n_starts) continue;
+        const int i = threadIdx.x + PREKEY_WINDOW;
+        const int tt = ts[i];
+        uint32_t f = 0;
+        if (tt >= 0) {
+            const int t = tt & 0xffff;
+            const bool dd = (tt >> 16) != 0;
+            const double tau = tabs.tau[t], tdd = tabs.tau_dd[t];
+            const cd z = zs[i], zero = {0.0, 0.0};
+            f = 1;
+            for (int d = 1; d <= window; ++d) {
+                const int tj = ts[i - d];
+                if (tj < 0 || (tj & 0xffff) != t) continue;
+                const bool dj = (tj >> 16) != 0;
+                // two double-double roots compare with their low parts (rare:
+                // read again from the descents' results)
+                const bool same = dd && dj ? same_root(z, lo_of(g, tdd), true, zs[i - d], lo_of(g - d, tdd), true,
+                                                       tau, tdd)
+                                           : same_root(z, zero, dd, zs[i - d], zero, dj, tau, tdd);
+                if (same) { f = 0; break; }
+            }
         }
+        flag[g] = f;
     }
-    flag[g] = f;
 }
 
 // Survivors (flag) to their scanned positions as (key, start index) pairs,
 // grouped by type in start order; surv_offs[t] = the first position of type
-// t, surv_offs[T] = the number of survivors.
+// t, surv_offs[T] = the number of survivors.  Grid-stride: the tables are
+// loaded once per block.
 __global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const cd *roots, const uint32_t *flag,
                                                            const uint32_t *pos, uint64_t *keys, uint32_t *vals)
 {
     __shared__ collect_tables tabs;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool v = g < b.n_starts;
-    const uint32_t f = v ? flag[g] : 0u;
-    const uint32_t p = v ? pos[g] : 0u;
-    const cd z = v && f ? roots[g] : cd{0.0, 0.0};
     load_tables_lds(tabs, b);
     __syncthreads();
-    if (!v) return;
-    const int t = find_type_lds(tabs.offs, b.T, g);
-    if (f) {
-        keys[p] = root_key(t, fold_snap(z, tabs.tau[t]).re);
-        vals[p] = (uint32_t)g;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < b.n_starts; g += stride) {
+        const uint32_t f = flag[g];
+        const uint32_t p = pos[g];
+        const int t = find_type_lds(tabs.offs, b.T, g);
+        if (f) {
+            keys[p] = root_key(t, fold_snap(roots[g], tabs.tau[t]).re);
+            vals[p] = (uint32_t)g;
+        }
+        if (g == tabs.offs[t]) b.surv_offs[t] = (int64_t)p;
+        if (g == b.n_starts - 1) b.surv_offs[b.T] = (int64_t)p + f;
     }
-    if (g == tabs.offs[t]) b.surv_offs[t] = (int64_t)p;
-    if (g == b.n_starts - 1) b.surv_offs[b.T] = (int64_t)p + f;
 }
 
 // The sorted candidates, folded and snapped, in sort order: one gather, so
@@ -1204,6 +1222,84 @@ __global__ void __launch_bounds__(256) k_emit(batch_args b, const cd *uz, const 
         nreal.v += z.im == 0.0;
     }
     flush_count(wc, C_REAL, nreal);
+}
+
+// MSPLIT_F_CONJUGATES: the output as all the roots of P, a non-real root of
+// the upper half plane followed by nothing but its conjugate (real
+// coefficients: conj(c) is a root, certified by the mirrored disk).  Over the
+// output index space (uniq_offs: type t's roots at out_off + rank): w[u] = 1
+// for a real root, 2 otherwise (scanned next), and the fields to a staging
+// copy, which the scatter then writes back expanded, in (Re, Im) order.
+struct conj_stage {
+    double *re, *im, *re_lo, *im_lo, *radius, *basin;
+    int32_t *period, *preperiod;
+    uint8_t *flags;
+};
+
+__device__ __forceinline__ int64_t out_index(const batch_args &b, const int64_t *uo, int64_t u, int &t)
+{
+    t = find_type_lds(uo, b.T, u);
+    return b.types[t].out_off + (u - uo[t]);
+}
+
+__global__ void k_conj_stage(batch_args b, const double *ore, const double *oim, const double *ore_lo,
+                             const double *oim_lo, const int32_t *period, const int32_t *preperiod,
+                             const uint8_t *flags, const double *radius, const double *basin, conj_stage s,
+                             uint32_t *w)
+{
+    __shared__ int64_t uo[MAX_TYPES + 1];
+    for (int i = threadIdx.x; i <= b.T; i += blockDim.x) uo[i] = b.uniq_offs[i];
+    __syncthreads();
+    const int64_t n = uo[b.T];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        int t;
+        const int64_t i = out_index(b, uo, u, t);
+        const double im = oim[i], lo = oim_lo ? oim_lo[i] : 0.0;
+        s.re[u] = ore[i];
+        s.im[u] = im;
+        if (ore_lo) s.re_lo[u] = ore_lo[i];
+        if (oim_lo) s.im_lo[u] = lo;
+        if (period) s.period[u] = period[i];
+        if (preperiod) s.preperiod[u] = preperiod[i];
+        if (flags) s.flags[u] = flags[i];
+        if (radius) s.radius[u] = radius[i];
+        if (basin) s.basin[u] = basin[i];
+        w[u] = (im == 0.0 && lo == 0.0) ? 1u : 2u;
+    }
+}
+
+__global__ void k_conj_scatter(batch_args b, conj_stage s, const uint32_t *pos, double *ore, double *oim,
+                               double *ore_lo, double *oim_lo, int32_t *period, int32_t *preperiod, uint8_t *flags,
+                               double *radius, double *basin)
+{
+    __shared__ int64_t uo[MAX_TYPES + 1];
+    for (int i = threadIdx.x; i <= b.T; i += blockDim.x) uo[i] = b.uniq_offs[i];
+    __syncthreads();
+    const int64_t n = uo[b.T];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        const int t = find_type_lds(uo, b.T, u);
+        const type_desc &td = b.types[t];
+        // position within the type: scanned weights from the type's first root
+        const int64_t r = (int64_t)pos[u] - (int64_t)pos[uo[t]];
+        const double im = s.im[u], lo = oim_lo ? s.im_lo[u] : 0.0;
+        const int w = (im == 0.0 && lo == 0.0) ? 1 : 2;
+        for (int k = 0; k < w; ++k) {
+            if ((uint64_t)(r + k) >= td.cap) break;
+            const int64_t i = td.out_off + r + k;
+            const double sg = (w == 2 && k == 0) ? -1.0 : 1.0; // the conjugate first
+            ore[i] = s.re[u];
+            oim[i] = sg * im;
+            if (ore_lo) ore_lo[i] = s.re_lo[u];
+            if (oim_lo) oim_lo[i] = sg * lo;
+            if (period) period[i] = s.period[u];
+            if (preperiod) preperiod[i] = s.preperiod[u];
+            if (flags) flags[i] = s.flags[u];
+            if (radius) radius[i] = s.radius[u];
+            if (basin) basin[i] = s.basin[u];
+        }
+    }
 }
 
 } // namespace msplit

@@ -398,7 +398,7 @@ struct batch_call {
     msplit_options o;
     msplit_roots out;
     int bs = 256;
-    bool cert = false, labels = true, any_tip = false, basin = false;
+    bool cert = false, labels = true, any_tip = false, basin = false, conj = false;
     batch_args ba;
     char *ws = nullptr;
     int64_t out_max = 0;
@@ -415,7 +415,6 @@ int check_options(batch_call &c, const msplit_options *opts, const msplit_roots 
     if (!starts_only && (!out || !out->re || !out->im)) return MSPLIT_E_ARG;
     if (opts->struct_size && opts->struct_size != sizeof(msplit_options)) return MSPLIT_E_ARG;
     if (opts->precision < 0 || opts->precision > 2) return MSPLIT_E_ARG;
-    if (opts->precision == MSPLIT_DD) return MSPLIT_E_UNSUPPORTED;
     // M: a power of two, 4 .. 64 (the walk takes phase indices and starts by masks)
     if (opts->points_per_turn && (opts->points_per_turn < 4 || opts->points_per_turn > 64 ||
                                   (opts->points_per_turn & (opts->points_per_turn - 1))))
@@ -424,10 +423,13 @@ int check_options(batch_call &c, const msplit_options *opts, const msplit_roots 
     if (c.bs % 64 || c.bs > 256) return MSPLIT_E_ARG;
     c.o = *opts;
     if (out) c.out = *out; else memset(&c.out, 0, sizeof(c.out));
+    // double-double roots need their low parts
+    if (!starts_only && opts->precision == MSPLIT_DD && (!out->re_lo || !out->im_lo)) return MSPLIT_E_ARG;
     c.cert = !starts_only && (opts->flags & MSPLIT_F_CERTIFY) != 0;
     if (c.cert && (!out->radius || !out->flags)) return MSPLIT_E_ARG;
     c.labels = !(opts->flags & MSPLIT_F_NO_LABEL);
     c.basin = c.cert && (opts->flags & MSPLIT_F_BASIN) && out->basin;
+    c.conj = !starts_only && (opts->flags & MSPLIT_F_CONJUGATES) != 0;
     return MSPLIT_OK;
 }
 
@@ -637,6 +639,14 @@ void enqueue_descents(const batch_call &c, const pipe_bufs &B, hipStream_t strea
     // the FP64 descent's queue: every wave starts on its static chunk, the
     // counter hands out the chunks after them
     const unsigned long long q0 = (unsigned long long)nb * (bs / 64) * ba.chunk_start;
+    if (c.o.precision == MSPLIT_DD) {
+        // every descent in double-double, from its starting point (Section
+        // 6.4.3: the high-precision tier for the whole job)
+        k_list_all<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, B.flag0);
+        k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, B.flag0, B.starts, B.tip_lo, B.roots, B.roots_lo,
+                                                           B.status, 1);
+        return;
+    }
     if (ba.n_fp32 > 0) {
         k_descend32<<<persistent_blocks(ba.n_fp32, bs), bs, 0, stream>>>(ba, B.roots, B.status, B.iters);
         k_set_counter<<<1, 64, 0, stream>>>(&ba.gctr[G_START_NEXT2], q0);
@@ -650,7 +660,7 @@ void enqueue_descents(const batch_call &c, const pipe_bufs &B, hipStream_t strea
     if (c.any_tip) {
         k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, B.roots, B.status, B.flag0);
         k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, B.flag0, B.starts, B.tip_lo, B.roots, B.roots_lo,
-                                                           B.status);
+                                                           B.status, 0);
     }
 }
 
@@ -664,11 +674,9 @@ collected enqueue_collect(const batch_call &c, const pipe_bufs &B, hipStream_t s
     const batch_args &ba = c.ba;
     const int T = bp.T;
     const unsigned gs = persistent_blocks(bp.n_starts, 256);
-    k_prekeys<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.roots_lo,
-                                                                                    B.status, B.flag0, window);
+    k_prekeys<<<gs, COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.roots_lo, B.status, B.flag0, window);
     scan_u32(B.flag0, B.pos0, B.isz + SZ_STARTS, bp.n_starts, B.part, stream);
-    k_compact<<<blocks_for(bp.n_starts, COLLECT_BLOCK), COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.flag0, B.pos0,
-                                                                                    B.keys, B.vals);
+    k_compact<<<gs, COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.flag0, B.pos0, B.keys, B.vals);
     uint64_t *skeys = B.keys;
     uint32_t *svals = B.vals;
     sort_pairs(&skeys, &svals, B.keys2, B.vals2, ba.surv_offs, B.rtile, T, KEY_BITS, bp.n_starts, B.rcounts,
@@ -752,6 +760,33 @@ void enqueue_certify(const batch_args &ba, const msplit_roots &out, bool cert, b
     }
 }
 
+// MSPLIT_F_CONJUGATES: every output slice expanded in place to all the roots
+// (the conjugate before each non-real root), through a staging copy in
+// buffers of the workspace that are free once the roots are emitted (at
+// most D/2 + D/16 roots per type, within the NS = 2D + 1 slots of each).
+void enqueue_conjugates(const batch_call &c, const pipe_bufs &B, hipStream_t stream)
+{
+    const batch_plan &bp = c.bp;
+    const batch_args &ba = c.ba;
+    const msplit_roots &o = c.out;
+    conj_stage s;
+    s.re = (double *)B.zs;
+    s.im = (double *)B.zs + bp.n_starts;
+    s.re_lo = (double *)B.zs_lo;
+    s.im_lo = (double *)B.zs_lo + bp.n_starts;
+    s.radius = (double *)B.keys;
+    s.basin = (double *)B.keys2;
+    s.period = (int32_t *)B.vals;
+    s.preperiod = (int32_t *)B.vals2;
+    s.flags = (uint8_t *)B.flag0;
+    const unsigned gs = persistent_blocks(c.out_max, 256);
+    k_conj_stage<<<gs, 256, 0, stream>>>(ba, o.re, o.im, o.re_lo, o.im_lo, o.period, o.preperiod, o.flags,
+                                          c.cert ? o.radius : nullptr, c.basin ? o.basin : nullptr, s, B.flag);
+    scan_u32(B.flag, B.pos, ba.uniq_offs + bp.T, std::max<int64_t>(c.out_max, 1), B.part, stream);
+    k_conj_scatter<<<gs, 256, 0, stream>>>(ba, s, B.pos, o.re, o.im, o.re_lo, o.im_lo, o.period, o.preperiod,
+                                            o.flags, c.cert ? o.radius : nullptr, c.basin ? o.basin : nullptr);
+}
+
 // Descents, collection, classification, certificate (events ev[3..6]).
 // Every size after the level line is computed and read on the device.
 void enqueue_roots(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
@@ -766,6 +801,7 @@ void enqueue_roots(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
     bool p_only = true;
     for (const type_desc &d : c.bp.td) p_only = p_only && d.p.l == 0;
     enqueue_certify(c.ba, c.out, c.cert, c.labels, c.basin, c.bp.T, c.out_max, (uint32_t *)C.fkeys, stream, p_only);
+    if (c.conj) enqueue_conjugates(c, B, stream);
     k_fold_counters<<<fold_blocks(c.bp.T), 256, 0, stream>>>(c.ba.ctr, c.ba.spread, c.bp.T);
     if (ev) (void)hipEventRecord(ev[6], stream);
 }
@@ -782,9 +818,12 @@ int finish(batch_call &c, hipStream_t stream, uint64_t *counts, msplit_stats *st
     auto H = [&](int t, int slot) { return c.h[(size_t)t * C_NCOUNTERS + slot]; };
     int status_all = MSPLIT_OK;
     for (int t = 0; t < T; ++t) {
-        const uint64_t u = H(t, C_KEPT);
-        counts[bp.slot[t]] = u;
-        if (u > bp.td[t].cap) status_all = MSPLIT_E_CAPACITY;
+        // roots written: the upper half plane, or all of them with their
+        // conjugates (MSPLIT_F_CONJUGATES)
+        const uint64_t u = H(t, C_KEPT), nr = H(t, C_REAL);
+        const uint64_t w = c.conj ? nr + 2 * (u - nr) : u;
+        counts[bp.slot[t]] = w;
+        if (w > bp.td[t].cap) status_all = MSPLIT_E_CAPACITY;
     }
     if (stats) memset(stats, 0, sizeof(msplit_stats) * T);
     for (int t = 0; t < T; ++t) {
@@ -1013,6 +1052,7 @@ int run_stream(int l, int n, const msplit_options *opts, uint64_t chunk_starts, 
         batch_call probe;
         r = check_options(probe, opts, out, false);
         if (r) return r;
+        if (probe.conj) return MSPLIT_E_UNSUPPORTED;
     }
     hipStream_t stream = (hipStream_t)stream_v;
     call_ctx ctx{stats, 1};

@@ -275,19 +275,25 @@ __global__ void k_route_tip(batch_args b, const cd *roots, const uint8_t *status
 // Work list length read on the device.
 constexpr int DD_CAP = 256;
 
+// primary: every descent of the call runs here (MSPLIT_DD), and the outcomes
+// are counted as the FP64 descent counts them (converged, diverged, time-outs)
+// instead of as routed starts.
 __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t *list, const cd *starts,
-                                                    const cd *tip_lo, cd *roots, cd *roots_lo, uint8_t *status)
+                                                    const cd *tip_lo, cd *roots, cd *roots_lo, uint8_t *status,
+                                                    int primary)
 {
     constexpr int64_t NONE = -1;
     unsigned long long *const wc = wave_ctr(b);
     const uint64_t n = b.gctr[G_DD_COUNT];
-    // per-lane counts of type ct: double-double steps, routed starts
+    // per-lane counts of type ct: double-double steps, then routed starts, or
+    // (primary) converged, diverged and timed-out descents
     int ct = -1;
     uint32_t cnt[4] = {0u, 0u, 0u, 0u};
-    const int slots[4] = {C_STEPS_DD, C_DD_ROUTED, C_STEPS_DD, C_STEPS_DD};
+    const int slots[4] = {C_STEPS_DD, primary ? C_CONVERGED : C_DD_ROUTED, primary ? C_DIVERGED : C_STEPS_DD,
+                          primary ? C_TIMEOUT : C_STEPS_DD};
     int64_t g = NONE;
     bool exhausted = false;
-    int t = -1, el = 0, eN = 1, it = 0;
+    int t = -1, el = 0, eN = 1, it = 0, cap = DD_CAP;
     bool fin = false;
     double prev = 0.0;
     cdd z = {{0.0, 0.0}, {0.0, 0.0}};
@@ -304,6 +310,9 @@ __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t
                 const type_desc &td = b.types[t];
                 el = td.p.el;
                 eN = td.p.eN;
+                // the routed descents near -2 need up to about 60 steps; as
+                // the primary descent, the type's own cap unless it has a tip
+                cap = primary && td.p.x_tip <= 0.0 ? td.p.cap : DD_CAP;
                 const cd s0 = starts[g];
                 z = {{s0.re, 0.0}, {s0.im, 0.0}};
                 const int64_t k = g - td.start_off;
@@ -320,12 +329,12 @@ __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t
         const bool change = g != NONE && t != ct;
         if (__ballot(change)) {
             wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
-            cnt[0] = cnt[1] = 0u;
+            cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0u;
             if (change) ct = t;
         }
         if (__ballot(g != NONE || !exhausted) == 0) break;
         if (g == NONE) continue;
-        cnt[1] += it == 0;
+        if (!primary) cnt[1] += it == 0;
         const dd_step r = dd_newton_step(el, eN, z);
         ++it;
         cnt[0] += 1u;
@@ -342,7 +351,7 @@ __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t
             // rounding, else after one more step
             if (a2 * a2 * a2 <= 0x1p-212 * fmax(az2, 0x1p-16) * prev * prev) st = ST_DD;
             else fin = true;
-        } else if (it >= DD_CAP) {
+        } else if (it >= cap) {
             st = ST_TIMEOUT;
         }
         prev = a2;
@@ -350,10 +359,23 @@ __global__ void __launch_bounds__(256) k_descend_dd(batch_args b, const uint32_t
             roots[g] = {z.re.hi, z.im.hi};
             roots_lo[g] = {z.re.lo, z.im.lo};
             status[g] = st;
+            if (primary) {
+                cnt[1] += st == ST_DD;
+                cnt[2] += st == ST_DIVERGED;
+                cnt[3] += st == ST_TIMEOUT;
+            }
             g = NONE;
         }
     }
     wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
+}
+
+// MSPLIT_DD: every start to the double-double descent's list.
+__global__ void k_list_all(batch_args b, uint32_t *list)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < b.n_starts) list[g] = (uint32_t)g;
+    if (g == 0) b.gctr[G_DD_COUNT] = (unsigned long long)b.n_starts;
 }
 
 } // namespace msplit

@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("MSPLIT_LIB") or os.path.join(_HERE, "libmsplit.so")
 # status codes
 OK, E_ARG, E_CAPACITY, E_WORKSPACE, E_DEVICE, E_INCOMPLETE, E_PRECISION, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED, DD = 0, 1, 2
-F_CERTIFY, F_NO_LABEL, F_BASIN, F_SIMPLE = 1, 2, 4, 8
+F_CERTIFY, F_NO_LABEL, F_BASIN, F_SIMPLE, F_CONJUGATES = 1, 2, 4, 8, 16
 R_REAL, R_CERTIFIED, R_LABEL, R_DD, R_BASIN = 1, 2, 4, 8, 16
 CERTIFY_WORKSPACE = 16384  # MSPLIT_CERTIFY_WORKSPACE
 
@@ -138,9 +138,10 @@ class MsplitError(RuntimeError):
 
 
 def make_options(precision=FP64, level=0.0, points_per_turn=0, seg_points=0, min_cap=0, cap_factor=0.0,
-                 block_size=0, certify=False, label=True, fp32_switch=0.0, basin=False, simple=False):
+                 block_size=0, certify=False, label=True, fp32_switch=0.0, basin=False, simple=False,
+                 conjugates=False):
     flags = ((F_CERTIFY if certify else 0) | (0 if label else F_NO_LABEL) | (F_BASIN if basin else 0) |
-             (F_SIMPLE if simple else 0))
+             (F_SIMPLE if simple else 0) | (F_CONJUGATES if conjugates else 0))
     prec = {"fp64": FP64, "mixed": MIXED, "dd": DD}.get(precision, precision)
     return Options(ctypes.sizeof(Options), prec, level, points_per_turn, seg_points, min_cap, cap_factor,
                    block_size, flags, fp32_switch)

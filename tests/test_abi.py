@@ -65,11 +65,14 @@ def test_header_constants_match_binding():
     text = open(HEADER).read()
     m = re.search(r"#define\s+MSPLIT_CERTIFY_WORKSPACE\s+(\d+)u?", text)
     assert m and int(m.group(1)) == msplit.CERTIFY_WORKSPACE
+    m = re.search(r"#define\s+MSPLIT_STATIC_SCRATCH_BYTES\s+\((\d+)ull << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == msplit.STATIC_SCRATCH_BYTES
     for name, val in [("MSPLIT_R_REAL", msplit.R_REAL), ("MSPLIT_R_CERTIFIED", msplit.R_CERTIFIED),
                       ("MSPLIT_R_LABEL", msplit.R_LABEL), ("MSPLIT_R_DD", msplit.R_DD), ("MSPLIT_F_CERTIFY", msplit.F_CERTIFY),
                       ("MSPLIT_F_NO_LABEL", msplit.F_NO_LABEL), ("MSPLIT_F_BASIN", msplit.F_BASIN),
                       ("MSPLIT_F_SIMPLE", msplit.F_SIMPLE), ("MSPLIT_R_BASIN", msplit.R_BASIN),
-                      ("MSPLIT_E_WORKSPACE", msplit.E_WORKSPACE)]:
+                      ("MSPLIT_E_WORKSPACE", msplit.E_WORKSPACE), ("MSPLIT_F_CONJUGATES", msplit.F_CONJUGATES),
+                      ("MSPLIT_DD", msplit.DD)]:
         m = re.search(name + r"\s*=\s*(-?\d+)u?", text)
         assert m and int(m.group(1)) == val, name
 

@@ -9,19 +9,25 @@
 - p_25, the first order whose tip goes through double-double: compared root by
   root with the oracle, double-double roots to 1e-25.
 - p_30 (2^29 roots): the GPU certificate on every root, exact per-period
-  counts, the oracle's set check (Thm certif: disjoint, quarter-separated
-  disks, count = degree) over the whole double-double list, and the oracle's
-  own certificate on the double-double roots, on the roots next to -2 and on
-  a uniform sample.  With MSPLIT_FULL_ORACLE=1 the oracle certifies every
-  root and the set check runs on the oracle's radii: by Thm certif that
-  proves the whole set with oracle arithmetic alone (about ten minutes of
-  the host's cores).
+  counts, then the oracle's own certificate (Thm proofRoots in long double,
+  the label proven) on every one of the 277 383 872 upper-half roots, from
+  their double-double values, and the oracle's set check (Thm certif:
+  disjoint, quarter-separated disks, count = degree) over the whole list with
+  the oracle's radii: by Thm certif that proves the whole set with oracle
+  arithmetic alone (about three minutes of the host's cores).  With
+  MSPLIT_QUICK_ORACLE=1 the oracle certifies a sample only (the
+  double-double roots, the roots within 1e-3 of -2 and 2M others).
 - a batch mixing p_n and Misiurewicz types, through q_{l,n} and through
   s_{l,n}, and the streamed split, each compared with the oracle type by type.
 - all 210 Misiurewicz types of order <= 22: every root certified again by
   the oracle and the set check per type.
-- the incomplete-split path: descents capped at one step through the normal
-  options must end in MSPLIT_E_INCOMPLETE with the roots still written.
+- the incomplete-split path: descents capped at five steps through the
+  normal options must end in MSPLIT_E_INCOMPLETE with the roots still
+  written.
+- MSPLIT_DD: every descent in double-double; every root a double-double
+  value equal to the oracle's to 1e-25, certified in double-double.
+- MSPLIT_F_CONJUGATES: all the roots of P, in (Re, Im) order; the same as
+  the upper-half output with each non-real root's conjugate put before it.
 """
 import os
 
@@ -119,12 +125,16 @@ def _flagged(flags, bit, step=1 << 28):
     return np.concatenate(out)
 
 
-def test_period_30_oracle_certificate():
-    """p_30 in the benchmark's launch configuration: the set check of Thm
-    certif by the oracle over all 2^29 roots, and the oracle's certificate on
-    every double-double root, every root within 1e-3 of -2 and a uniform
-    sample of 2M (every root with MSPLIT_FULL_ORACLE=1)."""
+def test_period_30_oracle_certificate(capsys):
+    """p_30 in the benchmark's launch configuration: the oracle's certificate
+    on every root and the set check of Thm certif by the oracle over all 2^29
+    roots (a sample with MSPLIT_QUICK_ORACLE=1).  The progress lines bypass
+    the output capture: the oracle's work takes minutes."""
     from paper_2402_06083_amd import msplit, tune
+
+    def say(msg):  # noqa: F811  (this test's own, uncaptured)
+        with capsys.disabled():
+            print(msg, flush=True)
     n = 30
     pairs = [(0, n)]
     opts, cand = tune.tuned_options(pairs, "fp64")
@@ -152,7 +162,7 @@ def test_period_30_oracle_certificate():
         sel = per == k
         cnt = int((sel & real).sum()) + 2 * int((sel & ~real).sum())
         assert cnt == counts.hyp_count(k), (k, cnt)
-    full = os.environ.get("MSPLIT_FULL_ORACLE") == "1"
+    full = os.environ.get("MSPLIT_QUICK_ORACLE") != "1"
     if full:
         idx = np.arange(m)
     else:
@@ -168,8 +178,8 @@ def test_period_30_oracle_certificate():
         assert np.all(ok == 3), (s, int((ok != 3).sum()))
         say(f"[oracle] p_30: {min(s + step, len(idx))} of {len(idx)} certified")
     assert orad.max() <= RADIUS_MAX
-    # Thm certif over the whole list: the oracle's radii where it certified,
-    # the GPU's elsewhere (all of them the oracle's with MSPLIT_FULL_ORACLE=1)
+    # Thm certif over the whole list: the oracle's radii where it certified
+    # (everywhere, unless MSPLIT_QUICK_ORACLE=1), the GPU's elsewhere
     rr = rad.copy()
     rr[idx] = orad
     say("[oracle] p_30: set check")
@@ -273,3 +283,84 @@ def test_incomplete_split_is_reported():
     from scipy.spatial import cKDTree
     d, _ = cKDTree(np.stack([o.re_hi, o.im_hi], axis=1)).query(np.stack([g.re, g.im], axis=1), k=1)
     assert d.max() <= 1e-10
+
+
+@pytest.mark.parametrize("ln", [(0, 12), (0, 20), (3, 9), (2, 16)])
+def test_double_double_precision_matches_oracle(ln):
+    """MSPLIT_DD: every descent in double-double from its starting point;
+    every root equal to the oracle's double-double root to 1e-25 (hi + lo),
+    flagged MSPLIT_R_DD unless exact in FP64, certified with its label
+    proven, exact counts."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    say(f"[gpu] double-double split l={l} n={n}")
+    r = msplit.split(l, n, msplit.make_options(precision="dd", certify=True), check=False)
+    torch.cuda.synchronize()
+    st = r.stats
+    assert r.status == msplit.OK, (r.status, st)
+    g = r.cpu()
+    check_type_stats(l, n, st, len(g))
+    # certified in double-double, except roots exact in FP64 (zero low parts,
+    # such as 0 and -1), which the FP64 certificate settles
+    exact = (g.re_lo == 0) & (g.im_lo == 0)
+    assert np.all((g.flags & msplit.R_DD != 0) | exact), "every root double-double"
+    assert exact.sum() <= 8, exact.sum()
+    assert st["steps_desc"] == 0 and st["steps_dd"] > 0
+    assert st["converged"] > 0
+    # every root (hi + lo) against the oracle's double-double value
+    c = compare_sets(g, oracle_split(l, n), dd_flags=np.full(len(g), msplit.R_DD, dtype=np.uint8))
+    say(f"[gpu] double-double l={l} n={n}: max |gpu - oracle| = {c['max_dd']:.3e}")
+    assert c["max_dd"] < 1e-25
+
+
+def test_double_double_precision_needs_low_parts():
+    from paper_2402_06083_amd import msplit
+    import ctypes
+    opts = msplit.make_options(precision="dd")
+    b = msplit.Buffers(0, 8, opts)
+    rs = b.roots_struct()
+    rs.re_lo = None
+    cnt = ctypes.c_uint64()
+    r = msplit.lib().msplit_hyperbolic(8, ctypes.byref(opts), ctypes.c_void_p(b.ws.data_ptr()), b.ws_bytes,
+                                       ctypes.byref(rs), ctypes.byref(cnt), None, None)
+    assert r == msplit.E_ARG
+
+
+@pytest.mark.parametrize("ln,prec", [((0, 12), "fp64"), ((0, 25), "fp64"), ((3, 9), "fp64"), ((0, 16), "dd")])
+def test_conjugates_flag(ln, prec):
+    """MSPLIT_F_CONJUGATES: the count is every root of P (2^(n-1) for p_n,
+    |Mis(l,n)| for q_{l,n}); the output is the upper-half output with each
+    non-real root preceded by its conjugate (same label, flags, radius),
+    sorted by (Re, Im); its closure under conjugation equals the oracle's
+    roots with their conjugates."""
+    from paper_2402_06083_amd import msplit
+    l, n = ln
+    say(f"[gpu] conjugates l={l} n={n} {prec}")
+    ru = msplit.split(l, n, msplit.make_options(precision=prec, certify=True), check=False)
+    torch.cuda.synchronize()
+    assert ru.status == msplit.OK, (ru.status, ru.stats)
+    gu = ru.cpu()
+    del ru
+    rc = msplit.split(l, n, msplit.make_options(precision=prec, certify=True, conjugates=True), check=False)
+    torch.cuda.synchronize()
+    assert rc.status == msplit.OK, (rc.status, rc.stats)
+    gc = rc.cpu()
+    del rc
+    torch.cuda.empty_cache()
+    exp = 2 ** (n - 1) if l == 0 else counts.mis_count(l, n)
+    assert len(gc) == exp == gu.stats["total"]
+    nonreal = (gu.im != 0) | (gu.im_lo != 0)
+    rep = np.where(nonreal, 2, 1)
+    idx = np.repeat(np.arange(len(gu)), rep)
+    first = np.concatenate([[True], idx[1:] != idx[:-1]])
+    sign = np.where(nonreal[idx] & first, -1.0, 1.0)
+    assert np.array_equal(gc.re, gu.re[idx]) and np.array_equal(gc.re_lo, gu.re_lo[idx])
+    assert np.array_equal(gc.im, sign * gu.im[idx]) and np.array_equal(gc.im_lo, sign * gu.im_lo[idx])
+    for k in ("period", "preperiod", "flags", "radius"):
+        assert np.array_equal(getattr(gc, k), getattr(gu, k)[idx]), k
+    assert np.all(np.diff(gc.re) >= -2.0 ** -45)
+    o = oracle_split(l, n)
+    oz = np.concatenate([o.re_hi + 1j * o.im_hi, o.re_hi[o.im_hi > 0] - 1j * o.im_hi[o.im_hi > 0]])
+    from scipy.spatial import cKDTree
+    d, j = cKDTree(np.stack([oz.real, oz.imag], axis=1)).query(np.stack([gc.re, gc.im], axis=1), k=1)
+    assert len(np.unique(j)) == len(oz) and d.max() <= 1e-10
