@@ -50,8 +50,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false, false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1268462857.0
-DESCEND_TRAFFIC_SHA256 = "cc9a86c18e78556b85e6024991adacbc0e3b868ae490af24a40e42e1ac766b6d"
+DESCEND_TRAFFIC_BYTES = 1270146791.0
+DESCEND_TRAFFIC_SHA256 = "80ab730a27b26e168bef4a8e9b5c5c573ff2830859d0b1de91873a72298d5c14"
 
 
 def descend_traffic():
