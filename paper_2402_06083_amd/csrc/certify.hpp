@@ -48,11 +48,13 @@ constexpr double ETA = 0x1p-1074;
 __device__ __forceinline__ double up(double x) { DD_EXACT return __dadd_rn(__dmul_rn(x, 1.0 + 0x1p-47), 0x1p-1000); }
 __device__ __forceinline__ double dn(double x) { DD_EXACT return __dsub_rn(__dmul_rn(x, 1.0 - 0x1p-47), 0x1p-1000); }
 // upper bound of |a|: sqrt(M^2 + m^2) <= M + m^2 / (2M) <= M + m / 2 for
-// M = max(|re|, |im|) >= m = min(|re|, |im|) (at most 6% above |a|)
+// M = max(|re|, |im|) >= m = min(|re|, |im|) (at most 6% above |a|), written
+// M + m / 2 = 3/4 (x + y) + 1/4 |x - y| (x = |re|, y = |im|: no max or min);
+// its four roundings are covered by up()
 __device__ __forceinline__ double abs_up(cd a)
 { DD_EXACT
     const double x = fabs(a.re), y = fabs(a.im);
-    return up(__dadd_rn(fmax(x, y), __dmul_rn(0.5, fmin(x, y))));
+    return up(__dadd_rn(__dmul_rn(0.75, __dadd_rn(x, y)), __dmul_rn(0.25, fabs(__dsub_rn(x, y)))));
 }
 // lower bound of |a|^2
 __device__ __forceinline__ double abs2_dn(cd a)
@@ -101,6 +103,58 @@ __device__ __forceinline__ void disk_orbit_step(disk_step &s, cd c, double R)
 
 struct cert_result { uint8_t flags; double R; };
 
+// Strict divisors of the label lab of a root of p_n as a bit mask (bit k set
+// when k | lab, k < lab; k < 32).  lab divides n, so they are among the
+// strict divisors of n (divmask_n); lab = n, the label of almost every root,
+// needs no division.
+__device__ __forceinline__ uint32_t label_divmask(int lab, int n, uint32_t divmask_n)
+{
+    if (lab == n) return divmask_n;
+    uint32_t m = 0u;
+    for (uint32_t r = divmask_n; r; r &= r - 1u) {
+        const int k = __builtin_ctz(r);
+        if (k < lab && lab % k == 0) m |= 1u << k;
+    }
+    return m;
+}
+
+// The disk pass of a root of p_n of order N with label lab on D(c, R), then
+// Thm proofRoots for p_n (and p_lab when lab != n).  UNI: every active lane
+// of the wave certifies a root of the same p_N with label N, and N and dmask
+// are wave-uniform, so the loop and the divisor tests are scalar branches and
+// no state of step lab is kept.
+template <bool UNI>
+__device__ __forceinline__ uint8_t certify_p_pass(int N, int lab, uint32_t dmask, cd c, double R)
+{ DD_EXACT
+    disk_step t = {{0.0, 0.0}, {0.0, 0.0}, 0.0, 0.0, 0.0};
+    cd Zk = {0, 0}, DZk = {0, 0};
+    double ek = 0.0, sk = 0.0;
+    bool label_ok = true;
+#pragma unroll 2
+    for (int kk = 1; kk <= N; ++kk) {
+        disk_orbit_step(t, c, R);
+        if (!UNI && kk == lab) { Zk = t.Z; DZk = t.DZ; ek = t.e; sk = t.sig; }
+        // p_j, j a strict divisor of the label, has no zero on the disk
+        if (kk < 32 && ((dmask >> kk) & 1u)) {
+            const double r = t.rho;
+            if (!(abs2_dn(t.Z) > up(r * r))) label_ok = false;
+        }
+    }
+    const cd P = t.Z, dP = t.DZ;
+    const double Pup = up(abs_up(P) + up(t.e + rnd(P)));
+    const double sP = up(t.sig + rnd(dP));
+    // Thm proofRoots: R (|P'(c)| - sigma) > |P(c)|
+    const double need = up(up(Pup / R) + sP);
+    if (!(abs2_dn(dP) > up(need * need))) return 0;
+    if (!UNI && lab != N) {
+        // Thm proofRoots for p_lab on the same disk
+        const double Pk = up(abs_up(Zk) + up(ek + rnd(Zk)));
+        const double nk = up(up(Pk / R) + up(sk + rnd(DZk)));
+        if (!(abs2_dn(DZk) > up(nk * nk))) label_ok = false;
+    }
+    return label_ok ? 2 | 4 : 2; // MSPLIT_R_CERTIFIED, MSPLIT_R_LABEL
+}
+
 // Certify c for P = q_{l,n} (l = 0: p_n) with label lab (p_n: period).
 // The radius is chosen from a plain evaluation: R ~ 4 |P/P'| plus the
 // rounding noise of a root, rounded up to a power of two; then one fused pass
@@ -121,37 +175,43 @@ __device__ cert_result certify_root(int l_arg, int n, int lab, uint32_t divmask_
     double R0 = 4.0 * sqrt(cabs2(P0) / cabs2(dP0)) + 64.0 * U53 * fmax(az, 0x1p-8);
     if (!(R0 > 0x1p-1000) || !isfinite(R0)) R0 = 0x1p-1000;
     double R = ldexp(1.0, ilogb(R0) + 1); // power of two above R0
+    if (l == 0) {
+        const uint32_t dmask = label_divmask(lab, n, divmask_n);
+        const int n0 = __builtin_amdgcn_readfirstlane(n);
+        const bool uni = __ballot(n != n0 || lab != n) == 0;
+        const uint32_t m0 = __builtin_amdgcn_readfirstlane(dmask);
+        for (int attempt = 0; attempt < 3; ++attempt, R *= 16.0) {
+            const uint8_t f = uni ? certify_p_pass<true>(n0, n0, m0, c, R) : certify_p_pass<false>(n, lab, dmask, c, R);
+            if (f) {
+                res.flags = f;
+                res.R = R;
+                return res;
+            }
+        }
+        return res;
+    }
     for (int attempt = 0; attempt < 3; ++attempt, R *= 16.0) {
         disk_step t = {{0.0, 0.0}, {0.0, 0.0}, 0.0, 0.0, 0.0};
-        cd Zl = {0, 0}, DZl = {0, 0}, Zlm = {0, 0}, Zk = {0, 0}, DZk = {0, 0};
-        double el = 0.0, rl = 0.0, sl = 0.0, rlm = 0.0, ek = 0.0, sk = 0.0;
+        cd Zl = {0, 0}, DZl = {0, 0}, Zlm = {0, 0};
+        double el = 0.0, rl = 0.0, sl = 0.0, rlm = 0.0;
         bool label_ok = true;
         for (int k = 0; k < N; ++k) {
             disk_orbit_step(t, c, R);
             const int kk = k + 1;
             if (kk == l - 1) { Zlm = t.Z; rlm = t.rho; }
             if (kk == l) { Zl = t.Z; DZl = t.DZ; el = t.e; rl = t.rho; sl = t.sig; }
-            if (l == 0) {
-                if (kk == lab) { Zk = t.Z; DZk = t.DZ; ek = t.e; sk = t.sig; }
-                // p_j, j a strict divisor of the label, has no zero on the disk
-                if (kk < lab && lab % kk == 0) {
-                    const double r = t.rho;
-                    if (!(abs2_dn(t.Z) > up(r * r))) label_ok = false;
-                }
-            } else {
-                // q_{l,k} = z_{l+k} - z_l, k a strict divisor of n
-                const int kd = kk - l;
-                if (kd >= 1 && kd < n && ((divmask_n >> kd) & 1u)) {
-                    const cd d = {__dsub_rn(t.Z.re, Zl.re), __dsub_rn(t.Z.im, Zl.im)};
-                    const double r = up(t.rho + rl + rnd(d));
-                    if (!(abs2_dn(d) > up(r * r))) label_ok = false;
-                }
-                // q_{l-1,n} = z_{l-1+n} - z_{l-1}
-                if (kk == l - 1 + n) {
-                    const cd d = {__dsub_rn(t.Z.re, Zlm.re), __dsub_rn(t.Z.im, Zlm.im)};
-                    const double r = up(t.rho + rlm + rnd(d));
-                    if (!(abs2_dn(d) > up(r * r))) label_ok = false;
-                }
+            // q_{l,k} = z_{l+k} - z_l, k a strict divisor of n
+            const int kd = kk - l;
+            if (kd >= 1 && kd < n && ((divmask_n >> kd) & 1u)) {
+                const cd d = {__dsub_rn(t.Z.re, Zl.re), __dsub_rn(t.Z.im, Zl.im)};
+                const double r = up(t.rho + rl + rnd(d));
+                if (!(abs2_dn(d) > up(r * r))) label_ok = false;
+            }
+            // q_{l-1,n} = z_{l-1+n} - z_{l-1}
+            if (kk == l - 1 + n) {
+                const cd d = {__dsub_rn(t.Z.re, Zlm.re), __dsub_rn(t.Z.im, Zlm.im)};
+                const double r = up(t.rho + rlm + rnd(d));
+                if (!(abs2_dn(d) > up(r * r))) label_ok = false;
             }
         }
         const cd P = {__dsub_rn(t.Z.re, Zl.re), __dsub_rn(t.Z.im, Zl.im)};
@@ -163,13 +223,7 @@ __device__ cert_result certify_root(int l_arg, int n, int lab, uint32_t divmask_
         if (abs2_dn(dP) > up(need * need)) {
             res.flags = 2; // MSPLIT_R_CERTIFIED
             res.R = R;
-            if (l == 0 && lab != n) {
-                // Thm proofRoots for p_lab on the same disk
-                const double Pk = up(abs_up(Zk) + up(ek + rnd(Zk)));
-                const double nk = up(up(Pk / R) + up(sk + rnd(DZk)));
-                if (!(abs2_dn(DZk) > up(nk * nk))) label_ok = false;
-            }
-            if (l > 0 && lab != n) label_ok = false;
+            if (lab != n) label_ok = false;
             if (label_ok) res.flags |= 4; // MSPLIT_R_LABEL
             return res;
         }
