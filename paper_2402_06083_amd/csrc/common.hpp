@@ -153,8 +153,13 @@ __device__ __forceinline__ void eval_q_t(int l, int N, C c, C &P, C &dP)
     const T c4r = T(4) * c.re, c2i = T(2) * c.im;
     orbit2_state<T> s = {T(2) * c.re, c2i, T(1), T(0)};
     if (l == 0) {
-#pragma unroll 2
-        for (int k = 1; k < N; ++k) orbit2_step(s, c4r, c2i);
+        // N - 1 steps: an odd one first, then pairs (a loop of two steps with
+        // no remainder: no register copies between the loop and the rest)
+        if ((N - 1) & 1) orbit2_step(s, c4r, c2i);
+        for (int j = (N - 1) >> 1; j > 0; --j) {
+            orbit2_step(s, c4r, c2i);
+            orbit2_step(s, c4r, c2i);
+        }
         P = {T(0.5) * s.ur, T(0.5) * s.ui};
         dP = {s.dr, s.di};
         return;

@@ -793,23 +793,30 @@ constexpr int PREKEY_WINDOW = 8;
 constexpr int COLLECT_BLOCK = 256;
 
 // window = 0 keeps every converged start (candidates that are already
-// identified, where only the sort's identification may decide).  Blocks
-// loop over tiles of COLLECT_BLOCK starts, so that each loads the type
-// tables into LDS once (a load per block and tile cost a full memory latency
-// for every 256 starts).
+// identified, where only the sort's identification may decide).  Tiles of
+// PK_TILE starts, four per thread (launched one tile per block; a smaller
+// grid loops over them): each thread has five starts' loads in flight at
+// once, and the barriers of a tile serve four starts per thread.  A tile
+// inside one type (almost every tile) takes its type from the previous tile
+// or one search, not one search per start, and each start reads its window
+// from LDS before comparing, so that no comparison waits on the one before.
+constexpr int PK_PER = 4;
+constexpr int PK_TILE = COLLECT_BLOCK * PK_PER;
+
 __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const cd *roots, const cd *roots_lo,
                                                            const uint8_t *status, uint32_t *flag, int window)
 {
     __shared__ collect_tables tabs;
-    __shared__ cd zs[COLLECT_BLOCK + PREKEY_WINDOW];
-    __shared__ int ts[COLLECT_BLOCK + PREKEY_WINDOW]; // type, | 1 << 16 when double-double; -1: not converged
+    __shared__ cd zs[PK_TILE + PREKEY_WINDOW];
+    __shared__ int ts[PK_TILE + PREKEY_WINDOW]; // type, | 1 << 16 when double-double; -1: not converged
     load_tables_lds(tabs, b);
-    const int64_t ntiles = (b.n_starts + COLLECT_BLOCK - 1) / COLLECT_BLOCK;
+    const int64_t ntiles = (b.n_starts + PK_TILE - 1) / PK_TILE;
     const bool has1 = threadIdx.x < PREKEY_WINDOW;
-    auto stage = [&](int i, int64_t g, uint8_t st, cd z) {
+    int tc = 0; // type of the last tile (block-uniform)
+    auto stage = [&](int i, int64_t g, uint8_t st, cd z, int tu) {
         int t = -1;
         if (st_converged(st)) {
-            t = find_type_lds(tabs.offs, b.T, g);
+            t = tu >= 0 ? tu : find_type_lds(tabs.offs, b.T, g);
             if (st == ST_DD) {
                 cd lo = roots_lo[g];
                 fold_snap_dd(z, lo, tabs.tau_dd[t]);
@@ -828,39 +835,78 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
         return lo;
     };
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t base = tile * COLLECT_BLOCK - PREKEY_WINDOW;
-        const int64_t g0 = base + threadIdx.x, g1 = base + COLLECT_BLOCK + threadIdx.x;
-        const bool v0 = g0 >= 0 && g0 < b.n_starts, v1 = has1 && g1 < b.n_starts;
-        const uint8_t s0 = v0 ? status[g0] : ST_NONE, s1 = v1 ? status[g1] : ST_NONE;
-        const cd z0 = v0 ? roots[g0] : cd{0.0, 0.0}, z1 = v1 ? roots[g1] : cd{0.0, 0.0};
+        // staged item k of the thread: start base + threadIdx.x + k COLLECT_BLOCK
+        // (k = PK_PER: the last PREKEY_WINDOW starts, threads below PREKEY_WINDOW)
+        const int64_t base = tile * PK_TILE - PREKEY_WINDOW;
+        uint8_t st[PK_PER + 1];
+        cd zz[PK_PER + 1];
+#pragma unroll
+        for (int k = 0; k <= PK_PER; ++k) {
+            const int64_t g = base + threadIdx.x + (int64_t)k * COLLECT_BLOCK;
+            const bool v = (k < PK_PER || has1) && g >= 0 && g < b.n_starts;
+            st[k] = v ? status[g] : ST_NONE;
+            zz[k] = v ? roots[g] : cd{0.0, 0.0};
+        }
         __syncthreads(); // the tables (first tile), or the previous tile's reads
-        stage(threadIdx.x, g0, s0, z0);
-        if (has1) stage(COLLECT_BLOCK + threadIdx.x, g1, s1, z1);
+        // the staged range [lo_g, hi_g] inside type tc: one type for the tile
+        const int64_t lo_g = base > 0 ? base : 0;
+        const int64_t hi_g = min(base + PK_TILE + PREKEY_WINDOW, b.n_starts) - 1;
+        if (!(tabs.offs[tc] <= lo_g && lo_g < tabs.offs[tc + 1])) tc = find_type_lds(tabs.offs, b.T, lo_g);
+        tc = __builtin_amdgcn_readfirstlane(tc);
+        const int tu = hi_g < tabs.offs[tc + 1] ? tc : -1;
+#pragma unroll
+        for (int k = 0; k <= PK_PER; ++k)
+            if (k < PK_PER || has1)
+                stage(threadIdx.x + k * COLLECT_BLOCK, base + threadIdx.x + (int64_t)k * COLLECT_BLOCK, st[k], zz[k],
+                      tu);
         __syncthreads();
-        const int64_t g = tile * COLLECT_BLOCK + threadIdx.x;
-        if (g >= b.n_starts) continue;
-        const int i = threadIdx.x + PREKEY_WINDOW;
-        const int tt = ts[i];
-        uint32_t f = 0;
-        if (tt >= 0) {
-            const int t = tt & 0xffff;
-            const bool dd = (tt >> 16) != 0;
-            const double tau = tabs.tau[t], tdd = tabs.tau_dd[t];
-            const cd z = zs[i], zero = {0.0, 0.0};
-            f = 1;
-            for (int d = 1; d <= window; ++d) {
-                const int tj = ts[i - d];
-                if (tj < 0 || (tj & 0xffff) != t) continue;
-                const bool dj = (tj >> 16) != 0;
+        for (int k = 0; k < PK_PER; ++k) {
+            const int i = PREKEY_WINDOW + threadIdx.x + k * COLLECT_BLOCK;
+            const int64_t g = base + i;
+            if (g >= b.n_starts) break;
+            const int tt = ts[i];
+            uint32_t f = 0;
+            if (tt >= 0) {
+                const int t = tt & 0xffff;
+                const bool dd = (tt >> 16) != 0;
+                const double tau = tabs.tau[t], tdd = tabs.tau_dd[t];
+                const cd z = zs[i], zero = {0.0, 0.0};
+                bool same = false, dd_pair = false;
+                // the window in two halves: each half read from LDS before its
+                // comparisons
+                constexpr int H = PREKEY_WINDOW / 2;
+#pragma unroll
+                for (int h = 0; h < PREKEY_WINDOW; h += H) {
+                    int tj[H];
+                    cd zj[H];
+#pragma unroll
+                    for (int d = 0; d < H; ++d) {
+                        tj[d] = ts[i - 1 - h - d];
+                        zj[d] = zs[i - 1 - h - d];
+                    }
+#pragma unroll
+                    for (int d = 0; d < H; ++d) {
+                        const bool ok = h + d < window && tj[d] >= 0 && (tj[d] & 0xffff) == t;
+                        const bool dj = (tj[d] >> 16) != 0;
+                        if (dd && dj) dd_pair = dd_pair || ok;
+                        else same = same || (ok && same_root(z, zero, dd, zj[d], zero, dj, tau, tdd));
+                    }
+                }
                 // two double-double roots compare with their low parts (rare:
                 // read again from the descents' results)
-                const bool same = dd && dj ? same_root(z, lo_of(g, tdd), true, zs[i - d], lo_of(g - d, tdd), true,
-                                                       tau, tdd)
-                                           : same_root(z, zero, dd, zs[i - d], zero, dj, tau, tdd);
-                if (same) { f = 0; break; }
+                if (!same && dd_pair) {
+                    const cd zl = lo_of(g, tdd);
+                    for (int d = 1; d <= window && !same; ++d) {
+                        const int tjd = ts[i - d];
+                        if (tjd < 0 || (tjd & 0xffff) != t || (tjd >> 16) == 0) continue;
+                        same = same_root(z, zl, true, zs[i - d], lo_of(g - d, tdd), true, tau, tdd);
+                    }
+                }
+                f = same ? 0u : 1u;
             }
+            flag[g] = f;
         }
-        flag[g] = f;
+        __syncthreads(); // the reads above before the next tile's staging
     }
 }
 
@@ -875,12 +921,23 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const c
     load_tables_lds(tabs, b);
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < b.n_starts; g += stride) {
+    int tc = 0; // type of the block's last range (block-uniform)
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < b.n_starts; g0 += stride) {
+        const int64_t g = g0 + threadIdx.x;
+        // the block's range [g0, hi] inside one type: no search per start
+        const int64_t hi = min(g0 + (int64_t)blockDim.x, b.n_starts) - 1;
+        if (!(tabs.offs[tc] <= g0 && g0 < tabs.offs[tc + 1])) tc = find_type_lds(tabs.offs, b.T, g0);
+        tc = __builtin_amdgcn_readfirstlane(tc);
+        if (g >= b.n_starts) continue;
+        // the root is read whether or not the start survived: a line of
+        // eight roots almost always holds a survivor, so this costs no HBM
+        // traffic and the three loads go out together
         const uint32_t f = flag[g];
         const uint32_t p = pos[g];
-        const int t = find_type_lds(tabs.offs, b.T, g);
+        const cd z = roots[g];
+        const int t = hi < tabs.offs[tc + 1] ? tc : find_type_lds(tabs.offs, b.T, g);
         if (f) {
-            keys[p] = root_key(t, fold_snap(roots[g], tabs.tau[t]).re);
+            keys[p] = root_key(t, fold_snap(z, tabs.tau[t]).re);
             vals[p] = (uint32_t)g;
         }
         if (g == tabs.offs[t]) b.surv_offs[t] = (int64_t)p;
@@ -1012,11 +1069,13 @@ __global__ void k_scatter(batch_args b, const uint32_t *flag, const uint32_t *po
 // not do.  One orbit pass serves all divisors.
 __device__ __forceinline__ int classify_p(int n, uint32_t divmask, double tau, cd c)
 {
-    orbit_state<double> s = {0.0, 0.0, 0.0, 0.0};
+    // the orbit on u = 2 p_k from p_1 = c, p_1' = 1; |p_k|^2 = |u|^2 / 4
+    orbit2_state<double> s = {2.0 * c.re, 2.0 * c.im, 1.0, 0.0};
+    const double c4r = 4.0 * c.re, c2i = 2.0 * c.im;
     for (int k = 1; k < n; ++k) {
-        orbit_step(s, c.re, c.im);
+        if (k > 1) orbit2_step(s, c4r, c2i);
         if ((divmask >> k) & 1u) {
-            const double a2 = s.zr * s.zr + s.zi * s.zi;
+            const double a2 = 0.25 * (s.ur * s.ur + s.ui * s.ui);
             const double d2 = s.dr * s.dr + s.di * s.di;
             if (a2 < tau * tau * d2) return k;
         }

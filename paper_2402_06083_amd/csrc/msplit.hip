@@ -674,7 +674,9 @@ collected enqueue_collect(const batch_call &c, const pipe_bufs &B, hipStream_t s
     const batch_args &ba = c.ba;
     const int T = bp.T;
     const unsigned gs = persistent_blocks(bp.n_starts, 256);
-    k_prekeys<<<gs, COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.roots_lo, B.status, B.flag0, window);
+    // one tile of PK_TILE starts per block: the blocks balance over the CUs
+    k_prekeys<<<blocks_for(std::max<int64_t>(bp.n_starts, 1), PK_TILE), COLLECT_BLOCK, 0, stream>>>(
+        ba, B.roots, B.roots_lo, B.status, B.flag0, window);
     scan_u32(B.flag0, B.pos0, B.isz + SZ_STARTS, bp.n_starts, B.part, stream);
     k_compact<<<gs, COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.flag0, B.pos0, B.keys, B.vals);
     uint64_t *skeys = B.keys;
