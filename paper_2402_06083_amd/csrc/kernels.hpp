@@ -702,14 +702,20 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
 constexpr int KEY_TYPE_SHIFT = 50;
 constexpr int KEY_RES = 46;
 constexpr int KEY_BITS = KEY_RES + 2;
+// Bit KEY_BITS of a stored candidate key: the candidate is a double-double
+// root.  The sort orders the KEY_BITS bits below it, so the flag travels with
+// its key (the gather then needs no status of the start).
+constexpr int KEY_DD_BIT = KEY_BITS;
+constexpr uint64_t KEY_POS_MASK = (1ull << KEY_BITS) - 1ull;
 
-__device__ __forceinline__ uint64_t root_key(int t, double re)
+__device__ __forceinline__ uint64_t root_key(int t, double re, bool dd = false)
 {
     const double x = fmin(fmax(re, -2.125), 1.875 - 0x1p-46);
     const int64_t q = (int64_t)floor(x * 0x1p46) + (int64_t)(17ll << 43); // 2.125 2^46
-    return ((uint64_t)t << KEY_TYPE_SHIFT) | (uint64_t)q;
+    return ((uint64_t)t << KEY_TYPE_SHIFT) | ((uint64_t)dd << KEY_DD_BIT) | (uint64_t)q;
 }
 __device__ __forceinline__ int key_type(uint64_t key) { return (int)(key >> KEY_TYPE_SHIFT); }
+__device__ __forceinline__ bool key_dd(uint64_t key) { return (key >> KEY_DD_BIT) & 1ull; }
 
 // Keys i > j of one type with key_i - key_j >= key_window(tau) have
 // re_i - re_j > (key_i - key_j - 1) 2^-KEY_RES >= tau, and so have all
@@ -914,8 +920,9 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
 // grouped by type in start order; surv_offs[t] = the first position of type
 // t, surv_offs[T] = the number of survivors.  Grid-stride: the tables are
 // loaded once per block.
-__global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const cd *roots, const uint32_t *flag,
-                                                           const uint32_t *pos, uint64_t *keys, uint32_t *vals)
+__global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const cd *roots, const uint8_t *status,
+                                                           const uint32_t *flag, const uint32_t *pos, uint64_t *keys,
+                                                           uint32_t *vals)
 {
     __shared__ collect_tables tabs;
     load_tables_lds(tabs, b);
@@ -935,9 +942,10 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const c
         const uint32_t f = flag[g];
         const uint32_t p = pos[g];
         const cd z = roots[g];
+        const uint8_t st = status[g];
         const int t = hi < tabs.offs[tc + 1] ? tc : find_type_lds(tabs.offs, b.T, g);
         if (f) {
-            keys[p] = root_key(t, fold_snap(z, tabs.tau[t]).re);
+            keys[p] = root_key(t, fold_snap(z, tabs.tau[t]).re, st == ST_DD);
             vals[p] = (uint32_t)g;
         }
         if (g == tabs.offs[t]) b.surv_offs[t] = (int64_t)p;
@@ -948,32 +956,34 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const c
 // The sorted candidates, folded and snapped, in sort order: one gather, so
 // that the identification and the output pass read them in sequence.
 // Grid-stride over the m = surv_offs[T] candidates.
-__global__ void k_gather(batch_args b, const cd *roots, const cd *roots_lo, const uint8_t *status,
-                         const uint64_t *keys, const uint32_t *vals, cd *zs, cd *zs_lo, uint8_t *zs_dd)
+// The low part (zs_lo) is written for double-double candidates only, and
+// read only where zs_dd is set.
+__global__ void k_gather(batch_args b, const cd *roots, const cd *roots_lo, const uint64_t *keys,
+                         const uint32_t *vals, cd *zs, cd *zs_lo, uint8_t *zs_dd)
 {
     const int64_t m = b.surv_offs[b.T];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
         const uint32_t v = vals[i];
-        const int t = key_type(keys[i]);
+        const uint64_t key = keys[i];
+        const int t = key_type(key);
         if (v >= b.n_starts || t >= b.T) { // not a sorted candidate: never matches
             const double nan = __longlong_as_double(0x7ff8000000000000ll);
             zs[i] = {nan, nan};
-            zs_lo[i] = {0.0, 0.0};
             zs_dd[i] = 0;
             continue;
         }
         const plan_t &pl = b.types[t].p;
-        cd z = roots[v], lo = {0.0, 0.0};
-        const bool dd = status[v] == ST_DD;
+        cd z = roots[v];
+        const bool dd = key_dd(key);
         if (dd) {
-            lo = roots_lo[v];
+            cd lo = roots_lo[v];
             fold_snap_dd(z, lo, pl.tau_dd);
+            zs_lo[i] = lo;
         } else {
             z = fold_snap(z, pl.tau);
         }
         zs[i] = z;
-        zs_lo[i] = lo;
         zs_dd[i] = dd;
     }
 }
@@ -1006,13 +1016,15 @@ __global__ void k_mark(batch_args b, const uint64_t *keys, const cd *zs, const c
             if (t < b.T) {
                 const double tau = b.types[t].p.tau, tdd = b.types[t].p.tau_dd;
                 const uint64_t win = key_window(tau);
-                const cd zi = zs[i], li = zs_lo[i];
+                const cd zero = {0.0, 0.0};
                 const bool di = zs_dd[i];
+                const cd zi = zs[i], li = di ? zs_lo[i] : zero;
                 int c = 0;
                 for (int64_t j = i - 1; j >= 0 && c < MARK_LOOKBACK; --j, ++c) {
                     const uint64_t kj = keys[j];
-                    if (key_type(kj) != t || ki - kj >= win) break;
-                    if (same_root(zi, li, di, zs[j], zs_lo[j], zs_dd[j], tau, tdd)) { f = 0; break; }
+                    if (key_type(kj) != t || (ki & KEY_POS_MASK) - (kj & KEY_POS_MASK) >= win) break;
+                    const bool dj = zs_dd[j];
+                    if (same_root(zi, li, di, zs[j], di && dj ? zs_lo[j] : zero, dj, tau, tdd)) { f = 0; break; }
                 }
                 cap_hit = f && c == MARK_LOOKBACK;
             }
@@ -1054,9 +1066,10 @@ __global__ void k_scatter(batch_args b, const uint32_t *flag, const uint32_t *po
         if (!flag[i]) continue;
         const uint32_t u = pos[i];
         if (u >= b.n_starts) continue;
+        const bool dd = zs_dd[i];
         uz[u] = zs[i];
-        uz_lo[u] = zs_lo[i];
-        uz_dd[u] = zs_dd[i];
+        uz_lo[u] = dd ? zs_lo[i] : cd{0.0, 0.0};
+        uz_dd[u] = dd;
     }
 }
 

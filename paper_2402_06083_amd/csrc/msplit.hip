@@ -678,7 +678,7 @@ collected enqueue_collect(const batch_call &c, const pipe_bufs &B, hipStream_t s
     k_prekeys<<<blocks_for(std::max<int64_t>(bp.n_starts, 1), PK_TILE), COLLECT_BLOCK, 0, stream>>>(
         ba, B.roots, B.roots_lo, B.status, B.flag0, window);
     scan_u32(B.flag0, B.pos0, B.isz + SZ_STARTS, bp.n_starts, B.part, stream);
-    k_compact<<<gs, COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.flag0, B.pos0, B.keys, B.vals);
+    k_compact<<<gs, COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.status, B.flag0, B.pos0, B.keys, B.vals);
     uint64_t *skeys = B.keys;
     uint32_t *svals = B.vals;
     sort_pairs(&skeys, &svals, B.keys2, B.vals2, ba.surv_offs, B.rtile, T, KEY_BITS, bp.n_starts, B.rcounts,
@@ -687,7 +687,7 @@ collected enqueue_collect(const batch_call &c, const pipe_bufs &B, hipStream_t s
     C.fkeys = skeys == B.keys ? B.keys2 : B.keys;
     C.fvals = svals == B.vals ? B.vals2 : B.vals;
     C.svals = svals;
-    k_gather<<<gs, 256, 0, stream>>>(ba, B.roots, B.roots_lo, B.status, skeys, svals, B.zs, B.zs_lo, B.iters);
+    k_gather<<<gs, 256, 0, stream>>>(ba, B.roots, B.roots_lo, skeys, svals, B.zs, B.zs_lo, B.iters);
     k_mark<<<gs, 256, 0, stream>>>(ba, skeys, B.zs, B.zs_lo, B.iters, B.flag);
     scan_u32(B.flag, B.pos, ba.surv_offs + T, bp.n_starts, B.part, stream);
     k_type_bounds<<<1, 256, 0, stream>>>(ba, B.flag, B.pos);
