@@ -449,7 +449,7 @@ __device__ __noinline__ cert_result certify_root_dd(int l, int n, int lab, uint3
 // those candidates are appended to it for k_certify_dd instead, so that
 // this kernel keeps the registers of the FP64 certificate alone.
 template <bool HARD_LIST, bool P_ONLY = false>
-__global__ void k_certify(batch_args b, const double *re, const double *im, const double *re_lo,
+__global__ void __launch_bounds__(256) k_certify(batch_args b, const double *re, const double *im, const double *re_lo,
                           const double *im_lo, const int32_t *period, uint8_t *flags, double *radius, uint32_t *list)
 {
     const int64_t n_uniq = b.uniq_offs[b.T];

@@ -282,21 +282,32 @@ __global__ void k_seeds(batch_args b, cd *seeds, cd *starts, cd *first)
 // others at |T_s / P - 1| < 2^-2, or when the update is at rounding level:
 // an intermediate point only has to lie in the Newton basin of the next
 // target, and the next target is aimed from the actual value, so no error
-// accumulates.  Lane state is 32-bit (segment index, fine point within the
-// segment).  M, q = M / 4 and F are powers of two: the phase index and the
-// start test are masks, and the M values e^{2 i pi r / M} sit in LDS.
+// accumulates.  M, q = M / 4 and F are powers of two: the phase index and
+// the start test are masks, and the M values e^{2 i pi r / M} sit in LDS.
+//
+// Each segment is walked by two lanes: forward from its seed (fine points
+// 1 .. F/2) and backward from the next seed (F - 1 .. F/2), which halves the
+// longest chain of dependent evaluations and doubles the lanes at work.  Both
+// end on the middle point; where they disagree by more than a tenth of a
+// Newton step, one of them changed turns (a skipped turn lands about
+// 2 pi |P/P'| away) and the segment fails its phase check (k_failed_list).
+// Work item h: segment h >> 1, backward when h is odd.
 // Per-type fields the walk reads, staged in LDS by every block (the lanes
-// keep only their segment, type, fine point and iterate in registers).
+// keep only their item, type, fine point and iterate in registers).
 struct walk_type {
     uint32_t seg_lo;   // first global segment of the type
     uint32_t start_lo; // first global start of the type
     uint32_t seg0;     // first segment of the item on the whole line
-    uint32_t F;        // fine points per segment (a power of two)
+    uint32_t F;        // fine points per segment (a power of two, >= 2)
     int l, N;          // the evaluated polynomial (eval_q_t)
     double level;      // lambda_0
 };
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *seg_flag, cd *first)
+// The middle fine point of a segment from both of its walks, and the squared
+// Newton step there (forward walk).
+struct walk_mid { cd f, b; double s2; };
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *item_flag, walk_mid *mid, cd *first)
 {
     constexpr uint32_t NONE = 0xffffffffu;
     // |T/P - 1| < 2^-5 sqrt(0.9) keeps |P/T - 1| = |v| / |1 + v| below 2^-5
@@ -320,18 +331,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
     }
     __syncthreads();
     unsigned long long *const wc = wave_ctr(b);
-    const uint32_t n_segs = (uint32_t)b.n_segs;
+    const uint32_t n_items = 2u * (uint32_t)b.n_segs;
     int ct = -1;
-    uint32_t cnt[4] = {0u, 0u, 0u, 0u}; // steps, phase failures
-    const int slots[4] = {C_STEPS_WALK, C_PHASE_FAIL, C_STEPS_WALK, C_STEPS_WALK};
-    uint32_t g = NONE; // current segment (global)
+    uint32_t cnt[4] = {0u, 0u, 0u, 0u}; // steps
+    const int slots[4] = {C_STEPS_WALK, C_STEPS_WALK, C_STEPS_WALK, C_STEPS_WALK};
+    uint32_t h = NONE; // current work item
     bool exhausted = false;
     int t = 0;
     // M and q are the same for every type of a call (wave-uniform), powers of two
     const int pl_M = b.types[0].p.M, pl_q = b.types[0].p.q;
     const uint32_t mmask = (uint32_t)pl_M - 1u, qmask = (uint32_t)pl_q - 1u;
     const int qshift = __builtin_ctz((uint32_t)pl_q);
-    uint32_t s = 0, r0 = 0; // fine point within the segment (1..F); (j F) mod M
+    uint32_t s = 0, r0 = 0; // fine point within the segment (1..F-1); (j F) mod M
     int it = 0;
     cd z = {0.0, 0.0};
     // P/P' at the last accepted fine point (the seed first), for the second-order
@@ -339,13 +350,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
     cf gprev = {0.f, 0.f};
     wave_queue wq = wave_queue_start(b.chunk_seg);
     while (true) {
-        const bool need = !exhausted && g == NONE;
-        const uint64_t got = wave_take(wq, &b.gctr[G_SEG_NEXT], b.chunk_seg, n_segs, need);
+        const bool need = !exhausted && h == NONE;
+        const uint64_t got = wave_take(wq, &b.gctr[G_SEG_NEXT], b.chunk_seg, n_items, need);
         if (need) {
-            if (got >= n_segs) {
+            if (got >= n_items) {
                 exhausted = true;
             } else {
-                g = (uint32_t)got;
+                h = (uint32_t)got;
+                const uint32_t g = h >> 1;
                 if (g < wt[t].seg_lo || g >= wt[t + 1].seg_lo) {
                     int lo = 0, hi = b.T; // wt[lo].seg_lo <= g < wt[hi].seg_lo
                     while (hi - lo > 1) {
@@ -356,78 +368,93 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
                 }
                 r0 = ((g - wt[t].seg_lo + wt[t].seg0) * wt[t].F) & mmask;
                 // seed j of the type sits at seed_offs[t] + j = g + t (a type of
-                // S segments has S + 1 seeds)
-                z = seeds[g + (uint32_t)t];
-                s = 1;
+                // S segments has S + 1 seeds); the backward walk starts on seed
+                // j + 1
+                const bool back = h & 1u;
+                z = seeds[g + (uint32_t)t + (back ? 1u : 0u)];
+                s = back ? wt[t].F - 1u : 1u;
                 it = 0;
             }
         }
-        const bool change = g != NONE && t != ct;
+        const bool change = h != NONE && t != ct;
         if (__ballot(change)) {
             wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);
-            cnt[0] = cnt[1] = 0u;
+            cnt[0] = 0u;
             if (change) ct = t;
         }
-        if (__ballot(g != NONE || !exhausted) == 0) break;
-        if (g == NONE) continue;
+        if (__ballot(h != NONE || !exhausted) == 0) break;
+        if (h == NONE) continue;
         cd P, dP;
         eval_q_wave(wt[t].l, wt[t].N, z, P, dP);
         cnt[0] += 1u;
-        // at the seed (P = T_{s-1} there, to rounding) the first update aims
-        // from T_{s-1}: log(T_s / P) = i dphi + log(T_{s-1} / P), whose log
-        // is near 1 where the series below is accurate
-        const bool at_seed = s == 1 && it == 0;
-        const uint32_t r = (r0 + s - (at_seed ? 1u : 0u)) & mmask;
+        const uint32_t g = h >> 1;
+        const bool back = h & 1u;
+        const uint32_t F = wt[t].F, Fh = F >> 1;
+        // at the seed (P = T of the seed's fine point, to rounding) the first
+        // update aims from that point: log(T_s / P) = +-i dphi + log(T_seed / P),
+        // whose log is near 1 where the series below is accurate
+        const bool at_seed = it == 0 && s == (back ? F - 1u : 1u);
+        const uint32_t r = (r0 + s + (at_seed ? (back ? 1u : 0xffffffffu) : 0u)) & mmask;
+        const double dphi = back ? -b.dphi : b.dphi;
         const double lev = wt[t].level;
         const cd T = {lev * cis_l[r], lev * cis_l[64 + r]};
         const cd w = cdiv_fast(T, P);
         const double a2 = cabs2({w.re - 1.0, w.im});
         const cd step = cdiv_fast(P, dP);
+        const uint32_t start0 = wt[t].start_lo + (g - wt[t].seg_lo) * (F >> qshift);
         if (!cfinite(w) || !cfinite(step) || it > 24) {
-            // the starts of the segment not reached yet get no value (NaN:
-            // their descents end as divergent)
+            // the starts of this half not reached yet get no value (NaN:
+            // their descents end as divergent); the middle start is the
+            // forward walk's
             const double nan = __longlong_as_double(0x7ff8000000000000ll);
-            const uint32_t F = wt[t].F;
-            const uint32_t start0 = wt[t].start_lo + (g - wt[t].seg_lo) * (F >> qshift);
-            for (uint32_t s2 = (s + qmask) & ~qmask; s2 < F; s2 += (uint32_t)pl_q) {
-                const uint32_t k = start0 + (s2 >> qshift);
-                starts[k] = {nan, nan};
-                first[k] = {nan, nan};
+            if (!back) {
+                for (uint32_t s2 = (s + qmask) & ~qmask; s2 <= Fh; s2 += (uint32_t)pl_q) {
+                    const uint32_t k = start0 + (s2 >> qshift);
+                    starts[k] = {nan, nan};
+                    first[k] = {nan, nan};
+                }
+            } else {
+                for (uint32_t s2 = s & ~qmask; s2 > Fh; s2 -= (uint32_t)pl_q) {
+                    const uint32_t k = start0 + (s2 >> qshift);
+                    starts[k] = {nan, nan};
+                    first[k] = {nan, nan};
+                }
             }
-            seg_flag[g] = 2;
-            cnt[1] += 1u;
-            g = NONE;
+            item_flag[h] = 2;
+            h = NONE;
             continue;
         }
         cd u0 = clog_series(w);
         if (at_seed) {
             gprev = {(float)step.re, (float)step.im};
-            u0.im += b.dphi;
+            u0.im += dphi;
         }
-        const cd h = cmul(u0, step);
+        const cd hs = cmul(u0, step);
         const bool is_start = (s & qmask) == 0;
-        const bool last = s == wt[t].F;
+        const bool last = s == Fh;
         if (!at_seed && (a2 < (is_start || last ? tol2_start : tol2_mid) ||
-                         cabs2(h) <= 0x1p-96 * fmax(cabs2(z), 0x1p-16))) {
-            if (last) {
-                // the walk must end on the next seed (phase check): a skipped
-                // turn would land about 2 pi |P/P'| away
-                const cd e = csub(z, seeds[g + (uint32_t)t + 1u]);
-                const bool ok = cabs2(e) < 1e-2 * cabs2(step);
-                seg_flag[g] = ok ? 0 : 1;
-                cnt[1] += !ok;
-                g = NONE;
-                continue;
-            }
-            if (is_start) {
-                const uint32_t k = wt[t].start_lo + (g - wt[t].seg_lo) * (wt[t].F >> qshift) + (s >> qshift);
+                         cabs2(hs) <= 0x1p-96 * fmax(cabs2(z), 0x1p-16))) {
+            if (is_start && !(back && last)) {
+                const uint32_t k = start0 + (s >> qshift);
                 starts[k] = z;
                 first[k] = csub(z, step);
             }
-            // aim at the next fine point: log(T_{s+1}/P) = i dphi + log(T_s/P)
-            ++s;
+            if (last) {
+                // the walks of the segment meet here (phase check in k_failed_list)
+                if (back) {
+                    mid[g].b = z;
+                } else {
+                    mid[g].f = z;
+                    mid[g].s2 = cabs2(step);
+                }
+                item_flag[h] = 0;
+                h = NONE;
+                continue;
+            }
+            // aim at the next fine point: log(T_{s+-1}/P) = +-i dphi + log(T_s/P)
+            s += back ? 0xffffffffu : 1u;
             it = 0;
-            u0.im += b.dphi;
+            u0.im += dphi;
             // second order along the level-line flow (uniform phase steps):
             // the change of P/P' since the last accepted point
             const cd dg = {step.re - (double)gprev.re, step.im - (double)gprev.im};
@@ -435,7 +462,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
             gprev = {(float)step.re, (float)step.im};
         } else {
             ++it;
-            z = cadd(z, h);
+            z = cadd(z, hs);
         }
     }
     wave_add4_by_key(wc, C_NCOUNTERS, ct, slots, cnt);

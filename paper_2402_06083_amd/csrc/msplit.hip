@@ -103,10 +103,11 @@ plan_t make_plan(int l, int n, const msplit_options *o)
         F = std::max<int64_t>(8, std::min<int64_t>(128, F));
     }
     F = std::min<int64_t>(F, half);
-    // power of two, multiple of q
+    // power of two, multiple of q, at least 2 (a segment is walked from both
+    // ends to its middle point)
     int64_t f2 = 1;
     while (f2 * 2 <= F) f2 *= 2;
-    F = std::max<int64_t>(f2, p.q);
+    F = std::max<int64_t>(f2, std::max<int64_t>(p.q, 2));
     p.F = F;
     p.S = half / F;
     p.seg0 = 0;
@@ -214,7 +215,7 @@ int make_batch(const int32_t *ln, int npairs, const msplit_options *o, const uin
 // ------------------------------------------------------------- workspace
 struct layout {
     size_t gctr, ctr, spread, isz, cis, types, offs, rtile, seeds, starts, status, iters, segf, flag0, pos0, keys,
-        vals, keys2, vals2, zs, zs_lo, roots, roots_lo, tip_lo, flag, pos, counts, part, total;
+        vals, keys2, vals2, zs, zs_lo, roots, roots_lo, tip_lo, flag, pos, counts, part, mid, total;
 };
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -246,7 +247,8 @@ layout make_layout(const batch_plan &bp)
     L.starts = take(sizeof(cd) * NS);
     L.status = take(NS);
     L.iters = take(NS);
-    L.segf = take(bp.n_segs);
+    L.segf = take(2 * (size_t)bp.n_segs); // one flag per walk (two per segment)
+    L.mid = take(sizeof(walk_mid) * (size_t)bp.n_segs);
     L.flag0 = take(4 * NS);
     L.pos0 = take(4 * NS);
     L.keys = take(8 * NS);
@@ -484,7 +486,7 @@ void setup_args(batch_call &c, char *ws)
     ba.n_seeds = bp.n_seeds;
     ba.n_segs = bp.n_segs;
     ba.n_starts = bp.n_starts;
-    ba.chunk_seg = chunk_for(bp.n_segs);
+    ba.chunk_seg = chunk_for(2 * bp.n_segs); // two walks per segment
     ba.chunk_start = chunk_for(bp.n_starts);
     ba.gctr = ws_at<unsigned long long>(c, c.L.gctr);
     ba.ctr = ws_at<unsigned long long>(c, c.L.ctr);
@@ -568,12 +570,13 @@ void enqueue_level_line(const batch_call &c, hipStream_t stream, hipEvent_t *ev)
     k_seeds<<<persistent_blocks(bp.n_seeds, bs), bs, 0, stream>>>(ba, seeds, starts, first);
     if (ev) (void)hipEventRecord(ev[1], stream);
     // level-line walk
-    k_walk<<<persistent_blocks(bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, ws_at<uint8_t>(c, c.L.segf), first);
+    k_walk<<<persistent_blocks(2 * bp.n_segs, bs), bs, 0, stream>>>(ba, seeds, starts, ws_at<uint8_t>(c, c.L.segf),
+                                                                    ws_at<walk_mid>(c, c.L.mid), first);
     // segments whose walk failed its phase check: starts lifted again in
     // double-double (the list lives in flag0, free until the descents)
     uint32_t *failed = ws_at<uint32_t>(c, c.L.flag0);
-    k_failed_list<<<blocks_for(std::max<int64_t>(bp.n_segs, 1), 256), 256, 0, stream>>>(ba, ws_at<uint8_t>(c, c.L.segf),
-                                                                                     failed);
+    k_failed_list<<<blocks_for(std::max<int64_t>(bp.n_segs, 1), 256), 256, 0, stream>>>(
+        ba, ws_at<uint8_t>(c, c.L.segf), ws_at<walk_mid>(c, c.L.mid), failed);
     k_relift_failed<<<device_cus() * 4, 64, 0, stream>>>(ba, failed, starts, first);
     if (bp.n_tip > 0)
         k_lift_tip_starts<<<blocks_for(bp.n_tip, 64), 64, 0, stream>>>(ba, starts, tip_lo, bp.n_tip, first);
@@ -734,18 +737,20 @@ void enqueue_certify(const batch_args &ba, const msplit_roots &out, bool cert, b
 {
     if (n_max <= 0) return;
     if (cert) {
+        // one root per thread: the blocks balance over the CUs (a persistent
+        // grid held 4 waves per SIMD and ended on its slowest blocks)
         const int32_t *lab = labels ? out.period : nullptr;
         if (out.re_lo && out.im_lo) {
             if (p_only)
-                k_certify<true, true><<<persistent_blocks(n_max, 128), 128, 0, stream>>>(
+                k_certify<true, true><<<blocks_for(n_max, 256), 256, 0, stream>>>(
                     ba, out.re, out.im, out.re_lo, out.im_lo, lab, out.flags, out.radius, hard_c);
             else
-                k_certify<true><<<persistent_blocks(n_max, 128), 128, 0, stream>>>(
+                k_certify<true><<<blocks_for(n_max, 256), 256, 0, stream>>>(
                     ba, out.re, out.im, out.re_lo, out.im_lo, lab, out.flags, out.radius, hard_c);
             k_certify_dd<<<device_cus() * 2, 128, 0, stream>>>(ba, out.re, out.im, out.re_lo, out.im_lo, lab,
                                                                out.flags, out.radius, hard_c);
         } else {
-            k_certify<false><<<persistent_blocks(n_max, 128), 128, 0, stream>>>(
+            k_certify<false><<<blocks_for(n_max, 256), 256, 0, stream>>>(
                 ba, out.re, out.im, nullptr, nullptr, lab, out.flags, out.radius, nullptr);
         }
         // k_separation reads the largest radius of each type
@@ -1498,7 +1503,7 @@ int msplit_certify(int l, int n, msplit_roots *roots, uint64_t count, void *work
     k_init_counters<<<blocks_for((int64_t)C_NCOUNTERS * CTR_SPREAD + G_NCOUNTERS, 256), 256, 0, stream>>>(
         gctr, ctr, spread, 1, nullptr, 0);
     if (count) {
-        k_certify<false><<<persistent_blocks((int64_t)count, 128), 128, 0, stream>>>(
+        k_certify<false><<<blocks_for((int64_t)count, 256), 256, 0, stream>>>(
             ba, roots->re, roots->im, roots->re_lo, roots->im_lo, roots->period, roots->flags, roots->radius,
             nullptr);
         k_fold_counters<<<fold_blocks(1), 256, 0, stream>>>(ctr, spread, 1);

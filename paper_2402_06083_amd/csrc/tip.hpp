@@ -188,10 +188,25 @@ __global__ void k_lift_tip_starts(batch_args b, cd *starts, cd *tip_lo, int64_t 
 
 // Segments whose FP64 walk failed its phase check (seg_flag != 0) to a list
 // (global segment indices, count in G_FAILED_SEGS; one atomic per wave).
-__global__ void k_failed_list(batch_args b, const uint8_t *seg_flag, uint32_t *list)
+// A segment fails when one of its two walks failed, or when they end on the
+// middle point more than a tenth of a Newton step apart (the phase check: a
+// walk that changed turns lands about 2 pi |P/P'| away).  Failures are
+// counted per type (C_PHASE_FAIL) and listed for k_relift_failed.
+__global__ void k_failed_list(batch_args b, const uint8_t *item_flag, const walk_mid *mid, uint32_t *list)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool bad = g < b.n_segs && seg_flag[g] != 0;
+    bool bad = false;
+    if (g < b.n_segs) {
+        bad = item_flag[2 * g] != 0 || item_flag[2 * g + 1] != 0;
+        if (!bad) {
+            const walk_mid m = mid[g];
+            bad = !(cabs2(csub(m.f, m.b)) < 1e-2 * m.s2);
+        }
+        if (bad) {
+            const int t = find_type(b.seg_offs, b.T, g);
+            atomicAdd(&wave_ctr(b)[(int64_t)t * C_NCOUNTERS + C_PHASE_FAIL], 1ull);
+        }
+    }
     wave_append(list, &b.gctr[G_FAILED_SEGS], bad, (uint32_t)g);
 }
 
