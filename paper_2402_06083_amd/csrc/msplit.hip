@@ -351,14 +351,17 @@ void sort_pairs(uint64_t **k, uint32_t **v, uint64_t *k2, uint32_t *v2, const in
 {
     k_rs_tiles<<<1, 64, 0, st>>>(seg, T, tile, n_counts);
     const int64_t tmax = sort_tiles_max(n_max, T);
-    const unsigned grid = (unsigned)std::min<int64_t>(tmax, (int64_t)device_cus() * 4);
+    // the upsweep holds little LDS: 8 blocks per CU; the downsweep's LDS
+    // allows fewer, and 4 per CU measured best
+    const unsigned grid_up = (unsigned)std::min<int64_t>(tmax, (int64_t)device_cus() * 8);
+    const unsigned grid_down = (unsigned)std::min<int64_t>(tmax, (int64_t)device_cus() * 4);
     const rs_segs s = {seg, tile, T};
     uint64_t *ka = *k, *kb = k2;
     uint32_t *va = *v, *vb = v2;
     for (int shift = 0; shift < bits; shift += 8) {
-        k_rs_upsweep<<<grid, SC_BLOCK, 0, st>>>(ka, s, shift, counts);
+        k_rs_upsweep<<<grid_up, SC_BLOCK, 0, st>>>(ka, s, shift, counts);
         scan_u32(counts, counts, n_counts, tmax * RS_BINS, part, st);
-        k_rs_downsweep<<<grid, SC_BLOCK, 0, st>>>(ka, va, kb, vb, s, shift, counts);
+        k_rs_downsweep<<<grid_down, SC_BLOCK, 0, st>>>(ka, va, kb, vb, s, shift, counts);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
