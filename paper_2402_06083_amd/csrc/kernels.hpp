@@ -1109,10 +1109,12 @@ __global__ void k_scatter(batch_args b, const uint32_t *flag, const uint32_t *po
 // not do.  One orbit pass serves all divisors.
 __device__ __forceinline__ int classify_p(int n, uint32_t divmask, double tau, cd c)
 {
-    // the orbit on u = 2 p_k from p_1 = c, p_1' = 1; |p_k|^2 = |u|^2 / 4
+    // the orbit on u = 2 p_k from p_1 = c, p_1' = 1; |p_k|^2 = |u|^2 / 4,
+    // up to the largest strict divisor of n (no test after it)
     orbit2_state<double> s = {2.0 * c.re, 2.0 * c.im, 1.0, 0.0};
     const double c4r = 4.0 * c.re, c2i = 2.0 * c.im;
-    for (int k = 1; k < n; ++k) {
+    const int kmax = divmask ? 31 - __builtin_clz(divmask) : 0;
+    for (int k = 1; k <= kmax; ++k) {
         if (k > 1) orbit2_step(s, c4r, c2i);
         if ((divmask >> k) & 1u) {
             const double a2 = 0.25 * (s.ur * s.ur + s.ui * s.ui);
@@ -1206,7 +1208,9 @@ __device__ __noinline__ int classify_p_dd(int n, uint32_t divmask, double tau, c
 {
     cdd z = {{0.0, 0.0}, {0.0, 0.0}};
     double dr = 0.0, di = 0.0;
-    for (int k = 1; k < n; ++k) {
+    // up to the largest strict divisor of n (no test after it)
+    const int kmax = divmask ? 31 - __builtin_clz(divmask) : 0;
+    for (int k = 1; k <= kmax; ++k) {
         const double tr = z.re.hi * dr - z.im.hi * di, ti = z.re.hi * di + z.im.hi * dr;
         dr = 2.0 * tr + 1.0;
         di = 2.0 * ti;
