@@ -110,7 +110,9 @@ typedef struct msplit_options {
     int32_t precision;        /* msplit_precision, default MSPLIT_FP64 */
     double level;             /* lambda_0: 5 for p_n, 100 for q_{l,n} (Section 4.2) */
     uint32_t points_per_turn; /* M, level-line points per turn: 8 (Section 6.3.1) */
-    uint32_t seg_points;      /* fine level-line points walked per lane: auto */
+    uint32_t seg_points;      /* fine level-line points per segment (a power of two,
+                                 at least 2; each segment is walked from both of
+                                 its seeds to its middle point): auto */
     uint32_t min_cap;         /* Newton cap floor: 20 (Algorithm S_par) */
     double cap_factor;        /* I_N of the cap max{20, I_N log d}: 1 (p), 2.6 (q) */
     uint32_t block_size;      /* threads per block: 256 */

@@ -4,8 +4,9 @@ The tuned knobs are the ones the splitting method leaves free (they change
 the work distribution, never the set of starting points, Section 4.1):
 
 - ``block_size``      threads per block of the persistent kernels (128, 256);
-- ``seg_points``      fine level-line points walked per lane (0 = the
-                      per-type default; else 32 .. 256);
+- ``seg_points``      fine level-line points per segment, walked by two
+                      lanes from its two seeds (0 = the per-type default;
+                      else 64 .. 1024);
 - ``points_per_turn`` M, level-line points per turn (8 or 16: the paper's
                       HPC runs use 8, its hypQuick runs 16, Section 6.3.1);
 - ``fp32_switch``     MIXED only: relative step at which a lane leaves FP32.
@@ -29,7 +30,7 @@ from . import msplit
 
 DEFAULT_SPACE = {
     "block_size": [128, 256],
-    "seg_points": [0, 32, 64, 128, 256],
+    "seg_points": [0, 64, 128, 256, 512, 1024],
     "points_per_turn": [8, 16],
 }
 MIXED_SWITCHES = [2.0 ** -10, 2.0 ** -14, 2.0 ** -18]
