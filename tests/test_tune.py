@@ -8,7 +8,7 @@ from paper_2402_06083_amd import tune
 def test_candidate_space():
     fp64 = list(tune.candidates("fp64"))
     mixed = list(tune.candidates("mixed"))
-    assert len(fp64) == 2 * 5 * 2
+    assert len(fp64) == 2 * 6 * 2
     assert len(mixed) == len(fp64) * len(tune.MIXED_SWITCHES)
     assert all(set(c) <= set(tune.TUNED_FIELDS) for c in mixed)
     assert len({json.dumps(c, sort_keys=True) for c in mixed}) == len(mixed)
