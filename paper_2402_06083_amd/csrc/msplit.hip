@@ -248,13 +248,16 @@ layout make_layout(const batch_plan &bp)
     L.status = take(NS);
     L.iters = take(NS);
     L.segf = take(2 * (size_t)bp.n_segs); // one flag per walk (two per segment)
-    L.mid = take(sizeof(walk_mid) * (size_t)bp.n_segs);
     L.flag0 = take(4 * NS);
     L.pos0 = take(4 * NS);
     L.keys = take(8 * NS);
     L.vals = take(4 * NS);
     L.keys2 = take(8 * NS);
     L.zs = take(sizeof(cd) * NS);
+    // the walks' meeting points live in zs (free until the collection) when
+    // they fit there (segments of at least 4 q fine points), else apart
+    const size_t mid_bytes = sizeof(walk_mid) * (size_t)bp.n_segs;
+    L.mid = mid_bytes <= sizeof(cd) * NS ? L.zs : take(mid_bytes);
     L.zs_lo = take(sizeof(cd) * NS);
     L.roots = take(sizeof(cd) * NS);
     L.roots_lo = take(sizeof(cd) * NS);

@@ -52,6 +52,20 @@ def test_hyperbolic_parity_small(n):
     assert np.all(np.diff(g.re) >= -2.0 ** -45)  # ordered to the key resolution 2^-46
 
 
+@pytest.mark.parametrize("n,seg_points,ppt", [(12, 2, 8), (12, 4, 8), (14, 1024, 8), (12, 4, 16), (13, 2, 16)])
+def test_segment_lengths_match_oracle(n, seg_points, ppt):
+    """Segments from the shortest (one start: the two walks of a segment meet
+    on it, and their meeting points need a buffer of their own) to the
+    longest, with 8 and 16 points per turn: the same root set as the
+    oracle, every root certified, no failed phase check."""
+    from paper_2402_06083_amd import msplit
+    r, g = gpu_split(0, n, seg_points=seg_points, points_per_turn=ppt, certify=True)
+    assert r.status == msplit.OK, (r.status, r.stats)
+    st = r.stats
+    assert st["phase_fail"] == 0 and st["missing"] == 0 and st["certified"] == st["unique"], st
+    compare_sets(g, oracle_split(0, n))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_hyperbolic_parity_n20(precision):
     from paper_2402_06083_amd import msplit
