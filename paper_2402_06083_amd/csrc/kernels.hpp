@@ -833,15 +833,25 @@ constexpr int COLLECT_BLOCK = 256;
 // inside one type (almost every tile) takes its type from the previous tile
 // or one search, not one search per start, and each start reads its window
 // from LDS before comparing, so that no comparison waits on the one before.
+//
+// The survivors of tile k leave as (key, start index) pairs at tile-local
+// positions k PK_TILE + rank (rank: survivors of the tile before it, in start
+// order), tcount[k] their number; k_compact moves them to the scanned
+// positions, so the roots are read once.  surv_offs[t] receives the
+// tile-local rank of type t's first start (made a position by k_compact).
 constexpr int PK_PER = 4;
 constexpr int PK_TILE = COLLECT_BLOCK * PK_PER;
+constexpr int PK_WAVES = COLLECT_BLOCK / 64;
 
 __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const cd *roots, const cd *roots_lo,
-                                                           const uint8_t *status, uint32_t *flag, int window)
+                                                           const uint8_t *status, uint64_t *tkeys, uint32_t *tvals,
+                                                           uint32_t *tcount, int window)
 {
     __shared__ collect_tables tabs;
     __shared__ cd zs[PK_TILE + PREKEY_WINDOW];
     __shared__ int ts[PK_TILE + PREKEY_WINDOW]; // type, | 1 << 16 when double-double; -1: not converged
+    __shared__ uint32_t wcnt[PK_PER][PK_WAVES];  // survivors per (start slot, wave) of the tile
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     load_tables_lds(tabs, b);
     const int64_t ntiles = (b.n_starts + PK_TILE - 1) / PK_TILE;
     const bool has1 = threadIdx.x < PREKEY_WINDOW;
@@ -893,17 +903,18 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
                 stage(threadIdx.x + k * COLLECT_BLOCK, base + threadIdx.x + (int64_t)k * COLLECT_BLOCK, st[k], zz[k],
                       tu);
         __syncthreads();
+        bool surv[PK_PER];
+#pragma unroll
         for (int k = 0; k < PK_PER; ++k) {
             const int i = PREKEY_WINDOW + threadIdx.x + k * COLLECT_BLOCK;
             const int64_t g = base + i;
-            if (g >= b.n_starts) break;
-            const int tt = ts[i];
-            uint32_t f = 0;
+            const int tt = g < b.n_starts ? ts[i] : -1;
+            bool f = false;
             if (tt >= 0) {
                 const int t = tt & 0xffff;
                 const bool dd = (tt >> 16) != 0;
                 const double tau = tabs.tau[t], tdd = tabs.tau_dd[t];
-                const cd z = zs[i], zero = {0.0, 0.0};
+                const cd z = zs[i];
                 bool same = false, dd_pair = false;
                 // the window in two halves: each half read from LDS before its
                 // comparisons
@@ -917,12 +928,14 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
                         tj[d] = ts[i - 1 - h - d];
                         zj[d] = zs[i - 1 - h - d];
                     }
+                    // bitwise, not short-circuit: no branch per comparison
 #pragma unroll
                     for (int d = 0; d < H; ++d) {
-                        const bool ok = h + d < window && tj[d] >= 0 && (tj[d] & 0xffff) == t;
-                        const bool dj = (tj[d] >> 16) != 0;
-                        if (dd && dj) dd_pair = dd_pair || ok;
-                        else same = same || (ok && same_root(z, zero, dd, zj[d], zero, dj, tau, tdd));
+                        const bool ok = (h + d < window) & (tj[d] >= 0) & ((tj[d] & 0xffff) == t);
+                        const bool both = dd & ((tj[d] >> 16) != 0);
+                        const bool near = (fabs(z.re - zj[d].re) < tau) & (fabs(z.im - zj[d].im) < tau);
+                        dd_pair |= ok & both;
+                        same |= ok & !both & near;
                     }
                 }
                 // two double-double roots compare with their low parts (rare:
@@ -935,48 +948,73 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
                         same = same_root(z, zl, true, zs[i - d], lo_of(g - d, tdd), true, tau, tdd);
                     }
                 }
-                f = same ? 0u : 1u;
+                f = !same;
             }
-            flag[g] = f;
+            surv[k] = f;
         }
+        // ranks in start order (slot k of every thread, then slot k + 1):
+        // survivors per (slot, wave) by ballot, then prefix sums
+        uint64_t bal[PK_PER];
+#pragma unroll
+        for (int k = 0; k < PK_PER; ++k) {
+            bal[k] = __ballot(surv[k]);
+            if (lane == 0) wcnt[k][wv] = (uint32_t)__popcll(bal[k]);
+        }
+        __syncthreads();
+        const int64_t tile0 = tile * PK_TILE;
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < PK_PER; ++k) {
+            uint32_t before = 0, all = 0;
+#pragma unroll
+            for (int w = 0; w < PK_WAVES; ++w) {
+                const uint32_t c = wcnt[k][w];
+                before += w < wv ? c : 0u;
+                all += c;
+            }
+            const uint32_t rank = run + before +
+                                  __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[k] >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal[k], 0u));
+            run += all;
+            const int i = PREKEY_WINDOW + threadIdx.x + k * COLLECT_BLOCK;
+            const int64_t g = base + i;
+            if (g >= b.n_starts) continue;
+            if (surv[k]) {
+                const int tt = ts[i];
+                tkeys[tile0 + rank] = root_key(tt & 0xffff, zs[i].re, (tt >> 16) != 0);
+                tvals[tile0 + rank] = (uint32_t)g;
+            }
+            const int t = tu >= 0 ? tu : find_type_lds(tabs.offs, b.T, g);
+            if (g == tabs.offs[t]) b.surv_offs[t] = (int64_t)rank;
+        }
+        if (threadIdx.x == 0) tcount[tile] = run;
         __syncthreads(); // the reads above before the next tile's staging
     }
 }
 
-// Survivors (flag) to their scanned positions as (key, start index) pairs,
-// grouped by type in start order; surv_offs[t] = the first position of type
-// t, surv_offs[T] = the number of survivors.  Grid-stride: the tables are
-// loaded once per block.
-__global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const cd *roots, const uint8_t *status,
-                                                           const uint32_t *flag, const uint32_t *pos, uint64_t *keys,
-                                                           uint32_t *vals)
+// Survivors of each prekeys tile to their positions tpos[k] (the scan of
+// tcount): (key, start index) pairs grouped by type in start order.  Block 0
+// turns surv_offs[t] (a tile-local rank) into the first position of type t,
+// and sets surv_offs[T] = the number of survivors.
+__global__ void __launch_bounds__(COLLECT_BLOCK) k_compact(batch_args b, const uint64_t *tkeys, const uint32_t *tvals,
+                                                           const uint32_t *tcount, const uint32_t *tpos,
+                                                           uint64_t *keys, uint32_t *vals)
 {
-    __shared__ collect_tables tabs;
-    load_tables_lds(tabs, b);
-    __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int tc = 0; // type of the block's last range (block-uniform)
-    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < b.n_starts; g0 += stride) {
-        const int64_t g = g0 + threadIdx.x;
-        // the block's range [g0, hi] inside one type: no search per start
-        const int64_t hi = min(g0 + (int64_t)blockDim.x, b.n_starts) - 1;
-        if (!(tabs.offs[tc] <= g0 && g0 < tabs.offs[tc + 1])) tc = find_type_lds(tabs.offs, b.T, g0);
-        tc = __builtin_amdgcn_readfirstlane(tc);
-        if (g >= b.n_starts) continue;
-        // the root is read whether or not the start survived: a line of
-        // eight roots almost always holds a survivor, so this costs no HBM
-        // traffic and the three loads go out together
-        const uint32_t f = flag[g];
-        const uint32_t p = pos[g];
-        const cd z = roots[g];
-        const uint8_t st = status[g];
-        const int t = hi < tabs.offs[tc + 1] ? tc : find_type_lds(tabs.offs, b.T, g);
-        if (f) {
-            keys[p] = root_key(t, fold_snap(z, tabs.tau[t]).re, st == ST_DD);
-            vals[p] = (uint32_t)g;
+    const int64_t ntiles = (b.n_starts + PK_TILE - 1) / PK_TILE;
+    if (blockIdx.x == 0) {
+        const int64_t total = ntiles ? (int64_t)tpos[ntiles - 1] + tcount[ntiles - 1] : 0;
+        for (int t = threadIdx.x; t <= b.T; t += blockDim.x) {
+            const int64_t g = b.start_offs[t];
+            b.surv_offs[t] = t < b.T && g < b.n_starts ? b.surv_offs[t] + (int64_t)tpos[g / PK_TILE] : total;
         }
-        if (g == tabs.offs[t]) b.surv_offs[t] = (int64_t)p;
-        if (g == b.n_starts - 1) b.surv_offs[b.T] = (int64_t)p + f;
+    }
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t c = tcount[tile];
+        const int64_t dst = tpos[tile], src = tile * PK_TILE;
+        for (uint32_t e = threadIdx.x; e < c; e += blockDim.x) {
+            keys[dst + e] = tkeys[src + e];
+            vals[dst + e] = tvals[src + e];
+        }
     }
 }
 

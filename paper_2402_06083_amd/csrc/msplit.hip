@@ -220,9 +220,9 @@ struct layout {
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// device sizes (int64 slots): the scan of the prekey flags runs over all
-// starts, the scan between the sweeps of the sort over the digit counts
-enum { SZ_STARTS = 0, SZ_COUNTS, SZ_N = 4 };
+// device sizes (int64 slots): the starts, the prekeys tiles (whose survivor
+// counts are scanned), the digit counts scanned between the sweeps of the sort
+enum { SZ_STARTS = 0, SZ_COUNTS, SZ_PKTILES, SZ_N = 4 };
 
 // tiles of the sort: every segment (type) rounds up to whole tiles
 int64_t sort_tiles_max(int64_t n, int T) { return n / RS_TILE + T + 1; }
@@ -285,7 +285,8 @@ __global__ void k_init_counters(unsigned long long *gctr, unsigned long long *ct
     if (i < G_NCOUNTERS) gctr[i] = 0;
     if (i < T * C_NCOUNTERS) ctr[i] = ctr_identity(i % C_NCOUNTERS);
     if (i < T * C_NCOUNTERS * CTR_SPREAD) spread[i] = ctr_identity(i % C_NCOUNTERS);
-    if (isz && i < SZ_N) isz[i] = i == SZ_STARTS ? n_starts : 0;
+    if (isz && i < SZ_N)
+        isz[i] = i == SZ_STARTS ? n_starts : i == SZ_PKTILES ? (n_starts + PK_TILE - 1) / PK_TILE : 0;
 }
 // ctr = the copies combined: sums, except the largest radius (max) and the
 // least separation and least basin radius (min); non-negative doubles order like their bit
@@ -683,11 +684,15 @@ collected enqueue_collect(const batch_call &c, const pipe_bufs &B, hipStream_t s
     const batch_args &ba = c.ba;
     const int T = bp.T;
     const unsigned gs = persistent_blocks(bp.n_starts, 256);
-    // one tile of PK_TILE starts per block: the blocks balance over the CUs
-    k_prekeys<<<blocks_for(std::max<int64_t>(bp.n_starts, 1), PK_TILE), COLLECT_BLOCK, 0, stream>>>(
-        ba, B.roots, B.roots_lo, B.status, B.flag0, window);
-    scan_u32(B.flag0, B.pos0, B.isz + SZ_STARTS, bp.n_starts, B.part, stream);
-    k_compact<<<gs, COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.status, B.flag0, B.pos0, B.keys, B.vals);
+    // one tile of PK_TILE starts per block: the blocks balance over the CUs;
+    // the survivors go tile-local to the sort's spare buffers, their counts
+    // to flag0, whose scan (pos0) places them
+    const int64_t pk_tiles = std::max<int64_t>((bp.n_starts + PK_TILE - 1) / PK_TILE, 1);
+    k_prekeys<<<pk_tiles, COLLECT_BLOCK, 0, stream>>>(ba, B.roots, B.roots_lo, B.status, B.keys2, B.vals2, B.flag0,
+                                                      window);
+    scan_u32(B.flag0, B.pos0, B.isz + SZ_PKTILES, pk_tiles, B.part, stream);
+    k_compact<<<(unsigned)std::min<int64_t>(pk_tiles, (int64_t)device_cus() * 16), COLLECT_BLOCK, 0, stream>>>(
+        ba, B.keys2, B.vals2, B.flag0, B.pos0, B.keys, B.vals);
     uint64_t *skeys = B.keys;
     uint32_t *svals = B.vals;
     sort_pairs(&skeys, &svals, B.keys2, B.vals2, ba.surv_offs, B.rtile, T, KEY_BITS, bp.n_starts, B.rcounts,
