@@ -122,9 +122,10 @@ __device__ __forceinline__ uint32_t label_divmask(int lab, int n, uint32_t divma
 // Thm proofRoots for p_n (and p_lab when lab != n).  UNI: every active lane
 // of the wave certifies a root of the same p_N with label N, and N and dmask
 // are wave-uniform, so the loop and the divisor tests are scalar branches and
-// no state of step lab is kept.
+// no state of step lab is kept.  P, dP: the centres of the last step, the
+// plain values P(c), P'(c) (whether or not the test holds).
 template <bool UNI>
-__device__ __forceinline__ uint8_t certify_p_pass(int N, int lab, uint32_t dmask, cd c, double R)
+__device__ __forceinline__ uint8_t certify_p_pass(int N, int lab, uint32_t dmask, cd c, double R, cd &P, cd &dP)
 { DD_EXACT
     disk_step t = {{0.0, 0.0}, {0.0, 0.0}, 0.0, 0.0, 0.0};
     cd Zk = {0, 0}, DZk = {0, 0};
@@ -140,7 +141,8 @@ __device__ __forceinline__ uint8_t certify_p_pass(int N, int lab, uint32_t dmask
             if (!(abs2_dn(t.Z) > up(r * r))) label_ok = false;
         }
     }
-    const cd P = t.Z, dP = t.DZ;
+    P = t.Z;
+    dP = t.DZ;
     const double Pup = up(abs_up(P) + up(t.e + rnd(P)));
     const double sP = up(t.sig + rnd(dP));
     // Thm proofRoots: R (|P'(c)| - sigma) > |P(c)|
@@ -156,10 +158,14 @@ __device__ __forceinline__ uint8_t certify_p_pass(int N, int lab, uint32_t dmask
 }
 
 // Certify c for P = q_{l,n} (l = 0: p_n) with label lab (p_n: period).
-// The radius is chosen from a plain evaluation: R ~ 4 |P/P'| plus the
-// rounding noise of a root, rounded up to a power of two; then one fused pass
-// carries the centres, the point radii e and the disk radii rho, sigma.
-// If the test fails, R grows by 16 (two more attempts).
+// The radius: R ~ 4 |P/P'| plus the rounding noise of a root, rounded up to a
+// power of two; one fused pass carries the centres, the point radii e and
+// the disk radii rho, sigma.  If the test fails, R grows by 16 (two more
+// attempts).  p_n: the first pass takes R from the noise alone (a converged
+// FP64 root has |P/P'| at rounding level, so this is almost always the same
+// power of two) and needs no plain evaluation first; if it fails, R is taken
+// from its centres P(c), P'(c) and the schedule above follows.  q_{l,n}: R
+// from a plain evaluation.
 // P_ONLY: a p_n-only instance (l = 0), without the registers of the q_{l,n}
 // label tests.
 template <bool P_ONLY = false>
@@ -167,29 +173,44 @@ __device__ cert_result certify_root(int l_arg, int n, int lab, uint32_t divmask_
 { DD_EXACT
     const int l = P_ONLY ? 0 : l_arg;
     const int N = l + n;
-    cd P0, dP0;
-    eval_q(l, N, c, P0, dP0);
     cert_result res = {0, 0.0};
-    if (!cfinite(P0) || !cfinite(dP0)) return res;
-    const double az = sqrt(cabs2(c));
-    double R0 = 4.0 * sqrt(cabs2(P0) / cabs2(dP0)) + 64.0 * U53 * fmax(az, 0x1p-8);
-    if (!(R0 > 0x1p-1000) || !isfinite(R0)) R0 = 0x1p-1000;
-    double R = ldexp(1.0, ilogb(R0) + 1); // power of two above R0
+    if (!cfinite(c)) return res;
+    const double noise = 64.0 * U53 * fmax(sqrt(cabs2(c)), 0x1p-8);
+    // power of two above 4 |P/P'| + noise
+    auto radius_for = [&](cd P0, cd dP0) {
+        double R0 = 4.0 * sqrt(cabs2(P0) / cabs2(dP0)) + noise;
+        if (!(R0 > 0x1p-1000) || !isfinite(R0)) R0 = 0x1p-1000;
+        return ldexp(1.0, ilogb(R0) + 1);
+    };
     if (l == 0) {
         const uint32_t dmask = label_divmask(lab, n, divmask_n);
         const int n0 = __builtin_amdgcn_readfirstlane(n);
         const bool uni = __ballot(n != n0 || lab != n) == 0;
         const uint32_t m0 = __builtin_amdgcn_readfirstlane(dmask);
-        for (int attempt = 0; attempt < 3; ++attempt, R *= 16.0) {
-            const uint8_t f = uni ? certify_p_pass<true>(n0, n0, m0, c, R) : certify_p_pass<false>(n, lab, dmask, c, R);
+        double R = ldexp(1.0, ilogb(noise) + 1);
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            cd P0, dP0;
+            const uint8_t f = uni ? certify_p_pass<true>(n0, n0, m0, c, R, P0, dP0)
+                                  : certify_p_pass<false>(n, lab, dmask, c, R, P0, dP0);
             if (f) {
                 res.flags = f;
                 res.R = R;
                 return res;
             }
+            if (attempt == 0) {
+                if (!cfinite(P0) || !cfinite(dP0)) return res;
+                const double R1 = radius_for(P0, dP0);
+                R = R1 > R ? R1 : 16.0 * R;
+            } else {
+                R *= 16.0;
+            }
         }
         return res;
     }
+    cd P0, dP0;
+    eval_q(l, N, c, P0, dP0);
+    if (!cfinite(P0) || !cfinite(dP0)) return res;
+    double R = radius_for(P0, dP0);
     for (int attempt = 0; attempt < 3; ++attempt, R *= 16.0) {
         disk_step t = {{0.0, 0.0}, {0.0, 0.0}, 0.0, 0.0, 0.0};
         cd Zl = {0, 0}, DZl = {0, 0}, Zlm = {0, 0};
