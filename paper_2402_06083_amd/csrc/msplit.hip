@@ -344,7 +344,6 @@ void scan_u32(const uint32_t *in, uint32_t *out, const int64_t *n_dev, int64_t n
     const int64_t tiles = std::max<int64_t>(1, (n_max + SC_TILE - 1) / SC_TILE);
     const unsigned grid = (unsigned)std::min<int64_t>(tiles, (int64_t)device_cus() * 8);
     k_scan_reduce<<<grid, SC_BLOCK, 0, st>>>(in, n_dev, part);
-    k_scan_parts<<<1, SC_BLOCK, 0, st>>>(part, n_dev, nullptr);
     k_scan_down<<<grid, SC_BLOCK, 0, st>>>(in, out, n_dev, part);
 }
 

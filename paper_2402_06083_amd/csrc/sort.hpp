@@ -46,45 +46,37 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *wsum, u
 }
 
 // ------------------------------------------------------------------ scan
-// out[i] = in[0] + ... + in[i-1] for i < *n (in == out allowed).  Three
-// launches: tile sums, a one-block scan of the tile sums, and the tiles
-// rescanned with their offsets.  part holds ceil(n / SC_TILE) entries.
+// out[i] = in[0] + ... + in[i-1] for i < *n (in == out allowed).  Two
+// launches of the same grid; block b owns the tiles [b k, (b + 1) k) of
+// SC_TILE values, k = ceil(tiles / grid): the first launch writes the sum of
+// each block's values to part[b], the second adds up part[0..b) (at most one
+// value per block of the grid) and rescans its tiles in order, carrying the
+// running sum.  part holds gridDim.x entries.
+__device__ __forceinline__ void scan_range(int64_t tiles, int64_t &t0, int64_t &t1)
+{
+    const int64_t k = (tiles + gridDim.x - 1) / gridDim.x;
+    t0 = min((int64_t)blockIdx.x * k, tiles);
+    t1 = min(t0 + k, tiles);
+}
+
 __global__ void __launch_bounds__(SC_BLOCK) k_scan_reduce(const uint32_t *in, const int64_t *n_dev, uint32_t *part)
 {
     __shared__ uint32_t wsum[4];
     const int64_t n = *n_dev;
-    const int64_t tiles = (n + SC_TILE - 1) / SC_TILE;
-    for (int64_t i = blockIdx.x; i < tiles; i += gridDim.x) {
+    int64_t t0, t1;
+    scan_range((n + SC_TILE - 1) / SC_TILE, t0, t1);
+    uint32_t s = 0;
+    for (int64_t i = t0; i < t1; ++i) {
         const int64_t base = i * SC_TILE;
-        uint32_t s = 0;
 #pragma unroll
         for (int k = 0; k < SC_ROWS; ++k) {
             const int64_t g = base + (int64_t)k * SC_BLOCK + threadIdx.x;
             s += g < n ? in[g] : 0u;
         }
-        uint32_t tot;
-        (void)block_excl_sum(s, wsum, tot);
-        if (threadIdx.x == 0) part[i] = tot;
     }
-}
-
-// One block: exclusive scan of the tile sums in place; the grand total to
-// *total (when non-null).
-__global__ void __launch_bounds__(SC_BLOCK) k_scan_parts(uint32_t *part, const int64_t *n_dev, int64_t *total)
-{
-    __shared__ uint32_t wsum[4];
-    const int64_t n = *n_dev;
-    const int64_t tiles = (n + SC_TILE - 1) / SC_TILE;
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < tiles; base += SC_BLOCK) {
-        const int64_t g = base + threadIdx.x;
-        const uint32_t v = g < tiles ? part[g] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_sum(v, wsum, tot);
-        if (g < tiles) part[g] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && total) *total = (int64_t)carry;
+    uint32_t tot;
+    (void)block_excl_sum(s, wsum, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 __global__ void __launch_bounds__(SC_BLOCK) k_scan_down(const uint32_t *in, uint32_t *out, const int64_t *n_dev,
@@ -92,8 +84,14 @@ __global__ void __launch_bounds__(SC_BLOCK) k_scan_down(const uint32_t *in, uint
 {
     __shared__ uint32_t wsum[4];
     const int64_t n = *n_dev;
-    const int64_t tiles = (n + SC_TILE - 1) / SC_TILE;
-    for (int64_t i = blockIdx.x; i < tiles; i += gridDim.x) {
+    int64_t t0, t1;
+    scan_range((n + SC_TILE - 1) / SC_TILE, t0, t1);
+    if (t0 >= t1) return; // (block-uniform)
+    uint32_t pre = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += SC_BLOCK) pre += part[k];
+    uint32_t carry;
+    (void)block_excl_sum(pre, wsum, carry);
+    for (int64_t i = t0; i < t1; ++i) {
         const int64_t base = i * SC_TILE;
         uint32_t v[SC_ROWS];
 #pragma unroll
@@ -101,7 +99,6 @@ __global__ void __launch_bounds__(SC_BLOCK) k_scan_down(const uint32_t *in, uint
             const int64_t g = base + (int64_t)k * SC_BLOCK + threadIdx.x;
             v[k] = g < n ? in[g] : 0u;
         }
-        uint32_t carry = part[i];
 #pragma unroll
         for (int k = 0; k < SC_ROWS; ++k) {
             uint32_t tot;
