@@ -96,6 +96,7 @@ struct batch_args {
     int64_t *surv_offs;       // sorted candidates per type, set on the device
     const double *cis;        // cos, then sin, of 2 pi s / M, s < 64 (k_cis)
     double dphi;              // 2 pi / M (a kernel argument: wave-uniform, no VGPR)
+    double x_tip_max;         // the largest tip radius of the call's types (0: none)
     int T;
     int64_t n_seeds, n_segs, n_starts;
     uint32_t chunk_seg, chunk_start;
@@ -603,10 +604,13 @@ __global__ void k_descend32(batch_args b, cd *roots, uint8_t *status, uint8_t *i
 // root is too ill-conditioned for an FP64 centre: the certificate needs the
 // image of D(c, R) under the orbit to stay small, R |P'| << 1, and an FP64
 // centre leaves R ~ 2^-46 |z|, so |P'| 2^-46 |z| > 1/16 asks for a
-// double-double centre.
+// double-double centre.  iters[g] receives 1 when the descent ended within
+// x_tip_max (the largest tip radius of the call, a kernel argument) of -2,
+// whatever its status, 0 else: the routing pass reads that byte and tests
+// the root against its type's own radius only where it is set.
 template <bool ROUTE, bool AFTER32>
 __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd *roots, uint8_t *status,
-                                                 const uint8_t *iters)
+                                                 uint8_t *iters)
 {
     constexpr uint32_t NONE = 0xffffffffu;
     unsigned long long *const wc = wave_ctr(b);
@@ -709,6 +713,10 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
         if (st != ST_NONE) {
             roots[g] = z;
             status[g] = st;
+            if (ROUTE) {
+                const double x = b.x_tip_max;
+                iters[g] = ((fabs(z.re + 2.0) < x) & (fabs(z.im) < x)) ? 1 : 0;
+            }
             cnt[1] += st == ST_CONVERGED || st == ST_STALL;
             cnt[2] += st == ST_DIVERGED;
             cnt[3] += st == ST_TIMEOUT;

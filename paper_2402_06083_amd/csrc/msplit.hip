@@ -488,6 +488,8 @@ void setup_args(batch_call &c, char *ws)
     ba.chunk_fp32 = (uint32_t)std::max<int64_t>(64, std::min<int64_t>(4096, (ba.n_fp32 + 8191) / 8192));
     ba.cis = ws_at<double>(c, c.L.cis);
     ba.dphi = 2.0 * M_PI / bp.td[0].p.M;
+    ba.x_tip_max = 0.0;
+    for (int t = 0; t < T; ++t) ba.x_tip_max = std::max(ba.x_tip_max, bp.td[t].p.x_tip);
     ba.T = T;
     ba.n_seeds = bp.n_seeds;
     ba.n_segs = bp.n_segs;
@@ -667,7 +669,7 @@ void enqueue_descents(const batch_call &c, const pipe_bufs &B, hipStream_t strea
         else k_descend<false, false><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
     }
     if (c.any_tip) {
-        k_route_tip<<<blocks_for(bp.n_starts, 256), 256, 0, stream>>>(ba, B.roots, B.status, B.flag0);
+        k_route_tip<<<persistent_blocks(bp.n_starts, ROUTE_ITEMS), 256, 0, stream>>>(ba, B.roots, B.status, B.iters, B.flag0);
         k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, B.flag0, B.starts, B.tip_lo, B.roots, B.roots_lo,
                                                            B.status, 0);
     }

@@ -245,37 +245,101 @@ __global__ void __launch_bounds__(64) k_relift_failed(batch_args b, const uint32
 }
 
 // Routing: starts whose FP64 descent ended within x_tip of -2 (any status:
-// a descent the FP64 rounding derailed there is retried), and descents that
-// stalled at the FP64 precision floor anywhere, go to a list; one atomic per
-// wave.
-__global__ void k_route_tip(batch_args b, const cd *roots, const uint8_t *status, uint32_t *list)
+// a descent the FP64 rounding derailed there is retried; k_descend sets
+// tip[g] within the call's largest radius, and the root is read and tested
+// against its type's radius only there), and descents that stalled at the
+// FP64 precision floor anywhere, go to a list (in no
+// particular order: the double-double descent takes them from a queue).  At
+// high order they are many and scattered, and one atomic per wave on the
+// list's length serialised the pass (p_30: 6.8 ms for 2 GB of status and
+// flags), so each block gathers them in LDS, ROUTE_ITEMS starts per round,
+// and appends its buffer to the list with one atomic when it fills.
+// Grid-stride over rounds of ROUTE_ITEMS starts.
+constexpr int ROUTE_PER = 8;
+constexpr int ROUTE_ITEMS = 256 * ROUTE_PER;
+constexpr int ROUTE_BUF = 2 * ROUTE_ITEMS;
+
+__global__ void __launch_bounds__(256) k_route_tip(batch_args b, const cd *roots, const uint8_t *status,
+                                                   const uint8_t *tip, uint32_t *list)
 {
     __shared__ int64_t offs[MAX_TYPES + 1];
     __shared__ double xt[MAX_TYPES];
+    __shared__ uint32_t buf[ROUTE_BUF];
+    __shared__ uint32_t nbuf;
+    __shared__ unsigned long long base;
     for (int i = threadIdx.x; i <= b.T; i += blockDim.x) {
         offs[i] = b.start_offs[i];
         if (i < b.T) xt[i] = b.types[i].p.x_tip;
     }
+    if (threadIdx.x == 0) nbuf = 0;
     __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool take = false;
-    if (g < b.n_starts && status[g] != ST_NONE) {
-        const int t = find_type_lds(offs, b.T, g);
-        const cd z = roots[g];
-        const double x = xt[t];
-        take = status[g] == ST_STALL || (x > 0.0 && fabs(z.re + 2.0) < x && fabs(z.im) < x);
+    // the buffer to the list (every thread, c read by all after a barrier)
+    auto flush = [&](uint32_t c) {
+        if (threadIdx.x == 0) base = atomicAdd(&b.gctr[G_DD_COUNT], (unsigned long long)c);
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < c; j += blockDim.x) list[base + j] = buf[j];
+        __syncthreads();
+        if (threadIdx.x == 0) nbuf = 0;
+        __syncthreads();
+    };
+    const int lane = threadIdx.x & 63;
+    for (int64_t r0 = (int64_t)blockIdx.x * ROUTE_ITEMS; r0 < b.n_starts; r0 += (int64_t)gridDim.x * ROUTE_ITEMS) {
+        // ROUTE_PER consecutive starts per thread, their status and tip bytes
+        // in one 8-byte load each where the round is whole (r0 and the
+        // workspace arrays are 8-byte aligned)
+        const int64_t g0 = r0 + (int64_t)threadIdx.x * ROUTE_PER;
+        uint8_t st[ROUTE_PER], tp[ROUTE_PER];
+        if (g0 + ROUTE_PER <= b.n_starts) {
+            const uint64_t s8 = *(const uint64_t *)(status + g0), t8 = *(const uint64_t *)(tip + g0);
+#pragma unroll
+            for (int k = 0; k < ROUTE_PER; ++k) {
+                st[k] = (uint8_t)(s8 >> (8 * k));
+                tp[k] = (uint8_t)(t8 >> (8 * k));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < ROUTE_PER; ++k) {
+                st[k] = g0 + k < b.n_starts ? status[g0 + k] : ST_NONE;
+                tp[k] = g0 + k < b.n_starts ? tip[g0 + k] : 0;
+            }
+        }
+        const int t = g0 < b.n_starts ? find_type_lds(offs, b.T, g0) : 0;
+        const int64_t t_end = offs[t + 1]; // a type boundary inside the thread's starts: search again
+#pragma unroll
+        for (int k = 0; k < ROUTE_PER; ++k) {
+            const int64_t g = g0 + k;
+            bool take = false;
+            if (st[k] != ST_NONE) {
+                const int tk = g < t_end ? t : find_type_lds(offs, b.T, g);
+                const double x = xt[tk];
+                if (st[k] == ST_STALL) {
+                    take = true;
+                } else if (x > 0.0 && tp[k] != 0) {
+                    const cd z = roots[g];
+                    take = fabs(z.re + 2.0) < x && fabs(z.im) < x;
+                }
+            }
+            const uint64_t mask = __ballot(take);
+            if (!mask) continue;
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            uint32_t wbase = 0;
+            if (lane == leader) wbase = atomicAdd(&nbuf, (uint32_t)__popcll(mask));
+            wbase = __shfl(wbase, leader, 64);
+            if (take) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                buf[wbase + rank] = (uint32_t)g;
+            }
+        }
+        __syncthreads();
+        const uint32_t c = nbuf; // the same in every thread: nothing changes it before the next barrier
+        __syncthreads();
+        if (c > (uint32_t)(ROUTE_BUF - ROUTE_ITEMS)) flush(c);
     }
-    const unsigned long long mask = __ballot(take);
-    if (!mask) return;
-    const int leader = __ffsll(mask) - 1;
-    unsigned long long base = 0;
-    if (lane_id() == leader) base = atomicAdd(&b.gctr[G_DD_COUNT], (unsigned long long)__popcll(mask));
-    base = read_lane_u64(base, leader);
-    if (take) {
-        const uint32_t rank =
-            __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        list[base + rank] = (uint32_t)g;
-    }
+    __syncthreads();
+    const uint32_t c = nbuf;
+    __syncthreads();
+    if (c) flush(c);
 }
 
 // Double-double Newton descent of the routed starts, from their starting
