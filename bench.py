@@ -50,8 +50,8 @@ FLOPS_WALK_UPDATE = 62
 # HBM traffic of k_descend<false, false> on p_1..p_24 (FETCH_SIZE and WRITE_SIZE
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
-DESCEND_TRAFFIC_BYTES = 1259287246.0
-DESCEND_TRAFFIC_SHA256 = "b0b9f37009042bc1d5daad64d1d874977458f21e4f713f8a895a0b30169230fc"
+DESCEND_TRAFFIC_BYTES = 1258570537.0
+DESCEND_TRAFFIC_SHA256 = "6936e66089fbbf1670e508593fc75d4285cf4133862813a1f795c9bdc3ddeec6"
 
 
 def descend_traffic():
