@@ -248,11 +248,11 @@ __global__ void __launch_bounds__(64) k_relift_failed(batch_args b, const uint32
 // a descent the FP64 rounding derailed there is retried; k_descend sets
 // tip[g] within the call's largest radius, and the root is read and tested
 // against its type's radius only there), and descents that stalled at the
-// FP64 precision floor anywhere, go to a list (in no
-// particular order: the double-double descent takes them from a queue).  At
-// high order they are many and scattered, and one atomic per wave on the
-// list's length serialised the pass (p_30: 6.8 ms for 2 GB of status and
-// flags), so each block gathers them in LDS, ROUTE_ITEMS starts per round,
+// FP64 precision floor anywhere, go to a list (in no particular order: the
+// double-double descent takes them from a queue).  At high order they are
+// many and scattered, and one atomic per wave on the list's length
+// serialised the pass, so each block gathers them in LDS, ROUTE_ITEMS starts
+// per round (each thread's status and flag bytes in one 8-byte load each),
 // and appends its buffer to the list with one atomic when it fills.
 // Grid-stride over rounds of ROUTE_ITEMS starts.
 constexpr int ROUTE_PER = 8;
