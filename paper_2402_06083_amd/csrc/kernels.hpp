@@ -715,7 +715,7 @@ __global__ void __launch_bounds__(256) k_descend(batch_args b, const cd *src, cd
             status[g] = st;
             if (ROUTE) {
                 const double x = b.x_tip_max;
-                iters[g] = ((fabs(z.re + 2.0) < x) & (fabs(z.im) < x)) ? 1 : 0;
+                iters[g] = (uint8_t)((int)(fabs(z.re + 2.0) < x) & (int)(fabs(z.im) < x));
             }
             cnt[1] += st == ST_CONVERGED || st == ST_STALL;
             cnt[2] += st == ST_DIVERGED;
@@ -941,7 +941,7 @@ __global__ void __launch_bounds__(COLLECT_BLOCK) k_prekeys(batch_args b, const c
                     for (int d = 0; d < H; ++d) {
                         const bool ok = (h + d < window) & (tj[d] >= 0) & ((tj[d] & 0xffff) == t);
                         const bool both = dd & ((tj[d] >> 16) != 0);
-                        const bool near = (fabs(z.re - zj[d].re) < tau) & (fabs(z.im - zj[d].im) < tau);
+                        const bool near = (int)(fabs(z.re - zj[d].re) < tau) & (int)(fabs(z.im - zj[d].im) < tau);
                         dd_pair |= ok & both;
                         same |= ok & !both & near;
                     }
