@@ -669,7 +669,9 @@ void enqueue_descents(const batch_call &c, const pipe_bufs &B, hipStream_t strea
         else k_descend<false, false><<<nb, bs, 0, stream>>>(ba, B.roots, B.roots, B.status, B.iters);
     }
     if (c.any_tip) {
-        k_route_tip<<<persistent_blocks(bp.n_starts, ROUTE_ITEMS), 256, 0, stream>>>(ba, B.roots, B.status, B.iters, B.flag0);
+        // (iters holds the descent's tip flags here)
+        k_route_tip<<<persistent_blocks(bp.n_starts, ROUTE_ITEMS), 256, 0, stream>>>(ba, B.roots, B.status, B.iters,
+                                                                                      B.flag0);
         k_descend_dd<<<device_cus() * 4, 256, 0, stream>>>(ba, B.flag0, B.starts, B.tip_lo, B.roots, B.roots_lo,
                                                            B.status, 0);
     }
