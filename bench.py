@@ -51,7 +51,7 @@ FLOPS_WALK_UPDATE = 62
 # per dispatch, scaled by the counts of a 1 GiB device copy), valid for the
 # kernel sources with this fingerprint (profiles/k_descend_batch24_traffic.md)
 DESCEND_TRAFFIC_BYTES = 1258570537.0
-DESCEND_TRAFFIC_SHA256 = "265f88313402ccb408277c888290b4a15edea06d5da3196c77f87bd96b8cc81b"
+DESCEND_TRAFFIC_SHA256 = "656b2dfb152bd8e0779723e92218ca4d1eaa922756fe367397a5c2f5b632409d"
 
 
 def descend_traffic():

@@ -308,7 +308,8 @@ struct walk_type {
 // Newton step there (forward walk).
 struct walk_mid { cd f, b; double s2; };
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *item_flag, walk_mid *mid, cd *first)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_walk(batch_args b, const cd *seeds, cd *starts, uint8_t *item_flag, walk_mid *mid, cd *first)
 {
     constexpr uint32_t NONE = 0xffffffffu;
     // |T/P - 1| < 2^-5 sqrt(0.9) keeps |P/T - 1| = |v| / |1 + v| below 2^-5
